@@ -1,0 +1,126 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only samples analytic initial states; it holds none of the
+method's arithmetic (no operators, fluxes, Riemann solvers or time
+stepping), so both the HIP library's callers and the CPU oracle's tests can
+consume its output.  Initial DG data are nodal values of the conserved
+variables at the Gauss-Legendre points of each cell (sampling points taken
+from numpy's Gauss-Legendre routine); finite-volume data are 16-point
+Gauss-Legendre cell averages.
+
+Workloads (1-D restatements of the paper's test problems, Sec. 2.1):
+  * Euler density wave: rho = 1 + A sin(2 pi k x) (+ seeded uniform noise on
+    the nodal rho), u = 1, p = 1, gamma = 1.4, periodic [0, 1]; the exact
+    solution is the translate rho(x - t).
+  * Euler with two reacting species, uniform state (ODE test): rho = 1,
+    u = 1, p = 1, c1 = 1, c2 = 0.
+  * Shallow water over a Gaussian bump: h = 1 + 0.1 sin(2 pi x),
+    b = 0.2 exp(-100 (x - 0.5)^2), u = 0.
+"""
+
+import numpy as np
+
+
+def gl_points_01(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def cell_points(ncells, n, x0=0.0, x1=1.0):
+    """Physical coordinates of the n Gauss-Legendre points of every cell: [C, n]."""
+    xi, _ = gl_points_01(n)
+    dx = (x1 - x0) / ncells
+    return x0 + dx * (np.arange(ncells)[:, None] + xi[None, :])
+
+
+def _euler_conserved(rho, u, p, gamma):
+    return np.stack([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u], axis=-1)
+
+
+def euler_density_wave(ncells, N, amp=0.2, k=1, noise=0.0, seed=0, gamma=1.4,
+                       x0=0.0, x1=1.0, phase=0.0, velocity=1.0, pressure=1.0):
+    """Nodal conserved state u[C, N+1, 3] of the 1-D density wave."""
+    xs = cell_points(ncells, N + 1, x0, x1)
+    rho = 1.0 + amp * np.sin(2.0 * np.pi * k * xs + phase)
+    if noise:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        rho = rho + rng.uniform(-noise, noise, size=rho.shape)
+    return _euler_conserved(rho, np.full_like(rho, velocity), np.full_like(rho, pressure), gamma)
+
+
+def euler_density_wave_exact(x, t, amp=0.2, k=1, velocity=1.0):
+    return 1.0 + amp * np.sin(2.0 * np.pi * k * (x - velocity * t))
+
+
+def euler_react_uniform(ncells, N, gamma=1.4, c1=1.0, c2=0.0):
+    """Uniform state of the ODE test: u[C, N+1, 5]."""
+    shape = (ncells, N + 1)
+    base = _euler_conserved(np.ones(shape), np.ones(shape), np.ones(shape), gamma)
+    return np.concatenate([base, np.full(shape + (1,), c1), np.full(shape + (1,), c2)], axis=-1)
+
+
+def swe_bump_fields(x):
+    h = 1.0 + 0.1 * np.sin(2.0 * np.pi * x)
+    b = 0.2 * np.exp(-100.0 * (x - 0.5) ** 2)
+    return h, np.zeros_like(h), b
+
+
+def swe_bump_nodal(ncells, N, x0=0.0, x1=1.0):
+    """Nodal (h, hu, b) at the GL points: u[C, N+1, 3]."""
+    h, hu, b = swe_bump_fields(cell_points(ncells, N + 1, x0, x1))
+    return np.stack([h, hu, b], axis=-1)
+
+
+def swe_bump_averages(ncells, x0=0.0, x1=1.0, npts=16):
+    """16-point Gauss-Legendre cell averages of (h, hu, b): v[C, 3]."""
+    xs = cell_points(ncells, npts, x0, x1)
+    _, w = gl_points_01(npts)
+    h, hu, b = swe_bump_fields(xs)
+    return np.stack([h @ w, hu @ w, b @ w], axis=-1)
+
+
+def smooth_averages(ncells, func, x0=0.0, x1=1.0, npts=16):
+    """16-point GL cell averages of an arbitrary scalar function."""
+    xs = cell_points(ncells, npts, x0, x1)
+    _, w = gl_points_01(npts)
+    return func(xs) @ w
+
+
+def advection_nodal(ncells, N, func, x0=0.0, x1=1.0):
+    return func(cell_points(ncells, N + 1, x0, x1))[..., None]
+
+
+def batched_euler_problems(nprob=256, seed=0, cmin=1_000, cmax=100_000, degrees=range(1, 8)):
+    """Specs of independent Euler density-wave problems: log-uniform cell counts,
+    uniform degrees, seeded wave numbers 1..4 and phases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    degrees = list(degrees)
+    out = []
+    for i in range(nprob):
+        ncells = int(round(np.exp(rng.uniform(np.log(cmin), np.log(cmax)))))
+        N = int(degrees[rng.integers(len(degrees))])
+        k = int(rng.integers(1, 5))
+        phase = float(rng.uniform(0.0, 2.0 * np.pi))
+        out.append({"id": i, "pde": "euler", "N": N, "ncells": ncells, "k": k, "phase": phase})
+    return out
+
+
+def request_trace(nreq=2000, rate=200.0, seed=0, degrees=range(2, 10), cmin=1_000,
+                  cmax=200_000, smin=50, smax=500):
+    """Poisson arrival trace of solve requests (Euler or shallow-water DG)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    degrees = list(degrees)
+    t = 0.0
+    out = []
+    for i in range(nreq):
+        t += rng.exponential(1.0 / rate)
+        out.append({
+            "id": i, "arrival": t,
+            "pde": "euler" if rng.uniform() < 0.5 else "swe",
+            "N": int(degrees[rng.integers(len(degrees))]),
+            "ncells": int(round(np.exp(rng.uniform(np.log(cmin), np.log(cmax))))),
+            "steps": int(rng.integers(smin, smax + 1)),
+            "k": int(rng.integers(1, 5)),
+            "phase": float(rng.uniform(0.0, 2.0 * np.pi)),
+        })
+    return out
