@@ -1,0 +1,181 @@
+"""Thin ctypes binding of include/aderdg.h (argument marshalling only).
+
+Every entry point keeps its C name.  Buffers may be torch tensors on the HIP
+device (their data_ptr() is passed) or raw integer device addresses.  All
+compute happens in libaderdg.so; if the library is missing, load() raises.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.environ.get("ADERDG_LIB", os.path.join(HERE, "libaderdg.so"))
+
+ADERDG_OK = 0
+ADERDG_E_INVAL = -1
+ADERDG_E_NOMEM = -2
+ADERDG_E_DEVICE = -3
+ADERDG_E_NOCONV = -4
+ADERDG_E_NONPHYS = -5
+
+PDE_ADVECTION, PDE_EULER, PDE_EULER_REACT, PDE_SWE = 0, 1, 2, 3
+FP64, FP32_PREDICTOR = 0, 1
+BC_PERIODIC = 0
+CFL_SUBCELL, CFL_NODAL = 0, 1
+SCHEME_DG, SCHEME_FV = 0, 1
+NVARS = {PDE_ADVECTION: 1, PDE_EULER: 3, PDE_EULER_REACT: 5, PDE_SWE: 3}
+
+EXPORTS = ["aderdg_init", "aderdg_predict", "aderdg_correct", "aderdg_step", "aderweno_step",
+           "aderdg_free", "aderdg_set_stream", "aderdg_sweep_count", "aderdg_operators",
+           "aderdg_last_error"]
+
+
+class PdeDesc(ctypes.Structure):
+    _fields_ = [("pde", ctypes.c_int32), ("nvars", ctypes.c_int32), ("gamma", ctypes.c_double),
+                ("g", ctypes.c_double), ("omega", ctypes.c_double), ("adv_speed", ctypes.c_double)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("bc", ctypes.c_int32), ("ncells", ctypes.c_int64),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("fixed_dt", ctypes.c_double), ("cfl_mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("picard_tol", ctypes.c_double),
+                ("picard_max_iter", ctypes.c_int32), ("scheme", ctypes.c_int32)]
+
+
+class AderdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"aderdg error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path=None):
+    """Load libaderdg.so (once).  Raises if it is absent: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIBPATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"{p} not built; run `python -m paper_2409_12483_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.aderdg_init.argtypes = [ctypes.POINTER(PdeDesc), ctypes.POINTER(Config), i32, vp, ctypes.POINTER(vp)]
+    lib.aderdg_predict.argtypes = [vp, i32, vp, dbl, dbl, vp, vp]
+    lib.aderdg_correct.argtypes = [vp, i32, vp, vp, dbl, dbl, vp]
+    lib.aderdg_step.argtypes = [vp, ctypes.POINTER(vp), vp, vp, vp, vp, i32]
+    lib.aderweno_step.argtypes = [vp, ctypes.POINTER(vp), vp, vp, vp, vp, i32]
+    lib.aderdg_free.argtypes = [vp]
+    lib.aderdg_set_stream.argtypes = [vp, vp]
+    lib.aderdg_sweep_count.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    lib.aderdg_operators.argtypes = [i32, ctypes.POINTER(dbl), i64]
+    lib.aderdg_last_error.argtypes = []
+    lib.aderdg_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _check(rc):
+    if rc != ADERDG_OK:
+        raise AderdgError(rc, aderdg_last_error())
+    return rc
+
+
+def _current_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def pde_desc(pde, gamma=1.4, g=9.81, omega=1.0, adv_speed=1.0):
+    return PdeDesc(pde, NVARS[pde], gamma, g, omega, adv_speed)
+
+
+def config(N, ncells, x0=0.0, x1=1.0, cfl=0.4, fixed_dt=0.0, cfl_mode=CFL_SUBCELL,
+           precision=FP64, picard_tol=0.0, picard_max_iter=0, scheme=SCHEME_DG):
+    return Config(N, BC_PERIODIC, ncells, x0, x1, cfl, fixed_dt, cfl_mode, precision,
+                  picard_tol, picard_max_iter, scheme)
+
+
+def aderdg_init(pdes, cfgs, stream=None):
+    """Returns an opaque handle (int).  stream: HIP stream handle (default: torch's current)."""
+    lib = load()
+    n = len(pdes)
+    P = (PdeDesc * n)(*pdes)
+    C = (Config * n)(*cfgs)
+    h = ctypes.c_void_p()
+    s = _current_stream() if stream is None else stream
+    _check(lib.aderdg_init(P, C, n, s, ctypes.byref(h)))
+    return h.value
+
+
+def aderdg_predict(h, k, u, t, dt, q_out, iters_out=None):
+    return _check(load().aderdg_predict(h, k, _ptr(u), t, dt, _ptr(q_out), _ptr(iters_out)))
+
+
+def aderdg_correct(h, k, u, q, t, dt, u_next):
+    return _check(load().aderdg_correct(h, k, _ptr(u), _ptr(q), t, dt, _ptr(u_next)))
+
+
+def _ptr_array(states):
+    arr = (ctypes.c_void_p * len(states))(*[_ptr(s) for s in states])
+    return arr
+
+
+def aderdg_step(h, u, t, t_end, dt, status, nsteps):
+    return _check(load().aderdg_step(h, _ptr_array(u), _ptr(t), _ptr(t_end), _ptr(dt), _ptr(status), nsteps))
+
+
+def aderweno_step(h, v, t, t_end, dt, status, nsteps):
+    return _check(load().aderweno_step(h, _ptr_array(v), _ptr(t), _ptr(t_end), _ptr(dt), _ptr(status), nsteps))
+
+
+def aderdg_free(h):
+    return _check(load().aderdg_free(h))
+
+
+def aderdg_set_stream(h, stream):
+    return _check(load().aderdg_set_stream(h, stream))
+
+
+def aderdg_sweep_count(h, k):
+    v = ctypes.c_int64()
+    _check(load().aderdg_sweep_count(h, k, ctypes.byref(v)))
+    return v.value
+
+
+def aderdg_operators(N):
+    """Host-only operator tables: dict of numpy arrays (no device involved)."""
+    import numpy as np
+    n = N + 1
+    Ns = 2 * N + 1
+    cap = 2 * n + 3 * n * n + 2 * n + Ns * n
+    buf = (ctypes.c_double * cap)()
+    got = load().aderdg_operators(N, buf, cap)
+    if got < 0:
+        _check(got)
+    a = np.frombuffer(buf, dtype=np.float64, count=cap).copy()
+    o = 0
+    out = {}
+    for name, size, shape in [("xi", n, (n,)), ("w", n, (n,)), ("ktil", n * n, (n, n)),
+                              ("kappa", n * n, (n, n)), ("Dtil", n * n, (n, n)),
+                              ("psi0", n, (n,)), ("psi1", n, (n,)), ("P", Ns * n, (Ns, n))]:
+        out[name] = a[o:o + size].reshape(shape)
+        o += size
+    return out
+
+
+def aderdg_last_error():
+    msg = load().aderdg_last_error()
+    return msg.decode() if msg else ""

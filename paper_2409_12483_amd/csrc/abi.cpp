@@ -1,0 +1,477 @@
+// Host side of the C ABI declared in include/aderdg.h.
+//
+// A handle owns, per problem, a device scratch state (ping-pong partner of
+// the caller's buffer: a fused step reads neighbour cells of u^n while other
+// workgroups write u^{n+1}, so the update cannot be in place) and a device
+// clock (time, rotating signal-speed maxima, last dt, status, sweep count).
+// Problems sharing (scheme, PDE, N, precision) form a launch group served by
+// one kernel launch per step; a workgroup finds its problem by binary search
+// on the group's tile prefix.  Nothing here synchronises the host during
+// aderdg_step / aderweno_step unless the caller's state pointers changed
+// since the previous call (then the group's pointer table is re-uploaded
+// after a stream synchronisation).
+#include "../../include/aderdg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "launch.hpp"
+#include "operators.hpp"
+
+using namespace aderdg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  return fail(ADERDG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int model_nvars(int pde) {
+  switch (pde) {
+    case ADERDG_PDE_ADVECTION: return 1;
+    case ADERDG_PDE_EULER: return 3;
+    case ADERDG_PDE_EULER_REACT: return 5;
+    case ADERDG_PDE_SWE: return 3;
+    default: return -1;
+  }
+}
+
+std::mutex g_tables_mutex;
+std::set<int> g_tables_devices;
+
+int ensure_tables(int device) {
+  std::lock_guard<std::mutex> lock(g_tables_mutex);
+  if (g_tables_devices.count(device)) return ADERDG_OK;
+  static DevOps ops[kDevMaxn];
+  static DevOpsF opsf[kDevMaxn];
+  static DevWeno weno[2];
+  std::memset(ops, 0, sizeof(ops));
+  std::memset(opsf, 0, sizeof(opsf));
+  std::memset(weno, 0, sizeof(weno));
+  for (int N = 0; N < kDevMaxn; ++N) {
+    OpTables t;
+    if (!build_op_tables(N, t)) return fail(ADERDG_E_DEVICE, "operator construction failed");
+    const int n = N + 1;
+    for (int i = 0; i < n; ++i) {
+      ops[N].xi[i] = t.xi[i];
+      ops[N].w[i] = t.w[i];
+      ops[N].winv[i] = 1.0 / t.w[i];
+      ops[N].psi0[i] = t.psi0[i];
+      ops[N].psi1[i] = t.psi1[i];
+      for (int j = 0; j < n; ++j) {
+        ops[N].ktil[i][j] = t.ktil[i][j];
+        ops[N].kappa[i][j] = t.kappa[i][j];
+        ops[N].Dtil[i][j] = t.Dtil[i][j];
+        opsf[N].ktil[i][j] = (float)t.ktil[i][j];
+        opsf[N].kappa[i][j] = (float)t.kappa[i][j];
+      }
+    }
+    for (int s = 0; s < t.Ns; ++s)
+      for (int k = 0; k < n; ++k) ops[N].P[s][k] = t.P[s][k];
+  }
+  for (int wi = 0; wi < 2; ++wi) {
+    WenoTables w;
+    if (!build_weno_tables(2 * (wi + 1), w)) return fail(ADERDG_E_DEVICE, "WENO table construction failed");
+    for (int s = 0; s < 3; ++s)
+      for (int i = 0; i < w.n; ++i)
+        for (int j = 0; j < w.n; ++j) {
+          weno[wi].R[s][i][j] = w.R[s][i][j];
+          weno[wi].S[s][i][j] = w.S[s][i][j];
+        }
+  }
+  hipError_t e = upload_tables(ops, opsf, weno);
+  if (e != hipSuccess) return fail_hip(e, "upload of operator tables");
+  g_tables_devices.insert(device);
+  return ADERDG_OK;
+}
+
+struct Group {
+  int scheme, pde, N, prec;
+  std::vector<int> pids;
+  std::vector<ProbDev> host;
+  ProbDev* dev = nullptr;
+  int64_t blocks = 0;       // step kernel workgroups
+  int64_t lam_blocks = 0;   // lambda kernel workgroups
+  std::vector<ProbDev> lam_host;
+  ProbDev* lam_dev = nullptr;
+  bool any_cfl = false;
+};
+
+}  // namespace
+
+struct aderdg_handle {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int nprob = 0;
+  std::vector<aderdg_pde_desc> pdes;
+  std::vector<aderdg_config> cfgs;
+  std::vector<double*> scratch;
+  std::vector<int64_t> elems;          // doubles of state per problem
+  std::vector<ProbDev> single_host;    // per-problem descriptor for the standalone kernels
+  ProbDev* single_dev = nullptr;
+  ProbClock* clocks = nullptr;
+  std::vector<Group> groups;
+};
+
+namespace {
+
+void release(aderdg_handle* h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
+  for (double* p : h->scratch) if (p) hipFree(p);
+  for (Group& g : h->groups) {
+    if (g.dev) hipFree(g.dev);
+    if (g.lam_dev) hipFree(g.lam_dev);
+  }
+  if (h->single_dev) hipFree(h->single_dev);
+  if (h->clocks) hipFree(h->clocks);
+  delete h;
+}
+
+int validate(const aderdg_pde_desc& p, const aderdg_config& c, int k) {
+  char buf[256];
+  auto bad = [&](const char* what) {
+    std::snprintf(buf, sizeof(buf), "problem %d: %s", k, what);
+    return fail(ADERDG_E_INVAL, buf);
+  };
+  const int M = model_nvars(p.pde);
+  if (M < 0) return bad("unknown pde");
+  if (p.nvars != M) return bad("nvars does not match the model");
+  if ((p.pde == ADERDG_PDE_EULER || p.pde == ADERDG_PDE_EULER_REACT) && !(p.gamma > 1.0))
+    return bad("gamma must be > 1");
+  if (p.pde == ADERDG_PDE_SWE && !(p.g > 0.0)) return bad("g must be > 0");
+  if (!std::isfinite(p.omega) || !std::isfinite(p.adv_speed)) return bad("non-finite model parameter");
+  if (c.scheme != ADERDG_SCHEME_DG && c.scheme != ADERDG_SCHEME_FV) return bad("unknown scheme");
+  if (c.scheme == ADERDG_SCHEME_DG && (c.N < 1 || c.N > kMaxN)) return bad("DG degree N must be in 1..9");
+  if (c.scheme == ADERDG_SCHEME_FV && c.N != 2 && c.N != 4) return bad("WENO degree N must be 2 or 4");
+  if (c.bc != ADERDG_BC_PERIODIC) return bad("only periodic boundaries are supported");
+  if (c.ncells < 1) return bad("ncells must be >= 1");
+  if (c.scheme == ADERDG_SCHEME_FV && c.ncells < 2 * c.N + 1) return bad("FV needs ncells >= 2N+1");
+  if (c.ncells > (int64_t)1 << 34) return bad("ncells too large");
+  if (!(std::isfinite(c.x0) && std::isfinite(c.x1) && c.x1 > c.x0)) return bad("need finite x1 > x0");
+  if (!(c.fixed_dt > 0.0) && !(c.cfl > 0.0 && c.cfl <= 1.0)) return bad("cfl must be in (0, 1]");
+  if (!std::isfinite(c.fixed_dt)) return bad("non-finite fixed_dt");
+  if (c.cfl_mode != ADERDG_CFL_SUBCELL && c.cfl_mode != ADERDG_CFL_NODAL) return bad("unknown cfl_mode");
+  if (c.precision != ADERDG_FP64 && c.precision != ADERDG_FP32_PREDICTOR) return bad("unknown precision");
+  if (!std::isfinite(c.picard_tol)) return bad("non-finite picard_tol");
+  if (c.picard_max_iter > 100000) return bad("picard_max_iter too large");
+  return ADERDG_OK;
+}
+
+ProbDev make_probdev(const aderdg_handle* h, int k) {
+  const aderdg_pde_desc& p = h->pdes[k];
+  const aderdg_config& c = h->cfgs[k];
+  ProbDev d;
+  std::memset(&d, 0, sizeof(d));
+  d.state[0] = nullptr;
+  d.state[1] = h->scratch[k];
+  d.ncells = c.ncells;
+  d.x0 = c.x0;
+  d.dx = (c.x1 - c.x0) / (double)c.ncells;
+  d.cfl = c.cfl;
+  d.fixed_dt = c.fixed_dt > 0.0 ? c.fixed_dt : 0.0;
+  d.tol = c.picard_tol > 0.0 ? c.picard_tol : (c.precision == ADERDG_FP32_PREDICTOR ? 1e-6 : 1e-14);
+  d.max_iter = c.picard_max_iter > 0 ? c.picard_max_iter : 64;
+  d.cfl_mode = c.cfl_mode;
+  d.pid = k;
+  d.pp.gamma = p.gamma;
+  d.pp.g = p.g;
+  d.pp.omega = p.omega;
+  d.pp.a = p.adv_speed;
+  return d;
+}
+
+int upload_group(aderdg_handle* h, Group& g) {
+  hipError_t e = hipMemcpy(g.dev, g.host.data(), sizeof(ProbDev) * g.host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail_hip(e, "upload of problem table");
+  e = hipMemcpy(g.lam_dev, g.lam_host.data(), sizeof(ProbDev) * g.lam_host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail_hip(e, "upload of problem table");
+  return ADERDG_OK;
+}
+
+// Point the group's tables at the caller's state buffers; re-upload on change.
+int bind_states(aderdg_handle* h, Group& g, double* const* u) {
+  bool changed = false;
+  for (size_t i = 0; i < g.pids.size(); ++i) {
+    double* p = u[g.pids[i]];
+    if (!p) return fail(ADERDG_E_INVAL, "null state pointer for problem " + std::to_string(g.pids[i]));
+    if (g.host[i].state[0] != p) {
+      g.host[i].state[0] = p;
+      g.lam_host[i].state[0] = p;
+      changed = true;
+    }
+  }
+  if (!changed) return ADERDG_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipStreamIsCapturing(h->stream, &cs);
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(ADERDG_E_INVAL, "state pointers changed during stream capture; call once eagerly first");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "stream synchronize");
+  return upload_group(h, g);
+}
+
+int run_steps(aderdg_handle* h, int scheme, double* const* u, double* t, const double* t_end,
+              double* dt, int32_t* status, int32_t nsteps) {
+  if (!h) return fail(ADERDG_E_INVAL, "null handle");
+  if (!u || !t || !t_end || !dt || !status) return fail(ADERDG_E_INVAL, "null argument");
+  if (nsteps < 0) return fail(ADERDG_E_INVAL, "nsteps must be >= 0");
+  std::vector<Group*> gs;
+  for (Group& g : h->groups)
+    if (g.scheme == scheme) gs.push_back(&g);
+  for (Group* g : gs) {
+    int rc = bind_states(h, *g, u);
+    if (rc) return rc;
+  }
+  hipError_t e = launch_clock_begin(h->clocks, t, h->nprob, h->stream);
+  if (e != hipSuccess) return fail_hip(e, "clock kernel");
+  if (nsteps > 0) {
+    for (Group* g : gs) {
+      if (!g->any_cfl) continue;
+      StepArgs A{};
+      A.probs = g->lam_dev;
+      A.nprob = (int)g->pids.size();
+      A.clocks = h->clocks;
+      A.t_end = t_end;
+      e = launch_lambda(g->pde, g->N, scheme == ADERDG_SCHEME_DG, A, g->lam_blocks, h->stream);
+      if (e != hipSuccess) return fail_hip(e, "lambda kernel");
+    }
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    for (Group* g : gs) {
+      StepArgs A{};
+      A.probs = g->dev;
+      A.nprob = (int)g->pids.size();
+      A.clocks = h->clocks;
+      A.t_end = t_end;
+      A.step = s;
+      e = scheme == ADERDG_SCHEME_DG ? launch_dg(g->pde, g->N, g->prec, 2, A, g->blocks, h->stream)
+                                      : launch_fv(g->pde, g->N, g->prec, A, g->blocks, h->stream);
+      if (e != hipSuccess) return fail_hip(e, "step kernel");
+    }
+  }
+  e = launch_clock_end(h->clocks, t, dt, status, h->nprob, nsteps & 1, h->stream);
+  if (e != hipSuccess) return fail_hip(e, "clock kernel");
+  if (nsteps & 1) {
+    for (Group* g : gs)
+      for (size_t i = 0; i < g->pids.size(); ++i) {
+        const int k = g->pids[i];
+        e = launch_copy(h->scratch[k], u[k], h->elems[k], h->stream);
+        if (e != hipSuccess) return fail_hip(e, "copy kernel");
+      }
+  }
+  return ADERDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t nprob,
+                void* hip_stream, aderdg_handle** out) {
+  g_last_error.clear();
+  if (!pdes || !cfgs || !out) return fail(ADERDG_E_INVAL, "null argument");
+  if (nprob < 1) return fail(ADERDG_E_INVAL, "nprob must be >= 1");
+  for (int k = 0; k < nprob; ++k) {
+    int rc = validate(pdes[k], cfgs[k], k);
+    if (rc) return rc;
+  }
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  int rc = ensure_tables(device);
+  if (rc) return rc;
+
+  aderdg_handle* h = new aderdg_handle();
+  h->stream = (hipStream_t)hip_stream;
+  h->device = device;
+  h->nprob = nprob;
+  h->pdes.assign(pdes, pdes + nprob);
+  h->cfgs.assign(cfgs, cfgs + nprob);
+  h->scratch.assign(nprob, nullptr);
+  h->elems.assign(nprob, 0);
+  for (int k = 0; k < nprob; ++k) {
+    const aderdg_config& c = cfgs[k];
+    const int64_t per_cell = c.scheme == ADERDG_SCHEME_DG ? (int64_t)(c.N + 1) * pdes[k].nvars : pdes[k].nvars;
+    h->elems[k] = per_cell * c.ncells;
+    e = hipMalloc((void**)&h->scratch[k], sizeof(double) * h->elems[k]);
+    if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
+  }
+  e = hipMalloc((void**)&h->clocks, sizeof(ProbClock) * nprob);
+  if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }
+  e = hipMemset(h->clocks, 0, sizeof(ProbClock) * nprob);
+  if (e != hipSuccess) { release(h); return fail_hip(e, "clock init"); }
+  // standalone descriptors
+  for (int k = 0; k < nprob; ++k) h->single_host.push_back(make_probdev(h, k));
+  e = hipMalloc((void**)&h->single_dev, sizeof(ProbDev) * nprob);
+  if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "table allocation"); }
+  e = hipMemcpy(h->single_dev, h->single_host.data(), sizeof(ProbDev) * nprob, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { release(h); return fail_hip(e, "table upload"); }
+  // launch groups
+  std::map<std::tuple<int, int, int, int>, int> index;
+  for (int k = 0; k < nprob; ++k) {
+    auto key = std::make_tuple(cfgs[k].scheme, pdes[k].pde, cfgs[k].N, cfgs[k].precision);
+    auto it = index.find(key);
+    if (it == index.end()) {
+      Group g;
+      g.scheme = cfgs[k].scheme;
+      g.pde = pdes[k].pde;
+      g.N = cfgs[k].N;
+      g.prec = cfgs[k].precision;
+      index[key] = (int)h->groups.size();
+      h->groups.push_back(g);
+      it = index.find(key);
+    }
+    h->groups[it->second].pids.push_back(k);
+  }
+  for (Group& g : h->groups) {
+    const int64_t tile = g.scheme == ADERDG_SCHEME_DG ? dg_tile_cells(g.N, true) : fv_tile_cells(g.N);
+    int64_t b = 0, lb = 0;
+    for (int k : g.pids) {
+      ProbDev d = make_probdev(h, k);
+      d.tile_begin = b;
+      d.tiles = (d.ncells + tile - 1) / tile;
+      b += d.tiles;
+      g.host.push_back(d);
+      ProbDev l = d;
+      l.tile_begin = lb;
+      l.tiles = (d.ncells + 255) / 256;
+      lb += l.tiles;
+      g.lam_host.push_back(l);
+      if (!(cfgs[k].fixed_dt > 0.0)) g.any_cfl = true;
+    }
+    g.blocks = b;
+    g.lam_blocks = lb;
+    if (b >= ((int64_t)1 << 31)) { release(h); return fail(ADERDG_E_INVAL, "grid too large"); }
+    e = hipMalloc((void**)&g.dev, sizeof(ProbDev) * g.host.size());
+    if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "table allocation"); }
+    e = hipMalloc((void**)&g.lam_dev, sizeof(ProbDev) * g.lam_host.size());
+    if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "table allocation"); }
+  }
+  *out = h;
+  return ADERDG_OK;
+}
+
+int aderdg_set_stream(aderdg_handle* h, void* hip_stream) {
+  if (!h) return fail(ADERDG_E_INVAL, "null handle");
+  h->stream = (hipStream_t)hip_stream;
+  return ADERDG_OK;
+}
+
+static int check_standalone(aderdg_handle* h, int32_t k, double t, double dt) {
+  if (!h) return fail(ADERDG_E_INVAL, "null handle");
+  if (k < 0 || k >= h->nprob) return fail(ADERDG_E_INVAL, "problem index out of range");
+  if (h->cfgs[k].scheme != ADERDG_SCHEME_DG) return fail(ADERDG_E_INVAL, "problem is not a DG problem");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return fail(ADERDG_E_INVAL, "need finite t and dt > 0");
+  return ADERDG_OK;
+}
+
+int aderdg_predict(aderdg_handle* h, int32_t k, const double* u, double t, double dt, void* q_out,
+                   int32_t* iters_out) {
+  int rc = check_standalone(h, k, t, dt);
+  if (rc) return rc;
+  if (!u || !q_out) return fail(ADERDG_E_INVAL, "null buffer");
+  const aderdg_config& c = h->cfgs[k];
+  StepArgs A{};
+  A.probs = h->single_dev + k;
+  A.nprob = 1;
+  A.k = 0;
+  A.clocks = h->clocks;
+  A.u_in = u;
+  A.q = q_out;
+  A.iters = iters_out;
+  A.t = t;
+  A.dt = dt;
+  const int64_t tile = dg_tile_cells(c.N, false);
+  hipError_t e = launch_dg(h->pdes[k].pde, c.N, c.precision, 0, A, (c.ncells + tile - 1) / tile, h->stream);
+  if (e != hipSuccess) return fail_hip(e, "predictor kernel");
+  return ADERDG_OK;
+}
+
+int aderdg_correct(aderdg_handle* h, int32_t k, const double* u, const void* q, double t, double dt,
+                   double* u_next) {
+  int rc = check_standalone(h, k, t, dt);
+  if (rc) return rc;
+  if (!u || !q || !u_next) return fail(ADERDG_E_INVAL, "null buffer");
+  if ((const void*)u == (const void*)u_next) return fail(ADERDG_E_INVAL, "u_next must not alias u");
+  const aderdg_config& c = h->cfgs[k];
+  StepArgs A{};
+  A.probs = h->single_dev + k;
+  A.nprob = 1;
+  A.k = 0;
+  A.clocks = h->clocks;
+  A.u_in = u;
+  A.u_out = u_next;
+  A.q = const_cast<void*>(q);
+  A.t = t;
+  A.dt = dt;
+  const int64_t tile = dg_tile_cells(c.N, true);
+  hipError_t e = launch_dg(h->pdes[k].pde, c.N, c.precision, 1, A, (c.ncells + tile - 1) / tile, h->stream);
+  if (e != hipSuccess) return fail_hip(e, "corrector kernel");
+  return ADERDG_OK;
+}
+
+int aderdg_step(aderdg_handle* h, double* const* u, double* t, const double* t_end, double* dt,
+                int32_t* status, int32_t nsteps) {
+  return run_steps(h, ADERDG_SCHEME_DG, u, t, t_end, dt, status, nsteps);
+}
+
+int aderweno_step(aderdg_handle* h, double* const* v, double* t, const double* t_end, double* dt,
+                  int32_t* status, int32_t nsteps) {
+  return run_steps(h, ADERDG_SCHEME_FV, v, t, t_end, dt, status, nsteps);
+}
+
+int aderdg_free(aderdg_handle* h) {
+  release(h);
+  return ADERDG_OK;
+}
+
+int aderdg_sweep_count(aderdg_handle* h, int32_t k, int64_t* sweeps_out) {
+  if (!h || !sweeps_out) return fail(ADERDG_E_INVAL, "null argument");
+  if (k < 0 || k >= h->nprob) return fail(ADERDG_E_INVAL, "problem index out of range");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "stream synchronize");
+  unsigned long long v = 0;
+  e = hipMemcpy(&v, &h->clocks[k].sweeps, sizeof(v), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "sweep count read");
+  *sweeps_out = (int64_t)v;
+  return ADERDG_OK;
+}
+
+int aderdg_operators(int32_t N, double* out, int64_t cap) {
+  OpTables t;
+  if (!out || !build_op_tables(N, t) || N < 0) return fail(ADERDG_E_INVAL, "bad degree or buffer");
+  const int n = N + 1;
+  const int64_t need = 2 * n + 3 * n * n + 2 * n + (int64_t)t.Ns * n;
+  if (cap < need) return fail(ADERDG_E_INVAL, "buffer too small");
+  int64_t o = 0;
+  for (int i = 0; i < n; ++i) out[o++] = t.xi[i];
+  for (int i = 0; i < n; ++i) out[o++] = t.w[i];
+  for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j) out[o++] = t.ktil[i][j];
+  for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j) out[o++] = t.kappa[i][j];
+  for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j) out[o++] = t.Dtil[i][j];
+  for (int i = 0; i < n; ++i) out[o++] = t.psi0[i];
+  for (int i = 0; i < n; ++i) out[o++] = t.psi1[i];
+  for (int s = 0; s < t.Ns; ++s) for (int k = 0; k < n; ++k) out[o++] = t.P[s][k];
+  return (int)o;
+}
+
+const char* aderdg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,220 @@
+// Device-side building blocks shared by the DG and FV kernels (gfx950).
+//
+//  * operator tables in constant memory, indexed with compile-time indices
+//    so that every coefficient is a wave-uniform scalar load;
+//  * point-wise PDE traits (flux, source, non-conservative product, signal
+//    speed), evaluated in registers straight from the AoS state (Sec. 1.1:
+//    fluxes, sources and non-conservative matrices are computed per node on
+//    q_{p,r} without transposition);
+//  * the interface solver (Rusanov + straight-path jump);
+//  * wave-level LDS synchronisation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aderdg {
+
+constexpr int kDevMaxn = 10;
+constexpr int kDevMaxNs = 19;
+constexpr int kWenoMaxn = 5;
+
+struct DevOps {
+  double xi[kDevMaxn];
+  double w[kDevMaxn];
+  double winv[kDevMaxn];
+  double ktil[kDevMaxn][kDevMaxn];
+  double kappa[kDevMaxn][kDevMaxn];
+  double Dtil[kDevMaxn][kDevMaxn];
+  double psi0[kDevMaxn];
+  double psi1[kDevMaxn];
+  double P[kDevMaxNs][kDevMaxn];
+};
+
+struct DevOpsF {
+  float ktil[kDevMaxn][kDevMaxn];
+  float kappa[kDevMaxn][kDevMaxn];
+};
+
+struct DevWeno {
+  double R[3][kWenoMaxn][kWenoMaxn];
+  double S[3][kWenoMaxn][kWenoMaxn];
+};
+
+struct PdeParams {
+  double gamma, g, omega, a;
+};
+
+// ---------------------------------------------------------------- sync ----
+// Orders LDS traffic among the lanes of one wavefront (no s_barrier needed:
+// every exchange in the predictor stays inside one wave).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
+template <class T> __device__ __forceinline__ T dmax(T a, T b) { return a > b ? a : b; }
+
+// ------------------------------------------------------------ PDE traits ----
+// Each model: M, kSource, kNcp, flux(q,f), speed(q), admissible(q); models
+// with sources add source(q,x,t,s); with non-conservative products
+// ncp(q,dq,b) = B(q).dq and jump(qm,qp,j) = B~ (qp - qm); diss(r) is the
+// Rusanov dissipation mask.
+
+struct Advection {
+  static constexpr int M = 1;
+  static constexpr bool kSource = false, kNcp = false;
+  template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
+    f[0] = T(p.a) * q[0];
+  }
+  template <class T> __device__ static T speed(const T*, const PdeParams& p) { return dabs(T(p.a)); }
+  __device__ static bool admissible(const double* q, const PdeParams&) { return isfinite(q[0]); }
+  __device__ static constexpr double diss(int) { return 1.0; }
+};
+
+struct Euler {  // Sec. 2, eq. system_of_equations in 1-D: (rho, rho u, E)
+  static constexpr int M = 3;
+  static constexpr bool kSource = false, kNcp = false;
+  template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
+    const T u = q[1] / q[0];
+    const T pr = T(p.gamma - 1.0) * (q[2] - T(0.5) * q[1] * u);
+    f[0] = q[1];
+    f[1] = q[1] * u + pr;
+    f[2] = u * (q[2] + pr);
+  }
+  template <class T> __device__ static T speed(const T* q, const PdeParams& p) {
+    const T u = q[1] / q[0];
+    const T pr = T(p.gamma - 1.0) * (q[2] - T(0.5) * q[1] * u);
+    return dabs(u) + sqrt(T(p.gamma) * pr / q[0]);
+  }
+  __device__ static bool admissible(const double* q, const PdeParams& p) {
+    const double u = q[1] / q[0];
+    const double pr = (p.gamma - 1.0) * (q[2] - 0.5 * q[1] * u);
+    return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && q[0] > 0.0 && pr > 0.0;
+  }
+  __device__ static constexpr double diss(int) { return 1.0; }
+};
+
+struct EulerReact {  // Sec. 2.1, eq. pdes_2_comps in 1-D: (rho, rho u, E, rho c1, rho c2)
+  static constexpr int M = 5;
+  static constexpr bool kSource = true, kNcp = false;
+  template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
+    const T u = q[1] / q[0];
+    const T pr = T(p.gamma - 1.0) * (q[2] - T(0.5) * q[1] * u);
+    f[0] = q[1];
+    f[1] = q[1] * u + pr;
+    f[2] = u * (q[2] + pr);
+    f[3] = q[3] * u;
+    f[4] = q[4] * u;
+  }
+  template <class T> __device__ static void source(const T* q, T, T, T* s, const PdeParams& p) {
+    s[0] = s[1] = s[2] = T(0);
+    s[3] = q[4];
+    s[4] = -T(p.omega * p.omega) * q[3];
+  }
+  template <class T> __device__ static T speed(const T* q, const PdeParams& p) {
+    return Euler::speed(q, p);
+  }
+  __device__ static bool admissible(const double* q, const PdeParams& p) {
+    return Euler::admissible(q, p) && isfinite(q[3]) && isfinite(q[4]);
+  }
+  __device__ static constexpr double diss(int) { return 1.0; }
+};
+
+struct ShallowWater {  // (h, hu, b); B(Q) dQ/dx = (0, g h db/dx, 0)
+  static constexpr int M = 3;
+  static constexpr bool kSource = false, kNcp = true;
+  template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
+    const T u = q[1] / q[0];
+    f[0] = q[1];
+    f[1] = q[1] * u + T(0.5 * p.g) * q[0] * q[0];
+    f[2] = T(0);
+  }
+  template <class T> __device__ static void ncp(const T* q, const T* dq, T* b, const PdeParams& p) {
+    b[0] = T(0);
+    b[1] = T(p.g) * q[0] * dq[2];
+    b[2] = T(0);
+  }
+  template <class T> __device__ static void jump(const T* qm, const T* qp, T* j, const PdeParams& p) {
+    j[0] = T(0);
+    j[1] = T(p.g) * T(0.5) * (qm[0] + qp[0]) * (qp[2] - qm[2]);
+    j[2] = T(0);
+  }
+  template <class T> __device__ static T speed(const T* q, const PdeParams& p) {
+    return dabs(q[1] / q[0]) + sqrt(T(p.g) * q[0]);
+  }
+  __device__ static bool admissible(const double* q, const PdeParams&) {
+    return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && q[0] > 0.0;
+  }
+  __device__ static constexpr double diss(int r) { return r == 2 ? 0.0 : 1.0; }
+};
+
+// Rusanov flux (unscaled): (F(qm)+F(qp))/2 - s/2 D (qp-qm), s = max signal speed.
+template <class PDE>
+__device__ __forceinline__ void rusanov(const double* qm, const double* qp, double* G,
+                                        const PdeParams& p) {
+  double fm[PDE::M], fp[PDE::M];
+  PDE::flux(qm, fm, p);
+  PDE::flux(qp, fp, p);
+  const double s = dmax(PDE::speed(qm, p), PDE::speed(qp, p));
+#pragma unroll
+  for (int r = 0; r < PDE::M; ++r)
+    G[r] = 0.5 * (fm[r] + fp[r]) - 0.5 * s * PDE::diss(r) * (qp[r] - qm[r]);
+}
+
+// ------------------------------------------------------------- problems ----
+// One problem of a launch group (library-owned device array).
+struct ProbDev {
+  double* state[2];       // [0] caller's buffer, [1] library scratch (ping-pong)
+  int64_t ncells;
+  int64_t tile_begin;     // first workgroup of this problem in the group's grid
+  int64_t tiles;
+  double x0, dx;
+  double cfl, fixed_dt, tol;
+  int32_t max_iter;
+  int32_t cfl_mode;
+  int32_t pid;            // index into the handle's per-problem arrays
+  int32_t pad;
+  PdeParams pp;
+};
+
+// Per-problem device clock (library-owned).
+struct ProbClock {
+  double t[2];                    // t^n of even / odd steps
+  unsigned long long lam[3];      // max signal speed (bit pattern of a non-negative double)
+  double dt_last;
+  unsigned long long sweeps;      // outer Picard sweeps summed over cells
+  int32_t status;
+  int32_t pad;
+};
+
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax(addr, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = dmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Workgroup -> problem of the launch group (binary search on tile_begin).
+__device__ __forceinline__ int find_problem(const ProbDev* probs, int nprob, int64_t block) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].tile_begin <= block) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace aderdg

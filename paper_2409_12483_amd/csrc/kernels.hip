@@ -1,0 +1,777 @@
+// HIP kernels of the 1-D ADER-DG / ADER-WENO-FV hot path for gfx950.
+//
+// One translation unit holds every kernel so that the constant-memory
+// operator tables need no relocatable device code.  Kernels:
+//   dg_kernel<MODE>   predictor only / corrector only / fused step
+//                     (Secs. 1.1-1.2, Algorithms 1-7)
+//   fv_kernel         ADER-WENO finite-volume step (Sec. 1.3, Algorithms 8-11)
+//   lambda_kernel     max signal speed for the CFL rule (Secs. 1.4-1.5)
+//   clock kernels     per-problem device time / dt / status bookkeeping
+//
+// Fused step, per workgroup of WAVES wavefronts: a tile of consecutive
+// cells plus one halo cell on each side, whose predictor is recomputed
+// redundantly so that the neighbour traces never leave the chip.  Each
+// cell is served by n = N+1 lanes (lane a = time row a of the predictor
+// tile, see predictor.hpp).  After the predictor:
+//   volume terms   in-lane (row a), summed over time rows through LDS;
+//   face traces    in-lane (psi, psi~ contractions), staged in LDS;
+//   Riemann flux   per (face, time node) by the left cell's lane a;
+//   surface update per (cell, space node) in column layout, AoS store;
+//   epilogue       signal speed on the 2N+1 subcell averages of u^{n+1},
+//                  wave max + one 64-bit atomic max per wave (exact).
+#include "device_common.hpp"
+#include "launch.hpp"
+#include "predictor.hpp"
+
+namespace aderdg {
+
+__constant__ DevOps c_ops[kDevMaxn];
+__constant__ DevOpsF c_opsf[kDevMaxn];
+__constant__ DevWeno c_weno[2];  // WENO degree 2 and 4
+
+enum Mode { kPredict = 0, kCorrect = 1, kStep = 2 };
+
+// Geometry of a workgroup for degree N and M variables.
+template <int N, int M, int WAVES, bool HALO>
+struct Geo {
+  static constexpr int n = N + 1;
+  static constexpr int CPW = 64 / n;                 // cells per wavefront
+  static constexpr int PC = WAVES * CPW;             // predictor cells per workgroup
+  static constexpr int TILE = HALO ? PC - 2 : PC;    // cells written per workgroup
+  static constexpr int XB = (CPW + 1) * n * n * M;   // doubles of LDS exchange per wave (+1 idle slot)
+  static constexpr int RED = (CPW + 1) * n * 2;      // reduction slots per wave
+};
+
+template <class T> __device__ __forceinline__ T clamp_dt(double dt) { return T(dt); }
+
+// Problem-level step parameters for a workgroup.
+struct StepCtx {
+  int pid;
+  double t, dt;
+  const double* u_in;
+  double* u_out;
+  int64_t tile;
+};
+
+// Resolve the problem, time and step size of this workgroup (step mode).
+template <bool DG, int N>
+__device__ __forceinline__ bool step_setup(const StepArgs& A, const ProbDev& P, StepCtx& c) {
+  ProbClock& clk = A.clocks[P.pid];
+  const int s = A.step;
+  c.pid = P.pid;
+  c.t = clk.t[s & 1];
+  double dt;
+  if (P.fixed_dt > 0.0) {
+    dt = P.fixed_dt;
+  } else {
+    const double lam = __longlong_as_double((long long)clk.lam[s % 3]);
+    dt = DG ? P.cfl * P.dx / ((2.0 * N + 1.0) * lam) : P.cfl * P.dx / lam;
+  }
+  const double rem = A.t_end[P.pid] - c.t;
+  if (dt > rem) dt = rem;
+  if (!(dt > 0.0)) dt = 0.0;
+  c.dt = dt;
+  c.u_in = P.state[s & 1];
+  c.u_out = P.state[(s + 1) & 1];
+  if (c.tile == 0 && threadIdx.x == 0) {
+    clk.t[(s + 1) & 1] = c.t + dt;
+    if (dt > 0.0) clk.dt_last = dt;
+    clk.lam[(s + 2) % 3] = 0ull;
+    if (dt == 0.0) clk.lam[(s + 1) % 3] = clk.lam[s % 3];   // state unchanged: carry lambda
+  }
+  return dt > 0.0;
+}
+
+// Copy a tile unchanged (problem already at t_end).
+__device__ __forceinline__ void copy_tile(const double* in, double* out, int64_t first,
+                                          int64_t count, int per_cell) {
+  const int64_t total = count * per_cell, base = first * per_cell;
+  for (int64_t i = threadIdx.x; i < total; i += blockDim.x) out[base + i] = in[base + i];
+}
+
+// ------------------------------------------------------------------ DG ----
+template <int N, class PDE, class TP, int WAVES, int MODE>
+__global__ void __launch_bounds__(WAVES * 64)
+dg_kernel(StepArgs A) {
+  constexpr bool HALO = MODE != kPredict;
+  using G = Geo<N, PDE::M, WAVES, HALO>;
+  constexpr int n = G::n, M = PDE::M, CPW = G::CPW, PC = G::PC;
+  using Pred = Predictor<N, PDE, TP>;
+
+  __shared__ double xb_all[WAVES * G::XB];
+  __shared__ TP red_all[WAVES * G::RED];
+  __shared__ double trL[PC * n * M];   // left-face traces  [pc][a][r]
+  __shared__ double trR[PC * n * M];   // right-face traces [pc][a][r]; reused for the face fluxes
+  __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
+  __shared__ double lam_wave[WAVES];
+
+  const int pidx = MODE == kStep ? find_problem(A.probs, A.nprob, blockIdx.x) : A.k;
+  const ProbDev& P = A.probs[pidx];
+  StepCtx c;
+  c.tile = (int64_t)blockIdx.x - (MODE == kStep ? P.tile_begin : 0);
+  const int64_t C = P.ncells;
+  const int64_t first = c.tile * G::TILE;
+  if (first >= C) return;
+  const int64_t count = (C - first < G::TILE) ? C - first : G::TILE;
+
+  if constexpr (MODE == kStep) {
+    if (!step_setup<true, N>(A, P, c)) {
+      copy_tile(c.u_in, c.u_out, first, count, n * M);
+      return;
+    }
+  } else {
+    c.pid = P.pid;
+    c.t = A.t;
+    c.dt = A.dt;
+    c.u_in = A.u_in;
+    c.u_out = A.u_out;
+  }
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot0 = lane / n;
+  const bool active = slot0 < CPW;
+  const int slot = active ? slot0 : CPW;               // idle lanes share a dummy slot
+  const int a = active ? lane % n : lane - CPW * n;
+  const int pc = wave * CPW + slot;                      // predictor cell in the workgroup
+  int64_t gc = first + pc - (HALO ? 1 : 0);              // global cell (periodic wrap)
+  gc %= C;
+  if (gc < 0) gc += C;
+  const bool out_cell = active && (HALO ? (pc >= 1 && pc <= PC - 2) : true) &&
+                        (first + pc - (HALO ? 1 : 0)) < C;
+
+  double* xb = xb_all + wave * G::XB + slot * n * n * M;
+  TP* red = red_all + wave * G::RED + slot * n * 2;
+
+  const double dx = P.dx, dt = c.dt, dtdx = dt / dx;
+  const double xl = P.x0 + dx * (double)gc;
+  const double* ucell = c.u_in + gc * (n * M);
+
+  // ---- predictor (or load of a given predictor) ----
+  TP q[n][M];
+  int sweeps = 0;
+  bool failed = false;
+  if constexpr (MODE == kCorrect) {
+    const TP* qin = reinterpret_cast<const TP*>(A.q) + gc * (n * n * M) + a * (n * M);
+#pragma unroll
+    for (int l = 0; l < n; ++l)
+#pragma unroll
+      for (int r = 0; r < M; ++r) q[l][r] = qin[l * M + r];
+  } else {
+    TP ucol[M];
+#pragma unroll
+    for (int l = 0; l < n; ++l)
+#pragma unroll
+      for (int r = 0; r < M; ++r) q[l][r] = TP(ucell[l * M + r]);
+#pragma unroll
+    for (int r = 0; r < M; ++r) ucol[r] = TP(ucell[a * M + r]);
+    const TP tol = TP(P.tol);
+    Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, TP(dt), TP(dtdx), xl, dx, c.t, P.pp,
+              tol, P.max_iter, sizeof(TP) == 4, active, sweeps, failed);
+  }
+
+  if constexpr (MODE == kPredict) {
+    if (out_cell) {
+      TP* qo = reinterpret_cast<TP*>(A.q) + gc * (n * n * M) + a * (n * M);
+#pragma unroll
+      for (int l = 0; l < n; ++l)
+#pragma unroll
+        for (int r = 0; r < M; ++r) qo[l * M + r] = q[l][r];
+      if (A.iters && a == 0) A.iters[gc] = sweeps;
+    }
+    if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);
+    return;
+  } else {
+    // ---- corrector: volume terms of time row a ----
+    const double wa = c_ops[N].w[a];
+    const double ta = c.t + dt * c_ops[N].xi[a];
+    double qd[n][M];
+#pragma unroll
+    for (int l = 0; l < n; ++l)
+#pragma unroll
+      for (int r = 0; r < M; ++r) qd[l][r] = (double)q[l][r];
+    double fd[n][M];
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      double f[M];
+      PDE::flux(qd[l], f, P.pp);
+#pragma unroll
+      for (int r = 0; r < M; ++r) fd[l][r] = dtdx * f[r];
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      double V[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < n; ++l) acc += c_ops[N].Dtil[k][l] * fd[l][r];
+        V[r] = acc * c_ops[N].winv[k];
+      }
+      if constexpr (PDE::kSource) {
+        double s[M];
+        PDE::source(qd[k], xl + dx * c_ops[N].xi[k], ta, s, P.pp);
+#pragma unroll
+        for (int r = 0; r < M; ++r) V[r] += dt * s[r];
+      }
+      if constexpr (PDE::kNcp) {
+        double dq[M], b[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < n; ++j) acc += c_ops[N].ktil[k][j] * qd[j][r];
+          dq[r] = acc;
+        }
+        PDE::ncp(qd[k], dq, b, P.pp);
+#pragma unroll
+        for (int r = 0; r < M; ++r) V[r] -= dtdx * b[r];
+      }
+#pragma unroll
+      for (int r = 0; r < M; ++r) xb[(a * n + k) * M + r] = wa * V[r];
+    }
+    // face traces of time row a
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        double sl = 0.0, sr = 0.0;
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          sl += c_ops[N].psi0[j] * qd[j][r];
+          sr += c_ops[N].psi1[j] * qd[j][r];
+        }
+        trL[(pc * n + a) * M + r] = sl;
+        trR[(pc * n + a) * M + r] = sr;
+      }
+    }
+    wave_sync();
+    // column role: lane a = space node k, volume increment summed over time rows
+    double vol[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < n; ++b) acc += xb[(b * n + a) * M + r];
+      vol[r] = acc;
+    }
+    __syncthreads();
+    // Riemann solver at face pc+1/2 and time node a (left cell's lane), weighted by w_a dt/dx
+    if (active && pc < PC - 1) {
+      double qm[M], qp[M], G[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        qm[r] = trR[(pc * n + a) * M + r];
+        qp[r] = trL[((pc + 1) * n + a) * M + r];
+      }
+      rusanov<PDE>(qm, qp, G, P.pp);
+      if constexpr (PDE::kNcp) {
+        double J[M];
+        PDE::jump(qm, qp, J, P.pp);
+#pragma unroll
+        for (int r = 0; r < M; ++r) jmp[(pc * n + a) * M + r] = 0.5 * wa * dtdx * J[r];
+      }
+#pragma unroll
+      for (int r = 0; r < M; ++r) trR[(pc * n + a) * M + r] = wa * dtdx * G[r];
+    }
+    __syncthreads();
+    // surface terms and store (column role, lane a = node k)
+    double unew[M];
+    bool bad = false;
+    if (out_cell) {
+      const int k = a;
+      const double winv = c_ops[N].winv[k], p0 = c_ops[N].psi0[k], p1 = c_ops[N].psi1[k];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        double GR = 0.0, GL = 0.0;
+#pragma unroll
+        for (int b = 0; b < n; ++b) {
+          GR += trR[(pc * n + b) * M + r];
+          GL += trR[((pc - 1) * n + b) * M + r];
+        }
+        double v = ucell[k * M + r] + vol[r] - winv * (p1 * GR - p0 * GL);
+        if constexpr (PDE::kNcp) {
+          double JR = 0.0, JL = 0.0;
+#pragma unroll
+          for (int b = 0; b < n; ++b) {
+            JR += jmp[(pc * n + b) * M + r];
+            JL += jmp[((pc - 1) * n + b) * M + r];
+          }
+          v -= winv * (p1 * JR + p0 * JL);
+        }
+        unew[r] = v;
+        c.u_out[gc * (n * M) + k * M + r] = v;
+      }
+      bad = !PDE::admissible(unew, P.pp);
+    }
+    // ---- epilogue: status, sweep count, signal speed of u^{n+1} ----
+    if constexpr (MODE == kStep) {
+      if (bad) atomicMin(&A.clocks[c.pid].status, -5);
+      else if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);
+      unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
+      sw = wave_sum(sw);
+      if (lane == 0 && sw) atomicAdd(&A.clocks[c.pid].sweeps, sw);
+      double lam = 0.0;
+      if (P.cfl_mode == 1) {
+        if (out_cell) lam = PDE::speed(unew, P.pp);
+      } else {
+        wave_sync();
+        if (out_cell) {
+#pragma unroll
+          for (int r = 0; r < M; ++r) xb[a * M + r] = unew[r];
+        }
+        wave_sync();
+        if (out_cell) {
+          constexpr int Ns = 2 * N + 1;
+#pragma unroll
+          for (int s0 = 0; s0 < Ns; s0 += n) {
+            const int s = s0 + a;
+            if (s < Ns) {
+              double v[M];
+#pragma unroll
+              for (int r = 0; r < M; ++r) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < n; ++k) acc += c_ops[N].P[s][k] * xb[k * M + r];
+                v[r] = acc;
+              }
+              lam = dmax(lam, PDE::speed(v, P.pp));
+            }
+          }
+        }
+      }
+      lam = wave_max(lam);
+      if (lane == 0) lam_wave[wave] = lam;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double m = 0.0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) m = dmax(m, lam_wave[w]);
+        atomic_max_nonneg(&A.clocks[c.pid].lam[(A.step + 1) % 3], m);
+      }
+    } else {
+      if (bad) atomicMin(&A.clocks[c.pid].status, -5);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ FV ----
+// ADER-WENO-FV step: WENO reconstruction (degree NW) -> predictor -> FV update.
+template <int NW, class PDE, class TP, int WAVES>
+__global__ void __launch_bounds__(WAVES * 64)
+fv_kernel(StepArgs A) {
+  using G = Geo<NW, PDE::M, WAVES, true>;
+  constexpr int n = G::n, M = PDE::M, CPW = G::CPW, PC = G::PC;
+  constexpr int NV = PC + 2 * NW;   // cell averages staged: predictor cells + WENO reach
+  using Pred = Predictor<NW, PDE, TP>;
+  constexpr int wi = NW / 2 - 1;    // c_weno index
+
+  __shared__ double vb[NV * M];
+  __shared__ double xb_all[WAVES * G::XB];
+  __shared__ TP red_all[WAVES * G::RED];
+  __shared__ double trL[PC * n * M];
+  __shared__ double trR[PC * n * M];
+  __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
+  __shared__ double volb[PC * n * M];
+  __shared__ double lam_wave[WAVES];
+
+  const int pidx = find_problem(A.probs, A.nprob, blockIdx.x);
+  const ProbDev& P = A.probs[pidx];
+  StepCtx c;
+  c.tile = (int64_t)blockIdx.x - P.tile_begin;
+  const int64_t C = P.ncells;
+  const int64_t first = c.tile * G::TILE;
+  if (first >= C) return;
+  const int64_t count = (C - first < G::TILE) ? C - first : G::TILE;
+  if (!step_setup<false, NW>(A, P, c)) {
+    copy_tile(c.u_in, c.u_out, first, count, M);
+    return;
+  }
+
+  // stage cell averages of cells first-1-NW .. first-1+PC+NW-1 (periodic)
+  for (int i = threadIdx.x; i < NV * M; i += blockDim.x) {
+    const int cc = i / M, r = i % M;
+    int64_t g = (first - 1 - NW + cc) % C;
+    if (g < 0) g += C;
+    vb[i] = c.u_in[g * M + r];
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot0 = lane / n;
+  const bool active = slot0 < CPW;
+  const int slot = active ? slot0 : CPW;
+  const int a = active ? lane % n : lane - CPW * n;
+  const int pc = wave * CPW + slot;
+  int64_t gc = (first + pc - 1) % C;
+  if (gc < 0) gc += C;
+  const bool out_cell = active && pc >= 1 && pc <= PC - 2 && (first + pc - 1) < C;
+  double* xb = xb_all + wave * G::XB + slot * n * n * M;
+  TP* red = red_all + wave * G::RED + slot * n * 2;
+  const double dx = P.dx, dt = c.dt, dtdx = dt / dx;
+  const double xl = P.x0 + dx * (double)gc;
+
+  // ---- WENO reconstruction at node a (reading of eq. weno_reconstr) ----
+  double what[M];
+  {
+    const int base = (active ? pc : 0) + NW;   // vb index of this cell
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      double wsum = 0.0, acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        const int off = s == 0 ? -NW : (s == 1 ? -NW / 2 : 0);
+        double v[n];
+#pragma unroll
+        for (int i = 0; i < n; ++i) v[i] = vb[(base + off + i) * M + r];
+        double sig = 0.0, val = 0.0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          double si = 0.0;
+#pragma unroll
+          for (int j = 0; j < n; ++j) si += c_weno[wi].S[s][i][j] * v[j];
+          sig += v[i] * si;
+          val += c_weno[wi].R[s][a < n ? a : 0][i] * v[i];
+        }
+        const double e = sig + 1.0e-14;
+        const double e2 = e * e, e4 = e2 * e2, e8 = e4 * e4;
+        const double om = (s == 1 ? 1.0e5 : 1.0) / e8;
+        wsum += om;
+        acc += om * val;
+      }
+      what[r] = acc / wsum;
+    }
+  }
+  // broadcast the reconstruction to every row of the cell
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < M; ++r) xb[a * M + r] = what[r];
+  wave_sync();
+  TP q[n][M], ucol[M];
+#pragma unroll
+  for (int l = 0; l < n; ++l)
+#pragma unroll
+    for (int r = 0; r < M; ++r) q[l][r] = TP(xb[l * M + r]);
+#pragma unroll
+  for (int r = 0; r < M; ++r) ucol[r] = TP(what[r]);
+  int sweeps = 0;
+  bool failed = false;
+  Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, TP(dt), TP(dtdx), xl, dx, c.t, P.pp,
+            TP(P.tol), P.max_iter, sizeof(TP) == 4, active, sweeps, failed);
+
+  // ---- FV corrector ----
+  const double wa = c_ops[NW].w[a < n ? a : 0];
+  const double ta = c.t + dt * c_ops[NW].xi[a < n ? a : 0];
+  double qd[n][M];
+#pragma unroll
+  for (int l = 0; l < n; ++l)
+#pragma unroll
+    for (int r = 0; r < M; ++r) qd[l][r] = (double)q[l][r];
+  if (active) {
+    double V[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) V[r] = 0.0;
+    if constexpr (PDE::kSource || PDE::kNcp) {
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        double sb[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) sb[r] = 0.0;
+        if constexpr (PDE::kSource) {
+          double s[M];
+          PDE::source(qd[k], xl + dx * c_ops[NW].xi[k], ta, s, P.pp);
+#pragma unroll
+          for (int r = 0; r < M; ++r) sb[r] += dt * s[r];
+        }
+        if constexpr (PDE::kNcp) {
+          double dq[M], b[M];
+#pragma unroll
+          for (int r = 0; r < M; ++r) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < n; ++j) acc += c_ops[NW].ktil[k][j] * qd[j][r];
+            dq[r] = acc;
+          }
+          PDE::ncp(qd[k], dq, b, P.pp);
+#pragma unroll
+          for (int r = 0; r < M; ++r) sb[r] -= dtdx * b[r];
+        }
+#pragma unroll
+        for (int r = 0; r < M; ++r) V[r] += c_ops[NW].w[k] * sb[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      volb[(pc * n + a) * M + r] = wa * V[r];
+      double sl = 0.0, sr = 0.0;
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        sl += c_ops[NW].psi0[j] * qd[j][r];
+        sr += c_ops[NW].psi1[j] * qd[j][r];
+      }
+      trL[(pc * n + a) * M + r] = sl;
+      trR[(pc * n + a) * M + r] = sr;
+    }
+  }
+  __syncthreads();
+  if (active && pc < PC - 1) {
+    double qm[M], qp[M], Gf[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      qm[r] = trR[(pc * n + a) * M + r];
+      qp[r] = trL[((pc + 1) * n + a) * M + r];
+    }
+    rusanov<PDE>(qm, qp, Gf, P.pp);
+    if constexpr (PDE::kNcp) {
+      double J[M];
+      PDE::jump(qm, qp, J, P.pp);
+#pragma unroll
+      for (int r = 0; r < M; ++r) jmp[(pc * n + a) * M + r] = 0.5 * wa * dtdx * J[r];
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r) trR[(pc * n + a) * M + r] = wa * dtdx * Gf[r];
+  }
+  __syncthreads();
+  double lam = 0.0;
+  bool bad = false;
+  if (out_cell && a == 0) {
+    double vnew[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      double GR = 0.0, GL = 0.0, VV = 0.0, JR = 0.0, JL = 0.0;
+#pragma unroll
+      for (int b = 0; b < n; ++b) {
+        GR += trR[(pc * n + b) * M + r];
+        GL += trR[((pc - 1) * n + b) * M + r];
+        VV += volb[(pc * n + b) * M + r];
+        if constexpr (PDE::kNcp) {
+          JR += jmp[(pc * n + b) * M + r];
+          JL += jmp[((pc - 1) * n + b) * M + r];
+        }
+      }
+      vnew[r] = vb[(pc + NW) * M + r] - (GR - GL) - (JR + JL) + VV;
+      c.u_out[gc * M + r] = vnew[r];
+    }
+    bad = !PDE::admissible(vnew, P.pp);
+    lam = PDE::speed(vnew, P.pp);
+  }
+  if (bad) atomicMin(&A.clocks[c.pid].status, -5);
+  else if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);
+  unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
+  sw = wave_sum(sw);
+  if (lane == 0 && sw) atomicAdd(&A.clocks[c.pid].sweeps, sw);
+  lam = wave_max(lam);
+  if (lane == 0) lam_wave[wave] = lam;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) m = dmax(m, lam_wave[w]);
+    atomic_max_nonneg(&A.clocks[c.pid].lam[(A.step + 1) % 3], m);
+  }
+}
+
+// ------------------------------------------------------- lambda / clock ----
+// Max signal speed of the current state of every problem of a group (one
+// thread per cell): DG on the 2N+1 subcell averages (or nodal values), FV on
+// the cell averages.
+template <int N, class PDE, bool DG>
+__global__ void __launch_bounds__(256)
+lambda_kernel(StepArgs A) {
+  constexpr int n = N + 1, M = PDE::M;
+  const int pidx = find_problem(A.probs, A.nprob, blockIdx.x);
+  const ProbDev& P = A.probs[pidx];
+  const int64_t cell = ((int64_t)blockIdx.x - P.tile_begin) * 256 + threadIdx.x;
+  double lam = 0.0;
+  if (cell < P.ncells) {
+    const double* u = P.state[0];
+    if (!DG) {
+      double v[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) v[r] = u[cell * M + r];
+      lam = PDE::speed(v, P.pp);
+    } else if (P.cfl_mode == 1) {
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        double v[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) v[r] = u[cell * n * M + k * M + r];
+        lam = dmax(lam, PDE::speed(v, P.pp));
+      }
+    } else {
+      double uc[n][M];
+#pragma unroll
+      for (int k = 0; k < n; ++k)
+#pragma unroll
+        for (int r = 0; r < M; ++r) uc[k][r] = u[cell * n * M + k * M + r];
+#pragma unroll
+      for (int s = 0; s < 2 * N + 1; ++s) {
+        double v[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < n; ++k) acc += c_ops[N].P[s][k] * uc[k][r];
+          v[r] = acc;
+        }
+        lam = dmax(lam, PDE::speed(v, P.pp));
+      }
+    }
+  }
+  lam = wave_max(lam);
+  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&A.clocks[P.pid].lam[0], lam);
+}
+
+__global__ void clock_begin_kernel(ProbClock* clocks, const double* t_user, int nprob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  ProbClock& c = clocks[p];
+  c.t[0] = t_user[p];
+  c.t[1] = t_user[p];
+  c.lam[0] = c.lam[1] = c.lam[2] = 0ull;
+  c.dt_last = 0.0;
+  c.status = 0;
+}
+
+__global__ void clock_end_kernel(const ProbClock* clocks, double* t_user, double* dt_user,
+                                 int32_t* status_user, int nprob, int parity) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  t_user[p] = clocks[p].t[parity];
+  dt_user[p] = clocks[p].dt_last;
+  status_user[p] = clocks[p].status;
+}
+
+__global__ void status_reset_kernel(ProbClock* clocks, int p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) clocks[p].status = 0;
+}
+
+__global__ void copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// -------------------------------------------------------------- dispatch ----
+template <int N, class PDE, class TP, int WAVES>
+static hipError_t launch_dg_t(int mode, const StepArgs& A, int64_t blocks, hipStream_t st) {
+  dim3 grid((unsigned)blocks), block(WAVES * 64);
+  switch (mode) {
+    case kPredict: hipLaunchKernelGGL((dg_kernel<N, PDE, TP, WAVES, kPredict>), grid, block, 0, st, A); break;
+    case kCorrect: hipLaunchKernelGGL((dg_kernel<N, PDE, TP, WAVES, kCorrect>), grid, block, 0, st, A); break;
+    default: hipLaunchKernelGGL((dg_kernel<N, PDE, TP, WAVES, kStep>), grid, block, 0, st, A); break;
+  }
+  return hipGetLastError();
+}
+
+template <class PDE, class TP>
+static hipError_t launch_dg_n(int N, int mode, const StepArgs& A, int64_t blocks, hipStream_t st) {
+  switch (N) {
+#define ADERDG_CASE(NN) case NN: return launch_dg_t<NN, PDE, TP, kDgWaves>(mode, A, blocks, st);
+    ADERDG_CASE(1) ADERDG_CASE(2) ADERDG_CASE(3) ADERDG_CASE(4) ADERDG_CASE(5)
+    ADERDG_CASE(6) ADERDG_CASE(7) ADERDG_CASE(8) ADERDG_CASE(9)
+#undef ADERDG_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class PDE>
+static hipError_t launch_dg_p(int N, int prec, int mode, const StepArgs& A, int64_t blocks,
+                              hipStream_t st) {
+  return prec == 1 ? launch_dg_n<PDE, float>(N, mode, A, blocks, st)
+                   : launch_dg_n<PDE, double>(N, mode, A, blocks, st);
+}
+
+hipError_t launch_dg(int pde, int N, int prec, int mode, const StepArgs& A, int64_t blocks,
+                     hipStream_t st) {
+  switch (pde) {
+    case 0: return launch_dg_p<Advection>(N, prec, mode, A, blocks, st);
+    case 1: return launch_dg_p<Euler>(N, prec, mode, A, blocks, st);
+    case 2: return launch_dg_p<EulerReact>(N, prec, mode, A, blocks, st);
+    case 3: return launch_dg_p<ShallowWater>(N, prec, mode, A, blocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class PDE, class TP>
+static hipError_t launch_fv_n(int NW, const StepArgs& A, int64_t blocks, hipStream_t st) {
+  dim3 grid((unsigned)blocks), block(kFvWaves * 64);
+  if (NW == 2) hipLaunchKernelGGL((fv_kernel<2, PDE, TP, kFvWaves>), grid, block, 0, st, A);
+  else if (NW == 4) hipLaunchKernelGGL((fv_kernel<4, PDE, TP, kFvWaves>), grid, block, 0, st, A);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_fv(int pde, int NW, int prec, const StepArgs& A, int64_t blocks, hipStream_t st) {
+  switch (pde) {
+    case 0: return prec ? launch_fv_n<Advection, float>(NW, A, blocks, st) : launch_fv_n<Advection, double>(NW, A, blocks, st);
+    case 1: return prec ? launch_fv_n<Euler, float>(NW, A, blocks, st) : launch_fv_n<Euler, double>(NW, A, blocks, st);
+    case 2: return prec ? launch_fv_n<EulerReact, float>(NW, A, blocks, st) : launch_fv_n<EulerReact, double>(NW, A, blocks, st);
+    case 3: return prec ? launch_fv_n<ShallowWater, float>(NW, A, blocks, st) : launch_fv_n<ShallowWater, double>(NW, A, blocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class PDE, bool DG>
+static hipError_t launch_lambda_p(int N, const StepArgs& A, int64_t blocks, hipStream_t st) {
+  dim3 grid((unsigned)blocks), block(256);
+  switch (N) {
+#define ADERDG_CASE(NN) case NN: hipLaunchKernelGGL((lambda_kernel<NN, PDE, DG>), grid, block, 0, st, A); break;
+    ADERDG_CASE(1) ADERDG_CASE(2) ADERDG_CASE(3) ADERDG_CASE(4) ADERDG_CASE(5)
+    ADERDG_CASE(6) ADERDG_CASE(7) ADERDG_CASE(8) ADERDG_CASE(9)
+#undef ADERDG_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda(int pde, int N, bool dg, const StepArgs& A, int64_t blocks, hipStream_t st) {
+  switch (pde) {
+    case 0: return dg ? launch_lambda_p<Advection, true>(N, A, blocks, st) : launch_lambda_p<Advection, false>(N, A, blocks, st);
+    case 1: return dg ? launch_lambda_p<Euler, true>(N, A, blocks, st) : launch_lambda_p<Euler, false>(N, A, blocks, st);
+    case 2: return dg ? launch_lambda_p<EulerReact, true>(N, A, blocks, st) : launch_lambda_p<EulerReact, false>(N, A, blocks, st);
+    case 3: return dg ? launch_lambda_p<ShallowWater, true>(N, A, blocks, st) : launch_lambda_p<ShallowWater, false>(N, A, blocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_clock_begin(ProbClock* clocks, const double* t_user, int nprob, hipStream_t st) {
+  hipLaunchKernelGGL(clock_begin_kernel, dim3((nprob + 63) / 64), dim3(64), 0, st, clocks, t_user, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_end(const ProbClock* clocks, double* t_user, double* dt_user,
+                            int32_t* status_user, int nprob, int parity, hipStream_t st) {
+  hipLaunchKernelGGL(clock_end_kernel, dim3((nprob + 63) / 64), dim3(64), 0, st, clocks, t_user,
+                     dt_user, status_user, nprob, parity);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_reset(ProbClock* clocks, int p, hipStream_t st) {
+  hipLaunchKernelGGL(status_reset_kernel, dim3(1), dim3(64), 0, st, clocks, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, int64_t count, hipStream_t st) {
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+
+int64_t dg_tile_cells(int N, bool halo) {
+  const int cpw = 64 / (N + 1);
+  return (int64_t)kDgWaves * cpw - (halo ? 2 : 0);
+}
+
+int64_t fv_tile_cells(int NW) { return (int64_t)kFvWaves * (64 / (NW + 1)) - 2; }
+
+hipError_t upload_tables(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno) {
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_ops), ops, sizeof(DevOps) * kDevMaxn);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_opsf), opsf, sizeof(DevOpsF) * kDevMaxn);
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_weno), weno, sizeof(DevWeno) * 2);
+}
+
+}  // namespace aderdg

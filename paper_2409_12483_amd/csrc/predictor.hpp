@@ -1,0 +1,236 @@
+// LST-DG predictor on one wavefront (Sec. 1.1).
+//
+// The nested Picard iteration of eq. (lst_dg_predictor_nested_picards) in
+// the factored form L^xi = kappa~ (x) k~, L^sigma = kappa~ (x) I,
+// L^0 u = broadcast of u over the time nodes (eq. ind_prop):
+//
+//   q^(l+1,m+1)[a][l] = u[l] + sum_b kappa~[a][b] ( s - b - k~ f^(l) )[b][l]
+//
+// Work mapping (MI355X, wave64): each cell is served by n = N+1 consecutive
+// lanes; lane a of a cell owns time row a of the AoS tile q[a][0..N][0..M-1]
+// in registers.  The space contraction k~ (Algorithm 2, k_ksi_kernel) and the
+// point-wise flux / source / non-conservative terms (Algorithms 2-3) are
+// in-lane, with the operator coefficients as wave-uniform scalar operands.
+// The time contraction kappa~ (Algorithm 1, kappa_kernel) needs a column of
+// the tile: the residual is transposed through the cell's LDS block, lane a
+// then owns space column a, applies kappa~ in-lane, and transposes the new
+// iterate back.  No exchange ever leaves the wavefront, so a wave-level
+// fence replaces workgroup barriers.
+//
+// Stopping test (the paper leaves the norm open): per cell,
+// max|q_new - q_old| <= tol * max(1, max|q_new|), each cell stopping on its
+// own; with no source and no non-conservative term the inner loop is one
+// pass.  With `stagnation` (FP32 predictor) a loop also stops once its
+// increment stops decreasing, so that float round-off cannot spin it to the
+// iteration limit.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace aderdg {
+
+extern __constant__ DevOps c_ops[kDevMaxn];
+extern __constant__ DevOpsF c_opsf[kDevMaxn];
+
+template <int N, class TP> struct OpK;
+template <int N> struct OpK<N, double> {
+  __device__ static double K(int l, int j) { return c_ops[N].ktil[l][j]; }
+  __device__ static double Kap(int a, int b) { return c_ops[N].kappa[a][b]; }
+};
+template <int N> struct OpK<N, float> {
+  __device__ static float K(int l, int j) { return c_opsf[N].ktil[l][j]; }
+  __device__ static float Kap(int a, int b) { return c_opsf[N].kappa[a][b]; }
+};
+
+template <int N, class PDE, class TP>
+struct Predictor {
+  static constexpr int n = N + 1;
+  static constexpr int M = PDE::M;
+  static constexpr bool kInner = PDE::kSource || PDE::kNcp;
+
+  // Row residual of time node a: -k~ f + s - b, evaluated on the inner iterate qi.
+  __device__ static void residual_row(const TP (&qi)[n][M], const TP (&KF)[n][M], TP* row,
+                                      int a, TP dt, TP dtdx, double xl, double dx, double t0,
+                                      const PdeParams& pp) {
+    const TP ta = TP(t0 + (double)dt * c_ops[N].xi[a]);
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      TP R[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) R[r] = -KF[l][r];
+      if constexpr (PDE::kSource) {
+        TP s[M];
+        PDE::source(qi[l], TP(xl + dx * c_ops[N].xi[l]), ta, s, pp);
+#pragma unroll
+        for (int r = 0; r < M; ++r) R[r] += dt * s[r];
+      }
+      if constexpr (PDE::kNcp) {
+        TP dq[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          TP acc = TP(0);
+#pragma unroll
+          for (int j = 0; j < n; ++j) acc += OpK<N, TP>::K(l, j) * qi[j][r];
+          dq[r] = acc;
+        }
+        TP b[M];
+        PDE::ncp(qi[l], dq, b, pp);
+#pragma unroll
+        for (int r = 0; r < M; ++r) R[r] -= dtdx * b[r];
+      }
+#pragma unroll
+      for (int r = 0; r < M; ++r) row[l * M + r] = R[r];
+    }
+  }
+
+  // Max over the n lanes of a cell of (e, qm), through the cell's reduction slots.
+  __device__ static void cell_reduce(TP* red, int a, TP& e, TP& qm) {
+    red[2 * a] = e;
+    red[2 * a + 1] = qm;
+    wave_sync();
+    TP E = TP(0), Q = TP(0);
+#pragma unroll
+    for (int b = 0; b < n; ++b) {
+      E = dmax(E, red[2 * b]);
+      Q = dmax(Q, red[2 * b + 1]);
+    }
+    wave_sync();
+    e = E;
+    qm = Q;
+  }
+
+  // One kappa~ application: row residual -> (transpose) -> column update -> (transpose) -> row.
+  // xb: the cell's LDS block [n][n][M].  On return `out` holds row a of
+  // q_init + kappa~ (residual).
+  __device__ static void time_contraction(const TP* rowres, const TP (&ucol)[M], TP* xb, int a,
+                                          TP (&out)[n][M]) {
+    wave_sync();
+#pragma unroll
+    for (int l = 0; l < n; ++l)
+#pragma unroll
+      for (int r = 0; r < M; ++r) xb[(a * n + l) * M + r] = rowres[l * M + r];
+    wave_sync();
+    TP col[n][M];
+#pragma unroll
+    for (int b = 0; b < n; ++b)
+#pragma unroll
+      for (int r = 0; r < M; ++r) col[b][r] = xb[(b * n + a) * M + r];
+    wave_sync();
+#pragma unroll
+    for (int a2 = 0; a2 < n; ++a2)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        TP acc = ucol[r];
+#pragma unroll
+        for (int b = 0; b < n; ++b) acc += OpK<N, TP>::Kap(a2, b) * col[b][r];
+        xb[(a2 * n + a) * M + r] = acc;
+      }
+    wave_sync();
+#pragma unroll
+    for (int l = 0; l < n; ++l)
+#pragma unroll
+      for (int r = 0; r < M; ++r) out[l][r] = xb[(a * n + l) * M + r];
+  }
+
+  // q: row a of the initial guess on entry (broadcast of the initial data),
+  // the converged row on exit.  ucol: initial data at space node a.
+  __device__ static void run(TP (&q)[n][M], const TP (&ucol)[M], int a, TP* xb, TP* red,
+                             TP dt, TP dtdx, double xl, double dx, double t0, const PdeParams& pp,
+                             TP tol, int max_iter, bool stagnation, bool active, int& sweeps,
+                             bool& failed) {
+    bool done = !active;
+    sweeps = 0;
+    failed = false;
+    TP eps_prev = TP(3.0e38);
+    TP row[n * M];
+    for (int it = 0; it < max_iter; ++it) {
+      if (!__any(!done)) break;
+      // Algorithm 2: rescaled fluxes at every node of the row, then k~ along space.
+      TP KF[n][M];
+#pragma unroll
+      for (int l = 0; l < n; ++l)
+#pragma unroll
+        for (int r = 0; r < M; ++r) KF[l][r] = TP(0);
+#pragma unroll
+      for (int j = 0; j < n; ++j) {
+        TP f[M];
+        PDE::flux(q[j], f, pp);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          const TP fj = dtdx * f[r];
+#pragma unroll
+          for (int l = 0; l < n; ++l) KF[l][r] += OpK<N, TP>::K(l, j) * fj;
+        }
+      }
+      TP qn[n][M];
+      if constexpr (!kInner) {
+        residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp);
+        time_contraction(row, ucol, xb, a, qn);
+      } else {
+        // inner loop over source / non-conservative terms (Algorithm 1, inner repeat)
+        TP qi[n][M];
+#pragma unroll
+        for (int l = 0; l < n; ++l)
+#pragma unroll
+          for (int r = 0; r < M; ++r) qi[l][r] = q[l][r];
+        bool idone = done;
+        TP ieps_prev = TP(3.0e38);
+        int m = 0;
+        for (; m < max_iter; ++m) {
+          if (!__any(!idone)) break;
+          residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
+          TP qt[n][M];
+          time_contraction(row, ucol, xb, a, qt);
+          TP e = TP(0), qm = TP(0);
+#pragma unroll
+          for (int l = 0; l < n; ++l)
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+              e = dmax(e, dabs(qt[l][r] - qi[l][r]));
+              qm = dmax(qm, dabs(qt[l][r]));
+            }
+          cell_reduce(red, a, e, qm);
+          if (!idone) {
+#pragma unroll
+            for (int l = 0; l < n; ++l)
+#pragma unroll
+              for (int r = 0; r < M; ++r) qi[l][r] = qt[l][r];
+            const bool conv = e <= tol * dmax(TP(1), qm);
+            const bool stag = stagnation && m >= 1 && e >= ieps_prev;
+            ieps_prev = e;
+            if (conv || stag) idone = true;
+          }
+        }
+        if (!idone) failed = true;
+#pragma unroll
+        for (int l = 0; l < n; ++l)
+#pragma unroll
+          for (int r = 0; r < M; ++r) qn[l][r] = qi[l][r];
+      }
+      // outer convergence
+      TP e = TP(0), qm = TP(0);
+#pragma unroll
+      for (int l = 0; l < n; ++l)
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          e = dmax(e, dabs(qn[l][r] - q[l][r]));
+          qm = dmax(qm, dabs(qn[l][r]));
+        }
+      cell_reduce(red, a, e, qm);
+      if (!done) {
+#pragma unroll
+        for (int l = 0; l < n; ++l)
+#pragma unroll
+          for (int r = 0; r < M; ++r) q[l][r] = qn[l][r];
+        ++sweeps;
+        const bool conv = e <= tol * dmax(TP(1), qm);
+        const bool stag = stagnation && sweeps >= 2 && e >= eps_prev;
+        eps_prev = e;
+        if (conv || stag) done = true;
+      }
+    }
+    if (!done) failed = true;
+  }
+};
+
+}  // namespace aderdg

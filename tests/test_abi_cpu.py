@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* libaderdg.so loads and exports every function declared in include/aderdg.h;
+* the library's host operator tables (an independent C++ construction)
+  agree with the oracle's;
+* argument validation returns ADERDG_E_INVAL before any device work.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import basis
+from paper_2409_12483_amd import abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "aderdg.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(abi.LIBPATH),
+                                reason="libaderdg.so not built (run __graft_entry__.build())")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aderdg_\w+|aderweno_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for required in ["aderdg_init", "aderdg_predict", "aderdg_correct", "aderdg_step",
+                     "aderweno_step", "aderdg_free"]:
+        assert required in names
+    assert set(names) == set(abi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(abi.LIBPATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("N", range(0, 10))
+def test_host_operator_tables_match_oracle(N):
+    t = abi.aderdg_operators(N)
+    ops = basis.build_operators(N)
+    scale = max(1.0, np.abs(ops.ktil).max())
+    assert np.allclose(t["xi"], ops.xi, atol=1e-15, rtol=0)
+    assert np.allclose(t["w"], ops.w, atol=1e-15, rtol=0)
+    assert np.allclose(t["ktil"], ops.ktil, atol=2e-14 * scale, rtol=0)
+    assert np.allclose(t["kappa"], ops.kappa, atol=1e-13, rtol=0)
+    assert np.allclose(t["Dtil"], ops.Dtil, atol=2e-14 * scale, rtol=0)
+    assert np.allclose(t["psi0"], ops.psi0, atol=1e-13, rtol=0)
+    assert np.allclose(t["psi1"], ops.psi1, atol=1e-13, rtol=0)
+    assert np.allclose(t["P"], ops.P, atol=1e-13, rtol=0)
+
+
+def _init(pde, cfg):
+    lib = abi.load()
+    h = ctypes.c_void_p()
+    P = (abi.PdeDesc * 1)(pde)
+    C = (abi.Config * 1)(cfg)
+    return lib.aderdg_init(P, C, 1, None, ctypes.byref(h)), h
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda p, c: setattr(p, "nvars", 4), "nvars"),
+    (lambda p, c: setattr(c, "N", 0), "degree"),
+    (lambda p, c: setattr(c, "N", 10), "degree"),
+    (lambda p, c: setattr(c, "ncells", 0), "ncells"),
+    (lambda p, c: setattr(c, "x1", -1.0), "x1 > x0"),
+    (lambda p, c: setattr(c, "cfl", 1.5), "cfl"),
+    (lambda p, c: setattr(c, "bc", 1), "periodic"),
+    (lambda p, c: setattr(c, "precision", 7), "precision"),
+    (lambda p, c: setattr(p, "gamma", 1.0), "gamma"),
+    (lambda p, c: setattr(p, "pde", 9), "pde"),
+    (lambda p, c: (setattr(c, "scheme", abi.SCHEME_FV), setattr(c, "N", 3)), "WENO"),
+    (lambda p, c: (setattr(c, "scheme", abi.SCHEME_FV), setattr(c, "N", 4), setattr(c, "ncells", 5)), "2N+1"),
+])
+def test_invalid_descriptors_are_rejected(mutate, needle):
+    p = abi.pde_desc(abi.PDE_EULER)
+    c = abi.config(3, 100)
+    mutate(p, c)
+    rc, h = _init(p, c)
+    assert rc == abi.ADERDG_E_INVAL
+    assert h.value is None
+    assert needle in abi.aderdg_last_error()
+
+
+def test_null_arguments_are_rejected():
+    lib = abi.load()
+    assert lib.aderdg_step(None, None, None, None, None, None, 1) == abi.ADERDG_E_INVAL
+    assert lib.aderweno_step(None, None, None, None, None, None, 1) == abi.ADERDG_E_INVAL
+    assert lib.aderdg_predict(None, 0, None, 0.0, 0.1, None, None) == abi.ADERDG_E_INVAL
+    assert lib.aderdg_correct(None, 0, None, None, 0.0, 0.1, None) == abi.ADERDG_E_INVAL
+    assert lib.aderdg_sweep_count(None, 0, None) == abi.ADERDG_E_INVAL
+    assert lib.aderdg_free(None) == abi.ADERDG_OK
+    with pytest.raises(abi.AderdgError):
+        abi.aderdg_operators(10)
+
+
+def test_config_struct_layout_matches_header():
+    # field offsets of the ctypes mirror follow the C declaration order and alignment
+    assert ctypes.sizeof(abi.PdeDesc) == 40
+    assert abi.Config.ncells.offset == 8 and abi.Config.x0.offset == 16
+    assert abi.Config.cfl_mode.offset == 48 and abi.Config.picard_tol.offset == 56
+    assert ctypes.sizeof(abi.Config) == 72

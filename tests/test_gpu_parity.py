@@ -1,0 +1,329 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 path 1e-12 relative (L2 over the compared arrays, and
+max-norm on predictor tiles); FP32-predictor path 1e-5 relative L2.
+Sizes span several workgroup tiles and a ragged last tile; the full-size
+configurations are checked on sampled cells that the oracle evaluates from
+their own neighbourhood windows.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import basis, dg, fv, predictor
+from oracle import pde as OP
+from paper_2409_12483_amd import abi
+from paper_2409_12483_amd import workloads as W
+
+from gpu_util import (BIG, oracle_dg_window, oracle_fv_window, rel_l2, rel_max, run_steps,
+                      tensor, torch_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _smooth_euler(C, N, seed=0, amp=0.3):
+    rng = np.random.default_rng(seed)
+    xs = W.cell_points(C, N + 1)
+    rho = 1.0 + amp * np.sin(2 * np.pi * xs + rng.uniform(0, 6)) + 0.02 * rng.uniform(-1, 1, xs.shape)
+    vel = 0.5 + 0.4 * np.cos(2 * np.pi * xs)
+    p = 1.0 + 0.2 * np.sin(4 * np.pi * xs)
+    return np.stack([rho, rho * vel, p / 0.4 + 0.5 * rho * vel ** 2], axis=-1)
+
+
+# ------------------------------------------------------------ predictor ----
+@pytest.mark.parametrize("N,C", [(1, 37), (2, 100), (3, 64), (5, 77), (7, 40), (9, 25)])
+def test_predict_parity_euler(N, C):
+    _say("predict euler", N, C)
+    torch, dev = torch_dev()
+    ops = basis.build_operators(N)
+    e = OP.Euler()
+    u = _smooth_euler(C, N, seed=N)
+    dx = 1.0 / C
+    dt = dg.cfl_dt(ops, e, u, dx, 0.9)
+    q_ref, it_ref, _ = predictor.predict(ops, e, u, dt, dx, dx * np.arange(C), 0.25)
+    h = abi.aderdg_init([abi.pde_desc(abi.PDE_EULER)], [abi.config(N, C)])
+    try:
+        ud = tensor(u)
+        q = torch.zeros((C, N + 1, N + 1, 3), dtype=torch.float64, device=dev)
+        it = torch.zeros(C, dtype=torch.int32, device=dev)
+        abi.aderdg_predict(h, 0, ud, 0.25, dt, q, it)
+        torch.cuda.synchronize()
+    finally:
+        abi.aderdg_free(h)
+    assert rel_max(q.cpu().numpy(), q_ref) <= 1e-12
+    assert (it.cpu().numpy() == it_ref).mean() >= 0.95
+    assert np.abs(it.cpu().numpy() - it_ref).max() <= 1
+
+
+@pytest.mark.parametrize("pdek,N,C", [(abi.PDE_SWE, 3, 40), (abi.PDE_SWE, 6, 33),
+                                      (abi.PDE_EULER_REACT, 2, 20), (abi.PDE_ADVECTION, 4, 50)])
+def test_predict_parity_inner_loop_models(pdek, N, C):
+    _say("predict model", pdek, N, C)
+    torch, dev = torch_dev()
+    ops = basis.build_operators(N)
+    d = abi.pde_desc(pdek, omega=3.0, adv_speed=-1.3)
+    from gpu_util import ORACLE_PDE
+    pde = ORACLE_PDE[pdek](d)
+    if pdek == abi.PDE_SWE:
+        u = W.swe_bump_nodal(C, N)
+        u[..., 1] = 0.3 * u[..., 0]
+        u[..., 2] *= 3.0
+    elif pdek == abi.PDE_EULER_REACT:
+        u = np.concatenate([_smooth_euler(C, N), np.full((C, N + 1, 1), 0.8),
+                            np.full((C, N + 1, 1), -0.2)], axis=-1)
+    else:
+        u = W.advection_nodal(C, N, lambda x: np.sin(2 * np.pi * x))
+    dx = 1.0 / C
+    dt = 0.8 * dx / ((2 * N + 1) * float(pde.max_speed(u).max()))
+    q_ref, it_ref, _ = predictor.predict(ops, pde, u, dt, dx, dx * np.arange(C), 0.1)
+    h = abi.aderdg_init([d], [abi.config(N, C)])
+    try:
+        q = torch.zeros((C, N + 1, N + 1, pde.M), dtype=torch.float64, device=dev)
+        abi.aderdg_predict(h, 0, tensor(u), 0.1, dt, q, None)
+        torch.cuda.synchronize()
+    finally:
+        abi.aderdg_free(h)
+    assert rel_max(q.cpu().numpy(), q_ref) <= 1e-12
+
+
+# ------------------------------------------------------------ corrector ----
+@pytest.mark.parametrize("pdek,N,C", [(abi.PDE_EULER, 2, 100), (abi.PDE_EULER, 5, 83),
+                                      (abi.PDE_SWE, 4, 41), (abi.PDE_EULER_REACT, 3, 10)])
+def test_correct_parity(pdek, N, C):
+    _say("correct", pdek, N, C)
+    torch, dev = torch_dev()
+    ops = basis.build_operators(N)
+    d = abi.pde_desc(pdek, omega=2.0)
+    from gpu_util import ORACLE_PDE
+    pde = ORACLE_PDE[pdek](d)
+    if pdek == abi.PDE_SWE:
+        u = W.swe_bump_nodal(C, N)
+    elif pdek == abi.PDE_EULER_REACT:
+        u = np.concatenate([_smooth_euler(C, N), np.full((C, N + 1, 1), 0.5),
+                            np.full((C, N + 1, 1), 0.1)], axis=-1)
+    else:
+        u = _smooth_euler(C, N, seed=3)
+    dx = 1.0 / C
+    dt = dg.cfl_dt(ops, pde, u, dx, 0.5)
+    x_left = dx * np.arange(C)
+    q, _, _ = predictor.predict(ops, pde, u, dt, dx, x_left, 0.3)
+    ref = dg.dg_correct(ops, pde, u, q, dt, dx, x_left, 0.3)
+    h = abi.aderdg_init([d], [abi.config(N, C)])
+    try:
+        un = torch.zeros_like(tensor(u))
+        abi.aderdg_correct(h, 0, tensor(u), tensor(q), 0.3, dt, un)
+        torch.cuda.synchronize()
+    finally:
+        abi.aderdg_free(h)
+    assert rel_max(un.cpu().numpy() - u, ref - u) <= 1e-11      # the increment itself
+    assert rel_l2(un.cpu().numpy(), ref) <= 1e-12
+
+
+# ----------------------------------------------------------- fused step ----
+def test_step_parity_c1_full_run():
+    """ADER-DG 1D Euler N=2, 100 cells, rho = 1 + 0.2 sin(2 pi x), u = 1, p = 1, CFL 0.4, t_end = 1."""
+    _say("C1 full run")
+    ops = basis.build_operators(2)
+    e = OP.Euler()
+    u0 = W.euler_density_wave(100, 2)
+    ref, t_ref, info = dg.dg_run(ops, e, u0, 0.0, 1.0, cfl=0.4, t_end=1.0)
+    (u,), t, dt, st, sweeps = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(2, 100)], [u0],
+                                        nsteps=info["steps"] + 5, t_end=np.array([1.0]))
+    assert st[0] == 0
+    assert abs(t[0] - t_ref) <= 1e-14
+    assert rel_l2(u, ref) <= 1e-12
+    assert sweeps[0] == sum(k * v for k, v in info["sweep_hist"].items())
+
+
+@pytest.mark.parametrize("N,C", [(1, 1), (1, 2), (2, 5), (5, 37), (5, 38), (5, 39), (3, 77),
+                                 (9, 23), (9, 24), (7, 100)])
+def test_step_parity_ragged(N, C):
+    _say("step ragged", N, C)
+    ops = basis.build_operators(N)
+    e = OP.Euler()
+    u0 = _smooth_euler(C, N, seed=C)
+    ref, t_ref, info = dg.dg_run(ops, e, u0, 0.0, 1.0, cfl=0.4, nsteps=6)
+    (u,), t, dt, st, _ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(N, C)], [u0], 6)
+    assert st[0] == 0
+    assert abs(t[0] - t_ref) <= 1e-14 * t_ref
+    assert abs(dt[0] - info["dts"][-1]) <= 1e-14 * dt[0]
+    assert rel_l2(u, ref) <= 1e-12
+
+
+def test_step_parity_even_and_odd_step_counts():
+    ops = basis.build_operators(4)
+    e = OP.Euler()
+    u0 = _smooth_euler(50, 4, seed=1)
+    for ns in (1, 2, 7):
+        _say("step count", ns)
+        ref, _, _ = dg.dg_run(ops, e, u0, 0.0, 1.0, cfl=0.4, nsteps=ns)
+        (u,), *_ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(4, 50)], [u0], ns)
+        assert rel_l2(u, ref) <= 1e-12
+
+
+def test_step_parity_swe_dg_and_nodal_cfl():
+    _say("swe dg")
+    ops = basis.build_operators(3)
+    swe = OP.ShallowWater()
+    u0 = W.swe_bump_nodal(60, 3)
+    ref, _, _ = dg.dg_run(ops, swe, u0, 0.0, 1.0, cfl=0.4, nsteps=8, cfl_mode="nodal")
+    (u,), _, _, st, _ = run_steps([abi.pde_desc(abi.PDE_SWE)],
+                                  [abi.config(3, 60, cfl_mode=abi.CFL_NODAL)], [u0], 8)
+    assert st[0] == 0
+    assert rel_l2(u, ref) <= 1e-12
+    assert np.array_equal(u[..., 2], u0[..., 2])
+
+
+def test_ode_problem_matches_pade():
+    """Sec. 2.1 ODE test on the GPU (source term, inner Picard loop, fixed dt)."""
+    from oracle import pade
+    N, ns = 3, 10
+    u0 = W.euler_react_uniform(1, N)
+    cfg = abi.config(N, 1, x0=0.0, x1=1000.0, fixed_dt=2 * np.pi / ns, picard_max_iter=200)
+    _say("ode")
+    (u,), t, *_ = run_steps([abi.pde_desc(abi.PDE_EULER_REACT, omega=1.0)], [cfg], [u0], ns,
+                            t_end=np.array([2 * np.pi]))
+    closed = pade.oscillator_trajectory(N, ns)[-1]
+    assert np.abs(u[0, :, 3:] - closed).max() <= 1e-12
+
+
+# ---------------------------------------------------- FP32 predictor mode ----
+def test_fp32_predictor_within_1e5():
+    _say("fp32 predictor")
+    N, C = 5, 2000
+    ops = basis.build_operators(N)
+    e = OP.Euler()
+    u0 = W.euler_density_wave(C, N, noise=1e-3, seed=0)
+    ref, _, _ = dg.dg_run(ops, e, u0, 0.0, 1.0, cfl=0.4, nsteps=20)
+    (u,), _, _, st, _ = run_steps([abi.pde_desc(abi.PDE_EULER)],
+                                  [abi.config(N, C, precision=abi.FP32_PREDICTOR)], [u0], 20)
+    assert st[0] == 0
+    err = rel_l2(u, ref)
+    assert err <= 1e-5, err
+    # and it is not secretly the FP64 path
+    (u64,), *_ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(N, C)], [u0], 20)
+    assert rel_l2(u64, ref) <= 1e-12 and err > 1e-13
+
+
+# ------------------------------------------------------------------ FV ----
+@pytest.mark.parametrize("prec,tol", [(abi.FP64, 1e-12), (abi.FP32_PREDICTOR, 1e-5)])
+def test_fv_swe_parity(prec, tol):
+    _say("fv swe", prec)
+    ops = basis.build_operators(4)
+    swe = OP.ShallowWater()
+    v0 = W.swe_bump_averages(300)
+    ref, t_ref, _ = fv.fv_run(ops, swe, v0, 0.0, 1.0, cfl=0.4, nsteps=12)
+    (v,), t, _, st, _ = run_steps([abi.pde_desc(abi.PDE_SWE)],
+                                  [abi.config(4, 300, precision=prec, scheme=abi.SCHEME_FV)],
+                                  [v0], 12, fv_scheme=True)
+    assert st[0] == 0
+    assert rel_l2(v, ref) <= tol
+    assert np.array_equal(v[:, 2], v0[:, 2])
+    assert abs(v[:, 0].sum() - v0[:, 0].sum()) <= 1e-13 * v0[:, 0].sum()
+
+
+def test_fv_euler_weno2_parity():
+    _say("fv euler weno2")
+    ops = basis.build_operators(2)
+    e = OP.Euler()
+    rho = W.smooth_averages(64, lambda x: 1 + 0.2 * np.sin(2 * np.pi * x))
+    v0 = np.stack([rho, 0.7 * rho, 2.5 + 0.5 * 0.49 * rho], axis=1)
+    ref, _, _ = fv.fv_run(ops, e, v0, 0.0, 1.0, cfl=0.4, nsteps=10)
+    (v,), *_ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(2, 64, scheme=abi.SCHEME_FV)],
+                         [v0], 10, fv_scheme=True)
+    assert rel_l2(v, ref) <= 1e-12
+
+
+# ------------------------------------------------------ invariants on GPU ----
+def test_gpu_conservation_and_constant_state():
+    _say("conservation")
+    N, C = 4, 120
+    ops = basis.build_operators(N)
+    u0 = W.euler_density_wave(C, N, noise=1e-3, seed=2)
+    (u,), *_ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(N, C)], [u0], 200)
+    m0 = dg.conserved_totals(ops, u0, 1.0 / C)
+    m1 = dg.conserved_totals(ops, u, 1.0 / C)
+    assert np.allclose(m1, m0, rtol=1e-13, atol=0)
+    uc = W.euler_density_wave(C, N, amp=0.0, velocity=0.3)
+    (u2,), *_ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(N, C)], [uc], 100)
+    assert np.abs(u2 - uc).max() <= 1e-13
+
+
+# ---------------------------------------------------------- full sizes ----
+def test_c2_full_size_sampled():
+    """ADER-DG Euler N=5, 1e5 cells, noisy density wave: one fused step, sampled cells."""
+    _say("C2 full size")
+    N, C = 5, 100_000
+    ops = basis.build_operators(N)
+    e = OP.Euler()
+    u0 = W.euler_density_wave(C, N, noise=1e-3, seed=0)
+    (u,), t, dt, st, _ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(N, C)], [u0], 1)
+    assert st[0] == 0
+    dt_ref = dg.cfl_dt(ops, e, u0, 1.0 / C, 0.4)
+    assert abs(dt[0] - dt_ref) <= 1e-15 * dt_ref
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([[0, 1, 37, 38, 39, C - 2, C - 1], rng.integers(0, C, 400)])
+    ref = oracle_dg_window(ops, e, u0, dt_ref, 1.0 / C, 0.0, idx)
+    assert rel_l2(u[idx] - u0[idx], ref - u0[idx]) <= 1e-10
+    assert rel_l2(u[idx], ref) <= 1e-12
+
+
+def test_c3_full_size_sampled():
+    """ADER-WENO-FV SWE, WENO degree 4 + predictor N=4, 1e6 cells: one step, sampled cells."""
+    _say("C3 full size")
+    C = 1_000_000
+    ops = basis.build_operators(4)
+    swe = OP.ShallowWater()
+    v0 = W.swe_bump_averages(C)
+    (v,), t, dt, st, _ = run_steps([abi.pde_desc(abi.PDE_SWE)],
+                                   [abi.config(4, C, scheme=abi.SCHEME_FV)], [v0], 1, fv_scheme=True)
+    assert st[0] == 0
+    dt_ref = fv.fv_dt(swe, v0, 1.0 / C, 0.4)
+    assert abs(dt[0] - dt_ref) <= 1e-15 * dt_ref
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([[0, 1, 45, 46, 47, C - 1], rng.integers(0, C, 60)])
+    ref = oracle_fv_window(ops, swe, v0, dt_ref, 1.0 / C, 0.0, idx)
+    assert rel_l2(v[idx], ref) <= 1e-12
+
+
+# --------------------------------------------------------------- batches ----
+def test_batch_equals_individual_runs_bitwise():
+    _say("batch")
+    descs = [abi.pde_desc(abi.PDE_EULER), abi.pde_desc(abi.PDE_SWE), abi.pde_desc(abi.PDE_EULER),
+             abi.pde_desc(abi.PDE_EULER)]
+    cfgs = [abi.config(3, 57), abi.config(2, 41), abi.config(3, 12), abi.config(6, 30)]
+    states = [W.euler_density_wave(57, 3, k=2), W.swe_bump_nodal(41, 2),
+              W.euler_density_wave(12, 3, phase=1.0), W.euler_density_wave(30, 6, k=3)]
+    t_end = np.array([BIG, BIG, 0.01, BIG])
+    batch, tb, dtb, stb, _ = run_steps(descs, cfgs, states, 9, t_end=t_end)
+    for k in range(4):
+        single, ts, dts, sts, _ = run_steps([descs[k]], [cfgs[k]], [states[k]], 9, t_end=t_end[k:k + 1])
+        assert np.array_equal(batch[k], single[0]), k
+        assert tb[k] == ts[0] and dtb[k] == dts[0]
+    assert tb[2] == 0.01
+
+
+# ---------------------------------------------------------- status flags ----
+def test_status_nonphysical_and_noconv():
+    _say("status")
+    u0 = W.euler_density_wave(20, 2)
+    bad = u0.copy()
+    bad[5, 1, 0] = -0.5
+    (_,), _, _, st, _ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(2, 20, fixed_dt=1e-3)],
+                                  [bad], 1)
+    assert st[0] == abi.ADERDG_E_NONPHYS
+    (_,), _, _, st, _ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(2, 20, picard_max_iter=1)],
+                                  [_smooth_euler(20, 2)], 1)
+    assert st[0] == abi.ADERDG_E_NOCONV
+
+
+def test_already_at_end_time_is_a_noop():
+    _say("noop")
+    u0 = W.euler_density_wave(20, 2)
+    (u,), t, dt, st, _ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(2, 20)], [u0], 3,
+                                   t0=np.array([0.5]), t_end=np.array([0.5]))
+    assert np.array_equal(u, u0) and t[0] == 0.5 and dt[0] == 0.0 and st[0] == 0
