@@ -1,0 +1,240 @@
+"""Benchmark of the fused ADER-DG hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3]
+
+Default workload (BASELINE configuration "ADER-DG 1D Euler, N=5, 1e5 cells,
+periodic smooth density wave + seeded 1e-3 noise, u=1, p=1"): a step is one
+ADER-DG time step of the whole mesh -- CFL dt, LST-DG predictor, corrector
+volume and surface terms -- in one fused kernel launch.  W untimed steps,
+then exactly K steps timed between device synchronisations; one JSON line.
+
+Reported beside the headline FP64 number:
+  * roofline of the fused step kernel (VALU-bound: algorithmic flops from the
+    flop model below with the measured Picard sweep counts, over the
+    kernel's time measured with HIP events on the library's stream);
+  * the FP32-predictor / FP64-corrector mode on the same workload;
+  * DoF-updates/s for N = 1..9 on the same mesh (FP64);
+  * per-step latency percentiles (event-timed two-step calls);
+  * the CPU oracle on a bounded sample of the same workload (cpu_baseline).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU = 78.6      # TFLOP/s: 256 CU x 4 SIMD x 16 FP64 FMA lanes x 2 flop x 2.4 GHz
+PEAK_FP32_VALU = 157.3     # TFLOP/s (AMD's published vector FP32 figure)
+PEAK_HBM = 8000.0          # GB/s
+
+FLUX_FLOPS = {"euler": 12, "swe": 8, "euler_react": 14, "advection": 1}
+RIEMANN_FLOPS = 48
+
+
+def dg_flops_per_cell(N, M, sweeps_per_cell, flux=12):
+    """Algorithmic flops of one fused step per cell (Kronecker-factored contractions):
+    predictor per sweep  n^2 F + 2n^3M (k~) + 2n^3M (kappa~) + 2n^2M (combine) + 2n^2M (test)
+    corrector            n^2 F + 2n^2M + 2n^2M + 4n^2M (traces) + n R + 9nM
+    CFL                  2(2N+1) n M + 8 (2N+1)
+    Returns (predictor flops, corrector + CFL flops)."""
+    n = N + 1
+    sweep = n * n * flux + 4 * n ** 3 * M + 4 * n * n * M
+    corr = n * n * flux + 8 * n * n * M + n * RIEMANN_FLOPS + 9 * n * M
+    cfl = 2 * (2 * N + 1) * n * M + 8 * (2 * N + 1)
+    return sweeps_per_cell * sweep, corr + cfl
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+class DGRun:
+    """One problem on the device, driven through the C ABI."""
+
+    def __init__(self, N, ncells, precision, noise=1e-3, seed=0):
+        import torch
+        from paper_2409_12483_amd import abi
+        from paper_2409_12483_amd import workloads as W
+        self.abi, self.torch = abi, torch
+        self.N, self.C, self.M = N, ncells, 3
+        dev = torch.device("cuda:0")
+        self.stream = torch.cuda.current_stream()
+        self.u0 = W.euler_density_wave(ncells, N, noise=noise, seed=seed)
+        self.u = torch.tensor(self.u0, device=dev)
+        self.t = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.te = torch.full((1,), 1.0e300, dtype=torch.float64, device=dev)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.st = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.h = abi.aderdg_init([abi.pde_desc(abi.PDE_EULER)],
+                                 [abi.config(N, ncells, precision=precision)],
+                                 stream=self.stream.cuda_stream)
+
+    def steps(self, k):
+        self.abi.aderdg_step(self.h, [self.u], self.t, self.te, self.dt, self.st, k)
+
+    def sweeps(self):
+        return self.abi.aderdg_sweep_count(self.h, 0)
+
+    def timed(self, k):
+        """Event-timed k steps; returns (seconds, sweeps in the region)."""
+        torch = self.torch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0 = self.sweeps()
+        _sync()
+        e0.record(self.stream)
+        self.steps(k)
+        e1.record(self.stream)
+        _sync()
+        return e0.elapsed_time(e1) * 1e-3, self.sweeps() - s0
+
+    def latency(self, reps=40):
+        torch = self.torch
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(self.stream)
+            self.steps(2)
+            e1.record(self.stream)
+            e1.synchronize()
+            out.append(e0.elapsed_time(e1) * 0.5)
+        return out
+
+    def close(self):
+        self.abi.aderdg_free(self.h)
+
+
+def roofline_entry(N, C, M, steps, seconds, sweeps, precision):
+    pred, rest = dg_flops_per_cell(N, M, sweeps / (C * steps))
+    pred_total = pred * C * steps
+    rest_total = rest * C * steps
+    achieved = (pred_total + rest_total) / seconds * 1e-12
+    if precision == "fp64":
+        peak = PEAK_FP64_VALU
+        t_roof = (pred_total + rest_total) / (PEAK_FP64_VALU * 1e12)
+    else:
+        t_roof = pred_total / (PEAK_FP32_VALU * 1e12) + rest_total / (PEAK_FP64_VALU * 1e12)
+        peak = (pred_total + rest_total) / t_roof * 1e-12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+            "unit": "TFLOP/s", "frac": round(t_roof / seconds, 4),
+            "flops_per_step": int(round((pred_total + rest_total) / steps)),
+            "sweeps_per_cell": round(sweeps / (C * steps), 3)}
+
+
+def cpu_baseline(N, target_s=12.0):
+    """The oracle, as is, on a bounded sample of the same workload."""
+    from oracle import basis, dg
+    from oracle import pde as OP
+    from paper_2409_12483_amd import workloads as W
+    ops = basis.build_operators(N)
+    C = 20_000
+    u = W.euler_density_wave(C, N, noise=1e-3, seed=0)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < target_s and steps < 50:
+        u, _, _ = dg.dg_run(ops, OP.Euler(), u, 0.0, 1.0, cfl=0.4, nsteps=1)
+        steps += 1
+    el = time.perf_counter() - t0
+    return {"value": round(steps * C * (N + 1) * 3 / el, 1), "unit": "DoF-updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{C} cells of the same mesh family (dx = 1/{C}), {steps} steps, NumPy FP64, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--N", type=int, default=5)
+    ap.add_argument("--ncells", type=int, default=100_000)
+    ap.add_argument("--no-extras", action="store_true", help="headline only (for profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 512 MiB device copy (HBM counter calibration)")
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the ADER-DG hot path "
+                                   "is measured on one GPU share"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2409_12483_amd import abi
+    abi.load()
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    N, C, M = a.N, a.ncells, 3
+    K, Wm = a.steps, a.warmup
+    if a.calibrate_copy:
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        _sync()
+        del x, y
+
+    run = DGRun(N, C, abi.FP64)
+    run.steps(Wm)
+    _sync()
+    wall0 = time.perf_counter()
+    secs, sweeps = run.timed(K)
+    wall = time.perf_counter() - wall0
+    status = int(run.st.item())
+    dofs = C * (N + 1) * M
+    value = K * dofs / secs
+    out = {
+        "metric": "ADER-DG DoF-updates/s (1-D Euler, fused predictor+corrector step)",
+        "value": round(value, 1), "unit": "DoF-updates/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": round(secs / K * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"ADER-DG 1D Euler gamma=1.4, N={N}, {C} periodic cells on [0,1], "
+                               "rho=1+0.2 sin(2 pi x)+U(-1e-3,1e-3) seed 0, u=1, p=1, CFL 0.4, "
+                               "Rusanov, FP64",
+                   "N": N, "ncells": C, "nvars": M, "precision": "fp64"},
+        "roofline": roofline_entry(N, C, M, K, secs, sweeps, "fp64"),
+        "status": status, "wall_s": round(wall, 4),
+    }
+    out["roofline"]["traffic"] = None
+    run.close()
+
+    if not a.no_extras:
+        r32 = DGRun(N, C, abi.FP32_PREDICTOR)
+        r32.steps(Wm)
+        s32, sw32 = r32.timed(K)
+        out["fp32_predictor"] = {"value": round(K * dofs / s32, 1), "ms_per_step": round(s32 / K * 1e3, 5),
+                                 "roofline": roofline_entry(N, C, M, K, s32, sw32, "fp32"),
+                                 "status": int(r32.st.item())}
+        lat = np.array(r32.latency(30))
+        r32.close()
+        rl = DGRun(N, C, abi.FP64)
+        rl.steps(2)
+        lat64 = np.array(rl.latency(30))
+        rl.close()
+        out["step_latency_ms"] = {
+            "fp64": {"p50": round(float(np.percentile(lat64, 50)), 4), "p99": round(float(np.percentile(lat64, 99)), 4)},
+            "fp32_predictor": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4)},
+            "method": "HIP-event time of aderdg_step calls of 2 steps, halved"}
+        per = []
+        for n_deg in range(1, 10):
+            r = DGRun(n_deg, C, abi.FP64)
+            r.steps(4)
+            kk = 20
+            s, sw = r.timed(kk)
+            rf = roofline_entry(n_deg, C, M, kk, s, sw, "fp64")
+            per.append({"N": n_deg, "value": round(kk * C * (n_deg + 1) * M / s, 1),
+                        "ms_per_step": round(s / kk * 1e3, 5), "frac": rf["frac"],
+                        "sweeps_per_cell": rf["sweeps_per_cell"]})
+            r.close()
+        out["per_degree_fp64"] = per
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(N)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -133,14 +133,14 @@ namespace {
 
 void release(aderdg_handle* h) {
   if (!h) return;
-  if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
-  for (double* p : h->scratch) if (p) hipFree(p);
+  if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
+  for (double* p : h->scratch) if (p) (void)hipFree(p);
   for (Group& g : h->groups) {
-    if (g.dev) hipFree(g.dev);
-    if (g.lam_dev) hipFree(g.lam_dev);
+    if (g.dev) (void)hipFree(g.dev);
+    if (g.lam_dev) (void)hipFree(g.lam_dev);
   }
-  if (h->single_dev) hipFree(h->single_dev);
-  if (h->clocks) hipFree(h->clocks);
+  if (h->single_dev) (void)hipFree(h->single_dev);
+  if (h->clocks) (void)hipFree(h->clocks);
   delete h;
 }
 
@@ -219,7 +219,7 @@ int bind_states(aderdg_handle* h, Group& g, double* const* u) {
   }
   if (!changed) return ADERDG_OK;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  hipStreamIsCapturing(h->stream, &cs);
+  (void)hipStreamIsCapturing(h->stream, &cs);
   if (cs != hipStreamCaptureStatusNone)
     return fail(ADERDG_E_INVAL, "state pointers changed during stream capture; call once eagerly first");
   hipError_t e = hipStreamSynchronize(h->stream);
@@ -447,10 +447,12 @@ int aderdg_sweep_count(aderdg_handle* h, int32_t k, int64_t* sweeps_out) {
   if (k < 0 || k >= h->nprob) return fail(ADERDG_E_INVAL, "problem index out of range");
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail_hip(e, "stream synchronize");
-  unsigned long long v = 0;
-  e = hipMemcpy(&v, &h->clocks[k].sweeps, sizeof(v), hipMemcpyDeviceToHost);
+  Slot slots[kSlots];
+  e = hipMemcpy(slots, h->clocks[k].sweeps, sizeof(slots), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail_hip(e, "sweep count read");
-  *sweeps_out = (int64_t)v;
+  int64_t total = 0;
+  for (int i = 0; i < kSlots; ++i) total += (int64_t)slots[i].v;
+  *sweeps_out = total;
   return ADERDG_OK;
 }
 

@@ -54,8 +54,10 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <class T> __device__ __forceinline__ T dabs(T x) { return x < T(0) ? -x : x; }
-template <class T> __device__ __forceinline__ T dmax(T a, T b) { return a > b ? a : b; }
+__device__ __forceinline__ double dabs(double x) { return fabs(x); }
+__device__ __forceinline__ float dabs(float x) { return fabsf(x); }
+__device__ __forceinline__ double dmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float dmax(float a, float b) { return fmaxf(a, b); }
 
 // ------------------------------------------------------------ PDE traits ----
 // Each model: M, kSource, kNcp, flux(q,f), speed(q), admissible(q); models
@@ -180,14 +182,23 @@ struct ProbDev {
   PdeParams pp;
 };
 
-// Per-problem device clock (library-owned).
+// Per-problem device clock (library-owned).  The signal-speed maxima and the
+// sweep counter are spread over kSlots counters on separate 128-byte lines:
+// thousands of workgroups updating one address would serialise at the
+// memory-side atomic unit.  Readers combine the slots.
+constexpr int kSlots = 32;
+struct alignas(128) Slot {
+  unsigned long long v;
+  unsigned long long pad[15];
+};
 struct ProbClock {
   double t[2];                    // t^n of even / odd steps
-  unsigned long long lam[3];      // max signal speed (bit pattern of a non-negative double)
   double dt_last;
-  unsigned long long sweeps;      // outer Picard sweeps summed over cells
   int32_t status;
   int32_t pad;
+  unsigned long long pad2[12];
+  Slot lam[3][kSlots];            // max signal speed (bit pattern of a non-negative double)
+  Slot sweeps[kSlots];            // outer Picard sweeps summed over cells
 };
 
 __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, double v) {

@@ -38,11 +38,10 @@ struct Geo {
   static constexpr int CPW = 64 / n;                 // cells per wavefront
   static constexpr int PC = WAVES * CPW;             // predictor cells per workgroup
   static constexpr int TILE = HALO ? PC - 2 : PC;    // cells written per workgroup
-  static constexpr int XB = (CPW + 1) * n * n * M;   // doubles of LDS exchange per wave (+1 idle slot)
-  static constexpr int RED = (CPW + 1) * n * 2;      // reduction slots per wave
+  static constexpr int XB = CPW * n * n * M;         // doubles of LDS exchange per wave
+  static constexpr int RED = CPW * n * 2;            // reduction slots per wave
 };
 
-template <class T> __device__ __forceinline__ T clamp_dt(double dt) { return T(dt); }
 
 // Problem-level step parameters for a workgroup.
 struct StepCtx {
@@ -53,9 +52,22 @@ struct StepCtx {
   int64_t tile;
 };
 
+// Max of a problem's signal-speed slots, read by wave 0 and broadcast through LDS.
+__device__ __forceinline__ double read_lambda(const ProbClock& clk, int buf, double* bcast) {
+  if (threadIdx.x < 64) {
+    double v = 0.0;
+    if (threadIdx.x < kSlots) v = __longlong_as_double((long long)clk.lam[buf][threadIdx.x].v);
+    v = wave_max(v);
+    if (threadIdx.x == 0) *bcast = v;
+  }
+  __syncthreads();
+  return *bcast;
+}
+
 // Resolve the problem, time and step size of this workgroup (step mode).
 template <bool DG, int N>
-__device__ __forceinline__ bool step_setup(const StepArgs& A, const ProbDev& P, StepCtx& c) {
+__device__ __forceinline__ bool step_setup(const StepArgs& A, const ProbDev& P, StepCtx& c,
+                                           double* bcast) {
   ProbClock& clk = A.clocks[P.pid];
   const int s = A.step;
   c.pid = P.pid;
@@ -64,7 +76,7 @@ __device__ __forceinline__ bool step_setup(const StepArgs& A, const ProbDev& P, 
   if (P.fixed_dt > 0.0) {
     dt = P.fixed_dt;
   } else {
-    const double lam = __longlong_as_double((long long)clk.lam[s % 3]);
+    const double lam = read_lambda(clk, s % 3, bcast);
     dt = DG ? P.cfl * P.dx / ((2.0 * N + 1.0) * lam) : P.cfl * P.dx / lam;
   }
   const double rem = A.t_end[P.pid] - c.t;
@@ -73,13 +85,45 @@ __device__ __forceinline__ bool step_setup(const StepArgs& A, const ProbDev& P, 
   c.dt = dt;
   c.u_in = P.state[s & 1];
   c.u_out = P.state[(s + 1) & 1];
-  if (c.tile == 0 && threadIdx.x == 0) {
-    clk.t[(s + 1) & 1] = c.t + dt;
-    if (dt > 0.0) clk.dt_last = dt;
-    clk.lam[(s + 2) % 3] = 0ull;
-    if (dt == 0.0) clk.lam[(s + 1) % 3] = clk.lam[s % 3];   // state unchanged: carry lambda
+  if (c.tile == 0) {
+    if (threadIdx.x == 0) {
+      clk.t[(s + 1) & 1] = c.t + dt;
+      if (dt > 0.0) clk.dt_last = dt;
+    }
+    if (threadIdx.x < kSlots) {
+      clk.lam[(s + 2) % 3][threadIdx.x].v = 0ull;
+      if (dt == 0.0)   // state unchanged: carry lambda
+        clk.lam[(s + 1) % 3][threadIdx.x].v = clk.lam[s % 3][threadIdx.x].v;
+    }
   }
   return dt > 0.0;
+}
+
+// Workgroup-level epilogue: sum of sweeps and max of signal speed over the
+// waves (per-wave partials in LDS), one atomic each into slot (tile % kSlots).
+template <int WAVES>
+__device__ __forceinline__ void publish(ProbClock& clk, int buf, int64_t tile, int wave, int lane,
+                                        unsigned long long sw, double lam,
+                                        unsigned long long* sw_wave, double* lam_wave) {
+  sw = wave_sum(sw);
+  lam = wave_max(lam);
+  if (lane == 0) {
+    sw_wave[wave] = sw;
+    lam_wave[wave] = lam;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long S = 0;
+    double L = 0.0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+      S += sw_wave[w];
+      L = dmax(L, lam_wave[w]);
+    }
+    const int slot = (int)(tile % kSlots);
+    if (S) atomicAdd(&clk.sweeps[slot].v, S);
+    atomic_max_nonneg(&clk.lam[buf][slot].v, L);
+  }
 }
 
 // Copy a tile unchanged (problem already at t_end).
@@ -100,10 +144,13 @@ dg_kernel(StepArgs A) {
 
   __shared__ double xb_all[WAVES * G::XB];
   __shared__ TP red_all[WAVES * G::RED];
+  __shared__ TP sK[n * n], sKs[n * n], sKap[n * n];
   __shared__ double trL[PC * n * M];   // left-face traces  [pc][a][r]
   __shared__ double trR[PC * n * M];   // right-face traces [pc][a][r]; reused for the face fluxes
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
   __shared__ double lam_wave[WAVES];
+  __shared__ unsigned long long sw_wave[WAVES];
+  __shared__ double bcast;
 
   const int pidx = MODE == kStep ? find_problem(A.probs, A.nprob, blockIdx.x) : A.k;
   const ProbDev& P = A.probs[pidx];
@@ -115,7 +162,7 @@ dg_kernel(StepArgs A) {
   const int64_t count = (C - first < G::TILE) ? C - first : G::TILE;
 
   if constexpr (MODE == kStep) {
-    if (!step_setup<true, N>(A, P, c)) {
+    if (!step_setup<true, N>(A, P, c, &bcast)) {
       copy_tile(c.u_in, c.u_out, first, count, n * M);
       return;
     }
@@ -127,10 +174,14 @@ dg_kernel(StepArgs A) {
     c.u_out = A.u_out;
   }
 
+  if constexpr (MODE != kCorrect) {
+    stage_operators<N, TP>(sK, sKs, sKap, c.dt / P.dx);
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int slot0 = lane / n;
   const bool active = slot0 < CPW;
-  const int slot = active ? slot0 : CPW;               // idle lanes share a dummy slot
+  const int slot = active ? slot0 : 0;                  // idle lanes read (never write) slot 0
   const int a = active ? lane % n : lane - CPW * n;
   const int pc = wave * CPW + slot;                      // predictor cell in the workgroup
   int64_t gc = first + pc - (HALO ? 1 : 0);              // global cell (periodic wrap)
@@ -165,8 +216,8 @@ dg_kernel(StepArgs A) {
 #pragma unroll
     for (int r = 0; r < M; ++r) ucol[r] = TP(ucell[a * M + r]);
     const TP tol = TP(P.tol);
-    Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, TP(dt), TP(dtdx), xl, dx, c.t, P.pp,
-              tol, P.max_iter, sizeof(TP) == 4, active, sweeps, failed);
+    Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, sK, sKs, sKap, TP(dt), TP(dtdx), xl, dx,
+              c.t, P.pp, tol, P.max_iter, sizeof(TP) == 4, active, sweeps, failed);
   }
 
   if constexpr (MODE == kPredict) {
@@ -227,8 +278,10 @@ dg_kernel(StepArgs A) {
 #pragma unroll
         for (int r = 0; r < M; ++r) V[r] -= dtdx * b[r];
       }
+      if (active) {
 #pragma unroll
-      for (int r = 0; r < M; ++r) xb[(a * n + k) * M + r] = wa * V[r];
+        for (int r = 0; r < M; ++r) xb[(a * n + k) * M + r] = wa * V[r];
+      }
     }
     // face traces of time row a
     if (active) {
@@ -307,9 +360,7 @@ dg_kernel(StepArgs A) {
     if constexpr (MODE == kStep) {
       if (bad) atomicMin(&A.clocks[c.pid].status, -5);
       else if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);
-      unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
-      sw = wave_sum(sw);
-      if (lane == 0 && sw) atomicAdd(&A.clocks[c.pid].sweeps, sw);
+      const unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
       double lam = 0.0;
       if (P.cfl_mode == 1) {
         if (out_cell) lam = PDE::speed(unew, P.pp);
@@ -339,15 +390,8 @@ dg_kernel(StepArgs A) {
           }
         }
       }
-      lam = wave_max(lam);
-      if (lane == 0) lam_wave[wave] = lam;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double m = 0.0;
-#pragma unroll
-        for (int w = 0; w < WAVES; ++w) m = dmax(m, lam_wave[w]);
-        atomic_max_nonneg(&A.clocks[c.pid].lam[(A.step + 1) % 3], m);
-      }
+      publish<WAVES>(A.clocks[c.pid], (A.step + 1) % 3, c.tile, wave, lane, sw, lam, sw_wave,
+                     lam_wave);
     } else {
       if (bad) atomicMin(&A.clocks[c.pid].status, -5);
     }
@@ -368,11 +412,14 @@ fv_kernel(StepArgs A) {
   __shared__ double vb[NV * M];
   __shared__ double xb_all[WAVES * G::XB];
   __shared__ TP red_all[WAVES * G::RED];
+  __shared__ TP sK[n * n], sKs[n * n], sKap[n * n];
   __shared__ double trL[PC * n * M];
   __shared__ double trR[PC * n * M];
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
   __shared__ double volb[PC * n * M];
   __shared__ double lam_wave[WAVES];
+  __shared__ unsigned long long sw_wave[WAVES];
+  __shared__ double bcast;
 
   const int pidx = find_problem(A.probs, A.nprob, blockIdx.x);
   const ProbDev& P = A.probs[pidx];
@@ -382,7 +429,7 @@ fv_kernel(StepArgs A) {
   const int64_t first = c.tile * G::TILE;
   if (first >= C) return;
   const int64_t count = (C - first < G::TILE) ? C - first : G::TILE;
-  if (!step_setup<false, NW>(A, P, c)) {
+  if (!step_setup<false, NW>(A, P, c, &bcast)) {
     copy_tile(c.u_in, c.u_out, first, count, M);
     return;
   }
@@ -394,12 +441,13 @@ fv_kernel(StepArgs A) {
     if (g < 0) g += C;
     vb[i] = c.u_in[g * M + r];
   }
+  stage_operators<NW, TP>(sK, sKs, sKap, c.dt / P.dx);
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int slot0 = lane / n;
   const bool active = slot0 < CPW;
-  const int slot = active ? slot0 : CPW;
+  const int slot = active ? slot0 : 0;
   const int a = active ? lane % n : lane - CPW * n;
   const int pc = wave * CPW + slot;
   int64_t gc = (first + pc - 1) % C;
@@ -443,8 +491,10 @@ fv_kernel(StepArgs A) {
   }
   // broadcast the reconstruction to every row of the cell
   wave_sync();
+  if (active) {
 #pragma unroll
-  for (int r = 0; r < M; ++r) xb[a * M + r] = what[r];
+    for (int r = 0; r < M; ++r) xb[a * M + r] = what[r];
+  }
   wave_sync();
   TP q[n][M], ucol[M];
 #pragma unroll
@@ -455,8 +505,8 @@ fv_kernel(StepArgs A) {
   for (int r = 0; r < M; ++r) ucol[r] = TP(what[r]);
   int sweeps = 0;
   bool failed = false;
-  Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, TP(dt), TP(dtdx), xl, dx, c.t, P.pp,
-            TP(P.tol), P.max_iter, sizeof(TP) == 4, active, sweeps, failed);
+  Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, sK, sKs, sKap, TP(dt), TP(dtdx), xl, dx, c.t,
+            P.pp, TP(P.tol), P.max_iter, sizeof(TP) == 4, active, sweeps, failed);
 
   // ---- FV corrector ----
   const double wa = c_ops[NW].w[a < n ? a : 0];
@@ -556,18 +606,8 @@ fv_kernel(StepArgs A) {
   }
   if (bad) atomicMin(&A.clocks[c.pid].status, -5);
   else if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);
-  unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
-  sw = wave_sum(sw);
-  if (lane == 0 && sw) atomicAdd(&A.clocks[c.pid].sweeps, sw);
-  lam = wave_max(lam);
-  if (lane == 0) lam_wave[wave] = lam;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) m = dmax(m, lam_wave[w]);
-    atomic_max_nonneg(&A.clocks[c.pid].lam[(A.step + 1) % 3], m);
-  }
+  const unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
+  publish<WAVES>(A.clocks[c.pid], (A.step + 1) % 3, c.tile, wave, lane, sw, lam, sw_wave, lam_wave);
 }
 
 // ------------------------------------------------------- lambda / clock ----
@@ -617,8 +657,15 @@ lambda_kernel(StepArgs A) {
       }
     }
   }
+  __shared__ double part[4];
   lam = wave_max(lam);
-  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&A.clocks[P.pid].lam[0], lam);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = lam;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = dmax(dmax(part[0], part[1]), dmax(part[2], part[3]));
+    const int64_t blk = (int64_t)blockIdx.x - P.tile_begin;
+    atomic_max_nonneg(&A.clocks[P.pid].lam[0][blk % kSlots].v, m);
+  }
 }
 
 __global__ void clock_begin_kernel(ProbClock* clocks, const double* t_user, int nprob) {
@@ -627,7 +674,8 @@ __global__ void clock_begin_kernel(ProbClock* clocks, const double* t_user, int 
   ProbClock& c = clocks[p];
   c.t[0] = t_user[p];
   c.t[1] = t_user[p];
-  c.lam[0] = c.lam[1] = c.lam[2] = 0ull;
+  for (int b = 0; b < 3; ++b)
+    for (int i = 0; i < kSlots; ++i) c.lam[b][i].v = 0ull;
   c.dt_last = 0.0;
   c.status = 0;
 }

@@ -10,12 +10,16 @@
 // lanes; lane a of a cell owns time row a of the AoS tile q[a][0..N][0..M-1]
 // in registers.  The space contraction k~ (Algorithm 2, k_ksi_kernel) and the
 // point-wise flux / source / non-conservative terms (Algorithms 2-3) are
-// in-lane, with the operator coefficients as wave-uniform scalar operands.
+// in-lane, with the operator coefficients as wave-uniform operands.
 // The time contraction kappa~ (Algorithm 1, kappa_kernel) needs a column of
 // the tile: the residual is transposed through the cell's LDS block, lane a
 // then owns space column a, applies kappa~ in-lane, and transposes the new
 // iterate back.  No exchange ever leaves the wavefront, so a wave-level
 // fence replaces workgroup barriers.
+//
+// The operator coefficients k~ and kappa~ are staged once per workgroup in
+// LDS and read with wave-uniform addresses (broadcast), so that they never
+// occupy scalar registers across the sweep loop.
 //
 // Stopping test (the paper leaves the norm open): per cell,
 // max|q_new - q_old| <= tol * max(1, max|q_new|), each cell stopping on its
@@ -32,15 +36,24 @@ namespace aderdg {
 extern __constant__ DevOps c_ops[kDevMaxn];
 extern __constant__ DevOpsF c_opsf[kDevMaxn];
 
-template <int N, class TP> struct OpK;
-template <int N> struct OpK<N, double> {
-  __device__ static double K(int l, int j) { return c_ops[N].ktil[l][j]; }
-  __device__ static double Kap(int a, int b) { return c_ops[N].kappa[a][b]; }
-};
-template <int N> struct OpK<N, float> {
-  __device__ static float K(int l, int j) { return c_opsf[N].ktil[l][j]; }
-  __device__ static float Kap(int a, int b) { return c_opsf[N].kappa[a][b]; }
-};
+// Copy k~, (dt/dx) k~ and kappa~ of degree N (in the predictor's precision)
+// into LDS.  Call from every thread of the workgroup, then __syncthreads().
+template <int N, class TP>
+__device__ __forceinline__ void stage_operators(TP* sK, TP* sKs, TP* sKap, double dtdx) {
+  constexpr int n = N + 1;
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+    const int l = i / n, j = i % n;
+    if constexpr (sizeof(TP) == 8) {
+      sK[i] = c_ops[N].ktil[l][j];
+      sKs[i] = dtdx * c_ops[N].ktil[l][j];
+      sKap[i] = c_ops[N].kappa[l][j];
+    } else {
+      sK[i] = c_opsf[N].ktil[l][j];
+      sKs[i] = (float)(dtdx * c_ops[N].ktil[l][j]);
+      sKap[i] = c_opsf[N].kappa[l][j];
+    }
+  }
+}
 
 template <int N, class PDE, class TP>
 struct Predictor {
@@ -48,21 +61,22 @@ struct Predictor {
   static constexpr int M = PDE::M;
   static constexpr bool kInner = PDE::kSource || PDE::kNcp;
 
-  // Row residual of time node a: -k~ f + s - b, evaluated on the inner iterate qi.
+  // Row residual of time node a, sign-flipped: k~ f - (s - b), evaluated on the
+  // inner iterate qi (the time contraction subtracts it from the initial data).
   __device__ static void residual_row(const TP (&qi)[n][M], const TP (&KF)[n][M], TP* row,
                                       int a, TP dt, TP dtdx, double xl, double dx, double t0,
-                                      const PdeParams& pp) {
+                                      const PdeParams& pp, const TP* sK) {
     const TP ta = TP(t0 + (double)dt * c_ops[N].xi[a]);
 #pragma unroll
     for (int l = 0; l < n; ++l) {
       TP R[M];
 #pragma unroll
-      for (int r = 0; r < M; ++r) R[r] = -KF[l][r];
+      for (int r = 0; r < M; ++r) R[r] = KF[l][r];
       if constexpr (PDE::kSource) {
         TP s[M];
         PDE::source(qi[l], TP(xl + dx * c_ops[N].xi[l]), ta, s, pp);
 #pragma unroll
-        for (int r = 0; r < M; ++r) R[r] += dt * s[r];
+        for (int r = 0; r < M; ++r) R[r] -= dt * s[r];
       }
       if constexpr (PDE::kNcp) {
         TP dq[M];
@@ -70,13 +84,13 @@ struct Predictor {
         for (int r = 0; r < M; ++r) {
           TP acc = TP(0);
 #pragma unroll
-          for (int j = 0; j < n; ++j) acc += OpK<N, TP>::K(l, j) * qi[j][r];
+          for (int j = 0; j < n; ++j) acc += sK[l * n + j] * qi[j][r];
           dq[r] = acc;
         }
         TP b[M];
         PDE::ncp(qi[l], dq, b, pp);
 #pragma unroll
-        for (int r = 0; r < M; ++r) R[r] -= dtdx * b[r];
+        for (int r = 0; r < M; ++r) R[r] += dtdx * b[r];
       }
 #pragma unroll
       for (int r = 0; r < M; ++r) row[l * M + r] = R[r];
@@ -84,9 +98,11 @@ struct Predictor {
   }
 
   // Max over the n lanes of a cell of (e, qm), through the cell's reduction slots.
-  __device__ static void cell_reduce(TP* red, int a, TP& e, TP& qm) {
-    red[2 * a] = e;
-    red[2 * a + 1] = qm;
+  __device__ static void cell_reduce(TP* red, int a, bool active, TP& e, TP& qm) {
+    if (active) {
+      red[2 * a] = e;
+      red[2 * a + 1] = qm;
+    }
     wave_sync();
     TP E = TP(0), Q = TP(0);
 #pragma unroll
@@ -101,30 +117,39 @@ struct Predictor {
 
   // One kappa~ application: row residual -> (transpose) -> column update -> (transpose) -> row.
   // xb: the cell's LDS block [n][n][M].  On return `out` holds row a of
-  // q_init + kappa~ (residual).
+  // q_init - kappa~ (sign-flipped residual).
   __device__ static void time_contraction(const TP* rowres, const TP (&ucol)[M], TP* xb, int a,
-                                          TP (&out)[n][M]) {
+                                          bool active, const TP* sKap, TP (&out)[n][M]) {
     wave_sync();
+    if (active) {
 #pragma unroll
-    for (int l = 0; l < n; ++l)
+      for (int l = 0; l < n; ++l)
 #pragma unroll
-      for (int r = 0; r < M; ++r) xb[(a * n + l) * M + r] = rowres[l * M + r];
+        for (int r = 0; r < M; ++r) xb[(a * n + l) * M + r] = rowres[l * M + r];
+    }
     wave_sync();
     TP col[n][M];
 #pragma unroll
     for (int b = 0; b < n; ++b)
 #pragma unroll
       for (int r = 0; r < M; ++r) col[b][r] = xb[(b * n + a) * M + r];
-    wave_sync();
+    TP nc[n][M];
 #pragma unroll
     for (int a2 = 0; a2 < n; ++a2)
 #pragma unroll
       for (int r = 0; r < M; ++r) {
         TP acc = ucol[r];
 #pragma unroll
-        for (int b = 0; b < n; ++b) acc += OpK<N, TP>::Kap(a2, b) * col[b][r];
-        xb[(a2 * n + a) * M + r] = acc;
+        for (int b = 0; b < n; ++b) acc -= sKap[a2 * n + b] * col[b][r];
+        nc[a2][r] = acc;
       }
+    wave_sync();
+    if (active) {
+#pragma unroll
+      for (int a2 = 0; a2 < n; ++a2)
+#pragma unroll
+        for (int r = 0; r < M; ++r) xb[(a2 * n + a) * M + r] = nc[a2][r];
+    }
     wave_sync();
 #pragma unroll
     for (int l = 0; l < n; ++l)
@@ -135,6 +160,7 @@ struct Predictor {
   // q: row a of the initial guess on entry (broadcast of the initial data),
   // the converged row on exit.  ucol: initial data at space node a.
   __device__ static void run(TP (&q)[n][M], const TP (&ucol)[M], int a, TP* xb, TP* red,
+                             const TP* sK, const TP* sKs, const TP* sKap,
                              TP dt, TP dtdx, double xl, double dx, double t0, const PdeParams& pp,
                              TP tol, int max_iter, bool stagnation, bool active, int& sweeps,
                              bool& failed) {
@@ -145,27 +171,23 @@ struct Predictor {
     TP row[n * M];
     for (int it = 0; it < max_iter; ++it) {
       if (!__any(!done)) break;
-      // Algorithm 2: rescaled fluxes at every node of the row, then k~ along space.
+      // Algorithm 2: fluxes at every node of the row, then (dt/dx) k~ along space.
       TP KF[n][M];
-#pragma unroll
-      for (int l = 0; l < n; ++l)
-#pragma unroll
-        for (int r = 0; r < M; ++r) KF[l][r] = TP(0);
 #pragma unroll
       for (int j = 0; j < n; ++j) {
         TP f[M];
         PDE::flux(q[j], f, pp);
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-          const TP fj = dtdx * f[r];
 #pragma unroll
-          for (int l = 0; l < n; ++l) KF[l][r] += OpK<N, TP>::K(l, j) * fj;
+          for (int l = 0; l < n; ++l)
+            KF[l][r] = j == 0 ? sKs[l * n] * f[r] : KF[l][r] + sKs[l * n + j] * f[r];
         }
       }
       TP qn[n][M];
       if constexpr (!kInner) {
-        residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp);
-        time_contraction(row, ucol, xb, a, qn);
+        residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp, sK);
+        time_contraction(row, ucol, xb, a, active, sKap, qn);
       } else {
         // inner loop over source / non-conservative terms (Algorithm 1, inner repeat)
         TP qi[n][M];
@@ -178,9 +200,9 @@ struct Predictor {
         int m = 0;
         for (; m < max_iter; ++m) {
           if (!__any(!idone)) break;
-          residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
+          residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp, sK);
           TP qt[n][M];
-          time_contraction(row, ucol, xb, a, qt);
+          time_contraction(row, ucol, xb, a, active, sKap, qt);
           TP e = TP(0), qm = TP(0);
 #pragma unroll
           for (int l = 0; l < n; ++l)
@@ -189,7 +211,7 @@ struct Predictor {
               e = dmax(e, dabs(qt[l][r] - qi[l][r]));
               qm = dmax(qm, dabs(qt[l][r]));
             }
-          cell_reduce(red, a, e, qm);
+          cell_reduce(red, a, active, e, qm);
           if (!idone) {
 #pragma unroll
             for (int l = 0; l < n; ++l)
@@ -216,7 +238,7 @@ struct Predictor {
           e = dmax(e, dabs(qn[l][r] - q[l][r]));
           qm = dmax(qm, dabs(qn[l][r]));
         }
-      cell_reduce(red, a, e, qm);
+      cell_reduce(red, a, active, e, qm);
       if (!done) {
 #pragma unroll
         for (int l = 0; l < n; ++l)
