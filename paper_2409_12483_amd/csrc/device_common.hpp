@@ -59,6 +59,19 @@ __device__ __forceinline__ float dabs(float x) { return fabsf(x); }
 __device__ __forceinline__ double dmax(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ float dmax(float a, float b) { return fmaxf(a, b); }
 
+// 1/x by the hardware reciprocal refined with two Newton steps (relative
+// error within a couple of ulps of the rounded quotient; x finite, non-zero).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // ------------------------------------------------------------ PDE traits ----
 // Each model: M, kSource, kNcp, flux(q,f), speed(q), admissible(q); models
 // with sources add source(q,x,t,s); with non-conservative products
@@ -80,7 +93,7 @@ struct Euler {  // Sec. 2, eq. system_of_equations in 1-D: (rho, rho u, E)
   static constexpr int M = 3;
   static constexpr bool kSource = false, kNcp = false;
   template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
-    const T u = q[1] / q[0];
+    const T u = q[1] * recip(q[0]);
     const T pr = T(p.gamma - 1.0) * (q[2] - T(0.5) * q[1] * u);
     f[0] = q[1];
     f[1] = q[1] * u + pr;
@@ -103,7 +116,7 @@ struct EulerReact {  // Sec. 2.1, eq. pdes_2_comps in 1-D: (rho, rho u, E, rho c
   static constexpr int M = 5;
   static constexpr bool kSource = true, kNcp = false;
   template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
-    const T u = q[1] / q[0];
+    const T u = q[1] * recip(q[0]);
     const T pr = T(p.gamma - 1.0) * (q[2] - T(0.5) * q[1] * u);
     f[0] = q[1];
     f[1] = q[1] * u + pr;
@@ -129,7 +142,7 @@ struct ShallowWater {  // (h, hu, b); B(Q) dQ/dx = (0, g h db/dx, 0)
   static constexpr int M = 3;
   static constexpr bool kSource = false, kNcp = true;
   template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
-    const T u = q[1] / q[0];
+    const T u = q[1] * recip(q[0]);
     f[0] = q[1];
     f[1] = q[1] * u + T(0.5 * p.g) * q[0] * q[0];
     f[2] = T(0);

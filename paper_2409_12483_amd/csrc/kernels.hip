@@ -144,7 +144,6 @@ dg_kernel(StepArgs A) {
 
   __shared__ double xb_all[WAVES * G::XB];
   __shared__ TP red_all[WAVES * G::RED];
-  __shared__ TP sK[n * n], sKs[n * n], sKap[n * n];
   __shared__ double trL[PC * n * M];   // left-face traces  [pc][a][r]
   __shared__ double trR[PC * n * M];   // right-face traces [pc][a][r]; reused for the face fluxes
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
@@ -174,10 +173,6 @@ dg_kernel(StepArgs A) {
     c.u_out = A.u_out;
   }
 
-  if constexpr (MODE != kCorrect) {
-    stage_operators<N, TP>(sK, sKs, sKap, c.dt / P.dx);
-    __syncthreads();
-  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int slot0 = lane / n;
   const bool active = slot0 < CPW;
@@ -193,6 +188,10 @@ dg_kernel(StepArgs A) {
   double* xb = xb_all + wave * G::XB + slot * n * n * M;
   TP* red = red_all + wave * G::RED + slot * n * 2;
 
+  // problem parameters in registers (the wave fences below would otherwise
+  // force them to be re-read from memory)
+  const PdeParams pp = P.pp;
+  const int max_iter = P.max_iter, cfl_mode = P.cfl_mode;
   const double dx = P.dx, dt = c.dt, dtdx = dt / dx;
   const double xl = P.x0 + dx * (double)gc;
   const double* ucell = c.u_in + gc * (n * M);
@@ -216,8 +215,8 @@ dg_kernel(StepArgs A) {
 #pragma unroll
     for (int r = 0; r < M; ++r) ucol[r] = TP(ucell[a * M + r]);
     const TP tol = TP(P.tol);
-    Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, sK, sKs, sKap, TP(dt), TP(dtdx), xl, dx,
-              c.t, P.pp, tol, P.max_iter, sizeof(TP) == 4, active, sweeps, failed);
+    Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, TP(dt), TP(dtdx), xl, dx, c.t, pp, tol,
+              max_iter, sizeof(TP) == 4, active, sweeps, failed);
   }
 
   if constexpr (MODE == kPredict) {
@@ -244,7 +243,7 @@ dg_kernel(StepArgs A) {
 #pragma unroll
     for (int l = 0; l < n; ++l) {
       double f[M];
-      PDE::flux(qd[l], f, P.pp);
+      PDE::flux(qd[l], f, pp);
 #pragma unroll
       for (int r = 0; r < M; ++r) fd[l][r] = dtdx * f[r];
     }
@@ -261,7 +260,7 @@ dg_kernel(StepArgs A) {
       }
       if constexpr (PDE::kSource) {
         double s[M];
-        PDE::source(qd[k], xl + dx * c_ops[N].xi[k], ta, s, P.pp);
+        PDE::source(qd[k], xl + dx * c_ops[N].xi[k], ta, s, pp);
 #pragma unroll
         for (int r = 0; r < M; ++r) V[r] += dt * s[r];
       }
@@ -274,7 +273,7 @@ dg_kernel(StepArgs A) {
           for (int j = 0; j < n; ++j) acc += c_ops[N].ktil[k][j] * qd[j][r];
           dq[r] = acc;
         }
-        PDE::ncp(qd[k], dq, b, P.pp);
+        PDE::ncp(qd[k], dq, b, pp);
 #pragma unroll
         for (int r = 0; r < M; ++r) V[r] -= dtdx * b[r];
       }
@@ -316,10 +315,10 @@ dg_kernel(StepArgs A) {
         qm[r] = trR[(pc * n + a) * M + r];
         qp[r] = trL[((pc + 1) * n + a) * M + r];
       }
-      rusanov<PDE>(qm, qp, G, P.pp);
+      rusanov<PDE>(qm, qp, G, pp);
       if constexpr (PDE::kNcp) {
         double J[M];
-        PDE::jump(qm, qp, J, P.pp);
+        PDE::jump(qm, qp, J, pp);
 #pragma unroll
         for (int r = 0; r < M; ++r) jmp[(pc * n + a) * M + r] = 0.5 * wa * dtdx * J[r];
       }
@@ -354,7 +353,7 @@ dg_kernel(StepArgs A) {
         unew[r] = v;
         c.u_out[gc * (n * M) + k * M + r] = v;
       }
-      bad = !PDE::admissible(unew, P.pp);
+      bad = !PDE::admissible(unew, pp);
     }
     // ---- epilogue: status, sweep count, signal speed of u^{n+1} ----
     if constexpr (MODE == kStep) {
@@ -362,8 +361,8 @@ dg_kernel(StepArgs A) {
       else if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);
       const unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
       double lam = 0.0;
-      if (P.cfl_mode == 1) {
-        if (out_cell) lam = PDE::speed(unew, P.pp);
+      if (cfl_mode == 1) {
+        if (out_cell) lam = PDE::speed(unew, pp);
       } else {
         wave_sync();
         if (out_cell) {
@@ -385,7 +384,7 @@ dg_kernel(StepArgs A) {
                 for (int k = 0; k < n; ++k) acc += c_ops[N].P[s][k] * xb[k * M + r];
                 v[r] = acc;
               }
-              lam = dmax(lam, PDE::speed(v, P.pp));
+              lam = dmax(lam, PDE::speed(v, pp));
             }
           }
         }
@@ -412,7 +411,6 @@ fv_kernel(StepArgs A) {
   __shared__ double vb[NV * M];
   __shared__ double xb_all[WAVES * G::XB];
   __shared__ TP red_all[WAVES * G::RED];
-  __shared__ TP sK[n * n], sKs[n * n], sKap[n * n];
   __shared__ double trL[PC * n * M];
   __shared__ double trR[PC * n * M];
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
@@ -441,7 +439,6 @@ fv_kernel(StepArgs A) {
     if (g < 0) g += C;
     vb[i] = c.u_in[g * M + r];
   }
-  stage_operators<NW, TP>(sK, sKs, sKap, c.dt / P.dx);
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -455,6 +452,8 @@ fv_kernel(StepArgs A) {
   const bool out_cell = active && pc >= 1 && pc <= PC - 2 && (first + pc - 1) < C;
   double* xb = xb_all + wave * G::XB + slot * n * n * M;
   TP* red = red_all + wave * G::RED + slot * n * 2;
+  const PdeParams pp = P.pp;
+  const int max_iter = P.max_iter;
   const double dx = P.dx, dt = c.dt, dtdx = dt / dx;
   const double xl = P.x0 + dx * (double)gc;
 
@@ -505,8 +504,8 @@ fv_kernel(StepArgs A) {
   for (int r = 0; r < M; ++r) ucol[r] = TP(what[r]);
   int sweeps = 0;
   bool failed = false;
-  Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, sK, sKs, sKap, TP(dt), TP(dtdx), xl, dx, c.t,
-            P.pp, TP(P.tol), P.max_iter, sizeof(TP) == 4, active, sweeps, failed);
+  Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, TP(dt), TP(dtdx), xl, dx, c.t, pp,
+            TP(P.tol), max_iter, sizeof(TP) == 4, active, sweeps, failed);
 
   // ---- FV corrector ----
   const double wa = c_ops[NW].w[a < n ? a : 0];
@@ -528,7 +527,7 @@ fv_kernel(StepArgs A) {
         for (int r = 0; r < M; ++r) sb[r] = 0.0;
         if constexpr (PDE::kSource) {
           double s[M];
-          PDE::source(qd[k], xl + dx * c_ops[NW].xi[k], ta, s, P.pp);
+          PDE::source(qd[k], xl + dx * c_ops[NW].xi[k], ta, s, pp);
 #pragma unroll
           for (int r = 0; r < M; ++r) sb[r] += dt * s[r];
         }
@@ -541,7 +540,7 @@ fv_kernel(StepArgs A) {
             for (int j = 0; j < n; ++j) acc += c_ops[NW].ktil[k][j] * qd[j][r];
             dq[r] = acc;
           }
-          PDE::ncp(qd[k], dq, b, P.pp);
+          PDE::ncp(qd[k], dq, b, pp);
 #pragma unroll
           for (int r = 0; r < M; ++r) sb[r] -= dtdx * b[r];
         }
@@ -570,10 +569,10 @@ fv_kernel(StepArgs A) {
       qm[r] = trR[(pc * n + a) * M + r];
       qp[r] = trL[((pc + 1) * n + a) * M + r];
     }
-    rusanov<PDE>(qm, qp, Gf, P.pp);
+    rusanov<PDE>(qm, qp, Gf, pp);
     if constexpr (PDE::kNcp) {
       double J[M];
-      PDE::jump(qm, qp, J, P.pp);
+      PDE::jump(qm, qp, J, pp);
 #pragma unroll
       for (int r = 0; r < M; ++r) jmp[(pc * n + a) * M + r] = 0.5 * wa * dtdx * J[r];
     }
@@ -601,8 +600,8 @@ fv_kernel(StepArgs A) {
       vnew[r] = vb[(pc + NW) * M + r] - (GR - GL) - (JR + JL) + VV;
       c.u_out[gc * M + r] = vnew[r];
     }
-    bad = !PDE::admissible(vnew, P.pp);
-    lam = PDE::speed(vnew, P.pp);
+    bad = !PDE::admissible(vnew, pp);
+    lam = PDE::speed(vnew, pp);
   }
   if (bad) atomicMin(&A.clocks[c.pid].status, -5);
   else if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);

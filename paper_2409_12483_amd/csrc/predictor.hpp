@@ -17,9 +17,8 @@
 // iterate back.  No exchange ever leaves the wavefront, so a wave-level
 // fence replaces workgroup barriers.
 //
-// The operator coefficients k~ and kappa~ are staged once per workgroup in
-// LDS and read with wave-uniform addresses (broadcast), so that they never
-// occupy scalar registers across the sweep loop.
+// The operator coefficients k~ and kappa~ are wave-uniform scalar operands,
+// re-read from constant memory (scalar cache) in every sweep.
 //
 // Stopping test (the paper leaves the norm open): per cell,
 // max|q_new - q_old| <= tol * max(1, max|q_new|), each cell stopping on its
@@ -36,24 +35,24 @@ namespace aderdg {
 extern __constant__ DevOps c_ops[kDevMaxn];
 extern __constant__ DevOpsF c_opsf[kDevMaxn];
 
-// Copy k~, (dt/dx) k~ and kappa~ of degree N (in the predictor's precision)
-// into LDS.  Call from every thread of the workgroup, then __syncthreads().
-template <int N, class TP>
-__device__ __forceinline__ void stage_operators(TP* sK, TP* sKs, TP* sKap, double dtdx) {
-  constexpr int n = N + 1;
-  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
-    const int l = i / n, j = i % n;
-    if constexpr (sizeof(TP) == 8) {
-      sK[i] = c_ops[N].ktil[l][j];
-      sKs[i] = dtdx * c_ops[N].ktil[l][j];
-      sKap[i] = c_ops[N].kappa[l][j];
-    } else {
-      sK[i] = c_opsf[N].ktil[l][j];
-      sKs[i] = (float)(dtdx * c_ops[N].ktil[l][j]);
-      sKap[i] = c_opsf[N].kappa[l][j];
-    }
-  }
+// Operator rows in the constant address space.  opaque() hides the pointer
+// from loop-invariant code motion, so each sweep re-reads its coefficients
+// with scalar loads (scalar cache hits) right where they are used instead of
+// holding both operators in scalar registers across the loop.
+template <class T> using cptr = const __attribute__((address_space(4))) T*;
+template <class T> __device__ __forceinline__ cptr<T> opaque(cptr<T> p) {
+  asm volatile("" : "+s"(p));
+  return p;
 }
+template <int N, class TP> struct OpSrc;
+template <int N> struct OpSrc<N, double> {
+  __device__ static cptr<double> K() { return (cptr<double>)&c_ops[N].ktil[0][0]; }
+  __device__ static cptr<double> Kap() { return (cptr<double>)&c_ops[N].kappa[0][0]; }
+};
+template <int N> struct OpSrc<N, float> {
+  __device__ static cptr<float> K() { return (cptr<float>)&c_opsf[N].ktil[0][0]; }
+  __device__ static cptr<float> Kap() { return (cptr<float>)&c_opsf[N].kappa[0][0]; }
+};
 
 template <int N, class PDE, class TP>
 struct Predictor {
@@ -61,12 +60,15 @@ struct Predictor {
   static constexpr int M = PDE::M;
   static constexpr bool kInner = PDE::kSource || PDE::kNcp;
 
-  // Row residual of time node a, sign-flipped: k~ f - (s - b), evaluated on the
-  // inner iterate qi (the time contraction subtracts it from the initial data).
+  // Row residual of time node a in flux units: k~ F - dx S + B(q) k~ q, evaluated
+  // on the inner iterate qi; the time contraction subtracts (dt/dx) kappa~ of it
+  // from the initial data (s = dt S and b = (dt/dx) B k~ q, so this is
+  // (dx/dt) (k~ f - s + b)).
   __device__ static void residual_row(const TP (&qi)[n][M], const TP (&KF)[n][M], TP* row,
                                       int a, TP dt, TP dtdx, double xl, double dx, double t0,
-                                      const PdeParams& pp, const TP* sK) {
+                                      const PdeParams& pp) {
     const TP ta = TP(t0 + (double)dt * c_ops[N].xi[a]);
+    const cptr<TP> Kc = opaque(OpSrc<N, TP>::K());
 #pragma unroll
     for (int l = 0; l < n; ++l) {
       TP R[M];
@@ -76,7 +78,7 @@ struct Predictor {
         TP s[M];
         PDE::source(qi[l], TP(xl + dx * c_ops[N].xi[l]), ta, s, pp);
 #pragma unroll
-        for (int r = 0; r < M; ++r) R[r] -= dt * s[r];
+        for (int r = 0; r < M; ++r) R[r] -= TP(dx) * s[r];
       }
       if constexpr (PDE::kNcp) {
         TP dq[M];
@@ -84,13 +86,13 @@ struct Predictor {
         for (int r = 0; r < M; ++r) {
           TP acc = TP(0);
 #pragma unroll
-          for (int j = 0; j < n; ++j) acc += sK[l * n + j] * qi[j][r];
+          for (int j = 0; j < n; ++j) acc += Kc[l * kDevMaxn + j] * qi[j][r];
           dq[r] = acc;
         }
         TP b[M];
         PDE::ncp(qi[l], dq, b, pp);
 #pragma unroll
-        for (int r = 0; r < M; ++r) R[r] += dtdx * b[r];
+        for (int r = 0; r < M; ++r) R[r] += b[r];
       }
 #pragma unroll
       for (int r = 0; r < M; ++r) row[l * M + r] = R[r];
@@ -119,7 +121,7 @@ struct Predictor {
   // xb: the cell's LDS block [n][n][M].  On return `out` holds row a of
   // q_init - kappa~ (sign-flipped residual).
   __device__ static void time_contraction(const TP* rowres, const TP (&ucol)[M], TP* xb, int a,
-                                          bool active, const TP* sKap, TP (&out)[n][M]) {
+                                          bool active, TP dtdx, TP (&out)[n][M]) {
     wave_sync();
     if (active) {
 #pragma unroll
@@ -134,14 +136,15 @@ struct Predictor {
 #pragma unroll
       for (int r = 0; r < M; ++r) col[b][r] = xb[(b * n + a) * M + r];
     TP nc[n][M];
+    const cptr<TP> Kp = opaque(OpSrc<N, TP>::Kap());
 #pragma unroll
     for (int a2 = 0; a2 < n; ++a2)
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        TP acc = ucol[r];
+        TP acc = Kp[a2 * kDevMaxn] * col[0][r];
 #pragma unroll
-        for (int b = 0; b < n; ++b) acc -= sKap[a2 * n + b] * col[b][r];
-        nc[a2][r] = acc;
+        for (int b = 1; b < n; ++b) acc += Kp[a2 * kDevMaxn + b] * col[b][r];
+        nc[a2][r] = ucol[r] - dtdx * acc;
       }
     wave_sync();
     if (active) {
@@ -160,7 +163,6 @@ struct Predictor {
   // q: row a of the initial guess on entry (broadcast of the initial data),
   // the converged row on exit.  ucol: initial data at space node a.
   __device__ static void run(TP (&q)[n][M], const TP (&ucol)[M], int a, TP* xb, TP* red,
-                             const TP* sK, const TP* sKs, const TP* sKap,
                              TP dt, TP dtdx, double xl, double dx, double t0, const PdeParams& pp,
                              TP tol, int max_iter, bool stagnation, bool active, int& sweeps,
                              bool& failed) {
@@ -171,23 +173,26 @@ struct Predictor {
     TP row[n * M];
     for (int it = 0; it < max_iter; ++it) {
       if (!__any(!done)) break;
-      // Algorithm 2: fluxes at every node of the row, then (dt/dx) k~ along space.
+      // Algorithm 2: fluxes at every node of the row, then k~ along space.
       TP KF[n][M];
+      {
+        const cptr<TP> Kc = opaque(OpSrc<N, TP>::K());
 #pragma unroll
-      for (int j = 0; j < n; ++j) {
-        TP f[M];
-        PDE::flux(q[j], f, pp);
+        for (int j = 0; j < n; ++j) {
+          TP f[M];
+          PDE::flux(q[j], f, pp);
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
+          for (int r = 0; r < M; ++r) {
 #pragma unroll
-          for (int l = 0; l < n; ++l)
-            KF[l][r] = j == 0 ? sKs[l * n] * f[r] : KF[l][r] + sKs[l * n + j] * f[r];
+            for (int l = 0; l < n; ++l)
+              KF[l][r] = j == 0 ? Kc[l * kDevMaxn] * f[r] : KF[l][r] + Kc[l * kDevMaxn + j] * f[r];
+          }
         }
       }
       TP qn[n][M];
       if constexpr (!kInner) {
-        residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp, sK);
-        time_contraction(row, ucol, xb, a, active, sKap, qn);
+        residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp);
+        time_contraction(row, ucol, xb, a, active, dtdx, qn);
       } else {
         // inner loop over source / non-conservative terms (Algorithm 1, inner repeat)
         TP qi[n][M];
@@ -200,9 +205,9 @@ struct Predictor {
         int m = 0;
         for (; m < max_iter; ++m) {
           if (!__any(!idone)) break;
-          residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp, sK);
+          residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
           TP qt[n][M];
-          time_contraction(row, ucol, xb, a, active, sKap, qt);
+          time_contraction(row, ucol, xb, a, active, dtdx, qt);
           TP e = TP(0), qm = TP(0);
 #pragma unroll
           for (int l = 0; l < n; ++l)
