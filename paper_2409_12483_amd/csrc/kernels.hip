@@ -135,7 +135,7 @@ __device__ __forceinline__ void copy_tile(const double* in, double* out, int64_t
 
 // ------------------------------------------------------------------ DG ----
 template <int N, class PDE, class TP, int WAVES, int MODE>
-__global__ void __launch_bounds__(WAVES * 64)
+__global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
 dg_kernel(StepArgs A) {
   constexpr bool HALO = MODE != kPredict;
   using G = Geo<N, PDE::M, WAVES, HALO>;
@@ -144,12 +144,15 @@ dg_kernel(StepArgs A) {
 
   __shared__ double xb_all[WAVES * G::XB];
   __shared__ TP red_all[WAVES * G::RED];
-  __shared__ double trL[PC * n * M];   // left-face traces  [pc][a][r]
-  __shared__ double trR[PC * n * M];   // right-face traces [pc][a][r]; reused for the face fluxes
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
   __shared__ double lam_wave[WAVES];
   __shared__ unsigned long long sw_wave[WAVES];
   __shared__ double bcast;
+  // After the predictor, the first 2nM doubles of every cell's exchange block
+  // hold its face traces: left [a][r], then right [a][r] (the right ones are
+  // overwritten by the weighted face flux of the face on the cell's right).
+  auto trL = [&](int cell) { return xb_all + (cell / CPW) * G::XB + (cell % CPW) * (n * n * M); };
+  auto trR = [&](int cell) { return trL(cell) + n * M; };
 
   const int pidx = MODE == kStep ? find_problem(A.probs, A.nprob, blockIdx.x) : A.k;
   const ProbDev& P = A.probs[pidx];
@@ -283,17 +286,15 @@ dg_kernel(StepArgs A) {
       }
     }
     // face traces of time row a
-    if (active) {
+    double sl[M], sr[M];
 #pragma unroll
-      for (int r = 0; r < M; ++r) {
-        double sl = 0.0, sr = 0.0;
+    for (int r = 0; r < M; ++r) {
+      sl[r] = 0.0;
+      sr[r] = 0.0;
 #pragma unroll
-        for (int j = 0; j < n; ++j) {
-          sl += c_ops[N].psi0[j] * qd[j][r];
-          sr += c_ops[N].psi1[j] * qd[j][r];
-        }
-        trL[(pc * n + a) * M + r] = sl;
-        trR[(pc * n + a) * M + r] = sr;
+      for (int j = 0; j < n; ++j) {
+        sl[r] += c_ops[N].psi0[j] * qd[j][r];
+        sr[r] += c_ops[N].psi1[j] * qd[j][r];
       }
     }
     wave_sync();
@@ -306,14 +307,22 @@ dg_kernel(StepArgs A) {
       for (int b = 0; b < n; ++b) acc += xb[(b * n + a) * M + r];
       vol[r] = acc;
     }
+    // traces into the block elements (0, a) and (1, a), which this lane just read
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        trL(pc)[a * M + r] = sl[r];
+        trR(pc)[a * M + r] = sr[r];
+      }
+    }
     __syncthreads();
     // Riemann solver at face pc+1/2 and time node a (left cell's lane), weighted by w_a dt/dx
     if (active && pc < PC - 1) {
       double qm[M], qp[M], G[M];
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        qm[r] = trR[(pc * n + a) * M + r];
-        qp[r] = trL[((pc + 1) * n + a) * M + r];
+        qm[r] = trR(pc)[a * M + r];
+        qp[r] = trL(pc + 1)[a * M + r];
       }
       rusanov<PDE>(qm, qp, G, pp);
       if constexpr (PDE::kNcp) {
@@ -323,7 +332,7 @@ dg_kernel(StepArgs A) {
         for (int r = 0; r < M; ++r) jmp[(pc * n + a) * M + r] = 0.5 * wa * dtdx * J[r];
       }
 #pragma unroll
-      for (int r = 0; r < M; ++r) trR[(pc * n + a) * M + r] = wa * dtdx * G[r];
+      for (int r = 0; r < M; ++r) trR(pc)[a * M + r] = wa * dtdx * G[r];
     }
     __syncthreads();
     // surface terms and store (column role, lane a = node k)
@@ -337,8 +346,8 @@ dg_kernel(StepArgs A) {
         double GR = 0.0, GL = 0.0;
 #pragma unroll
         for (int b = 0; b < n; ++b) {
-          GR += trR[(pc * n + b) * M + r];
-          GL += trR[((pc - 1) * n + b) * M + r];
+          GR += trR(pc)[b * M + r];
+          GL += trR(pc - 1)[b * M + r];
         }
         double v = ucell[k * M + r] + vol[r] - winv * (p1 * GR - p0 * GL);
         if constexpr (PDE::kNcp) {
@@ -411,13 +420,17 @@ fv_kernel(StepArgs A) {
   __shared__ double vb[NV * M];
   __shared__ double xb_all[WAVES * G::XB];
   __shared__ TP red_all[WAVES * G::RED];
-  __shared__ double trL[PC * n * M];
-  __shared__ double trR[PC * n * M];
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
-  __shared__ double volb[PC * n * M];
   __shared__ double lam_wave[WAVES];
   __shared__ unsigned long long sw_wave[WAVES];
   __shared__ double bcast;
+
+  // After the predictor, every cell's exchange block holds its left traces
+  // [a][r], right traces [a][r] (later the weighted face flux) and weighted
+  // volume source terms [a][r].
+  auto trL = [&](int cell) { return xb_all + (cell / CPW) * G::XB + (cell % CPW) * (n * n * M); };
+  auto trR = [&](int cell) { return trL(cell) + n * M; };
+  auto volb = [&](int cell) { return trL(cell) + 2 * n * M; };
 
   const int pidx = find_problem(A.probs, A.nprob, blockIdx.x);
   const ProbDev& P = A.probs[pidx];
@@ -548,17 +561,18 @@ fv_kernel(StepArgs A) {
         for (int r = 0; r < M; ++r) V[r] += c_ops[NW].w[k] * sb[r];
       }
     }
+    // block elements (0..2, a) of this lane's own column: last read by this lane
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      volb[(pc * n + a) * M + r] = wa * V[r];
+      volb(pc)[a * M + r] = wa * V[r];
       double sl = 0.0, sr = 0.0;
 #pragma unroll
       for (int j = 0; j < n; ++j) {
         sl += c_ops[NW].psi0[j] * qd[j][r];
         sr += c_ops[NW].psi1[j] * qd[j][r];
       }
-      trL[(pc * n + a) * M + r] = sl;
-      trR[(pc * n + a) * M + r] = sr;
+      trL(pc)[a * M + r] = sl;
+      trR(pc)[a * M + r] = sr;
     }
   }
   __syncthreads();
@@ -566,8 +580,8 @@ fv_kernel(StepArgs A) {
     double qm[M], qp[M], Gf[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      qm[r] = trR[(pc * n + a) * M + r];
-      qp[r] = trL[((pc + 1) * n + a) * M + r];
+      qm[r] = trR(pc)[a * M + r];
+      qp[r] = trL(pc + 1)[a * M + r];
     }
     rusanov<PDE>(qm, qp, Gf, pp);
     if constexpr (PDE::kNcp) {
@@ -577,7 +591,7 @@ fv_kernel(StepArgs A) {
       for (int r = 0; r < M; ++r) jmp[(pc * n + a) * M + r] = 0.5 * wa * dtdx * J[r];
     }
 #pragma unroll
-    for (int r = 0; r < M; ++r) trR[(pc * n + a) * M + r] = wa * dtdx * Gf[r];
+    for (int r = 0; r < M; ++r) trR(pc)[a * M + r] = wa * dtdx * Gf[r];
   }
   __syncthreads();
   double lam = 0.0;
@@ -589,9 +603,9 @@ fv_kernel(StepArgs A) {
       double GR = 0.0, GL = 0.0, VV = 0.0, JR = 0.0, JL = 0.0;
 #pragma unroll
       for (int b = 0; b < n; ++b) {
-        GR += trR[(pc * n + b) * M + r];
-        GL += trR[((pc - 1) * n + b) * M + r];
-        VV += volb[(pc * n + b) * M + r];
+        GR += trR(pc)[b * M + r];
+        GL += trR(pc - 1)[b * M + r];
+        VV += volb(pc)[b * M + r];
         if constexpr (PDE::kNcp) {
           JR += jmp[(pc * n + b) * M + r];
           JL += jmp[((pc - 1) * n + b) * M + r];

@@ -22,8 +22,12 @@
 //
 // Stopping test (the paper leaves the norm open): per cell,
 // max|q_new - q_old| <= tol * max(1, max|q_new|), each cell stopping on its
-// own; with no source and no non-conservative term the inner loop is one
-// pass.  With `stagnation` (FP32 predictor) a loop also stops once its
+// own: once converged, a cell's lanes skip their LDS writes, so the tile
+// they read back each sweep is their frozen result.  A cell's result thus
+// depends on its own data only (not on which cells share its wavefront),
+// which keeps the face fluxes of recomputed halo cells bitwise identical
+// and the scheme exactly conservative.  With no source and no
+// non-conservative term the inner loop is one pass.  With `stagnation` (FP32 predictor) a loop also stops once its
 // increment stops decreasing, so that float round-off cannot spin it to the
 // iteration limit.
 #pragma once
@@ -119,11 +123,15 @@ struct Predictor {
 
   // One kappa~ application: row residual -> (transpose) -> column update -> (transpose) -> row.
   // xb: the cell's LDS block [n][n][M].  On return `out` holds row a of
-  // q_init - kappa~ (sign-flipped residual).
+  // q_init - (dt/dx) kappa~ (residual).  Every lane overwrites only block
+  // elements it has itself read before, so the only cross-lane ordering
+  // needed is write-then-read, provided by wave_sync().
+  // A converged cell (write == false on all its lanes) writes nothing: its
+  // block still holds the tile read back at its last update, so `out`
+  // returns that tile unchanged and the cell stays frozen bit for bit.
   __device__ static void time_contraction(const TP* rowres, const TP (&ucol)[M], TP* xb, int a,
-                                          bool active, TP dtdx, TP (&out)[n][M]) {
-    wave_sync();
-    if (active) {
+                                          bool write, TP dtdx, TP (&out)[n][M]) {
+    if (write) {
 #pragma unroll
       for (int l = 0; l < n; ++l)
 #pragma unroll
@@ -135,7 +143,6 @@ struct Predictor {
     for (int b = 0; b < n; ++b)
 #pragma unroll
       for (int r = 0; r < M; ++r) col[b][r] = xb[(b * n + a) * M + r];
-    TP nc[n][M];
     const cptr<TP> Kp = opaque(OpSrc<N, TP>::Kap());
 #pragma unroll
     for (int a2 = 0; a2 < n; ++a2)
@@ -144,15 +151,8 @@ struct Predictor {
         TP acc = Kp[a2 * kDevMaxn] * col[0][r];
 #pragma unroll
         for (int b = 1; b < n; ++b) acc += Kp[a2 * kDevMaxn + b] * col[b][r];
-        nc[a2][r] = ucol[r] - dtdx * acc;
+        if (write) xb[(a2 * n + a) * M + r] = ucol[r] - dtdx * acc;
       }
-    wave_sync();
-    if (active) {
-#pragma unroll
-      for (int a2 = 0; a2 < n; ++a2)
-#pragma unroll
-        for (int r = 0; r < M; ++r) xb[(a2 * n + a) * M + r] = nc[a2][r];
-    }
     wave_sync();
 #pragma unroll
     for (int l = 0; l < n; ++l)
@@ -192,7 +192,7 @@ struct Predictor {
       TP qn[n][M];
       if constexpr (!kInner) {
         residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp);
-        time_contraction(row, ucol, xb, a, active, dtdx, qn);
+        time_contraction(row, ucol, xb, a, active && !done, dtdx, qn);
       } else {
         // inner loop over source / non-conservative terms (Algorithm 1, inner repeat)
         TP qi[n][M];
@@ -207,7 +207,7 @@ struct Predictor {
           if (!__any(!idone)) break;
           residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
           TP qt[n][M];
-          time_contraction(row, ucol, xb, a, active, dtdx, qt);
+          time_contraction(row, ucol, xb, a, active && !idone, dtdx, qt);
           TP e = TP(0), qm = TP(0);
 #pragma unroll
           for (int l = 0; l < n; ++l)
@@ -217,11 +217,11 @@ struct Predictor {
               qm = dmax(qm, dabs(qt[l][r]));
             }
           cell_reduce(red, a, active, e, qm);
+#pragma unroll
+          for (int l = 0; l < n; ++l)
+#pragma unroll
+            for (int r = 0; r < M; ++r) qi[l][r] = qt[l][r];
           if (!idone) {
-#pragma unroll
-            for (int l = 0; l < n; ++l)
-#pragma unroll
-              for (int r = 0; r < M; ++r) qi[l][r] = qt[l][r];
             const bool conv = e <= tol * dmax(TP(1), qm);
             const bool stag = stagnation && m >= 1 && e >= ieps_prev;
             ieps_prev = e;
@@ -244,11 +244,11 @@ struct Predictor {
           qm = dmax(qm, dabs(qn[l][r]));
         }
       cell_reduce(red, a, active, e, qm);
+#pragma unroll
+      for (int l = 0; l < n; ++l)
+#pragma unroll
+        for (int r = 0; r < M; ++r) q[l][r] = qn[l][r];
       if (!done) {
-#pragma unroll
-        for (int l = 0; l < n; ++l)
-#pragma unroll
-          for (int r = 0; r < M; ++r) q[l][r] = qn[l][r];
         ++sweeps;
         const bool conv = e <= tol * dmax(TP(1), qm);
         const bool stag = stagnation && sweeps >= 2 && e >= eps_prev;
