@@ -179,6 +179,51 @@ __device__ __forceinline__ void rusanov(const double* qm, const double* qp, doub
     G[r] = 0.5 * (fm[r] + fp[r]) - 0.5 * s * PDE::diss(r) * (qp[r] - qm[r]);
 }
 
+// ------------------------------------------------------- LDS layout ----
+// Layout of a cell's LDS exchange block [n rows][n cols][M vars] of element
+// type T: row stride RS and block stride CB (in elements) padded so that the
+// lanes of a wavefront (cell c, row/column a) hit distinct LDS banks in both
+// the row phase (lane a touches row a) and the column phase (lane a touches
+// column a).  Bank model: 32 four-byte banks, 64-bit accesses served 16
+// lanes at a time (32 lanes for 32-bit accesses); the padding minimising
+// the worst bank multiplicity per lane group is found at compile time.
+template <int n, int M, int ES>
+struct LdsLayout {
+  static constexpr int conflicts(int RS, int CB) {
+    const int banks = 128 / ES;
+    const int G = ES == 8 ? 16 : 32;
+    const int cpw = 64 / n;
+    int total = 0;
+    for (int phase = 0; phase < 2; ++phase) {
+      for (int g0 = 0; g0 < cpw * n; g0 += G) {
+        int cnt[32] = {};
+        int worst = 0;
+        for (int L = g0; L < g0 + G && L < cpw * n; ++L) {
+          const int c = L / n, a = L % n;
+          const int off = c * CB + (phase == 0 ? a * RS : a * M);
+          const int b = off % banks;
+          cnt[b] += 1;
+          if (cnt[b] > worst) worst = cnt[b];
+        }
+        total += worst;
+      }
+    }
+    return total;
+  }
+  static constexpr int search(bool want_rs) {
+    int best = 1 << 30, best_rs = n * M, best_cb = n * n * M;
+    for (int pr = 0; pr < 4; ++pr)
+      for (int pc = 0; pc < 32; ++pc) {
+        const int RS = n * M + pr, CB = n * RS + pc;
+        const int c = conflicts(RS, CB) * 64 + pr + pc;
+        if (c < best) { best = c; best_rs = RS; best_cb = CB; }
+      }
+    return want_rs ? best_rs : best_cb;
+  }
+  static constexpr int RS = search(true);
+  static constexpr int CB = search(false);
+};
+
 // ------------------------------------------------------------- problems ----
 // One problem of a launch group (library-owned device array).
 struct ProbDev {
@@ -204,14 +249,19 @@ struct alignas(128) Slot {
   unsigned long long v;
   unsigned long long pad[15];
 };
+struct alignas(128) StatusSlot {
+  int32_t v;
+  int32_t pad[31];
+};
 struct ProbClock {
   double t[2];                    // t^n of even / odd steps
   double dt_last;
-  int32_t status;
+  int32_t status;                 // unused by the step kernels (see stat)
   int32_t pad;
   unsigned long long pad2[12];
   Slot lam[3][kSlots];            // max signal speed (bit pattern of a non-negative double)
   Slot sweeps[kSlots];            // outer Picard sweeps summed over cells
+  StatusSlot stat[kSlots];        // most severe status code seen (min)
 };
 
 __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, double v) {

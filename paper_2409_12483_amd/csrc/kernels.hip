@@ -31,16 +31,30 @@ __constant__ DevWeno c_weno[2];  // WENO degree 2 and 4
 
 enum Mode { kPredict = 0, kCorrect = 1, kStep = 2 };
 
-// Geometry of a workgroup for degree N and M variables.
+// Geometry of a workgroup for degree N and M variables.  Each cell owns an
+// LDS exchange block: rows of RSD doubles, CBD doubles per block (padded
+// against bank conflicts); in FP32-predictor mode the predictor addresses
+// the same block as floats with its own padded strides.
 template <int N, int M, int WAVES, bool HALO>
 struct Geo {
   static constexpr int n = N + 1;
   static constexpr int CPW = 64 / n;                 // cells per wavefront
   static constexpr int PC = WAVES * CPW;             // predictor cells per workgroup
   static constexpr int TILE = HALO ? PC - 2 : PC;    // cells written per workgroup
-  static constexpr int XB = CPW * n * n * M;         // doubles of LDS exchange per wave
+  static constexpr int RSD = LdsLayout<n, M, 8>::RS;
+  static constexpr int CBD = LdsLayout<n, M, 8>::CB;
+  static constexpr int CBF = LdsLayout<n, M, 4>::CB;
+  static_assert(CBF <= 2 * CBD, "float block must fit the double block");
+  static constexpr int XB = CPW * CBD;               // doubles of LDS exchange per wave
   static constexpr int RED = CPW * n * 2;            // reduction slots per wave
 };
+
+// Predictor view (element type TP) of a cell's exchange block.
+template <class G, class TP>
+__device__ __forceinline__ TP* pred_block(double* xb_all, int wave, int slot) {
+  constexpr int CB = sizeof(TP) == 8 ? G::CBD : G::CBF;
+  return reinterpret_cast<TP*>(xb_all + wave * G::XB) + slot * CB;
+}
 
 
 // Problem-level step parameters for a workgroup.
@@ -126,6 +140,18 @@ __device__ __forceinline__ void publish(ProbClock& clk, int buf, int64_t tile, i
   }
 }
 
+// Most severe status of the wavefront (non-physical state over Picard
+// non-convergence), at most one atomic per wave, into one of kSlots status
+// slots so that a failing problem does not serialise its workgroups on one
+// address.  Call from all lanes.
+__device__ __forceinline__ void report_status(ProbClock& clk, int64_t tile, bool bad, bool failed) {
+  const bool any_bad = __any(bad), any_fail = __any(failed);
+  if ((threadIdx.x & 63) == 0 && (any_bad || any_fail)) {
+    const int slot = (int)((tile * 17 + (threadIdx.x >> 6)) % kSlots);
+    atomicMin(&clk.stat[slot].v, any_bad ? -5 : -4);
+  }
+}
+
 // Copy a tile unchanged (problem already at t_end).
 __device__ __forceinline__ void copy_tile(const double* in, double* out, int64_t first,
                                           int64_t count, int per_cell) {
@@ -151,8 +177,9 @@ dg_kernel(StepArgs A) {
   // After the predictor, the first 2nM doubles of every cell's exchange block
   // hold its face traces: left [a][r], then right [a][r] (the right ones are
   // overwritten by the weighted face flux of the face on the cell's right).
-  auto trL = [&](int cell) { return xb_all + (cell / CPW) * G::XB + (cell % CPW) * (n * n * M); };
-  auto trR = [&](int cell) { return trL(cell) + n * M; };
+  auto trL = [&](int cell) { return xb_all + (cell / CPW) * G::XB + (cell % CPW) * G::CBD; };
+  auto trR = [&](int cell) { return trL(cell) + G::RSD; };
+  constexpr int RSD = G::RSD;
 
   const int pidx = MODE == kStep ? find_problem(A.probs, A.nprob, blockIdx.x) : A.k;
   const ProbDev& P = A.probs[pidx];
@@ -162,19 +189,6 @@ dg_kernel(StepArgs A) {
   const int64_t first = c.tile * G::TILE;
   if (first >= C) return;
   const int64_t count = (C - first < G::TILE) ? C - first : G::TILE;
-
-  if constexpr (MODE == kStep) {
-    if (!step_setup<true, N>(A, P, c, &bcast)) {
-      copy_tile(c.u_in, c.u_out, first, count, n * M);
-      return;
-    }
-  } else {
-    c.pid = P.pid;
-    c.t = A.t;
-    c.dt = A.dt;
-    c.u_in = A.u_in;
-    c.u_out = A.u_out;
-  }
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int slot0 = lane / n;
@@ -188,7 +202,22 @@ dg_kernel(StepArgs A) {
   const bool out_cell = active && (HALO ? (pc >= 1 && pc <= PC - 2) : true) &&
                         (first + pc - (HALO ? 1 : 0)) < C;
 
-  double* xb = xb_all + wave * G::XB + slot * n * n * M;
+  if constexpr (MODE == kStep) {
+    if (!step_setup<true, N>(A, P, c, &bcast)) {
+      copy_tile(c.u_in, c.u_out, first, count, n * M);
+      return;
+    }
+  } else {
+    c.pid = P.pid;
+    c.t = A.t;
+    c.dt = A.dt;
+    c.u_in = A.u_in;
+    c.u_out = A.u_out;
+  }
+  const double* ucell = c.u_in + gc * (n * M);   // the cell's state [n][M]
+
+  double* xb = xb_all + wave * G::XB + slot * G::CBD;
+  TP* xbp = pred_block<G, TP>(xb_all, wave, slot);
   TP* red = red_all + wave * G::RED + slot * n * 2;
 
   // problem parameters in registers (the wave fences below would otherwise
@@ -197,7 +226,6 @@ dg_kernel(StepArgs A) {
   const int max_iter = P.max_iter, cfl_mode = P.cfl_mode;
   const double dx = P.dx, dt = c.dt, dtdx = dt / dx;
   const double xl = P.x0 + dx * (double)gc;
-  const double* ucell = c.u_in + gc * (n * M);
 
   // ---- predictor (or load of a given predictor) ----
   TP q[n][M];
@@ -218,8 +246,8 @@ dg_kernel(StepArgs A) {
 #pragma unroll
     for (int r = 0; r < M; ++r) ucol[r] = TP(ucell[a * M + r]);
     const TP tol = TP(P.tol);
-    Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, TP(dt), TP(dtdx), xl, dx, c.t, pp, tol,
-              max_iter, sizeof(TP) == 4, active, sweeps, failed);
+    Pred::run(q, ucol, a, xbp, red, TP(dt), TP(dtdx), xl, dx, c.t, pp, tol, max_iter,
+              sizeof(TP) == 4, active, sweeps, failed);
   }
 
   if constexpr (MODE == kPredict) {
@@ -231,7 +259,7 @@ dg_kernel(StepArgs A) {
         for (int r = 0; r < M; ++r) qo[l * M + r] = q[l][r];
       if (A.iters && a == 0) A.iters[gc] = sweeps;
     }
-    if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);
+    report_status(A.clocks[c.pid], c.tile, false, failed && out_cell);
     return;
   } else {
     // ---- corrector: volume terms of time row a ----
@@ -282,7 +310,7 @@ dg_kernel(StepArgs A) {
       }
       if (active) {
 #pragma unroll
-        for (int r = 0; r < M; ++r) xb[(a * n + k) * M + r] = wa * V[r];
+        for (int r = 0; r < M; ++r) xb[a * RSD + k * M + r] = wa * V[r];
       }
     }
     // face traces of time row a
@@ -304,7 +332,7 @@ dg_kernel(StepArgs A) {
     for (int r = 0; r < M; ++r) {
       double acc = 0.0;
 #pragma unroll
-      for (int b = 0; b < n; ++b) acc += xb[(b * n + a) * M + r];
+      for (int b = 0; b < n; ++b) acc += xb[b * RSD + a * M + r];
       vol[r] = acc;
     }
     // traces into the block elements (0, a) and (1, a), which this lane just read
@@ -366,8 +394,7 @@ dg_kernel(StepArgs A) {
     }
     // ---- epilogue: status, sweep count, signal speed of u^{n+1} ----
     if constexpr (MODE == kStep) {
-      if (bad) atomicMin(&A.clocks[c.pid].status, -5);
-      else if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);
+      report_status(A.clocks[c.pid], c.tile, bad, failed && out_cell);
       const unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
       double lam = 0.0;
       if (cfl_mode == 1) {
@@ -401,7 +428,7 @@ dg_kernel(StepArgs A) {
       publish<WAVES>(A.clocks[c.pid], (A.step + 1) % 3, c.tile, wave, lane, sw, lam, sw_wave,
                      lam_wave);
     } else {
-      if (bad) atomicMin(&A.clocks[c.pid].status, -5);
+      report_status(A.clocks[c.pid], c.tile, bad, false);
     }
   }
 }
@@ -428,9 +455,9 @@ fv_kernel(StepArgs A) {
   // After the predictor, every cell's exchange block holds its left traces
   // [a][r], right traces [a][r] (later the weighted face flux) and weighted
   // volume source terms [a][r].
-  auto trL = [&](int cell) { return xb_all + (cell / CPW) * G::XB + (cell % CPW) * (n * n * M); };
-  auto trR = [&](int cell) { return trL(cell) + n * M; };
-  auto volb = [&](int cell) { return trL(cell) + 2 * n * M; };
+  auto trL = [&](int cell) { return xb_all + (cell / CPW) * G::XB + (cell % CPW) * G::CBD; };
+  auto trR = [&](int cell) { return trL(cell) + G::RSD; };
+  auto volb = [&](int cell) { return trL(cell) + 2 * G::RSD; };
 
   const int pidx = find_problem(A.probs, A.nprob, blockIdx.x);
   const ProbDev& P = A.probs[pidx];
@@ -440,17 +467,20 @@ fv_kernel(StepArgs A) {
   const int64_t first = c.tile * G::TILE;
   if (first >= C) return;
   const int64_t count = (C - first < G::TILE) ? C - first : G::TILE;
+  // stage cell averages of cells first-1-NW .. first-1+PC+NW-1 (periodic);
+  // issued before the clock read so that the two latencies overlap
+  {
+    const double* v_src = P.state[A.step & 1];
+    for (int i = threadIdx.x; i < NV * M; i += blockDim.x) {
+      const int cc = i / M, r = i % M;
+      int64_t g = (first - 1 - NW + cc) % C;
+      if (g < 0) g += C;
+      vb[i] = v_src[g * M + r];
+    }
+  }
   if (!step_setup<false, NW>(A, P, c, &bcast)) {
     copy_tile(c.u_in, c.u_out, first, count, M);
     return;
-  }
-
-  // stage cell averages of cells first-1-NW .. first-1+PC+NW-1 (periodic)
-  for (int i = threadIdx.x; i < NV * M; i += blockDim.x) {
-    const int cc = i / M, r = i % M;
-    int64_t g = (first - 1 - NW + cc) % C;
-    if (g < 0) g += C;
-    vb[i] = c.u_in[g * M + r];
   }
   __syncthreads();
 
@@ -463,7 +493,8 @@ fv_kernel(StepArgs A) {
   int64_t gc = (first + pc - 1) % C;
   if (gc < 0) gc += C;
   const bool out_cell = active && pc >= 1 && pc <= PC - 2 && (first + pc - 1) < C;
-  double* xb = xb_all + wave * G::XB + slot * n * n * M;
+  double* xb = xb_all + wave * G::XB + slot * G::CBD;
+  TP* xbp = pred_block<G, TP>(xb_all, wave, slot);
   TP* red = red_all + wave * G::RED + slot * n * 2;
   const PdeParams pp = P.pp;
   const int max_iter = P.max_iter;
@@ -517,8 +548,8 @@ fv_kernel(StepArgs A) {
   for (int r = 0; r < M; ++r) ucol[r] = TP(what[r]);
   int sweeps = 0;
   bool failed = false;
-  Pred::run(q, ucol, a, reinterpret_cast<TP*>(xb), red, TP(dt), TP(dtdx), xl, dx, c.t, pp,
-            TP(P.tol), max_iter, sizeof(TP) == 4, active, sweeps, failed);
+  Pred::run(q, ucol, a, xbp, red, TP(dt), TP(dtdx), xl, dx, c.t, pp, TP(P.tol), max_iter,
+            sizeof(TP) == 4, active, sweeps, failed);
 
   // ---- FV corrector ----
   const double wa = c_ops[NW].w[a < n ? a : 0];
@@ -617,8 +648,7 @@ fv_kernel(StepArgs A) {
     bad = !PDE::admissible(vnew, pp);
     lam = PDE::speed(vnew, pp);
   }
-  if (bad) atomicMin(&A.clocks[c.pid].status, -5);
-  else if (failed && out_cell) atomicMin(&A.clocks[c.pid].status, -4);
+  report_status(A.clocks[c.pid], c.tile, bad, failed && out_cell);
   const unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
   publish<WAVES>(A.clocks[c.pid], (A.step + 1) % 3, c.tile, wave, lane, sw, lam, sw_wave, lam_wave);
 }
@@ -689,6 +719,7 @@ __global__ void clock_begin_kernel(ProbClock* clocks, const double* t_user, int 
   c.t[1] = t_user[p];
   for (int b = 0; b < 3; ++b)
     for (int i = 0; i < kSlots; ++i) c.lam[b][i].v = 0ull;
+  for (int i = 0; i < kSlots; ++i) c.stat[i].v = 0;
   c.dt_last = 0.0;
   c.status = 0;
 }
@@ -699,11 +730,13 @@ __global__ void clock_end_kernel(const ProbClock* clocks, double* t_user, double
   if (p >= nprob) return;
   t_user[p] = clocks[p].t[parity];
   dt_user[p] = clocks[p].dt_last;
-  status_user[p] = clocks[p].status;
+  int st = 0;
+  for (int i = 0; i < kSlots; ++i) st = min(st, clocks[p].stat[i].v);
+  status_user[p] = st;
 }
 
 __global__ void status_reset_kernel(ProbClock* clocks, int p) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) clocks[p].status = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kSlots) clocks[p].stat[threadIdx.x].v = 0;
 }
 
 __global__ void copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t count) {

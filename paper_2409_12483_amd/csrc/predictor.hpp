@@ -62,7 +62,11 @@ template <int N, class PDE, class TP>
 struct Predictor {
   static constexpr int n = N + 1;
   static constexpr int M = PDE::M;
+  static constexpr int RS = LdsLayout<n, M, sizeof(TP)>::RS;   // row stride of the exchange block
   static constexpr bool kInner = PDE::kSource || PDE::kNcp;
+  // k~ is held in scalar registers across a sweep only while it fits beside
+  // kappa~'s fetch (72 dwords); larger operators are read where they are used
+  static constexpr bool kPreloadK = n * n * sizeof(TP) <= 288;
 
   // Row residual of time node a in flux units: k~ F - dx S + B(q) k~ q, evaluated
   // on the inner iterate qi; the time contraction subtracts (dt/dx) kappa~ of it
@@ -122,42 +126,66 @@ struct Predictor {
   }
 
   // One kappa~ application: row residual -> (transpose) -> column update -> (transpose) -> row.
-  // xb: the cell's LDS block [n][n][M].  On return `out` holds row a of
+  // xb: the cell's LDS block (rows of RS elements).  On return `out` holds row a of
   // q_init - (dt/dx) kappa~ (residual).  Every lane overwrites only block
   // elements it has itself read before, so the only cross-lane ordering
   // needed is write-then-read, provided by wave_sync().
   // A converged cell (write == false on all its lanes) writes nothing: its
   // block still holds the tile read back at its last update, so `out`
   // returns that tile unchanged and the cell stays frozen bit for bit.
+  __device__ static void load_k(TP (&kt)[n][n]) {
+    if constexpr (!kPreloadK) return;
+    const cptr<TP> K = opaque(OpSrc<N, TP>::K());
+#pragma unroll
+    for (int l = 0; l < n; ++l)
+#pragma unroll
+      for (int j = 0; j < n; ++j) kt[l][j] = K[l * kDevMaxn + j];
+  }
+
+  // RELOAD_K: also fetch k~ for the next sweep once kappa~ is dead, ahead of
+  // the read-back fence, so that its scalar-load latency overlaps the LDS
+  // round trip (k~ and kappa~ never need scalar registers at the same time).
+  template <bool RELOAD_K>
   __device__ static void time_contraction(const TP* rowres, const TP (&ucol)[M], TP* xb, int a,
-                                          bool write, TP dtdx, TP (&out)[n][M]) {
+                                          bool write, TP dtdx, TP (&out)[n][M], TP (&kt)[n][n]) {
     if (write) {
 #pragma unroll
       for (int l = 0; l < n; ++l)
 #pragma unroll
-        for (int r = 0; r < M; ++r) xb[(a * n + l) * M + r] = rowres[l * M + r];
+        for (int r = 0; r < M; ++r) xb[a * RS + l * M + r] = rowres[l * M + r];
     }
+    // kappa~ is fetched before the fence (when it fits the scalar budget):
+    // its latency then overlaps the transpose
+    TP kap[n][n];
+    const cptr<TP> Kp = opaque(OpSrc<N, TP>::Kap());
+    if constexpr (kPreloadK) {
+#pragma unroll
+      for (int a2 = 0; a2 < n; ++a2)
+#pragma unroll
+        for (int b = 0; b < n; ++b) kap[a2][b] = Kp[a2 * kDevMaxn + b];
+    }
+    auto kp = [&](int a2, int b) -> TP { return kPreloadK ? kap[a2][b] : Kp[a2 * kDevMaxn + b]; };
     wave_sync();
     TP col[n][M];
 #pragma unroll
     for (int b = 0; b < n; ++b)
 #pragma unroll
-      for (int r = 0; r < M; ++r) col[b][r] = xb[(b * n + a) * M + r];
-    const cptr<TP> Kp = opaque(OpSrc<N, TP>::Kap());
+      for (int r = 0; r < M; ++r) col[b][r] = xb[b * RS + a * M + r];
 #pragma unroll
     for (int a2 = 0; a2 < n; ++a2)
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        TP acc = Kp[a2 * kDevMaxn] * col[0][r];
+        TP acc = kp(a2, 0) * col[0][r];
 #pragma unroll
-        for (int b = 1; b < n; ++b) acc += Kp[a2 * kDevMaxn + b] * col[b][r];
-        if (write) xb[(a2 * n + a) * M + r] = ucol[r] - dtdx * acc;
+        for (int b = 1; b < n; ++b) acc += kp(a2, b) * col[b][r];
+        if (write) xb[a2 * RS + a * M + r] = ucol[r] - dtdx * acc;
       }
+    if constexpr (RELOAD_K) load_k(kt);
     wave_sync();
 #pragma unroll
     for (int l = 0; l < n; ++l)
 #pragma unroll
-      for (int r = 0; r < M; ++r) out[l][r] = xb[(a * n + l) * M + r];
+      for (int r = 0; r < M; ++r) out[l][r] = xb[a * RS + l * M + r];
   }
 
   // q: row a of the initial guess on entry (broadcast of the initial data),
@@ -171,28 +199,30 @@ struct Predictor {
     failed = false;
     TP eps_prev = TP(3.0e38);
     TP row[n * M];
+    TP kt[n][n];
+    load_k(kt);
     for (int it = 0; it < max_iter; ++it) {
       if (!__any(!done)) break;
+      if constexpr (kInner) load_k(kt);
       // Algorithm 2: fluxes at every node of the row, then k~ along space.
       TP KF[n][M];
-      {
-        const cptr<TP> Kc = opaque(OpSrc<N, TP>::K());
+      const cptr<TP> Kc = opaque(OpSrc<N, TP>::K());
+      auto kc = [&](int l, int j) -> TP { return kPreloadK ? kt[l][j] : Kc[l * kDevMaxn + j]; };
 #pragma unroll
-        for (int j = 0; j < n; ++j) {
-          TP f[M];
-          PDE::flux(q[j], f, pp);
+      for (int j = 0; j < n; ++j) {
+        TP f[M];
+        PDE::flux(q[j], f, pp);
 #pragma unroll
-          for (int r = 0; r < M; ++r) {
+        for (int r = 0; r < M; ++r) {
 #pragma unroll
-            for (int l = 0; l < n; ++l)
-              KF[l][r] = j == 0 ? Kc[l * kDevMaxn] * f[r] : KF[l][r] + Kc[l * kDevMaxn + j] * f[r];
-          }
+          for (int l = 0; l < n; ++l)
+            KF[l][r] = j == 0 ? kc(l, 0) * f[r] : KF[l][r] + kc(l, j) * f[r];
         }
       }
       TP qn[n][M];
       if constexpr (!kInner) {
         residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp);
-        time_contraction(row, ucol, xb, a, active && !done, dtdx, qn);
+        time_contraction<true>(row, ucol, xb, a, active && !done, dtdx, qn, kt);
       } else {
         // inner loop over source / non-conservative terms (Algorithm 1, inner repeat)
         TP qi[n][M];
@@ -207,7 +237,7 @@ struct Predictor {
           if (!__any(!idone)) break;
           residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
           TP qt[n][M];
-          time_contraction(row, ucol, xb, a, active && !idone, dtdx, qt);
+          time_contraction<false>(row, ucol, xb, a, active && !idone, dtdx, qt, kt);
           TP e = TP(0), qm = TP(0);
 #pragma unroll
           for (int l = 0; l < n; ++l)
