@@ -59,6 +59,32 @@ __device__ __forceinline__ float dabs(float x) { return fabsf(x); }
 __device__ __forceinline__ double dmax(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ float dmax(float a, float b) { return fmaxf(a, b); }
 
+// max(a, |b|) and max(|a|, |b|) as single VALU instructions.  fmax() on a
+// value read from memory costs an extra instruction that quiets signalling
+// NaNs; the operands here are arithmetic results or values this kernel
+// wrote itself, so that step is skipped.  A NaN operand still yields the
+// other operand, as fmax does.
+__device__ __forceinline__ double max_abs(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, |%2|" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float max_abs(float a, float b) {
+  float r;
+  asm("v_max_f32_e64 %0, %1, |%2|" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double max_abs2(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float max_abs2(float a, float b) {
+  float r;
+  asm("v_max_f32_e64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // 1/x by the hardware reciprocal refined with two Newton steps (relative
 // error within a couple of ulps of the rounded quotient; x finite, non-zero).
 __device__ __forceinline__ double recip(double x) {

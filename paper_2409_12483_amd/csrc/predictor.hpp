@@ -114,11 +114,12 @@ struct Predictor {
       red[2 * a + 1] = qm;
     }
     wave_sync();
-    TP E = TP(0), Q = TP(0);
+    // the stored norms are non-negative
+    TP E = max_abs2(red[0], red[2]), Q = max_abs2(red[1], red[3]);
 #pragma unroll
-    for (int b = 0; b < n; ++b) {
-      E = dmax(E, red[2 * b]);
-      Q = dmax(Q, red[2 * b + 1]);
+    for (int b = 2; b < n; ++b) {
+      E = max_abs(E, red[2 * b]);
+      Q = max_abs(Q, red[2 * b + 1]);
     }
     wave_sync();
     e = E;
@@ -126,8 +127,9 @@ struct Predictor {
   }
 
   // One kappa~ application: row residual -> (transpose) -> column update -> (transpose) -> row.
-  // xb: the cell's LDS block (rows of RS elements).  On return `out` holds row a of
-  // q_init - (dt/dx) kappa~ (residual).  Every lane overwrites only block
+  // xb: the cell's LDS block (rows of RS elements).  On return `q` holds row a of
+  // q_init - (dt/dx) kappa~ (residual), and e, qm this lane's part of the
+  // convergence norms of the update.  Every lane overwrites only block
   // elements it has itself read before, so the only cross-lane ordering
   // needed is write-then-read, provided by wave_sync().
   // A converged cell (write == false on all its lanes) writes nothing: its
@@ -147,7 +149,8 @@ struct Predictor {
   // round trip (k~ and kappa~ never need scalar registers at the same time).
   template <bool RELOAD_K>
   __device__ static void time_contraction(const TP* rowres, const TP (&ucol)[M], TP* xb, int a,
-                                          bool write, TP dtdx, TP (&out)[n][M], TP (&kt)[n][n]) {
+                                          bool write, TP dtdx, TP (&q)[n][M], TP (&kt)[n][n],
+                                          TP& e, TP& qm) {
     if (write) {
 #pragma unroll
       for (int l = 0; l < n; ++l)
@@ -182,10 +185,23 @@ struct Predictor {
       }
     if constexpr (RELOAD_K) load_k(kt);
     wave_sync();
+    // read back in place, with the lane's share of the convergence norms:
+    // e = max |q_new - q|, qm = max |q_new| over the row
 #pragma unroll
     for (int l = 0; l < n; ++l)
 #pragma unroll
-      for (int r = 0; r < M; ++r) out[l][r] = xb[a * RS + l * M + r];
+      for (int r = 0; r < M; ++r) {
+        const TP v = xb[a * RS + l * M + r];
+        const TP d = v - q[l][r];
+        if (l == 0 && r == 0) {
+          e = dabs(d);
+          qm = dabs(v);
+        } else {
+          e = max_abs(e, d);
+          qm = max_abs(qm, v);
+        }
+        q[l][r] = v;
+      }
   }
 
   // q: row a of the initial guess on entry (broadcast of the initial data),
@@ -201,8 +217,8 @@ struct Predictor {
     TP row[n * M];
     TP kt[n][n];
     load_k(kt);
-    for (int it = 0; it < max_iter; ++it) {
-      if (!__any(!done)) break;
+    // one outer sweep
+    auto sweep = [&]() __attribute__((always_inline)) {
       if constexpr (kInner) load_k(kt);
       // Algorithm 2: fluxes at every node of the row, then k~ along space.
       TP KF[n][M];
@@ -219,10 +235,10 @@ struct Predictor {
             KF[l][r] = j == 0 ? kc(l, 0) * f[r] : KF[l][r] + kc(l, j) * f[r];
         }
       }
-      TP qn[n][M];
+      TP e, qm;
       if constexpr (!kInner) {
         residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp);
-        time_contraction<true>(row, ucol, xb, a, active && !done, dtdx, qn, kt);
+        time_contraction<true>(row, ucol, xb, a, active && !done, dtdx, q, kt, e, qm);
       } else {
         // inner loop over source / non-conservative terms (Algorithm 1, inner repeat)
         TP qi[n][M];
@@ -236,48 +252,35 @@ struct Predictor {
         for (; m < max_iter; ++m) {
           if (!__any(!idone)) break;
           residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
-          TP qt[n][M];
-          time_contraction<false>(row, ucol, xb, a, active && !idone, dtdx, qt, kt);
-          TP e = TP(0), qm = TP(0);
-#pragma unroll
-          for (int l = 0; l < n; ++l)
-#pragma unroll
-            for (int r = 0; r < M; ++r) {
-              e = dmax(e, dabs(qt[l][r] - qi[l][r]));
-              qm = dmax(qm, dabs(qt[l][r]));
-            }
-          cell_reduce(red, a, active, e, qm);
-#pragma unroll
-          for (int l = 0; l < n; ++l)
-#pragma unroll
-            for (int r = 0; r < M; ++r) qi[l][r] = qt[l][r];
+          TP ie, iqm;
+          time_contraction<false>(row, ucol, xb, a, active && !idone, dtdx, qi, kt, ie, iqm);
+          cell_reduce(red, a, active, ie, iqm);
           if (!idone) {
-            const bool conv = e <= tol * dmax(TP(1), qm);
-            const bool stag = stagnation && m >= 1 && e >= ieps_prev;
-            ieps_prev = e;
+            const bool conv = ie <= tol * dmax(TP(1), iqm);
+            const bool stag = stagnation && m >= 1 && ie >= ieps_prev;
+            ieps_prev = ie;
             if (conv || stag) idone = true;
           }
         }
         if (!idone) failed = true;
+        // outer update and its norms
 #pragma unroll
         for (int l = 0; l < n; ++l)
 #pragma unroll
-          for (int r = 0; r < M; ++r) qn[l][r] = qi[l][r];
+          for (int r = 0; r < M; ++r) {
+            const TP d = qi[l][r] - q[l][r];
+            if (l == 0 && r == 0) {
+              e = dabs(d);
+              qm = dabs(qi[l][r]);
+            } else {
+              e = max_abs(e, d);
+              qm = max_abs(qm, qi[l][r]);
+            }
+            q[l][r] = qi[l][r];
+          }
       }
       // outer convergence
-      TP e = TP(0), qm = TP(0);
-#pragma unroll
-      for (int l = 0; l < n; ++l)
-#pragma unroll
-        for (int r = 0; r < M; ++r) {
-          e = dmax(e, dabs(qn[l][r] - q[l][r]));
-          qm = dmax(qm, dabs(qn[l][r]));
-        }
       cell_reduce(red, a, active, e, qm);
-#pragma unroll
-      for (int l = 0; l < n; ++l)
-#pragma unroll
-        for (int r = 0; r < M; ++r) q[l][r] = qn[l][r];
       if (!done) {
         ++sweeps;
         const bool conv = e <= tol * dmax(TP(1), qm);
@@ -285,6 +288,14 @@ struct Predictor {
         eps_prev = e;
         if (conv || stag) done = true;
       }
+    };
+    // two sweeps per trip: the in-place update of q then alternates between
+    // two register sets instead of being copied back at the loop edge
+    for (int it = 0; it < max_iter; it += 2) {
+      if (!__any(!done)) break;
+      sweep();
+      if (it + 1 >= max_iter || !__any(!done)) break;
+      sweep();
     }
     if (!done) failed = true;
   }
