@@ -2,8 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3]
 
-Default workload (BASELINE configuration "ADER-DG 1D Euler, N=5, 1e5 cells,
-periodic smooth density wave + seeded 1e-3 noise, u=1, p=1"): a step is one
+Default workload (1-D Euler, N=5, 1e5 periodic cells, smooth density wave
+with seeded 1e-3 nodal noise, u=1, p=1): a step is one
 ADER-DG time step of the whole mesh -- CFL dt, LST-DG predictor, corrector
 volume and surface terms -- in one fused kernel launch.  W untimed steps,
 then exactly K steps timed between device synchronisations; one JSON line.

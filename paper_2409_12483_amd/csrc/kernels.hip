@@ -160,8 +160,18 @@ __device__ __forceinline__ void copy_tile(const double* in, double* out, int64_t
 }
 
 // ------------------------------------------------------------------ DG ----
+// Requested waves per SIMD: 4 for conservation laws up to N = 5, whose
+// working sets fit 128 VGPRs without spilling; other variants (larger N, or
+// an inner loop for source / non-conservative terms) take what their
+// registers allow rather than spill.
+template <int N, class PDE>
+struct DgOccupancy {
+  static constexpr int value = (PDE::kSource || PDE::kNcp || N > 5) ? 1 : 4;
+};
+
 template <int N, class PDE, class TP, int WAVES, int MODE>
-__global__ void __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(WAVES * 64)
+__attribute__((amdgpu_waves_per_eu(DgOccupancy<N, PDE>::value)))
 dg_kernel(StepArgs A) {
   constexpr bool HALO = MODE != kPredict;
   using G = Geo<N, PDE::M, WAVES, HALO>;
@@ -197,8 +207,11 @@ dg_kernel(StepArgs A) {
   const int a = active ? lane % n : lane - CPW * n;
   const int pc = wave * CPW + slot;                      // predictor cell in the workgroup
   int64_t gc = first + pc - (HALO ? 1 : 0);              // global cell (periodic wrap)
-  gc %= C;
   if (gc < 0) gc += C;
+  if (gc >= C) {
+    gc -= C;
+    if (gc >= C) gc %= C;                                // meshes smaller than a tile
+  }
   const bool out_cell = active && (HALO ? (pc >= 1 && pc <= PC - 2) : true) &&
                         (first + pc - (HALO ? 1 : 0)) < C;
 
@@ -473,8 +486,13 @@ fv_kernel(StepArgs A) {
     const double* v_src = P.state[A.step & 1];
     for (int i = threadIdx.x; i < NV * M; i += blockDim.x) {
       const int cc = i / M, r = i % M;
-      int64_t g = (first - 1 - NW + cc) % C;
+      int64_t g = first - 1 - NW + cc;
       if (g < 0) g += C;
+      if (g >= C) g -= C;
+      if (g < 0 || g >= C) {                            // meshes smaller than the stencil reach
+        g %= C;
+        if (g < 0) g += C;
+      }
       vb[i] = v_src[g * M + r];
     }
   }
@@ -490,8 +508,12 @@ fv_kernel(StepArgs A) {
   const int slot = active ? slot0 : 0;
   const int a = active ? lane % n : lane - CPW * n;
   const int pc = wave * CPW + slot;
-  int64_t gc = (first + pc - 1) % C;
+  int64_t gc = first + pc - 1;
   if (gc < 0) gc += C;
+  if (gc >= C) {
+    gc -= C;
+    if (gc >= C) gc %= C;                                // meshes smaller than a tile
+  }
   const bool out_cell = active && pc >= 1 && pc <= PC - 2 && (first + pc - 1) < C;
   double* xb = xb_all + wave * G::XB + slot * G::CBD;
   TP* xbp = pred_block<G, TP>(xb_all, wave, slot);

@@ -289,13 +289,20 @@ struct Predictor {
         if (conv || stag) done = true;
       }
     };
-    // two sweeps per trip: the in-place update of q then alternates between
-    // two register sets instead of being copied back at the loop edge
-    for (int it = 0; it < max_iter; it += 2) {
-      if (!__any(!done)) break;
-      sweep();
-      if (it + 1 >= max_iter || !__any(!done)) break;
-      sweep();
+    if constexpr (!kInner) {
+      // two sweeps per trip: the in-place update of q then alternates between
+      // two register sets instead of being copied back at the loop edge
+      for (int it = 0; it < max_iter; it += 2) {
+        if (!__any(!done)) break;
+        sweep();
+        if (it + 1 >= max_iter || !__any(!done)) break;
+        sweep();
+      }
+    } else {
+      for (int it = 0; it < max_iter; ++it) {
+        if (!__any(!done)) break;
+        sweep();
+      }
     }
     if (!done) failed = true;
   }
