@@ -19,6 +19,7 @@ Reported beside the headline FP64 number:
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -49,6 +50,35 @@ def dg_flops_per_cell(N, M, sweeps_per_cell, flux=12):
     corr = n * n * flux + 8 * n * n * M + n * RIEMANN_FLOPS + 9 * n * M
     cfl = 2 * (2 * N + 1) * n * M + 8 * (2 * N + 1)
     return sweeps_per_cell * sweep, corr + cfl
+
+
+KERNEL_SOURCES = ("kernels.hip", "predictor.hpp", "device_common.hpp", "launch.hpp", "operators.hpp")
+PROFILE = os.path.join(ROOT, "profiles", "dg_step_euler_n5_c1e5_fp64.md")
+
+
+def kernel_source_hash():
+    """sha256 over the device sources of the step kernels (detects stale counter data)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2409_12483_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, or None when that summary is missing or the kernel changed since."""
+    try:
+        vals = {}
+        with open(PROFILE) as fh:
+            for line in fh:
+                k, _, v = line.strip().partition(": ")
+                vals[k] = v
+        if vals.get("kernel_sources_sha256") != kernel_source_hash():
+            return None
+        return int(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _sync():
@@ -109,6 +139,92 @@ class DGRun:
 
     def close(self):
         self.abi.aderdg_free(self.h)
+
+
+def fv_swe_run(C, precision, steps, warmup):
+    """ADER-WENO-FV shallow water (WENO degree 4, predictor N = 4), periodic,
+    Gaussian bump: ms per step and DoF-updates/s (DoF = cells * M)."""
+    import torch
+    from paper_2409_12483_amd import abi
+    from paper_2409_12483_amd import workloads as W
+    dev = torch.device("cuda:0")
+    v = torch.tensor(W.swe_bump_averages(C), device=dev)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    te = torch.full((1,), 1.0e300, dtype=torch.float64, device=dev)
+    dt = torch.zeros_like(t)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    h = abi.aderdg_init([abi.pde_desc(abi.PDE_SWE)],
+                        [abi.config(4, C, precision=precision, scheme=abi.SCHEME_FV)],
+                        stream=stream.cuda_stream)
+    abi.aderweno_step(h, [v], t, te, dt, st, warmup)
+    _sync()
+    s0 = abi.aderdg_sweep_count(h, 0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    abi.aderweno_step(h, [v], t, te, dt, st, steps)
+    e1.record(stream)
+    _sync()
+    secs = e0.elapsed_time(e1) * 1e-3
+    sw = abi.aderdg_sweep_count(h, 0) - s0
+    status = int(st.item())
+    abi.aderdg_free(h)
+    return {"ms_per_step": round(secs / steps * 1e3, 5), "value": round(steps * C * 3 / secs, 1),
+            "unit": "DoF-updates/s", "outer_sweeps_per_cell": round(sw / (C * steps), 3),
+            "status": status}
+
+
+def c1_latency(reps=100, k=10):
+    """C1 (Euler, N=2, 100 cells): per-step latency of k-step calls, eager and
+    replayed from a captured HIP graph (the graph holds the whole call)."""
+    import torch
+    from paper_2409_12483_amd import abi
+    from paper_2409_12483_amd import workloads as W
+    dev = torch.device("cuda:0")
+    N, C = 2, 100
+    s = torch.cuda.Stream()
+    u = torch.tensor(W.euler_density_wave(C, N), device=dev)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    te = torch.full((1,), 1.0e300, dtype=torch.float64, device=dev)
+    dt = torch.zeros_like(t)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    h = abi.aderdg_init([abi.pde_desc(abi.PDE_EULER)], [abi.config(N, C)], stream=s.cuda_stream)
+    with torch.cuda.stream(s):
+        abi.aderdg_step(h, [u], t, te, dt, st, k)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        abi.aderdg_step(h, [u], t, te, dt, st, k)
+
+    def timed(fn):
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            out.append(e0.elapsed_time(e1) / k)
+        return np.array(out)
+
+    def eager():
+        abi.aderdg_step(h, [u], t, te, dt, st, k)
+
+    def replay():
+        with torch.cuda.stream(s):
+            g.replay()
+
+    for _ in range(10):
+        replay()
+    lg = timed(replay)
+    le = timed(eager)
+    status = int(st.item())
+    del g
+    abi.aderdg_free(h)
+    pct = lambda a, q: round(float(np.percentile(a, q)) * 1e3, 2)
+    return {"unit": "us per step", "steps_per_call": k,
+            "graph": {"p50": pct(lg, 50), "p99": pct(lg, 99)},
+            "eager": {"p50": pct(le, 50), "p99": pct(le, 99)}, "status": status}
 
 
 def roofline_entry(N, C, M, steps, seconds, sweeps, precision):
@@ -199,7 +315,8 @@ def main():
         "roofline": roofline_entry(N, C, M, K, secs, sweeps, "fp64"),
         "status": status, "wall_s": round(wall, 4),
     }
-    out["roofline"]["traffic"] = None
+    out["roofline"]["traffic"] = profiled_traffic()
+    out["roofline"]["algorithmic_bytes_per_launch"] = 2 * dofs * 8
     run.close()
 
     if not a.no_extras:
@@ -235,6 +352,12 @@ def main():
                         "sweeps_per_cell": rf["sweeps_per_cell"]})
             r.close()
         out["per_degree_fp64"] = per
+        out["fv_swe_weno4_1e6"] = {
+            "workload": "ADER-WENO-FV shallow water, WENO degree 4 + LST-DG predictor N=4, 1e6 periodic "
+                        "cells, h=1+0.1 sin(2 pi x), b=0.2 exp(-100(x-0.5)^2), u=0, CFL 0.4",
+            "fp64": fv_swe_run(1_000_000, abi.FP64, 50, 20),
+            "fp32_predictor": fv_swe_run(1_000_000, abi.FP32_PREDICTOR, 50, 20)}
+        out["c1_step_latency"] = c1_latency()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N)
     print(json.dumps(out))
