@@ -1,6 +1,6 @@
 """Benchmark of the fused ADER-DG hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c1|c3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu-baseline]
 
 Default workload (1-D Euler, N=5, 1e5 periodic cells, smooth density wave
 with seeded 1e-3 nodal noise, u=1, p=1): a step is one
@@ -227,6 +227,96 @@ def c1_latency(reps=100, k=10):
             "eager": {"p50": pct(le, 50), "p99": pct(le, 99)}, "status": status}
 
 
+def c4_batched(nprob=256, k=10, reps=6):
+    """256 independent Euler problems (log-uniform 1e3..1e5 cells, N uniform in
+    1..7, seeded wave numbers and phases) advanced as one batch -- one launch
+    per degree group and step, replayed from a captured HIP graph of k steps --
+    against the plain per-problem FP64 loop on the same GPU."""
+    import torch
+    from paper_2409_12483_amd import abi
+    from paper_2409_12483_amd import batch as B
+    from paper_2409_12483_amd import workloads as W
+    specs = W.batched_euler_problems(nprob=nprob, seed=0)
+    dofs = sum(s["ncells"] * (s["N"] + 1) * 3 for s in specs)
+    out = {"problems": nprob, "cells": sum(s["ncells"] for s in specs), "dof_per_step": dofs,
+           "degrees": sorted({s["N"] for s in specs}), "steps_per_graph": k}
+
+    def batched(prec):
+        s = torch.cuda.Stream()
+        b = B.Batch(specs, precision=prec, stream=s)
+        b.capture(k)
+        for _ in range(2):
+            b.replay()
+        s.synchronize()
+        lat = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            b.replay()
+            e1.record(s)
+            e1.synchronize()
+            lat.append(e0.elapsed_time(e1) / k)
+        lat = np.array(lat)
+        st = b.status.cpu().numpy()
+        res = {"value": round(dofs / (float(np.mean(lat)) * 1e-3), 1), "unit": "DoF-updates/s",
+               "ms_per_step": round(float(np.mean(lat)), 4),
+               "step_ms_p50": round(float(np.percentile(lat, 50)), 4),
+               "step_ms_p99": round(float(np.percentile(lat, 99)), 4),
+               "status_ok": bool((st == 0).all())}
+        states = [u.cpu().numpy() for u in b.u]
+        nsteps_done = (1 + 2 + reps) * k          # capture's eager call, warm-up, timed replays
+        b.close()
+        return res, states, nsteps_done
+
+    r32, s32, n32 = batched(abi.FP32_PREDICTOR)
+    r64, _, _ = batched(abi.FP64)
+    out["batched_fp32_predictor"] = r32
+    out["batched_fp64"] = r64
+    # plain loop: one handle per problem, FP64, k steps per call, one problem after another
+    runs = [B.Batch([sp]) for sp in specs]
+    for r in runs:
+        r.step(k)
+    _sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in runs:
+        r.step(k)
+    e1.record()
+    _sync()
+    ms = e0.elapsed_time(e1) / k
+    out["per_problem_fp64_loop"] = {"value": round(dofs / (ms * 1e-3), 1), "unit": "DoF-updates/s",
+                                    "ms_per_step": round(ms, 4),
+                                    "launches_per_step": nprob}
+    # accuracy of the FP32-predictor batch: the same number of steps in FP64
+    for r in runs:
+        r.step(n32 - 2 * k)
+    _sync()
+    err = max(float(np.linalg.norm(s32[i] - runs[i].u[0].cpu().numpy()) /
+                    np.linalg.norm(runs[i].u[0].cpu().numpy())) for i in range(nprob))
+    for r in runs:
+        r.close()
+    out["fp32_predictor_vs_fp64_max_rel_l2"] = float(f"{err:.3e}")
+    out["speedup_fp32_batched_vs_fp64_loop"] = round(r32["value"] / out["per_problem_fp64_loop"]["value"], 2)
+    return out
+
+
+def c5_serving(rate, nreq, seed=0):
+    """Continuous-batching service of a Poisson trace of solve requests
+    (Euler / shallow-water DG 50/50, N uniform in 2..9, 1e3..2e5 cells
+    log-uniform, 50..500 steps), FP64, 200 GB device-memory budget, 256 slots."""
+    from paper_2409_12483_amd import serve
+    from paper_2409_12483_amd import workloads as W
+    trace = W.request_trace(nreq=nreq, rate=rate, seed=seed)
+    reqs = serve.requests_from_trace(trace)
+    sch = serve.Scheduler(serve.GpuExecutor(), hbm_budget=200e9, max_active=256)
+    m = sch.run(reqs)
+    mean_dof = float(np.mean([r.dofs * r.steps for r in reqs]))
+    m["rate_req_per_s"] = rate
+    m["offered_dof_updates_per_s"] = round(rate * mean_dof, 1)
+    m["nonzero_status"] = len(sch.bad)
+    return m
+
+
 def roofline_entry(N, C, M, steps, seconds, sweeps, precision):
     pred, rest = dg_flops_per_cell(N, M, sweeps / (C * steps))
     pred_total = pred * C * steps
@@ -272,6 +362,8 @@ def main():
     ap.add_argument("--ncells", type=int, default=100_000)
     ap.add_argument("--no-extras", action="store_true", help="headline only (for profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--c5-full", action="store_true",
+                    help="also serve the full 2000-request trace at 200 req/s")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy (HBM counter calibration)")
     a = ap.parse_args()
@@ -358,6 +450,10 @@ def main():
             "fp64": fv_swe_run(1_000_000, abi.FP64, 50, 20),
             "fp32_predictor": fv_swe_run(1_000_000, abi.FP32_PREDICTOR, 50, 20)}
         out["c1_step_latency"] = c1_latency()
+        out["c4_batched_256"] = c4_batched()
+        out["c5_serving"] = [c5_serving(rate, 150) for rate in (25.0, 50.0, 100.0)]
+    if a.c5_full:
+        out["c5_serving_full"] = c5_serving(200.0, 2000)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N)
     print(json.dumps(out))

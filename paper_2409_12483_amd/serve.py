@@ -1,0 +1,231 @@
+"""Continuous-batching service for ADER-DG solve requests.
+
+Requests (PDE, degree N, cells, number of steps) arrive over time.  The
+scheduler admits them first-come first-served while two budgets hold: device
+memory (each request holds its state and the library's ping-pong copy) and a
+slot limit on concurrently active requests.  Requests admitted in the same
+tick with the same (PDE, N) form a cohort, i.e. one library handle and one
+kernel launch per step for all of them.  Every tick advances every active
+cohort by the smallest number of steps any of its unfinished requests still
+needs (capped), then retires the requests that have run all their steps
+(their end time is frozen, so they no longer advance) and frees a cohort
+once all its requests are done.  A request's numbers never depend on the
+other requests of its cohort or tick: each problem of a launch reads only
+its own state and clock.
+
+The scheduler talks to an executor (``GpuExecutor`` here; tests use a CPU
+stand-in with the same methods):
+    create(specs) -> cohort      step(cohort, n)      freeze(cohort, idx)
+    sync()                       state(cohort, i)     free(cohort)
+"""
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import batch as B
+
+
+@dataclass
+class Request:
+    id: int
+    arrival: float
+    pde: str
+    N: int
+    ncells: int
+    steps: int
+    k: int = 1
+    phase: float = 0.0
+    admitted: float = None
+    done: float = None
+    steps_done: int = 0
+
+    @property
+    def spec(self):
+        return {"pde": self.pde, "N": self.N, "ncells": self.ncells, "k": self.k,
+                "phase": self.phase}
+
+    @property
+    def nbytes(self):
+        return B.state_bytes(self.spec)
+
+    @property
+    def dofs(self):
+        return self.ncells * (self.N + 1) * 3
+
+
+@dataclass
+class Cohort:
+    requests: list
+    handle: object
+    remaining: list = field(default_factory=list)
+
+    def active(self):
+        return [i for i, r in enumerate(self.remaining) if r > 0]
+
+
+def cfl_for(N):
+    """Courant number of a request: 0.4, or 0.3 for N >= 8, where 0.4 lies
+    beyond the scheme's stability bound."""
+    return 0.4 if N <= 7 else 0.3
+
+
+class GpuExecutor:
+    """Cohorts as library handles on one HIP stream."""
+
+    def __init__(self, precision=None, stream=None):
+        import torch
+        from . import abi
+        self.torch = torch
+        self.precision = abi.FP64 if precision is None else precision
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+
+    def create(self, specs):
+        cfls = {cfl_for(s["N"]) for s in specs}
+        assert len(cfls) == 1, "a cohort shares one degree"
+        return B.Batch(specs, precision=self.precision, stream=self.stream, cfl=cfls.pop())
+
+    def step(self, cohort, n):
+        cohort.step(n)
+
+    def freeze(self, cohort, idx):
+        cohort.freeze(idx)
+
+    def sync(self):
+        self.stream.synchronize()
+
+    def status(self, cohort):
+        return cohort.status.cpu().numpy()
+
+    def state(self, cohort, i):
+        return cohort.u[i].cpu().numpy()
+
+    def free(self, cohort):
+        cohort.close()
+
+
+class Scheduler:
+    def __init__(self, executor, hbm_budget=200e9, max_active=256, max_steps_per_tick=50,
+                 clock=time.perf_counter, keep_states=False):
+        self.ex = executor
+        self.budget = float(hbm_budget)
+        self.max_active = int(max_active)
+        self.cap = int(max_steps_per_tick)
+        self.clock = clock
+        self.keep = keep_states
+        self.queue = []          # waiting requests, FIFO
+        self.cohorts = []
+        self.used = 0.0
+        self.nactive = 0
+        self.finished = []
+        self.states = {}
+        self.bad = {}
+        self.ticks = 0
+
+    # -- admission -------------------------------------------------------
+    def submit(self, req):
+        if req.nbytes > self.budget:
+            raise ValueError(f"request {req.id} needs {req.nbytes} bytes, over the whole budget")
+        self.queue.append(req)
+
+    def admit(self, now):
+        took = []
+        while self.queue:
+            r = self.queue[0]
+            if self.nactive + 1 > self.max_active or self.used + r.nbytes > self.budget:
+                break            # first come, first served: the head waits for room
+            self.queue.pop(0)
+            r.admitted = now
+            self.used += r.nbytes
+            self.nactive += 1
+            took.append(r)
+        groups = {}
+        for r in took:
+            groups.setdefault((r.pde, r.N), []).append(r)
+        for reqs in groups.values():
+            h = self.ex.create([r.spec for r in reqs])
+            self.cohorts.append(Cohort(reqs, h, [r.steps for r in reqs]))
+        return took
+
+    # -- one tick: advance every cohort, retire finished requests --------
+    def advance(self):
+        plan = []
+        for c in self.cohorts:
+            act = c.active()
+            n = min(min(c.remaining[i] for i in act), self.cap)
+            self.ex.step(c.handle, n)
+            plan.append((c, act, n))
+        self.ex.sync()
+        now = self.clock()
+        self.ticks += 1
+        keep = []
+        for c, act, n in plan:
+            done_idx = []
+            for i in act:
+                c.remaining[i] -= n
+                c.requests[i].steps_done += n
+                if c.remaining[i] == 0:
+                    done_idx.append(i)
+            if done_idx:
+                st = self.ex.status(c.handle)
+                for i in done_idx:
+                    r = c.requests[i]
+                    r.done = now
+                    self.finished.append(r)
+                    if st[i] != 0:
+                        self.bad[r.id] = int(st[i])
+                    if self.keep:
+                        self.states[r.id] = self.ex.state(c.handle, i)
+                if len(done_idx) < len(act):
+                    self.ex.freeze(c.handle, done_idx)
+            if c.active():
+                keep.append(c)
+            else:
+                self.ex.free(c.handle)
+                for r in c.requests:
+                    self.used -= r.nbytes
+                    self.nactive -= 1
+        self.cohorts = keep
+
+    # -- the service loop over an arrival trace --------------------------
+    def run(self, requests, sleep=time.sleep):
+        """Serve requests (arrival times in seconds from the start); returns metrics."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        t0 = self.clock()
+        base = self.clock
+        self.clock = lambda: base() - t0
+        try:
+            j = 0
+            while j < len(pending) or self.queue or self.cohorts:
+                now = self.clock()
+                while j < len(pending) and pending[j].arrival <= now:
+                    self.submit(pending[j])
+                    j += 1
+                self.admit(now)
+                if self.cohorts:
+                    self.advance()
+                elif j < len(pending):
+                    sleep(max(0.0, pending[j].arrival - self.clock()))
+            makespan = self.clock()
+        finally:
+            self.clock = base
+        return summarize(self.finished, makespan, self.ticks)
+
+
+def summarize(finished, makespan, ticks):
+    lat = np.array([r.done - r.arrival for r in finished])
+    que = np.array([r.admitted - r.arrival for r in finished])
+    svc = np.array([r.done - r.admitted for r in finished])
+    dof = float(sum(r.dofs * r.steps for r in finished))
+    pct = lambda a, q: round(float(np.percentile(a, q)) * 1e3, 2) if len(a) else None
+    return {"requests": len(finished), "makespan_s": round(makespan, 3), "ticks": ticks,
+            "dof_updates_per_s": round(dof / makespan, 1) if makespan > 0 else None,
+            "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+            "queue_ms": {"p50": pct(que, 50), "p99": pct(que, 99)},
+            "service_ms": {"p50": pct(svc, 50), "p99": pct(svc, 99)}}
+
+
+def requests_from_trace(trace):
+    return [Request(id=t["id"], arrival=t["arrival"], pde=t["pde"], N=t["N"], ncells=t["ncells"],
+                    steps=t["steps"], k=t.get("k", 1), phase=t.get("phase", 0.0)) for t in trace]
