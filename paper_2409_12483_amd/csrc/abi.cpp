@@ -77,7 +77,7 @@ int ensure_tables(int device) {
       for (int j = 0; j < n; ++j) {
         ops[N].ktil[i][j] = t.ktil[i][j];
         ops[N].kappa[i][j] = t.kappa[i][j];
-        ops[N].Dtil[i][j] = t.Dtil[i][j];
+        ops[N].Dw[i][j] = t.Dtil[i][j] / t.w[i];
         opsf[N].ktil[i][j] = (float)t.ktil[i][j];
         opsf[N].kappa[i][j] = (float)t.kappa[i][j];
       }

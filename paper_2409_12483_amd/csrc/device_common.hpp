@@ -25,7 +25,7 @@ struct DevOps {
   double winv[kDevMaxn];
   double ktil[kDevMaxn][kDevMaxn];
   double kappa[kDevMaxn][kDevMaxn];
-  double Dtil[kDevMaxn][kDevMaxn];
+  double Dw[kDevMaxn][kDevMaxn];     // D~[k][l] / w_k (DG volume term at node k)
   double psi0[kDevMaxn];
   double psi1[kDevMaxn];
   double P[kDevMaxNs][kDevMaxn];
@@ -126,12 +126,13 @@ struct Euler {  // Sec. 2, eq. system_of_equations in 1-D: (rho, rho u, E)
     f[2] = u * (q[2] + pr);
   }
   template <class T> __device__ static T speed(const T* q, const PdeParams& p) {
-    const T u = q[1] / q[0];
+    const T ri = recip(q[0]);
+    const T u = q[1] * ri;
     const T pr = T(p.gamma - 1.0) * (q[2] - T(0.5) * q[1] * u);
-    return dabs(u) + sqrt(T(p.gamma) * pr / q[0]);
+    return dabs(u) + sqrt(T(p.gamma) * pr * ri);
   }
   __device__ static bool admissible(const double* q, const PdeParams& p) {
-    const double u = q[1] / q[0];
+    const double u = q[1] * recip(q[0]);
     const double pr = (p.gamma - 1.0) * (q[2] - 0.5 * q[1] * u);
     return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && q[0] > 0.0 && pr > 0.0;
   }
@@ -184,7 +185,7 @@ struct ShallowWater {  // (h, hu, b); B(Q) dQ/dx = (0, g h db/dx, 0)
     j[2] = T(0);
   }
   template <class T> __device__ static T speed(const T* q, const PdeParams& p) {
-    return dabs(q[1] / q[0]) + sqrt(T(p.g) * q[0]);
+    return dabs(q[1] * recip(q[0])) + sqrt(T(p.g) * q[0]);
   }
   __device__ static bool admissible(const double* q, const PdeParams&) {
     return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && q[0] > 0.0;
@@ -294,6 +295,18 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, doub
   // non-negative doubles order like their bit patterns
   atomicMax(addr, (unsigned long long)__double_as_longlong(v));
 }
+
+// Order-preserving bit patterns of non-negative floating-point values, so
+// that integer max on LDS words (ds_max) reduces them exactly; a NaN (all
+// exponent bits set) compares above every finite value.
+__device__ __forceinline__ unsigned long long ord_bits(double v) {
+  return (unsigned long long)__double_as_longlong(v);
+}
+__device__ __forceinline__ unsigned int ord_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ double from_bits(unsigned long long b) {
+  return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ float from_bits(unsigned int b) { return __uint_as_float(b); }
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll

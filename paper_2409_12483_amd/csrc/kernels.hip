@@ -46,7 +46,7 @@ struct Geo {
   static constexpr int CBF = LdsLayout<n, M, 4>::CB;
   static_assert(CBF <= 2 * CBD, "float block must fit the double block");
   static constexpr int XB = CPW * CBD;               // doubles of LDS exchange per wave
-  static constexpr int RED = CPW * n * 2;            // reduction slots per wave
+  static constexpr int RED = (CPW + 1) * 2;          // per wave: 2 reduction words per cell + idle lanes' pair
 };
 
 // Predictor view (element type TP) of a cell's exchange block.
@@ -231,7 +231,7 @@ dg_kernel(StepArgs A) {
 
   double* xb = xb_all + wave * G::XB + slot * G::CBD;
   TP* xbp = pred_block<G, TP>(xb_all, wave, slot);
-  TP* red = red_all + wave * G::RED + slot * n * 2;
+  TP* red = red_all + wave * G::RED + (active ? slot : CPW) * 2;   // idle lanes: a pair of their own
 
   // problem parameters in registers (the wave fences below would otherwise
   // force them to be re-read from memory)
@@ -285,28 +285,26 @@ dg_kernel(StepArgs A) {
       for (int r = 0; r < M; ++r) qd[l][r] = (double)q[l][r];
     double fd[n][M];
 #pragma unroll
-    for (int l = 0; l < n; ++l) {
-      double f[M];
-      PDE::flux(qd[l], f, pp);
-#pragma unroll
-      for (int r = 0; r < M; ++r) fd[l][r] = dtdx * f[r];
-    }
+    for (int l = 0; l < n; ++l) PDE::flux(qd[l], fd[l], pp);
     wave_sync();
+    // row a's share of the volume term at node k: w_a (dt/dx) (D~ F)_k / w_k
+    // (+ w_a dt S - w_a (dt/dx) B(q) k~q)
+    const double wdx = wa * dtdx;
 #pragma unroll
     for (int k = 0; k < n; ++k) {
       double V[M];
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        double acc = 0.0;
+        double acc = c_ops[N].Dw[k][0] * fd[0][r];
 #pragma unroll
-        for (int l = 0; l < n; ++l) acc += c_ops[N].Dtil[k][l] * fd[l][r];
-        V[r] = acc * c_ops[N].winv[k];
+        for (int l = 1; l < n; ++l) acc += c_ops[N].Dw[k][l] * fd[l][r];
+        V[r] = wdx * acc;
       }
       if constexpr (PDE::kSource) {
         double s[M];
         PDE::source(qd[k], xl + dx * c_ops[N].xi[k], ta, s, pp);
 #pragma unroll
-        for (int r = 0; r < M; ++r) V[r] += dt * s[r];
+        for (int r = 0; r < M; ++r) V[r] += (wa * dt) * s[r];
       }
       if constexpr (PDE::kNcp) {
         double dq[M], b[M];
@@ -319,11 +317,11 @@ dg_kernel(StepArgs A) {
         }
         PDE::ncp(qd[k], dq, b, pp);
 #pragma unroll
-        for (int r = 0; r < M; ++r) V[r] -= dtdx * b[r];
+        for (int r = 0; r < M; ++r) V[r] -= wdx * b[r];
       }
       if (active) {
 #pragma unroll
-        for (int r = 0; r < M; ++r) xb[a * RSD + k * M + r] = wa * V[r];
+        for (int r = 0; r < M; ++r) xb[a * RSD + k * M + r] = V[r];
       }
     }
     // face traces of time row a
@@ -517,22 +515,25 @@ fv_kernel(StepArgs A) {
   const bool out_cell = active && pc >= 1 && pc <= PC - 2 && (first + pc - 1) < C;
   double* xb = xb_all + wave * G::XB + slot * G::CBD;
   TP* xbp = pred_block<G, TP>(xb_all, wave, slot);
-  TP* red = red_all + wave * G::RED + slot * n * 2;
+  TP* red = red_all + wave * G::RED + (active ? slot : CPW) * 2;   // idle lanes: a pair of their own
   const PdeParams pp = P.pp;
   const int max_iter = P.max_iter;
   const double dx = P.dx, dt = c.dt, dtdx = dt / dx;
   const double xl = P.x0 + dx * (double)gc;
 
   // ---- WENO reconstruction at node a (reading of eq. weno_reconstr) ----
+  // Stencils outermost: the oscillation-indicator form of one stencil (wave-
+  // uniform, scalar registers) is live for all M variables, then released.
   double what[M];
   {
     const int base = (active ? pc : 0) + NW;   // vb index of this cell
+    double wsum[M], acc[M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) {
-      double wsum = 0.0, acc = 0.0;
+    for (int s = 0; s < 3; ++s) {
+      const int off = s == 0 ? -NW : (s == 1 ? -NW / 2 : 0);
+      const cptr<double> S = opaque((cptr<double>)&c_weno[wi].S[s][0][0]);
 #pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        const int off = s == 0 ? -NW : (s == 1 ? -NW / 2 : 0);
+      for (int r = 0; r < M; ++r) {
         double v[n];
 #pragma unroll
         for (int i = 0; i < n; ++i) v[i] = vb[(base + off + i) * M + r];
@@ -541,18 +542,19 @@ fv_kernel(StepArgs A) {
         for (int i = 0; i < n; ++i) {
           double si = 0.0;
 #pragma unroll
-          for (int j = 0; j < n; ++j) si += c_weno[wi].S[s][i][j] * v[j];
+          for (int j = 0; j < n; ++j) si += S[i * kWenoMaxn + j] * v[j];
           sig += v[i] * si;
           val += c_weno[wi].R[s][a < n ? a : 0][i] * v[i];
         }
         const double e = sig + 1.0e-14;
         const double e2 = e * e, e4 = e2 * e2, e8 = e4 * e4;
         const double om = (s == 1 ? 1.0e5 : 1.0) / e8;
-        wsum += om;
-        acc += om * val;
+        wsum[r] = s == 0 ? om : wsum[r] + om;
+        acc[r] = s == 0 ? om * val : acc[r] + om * val;
       }
-      what[r] = acc / wsum;
     }
+#pragma unroll
+    for (int r = 0; r < M; ++r) what[r] = acc[r] / wsum[r];
   }
   // broadcast the reconstruction to every row of the cell
   wave_sync();

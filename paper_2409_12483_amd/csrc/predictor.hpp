@@ -108,20 +108,22 @@ struct Predictor {
   }
 
   // Max over the n lanes of a cell of (e, qm), through the cell's reduction slots.
-  __device__ static void cell_reduce(TP* red, int a, bool active, TP& e, TP& qm) {
-    if (active) {
-      red[2 * a] = e;
-      red[2 * a + 1] = qm;
-    }
+  // Per-cell max of the lanes' norms: an integer max on the cell's two LDS
+  // words (order-preserving bit patterns of the non-negative norms; a NaN
+  // wins), read back by every lane of the cell, then cleared by all of them
+  // for the next reduction.  The cell's lanes share a wavefront, whose LDS
+  // accesses complete in program order; idle lanes own a separate pair, so
+  // no lane needs a branch here.
+  using Bits = decltype(ord_bits(TP(0)));
+  __device__ static void cell_reduce(TP* red, TP& e, TP& qm) {
+    Bits* w = reinterpret_cast<Bits*>(red);
+    atomicMax(&w[0], ord_bits(e));
+    atomicMax(&w[1], ord_bits(qm));
     wave_sync();
-    // the stored norms are non-negative
-    TP E = max_abs2(red[0], red[2]), Q = max_abs2(red[1], red[3]);
-#pragma unroll
-    for (int b = 2; b < n; ++b) {
-      E = max_abs(E, red[2 * b]);
-      Q = max_abs(Q, red[2 * b + 1]);
-    }
+    const TP E = from_bits(w[0]), Q = from_bits(w[1]);
     wave_sync();
+    w[0] = 0;
+    w[1] = 0;
     e = E;
     qm = Q;
   }
@@ -217,6 +219,8 @@ struct Predictor {
     TP row[n * M];
     TP kt[n][n];
     load_k(kt);
+    reinterpret_cast<Bits*>(red)[0] = 0;   // the cell's reduction words start cleared
+    reinterpret_cast<Bits*>(red)[1] = 0;
     // one outer sweep
     auto sweep = [&]() __attribute__((always_inline)) {
       if constexpr (kInner) load_k(kt);
@@ -254,7 +258,7 @@ struct Predictor {
           residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
           TP ie, iqm;
           time_contraction<false>(row, ucol, xb, a, active && !idone, dtdx, qi, kt, ie, iqm);
-          cell_reduce(red, a, active, ie, iqm);
+          cell_reduce(red, ie, iqm);
           if (!idone) {
             const bool conv = ie <= tol * dmax(TP(1), iqm);
             const bool stag = stagnation && m >= 1 && ie >= ieps_prev;
@@ -280,7 +284,7 @@ struct Predictor {
           }
       }
       // outer convergence
-      cell_reduce(red, a, active, e, qm);
+      cell_reduce(red, e, qm);
       if (!done) {
         ++sweeps;
         const bool conv = e <= tol * dmax(TP(1), qm);
