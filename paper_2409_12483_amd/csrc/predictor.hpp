@@ -107,7 +107,6 @@ struct Predictor {
     }
   }
 
-  // Max over the n lanes of a cell of (e, qm), through the cell's reduction slots.
   // Per-cell max of the lanes' norms: an integer max on the cell's two LDS
   // words (order-preserving bit patterns of the non-negative norms; a NaN
   // wins), read back by every lane of the cell, then cleared by all of them
