@@ -15,6 +15,11 @@ Reported beside the headline FP64 number:
   * the FP32-predictor / FP64-corrector mode on the same workload;
   * DoF-updates/s for N = 1..9 on the same mesh (FP64);
   * per-step latency percentiles (event-timed two-step calls);
+  * the Picard sweep histogram of the workload's first predictor;
+  * ADER-WENO-FV shallow water on 1e6 cells (FP64 / FP32 predictor) with
+    its roofline from the measured outer sweeps and kappa~ applications;
+  * C1 step latency eager and HIP-graph replayed; the 256-problem batch
+    against the per-problem loop; the serving loop at three arrival rates;
   * the CPU oracle on a bounded sample of the same workload (cpu_baseline).
 """
 
@@ -81,6 +86,24 @@ def profiled_traffic():
         return None
 
 
+def fv_flops_per_cell(NW, M, outer, contractions, flux=8):
+    """Algorithmic flops of one ADER-WENO-FV step per cell (SWE, WENO degree
+    NW, predictor n = NW+1 nodes; an FMA counts 2):
+      WENO        M [3 (2 n^2 + 2n) (indicators) + n (3 * 2n + 25) (values, weights)]
+      per outer sweep        n^2 F + 2n^3 M (k~ F) + 2n^2 M (outer norms)
+      per kappa~ application n (2nM + 2) (B(q) k~q) + nM + 2n^3 M (kappa~)
+                             + 2n^2 M (update) + 2n^2 M (norms)
+      FV update   4n^2 M (traces) + 48 n (Riemann) + n^2 (2nM + 2) (NC volume term)
+                  + 2n^2 M (weights) + 8 (CFL)
+    with the measured outer sweeps and kappa~ applications per cell."""
+    n = NW + 1
+    weno = M * (3 * (2 * n * n + 2 * n) + n * (3 * 2 * n + 25))
+    sweep = n * n * flux + 2 * n ** 3 * M + 2 * n * n * M
+    contr = n * (2 * n * M + 2) + n * M + 2 * n ** 3 * M + 4 * n * n * M
+    update = 4 * n * n * M + 48 * n + n * n * (2 * n * M + 2) + 2 * n * n * M + 8
+    return weno + outer * sweep + contractions * contr + update
+
+
 def _sync():
     import torch
     torch.cuda.synchronize()
@@ -141,6 +164,25 @@ class DGRun:
         self.abi.aderdg_free(self.h)
 
 
+def sweep_histogram(N, C):
+    """Outer Picard sweeps per cell of the first predictor of the workload
+    (predictor-only entry point, CFL dt of the initial state)."""
+    import torch
+    from paper_2409_12483_amd import abi
+    r = DGRun(N, C, abi.FP64)
+    r.steps(1)                      # dt of the initial state, from the CFL rule
+    _sync()
+    dt = float(r.dt.item())
+    u0 = torch.tensor(r.u0, device="cuda:0")
+    q = torch.empty((C, N + 1, N + 1, 3), dtype=torch.float64, device="cuda:0")
+    it = torch.zeros(C, dtype=torch.int32, device="cuda:0")
+    abi.aderdg_predict(r.h, 0, u0, 0.0, dt, q, it)
+    _sync()
+    counts = np.bincount(it.cpu().numpy())
+    r.close()
+    return {str(k): int(v) for k, v in enumerate(counts) if v}
+
+
 def fv_swe_run(C, precision, steps, warmup):
     """ADER-WENO-FV shallow water (WENO degree 4, predictor N = 4), periodic,
     Gaussian bump: ms per step and DoF-updates/s (DoF = cells * M)."""
@@ -160,18 +202,34 @@ def fv_swe_run(C, precision, steps, warmup):
     abi.aderweno_step(h, [v], t, te, dt, st, warmup)
     _sync()
     s0 = abi.aderdg_sweep_count(h, 0)
+    k0 = abi.aderdg_contraction_count(h, 0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     abi.aderweno_step(h, [v], t, te, dt, st, steps)
     e1.record(stream)
     _sync()
     secs = e0.elapsed_time(e1) * 1e-3
-    sw = abi.aderdg_sweep_count(h, 0) - s0
+    sw = (abi.aderdg_sweep_count(h, 0) - s0) / (C * steps)
+    kc = (abi.aderdg_contraction_count(h, 0) - k0) / (C * steps)
     status = int(st.item())
     abi.aderdg_free(h)
+    # the FP32-predictor mode runs its sweeps in FP32 and the rest in FP64
+    n, M = 5, 3
+    total = fv_flops_per_cell(4, M, sw, kc) * C * steps
+    pred = (sw * (n * n * 8 + 2 * n ** 3 * M + 2 * n * n * M)
+            + kc * (n * (2 * n * M + 2) + n * M + 2 * n ** 3 * M + 4 * n * n * M)) * C * steps
+    if precision == abi.FP64:
+        t_roof = total / (PEAK_FP64_VALU * 1e12)
+        peak = PEAK_FP64_VALU
+    else:
+        t_roof = pred / (PEAK_FP32_VALU * 1e12) + (total - pred) / (PEAK_FP64_VALU * 1e12)
+        peak = total / t_roof * 1e-12
+    roof = {"bound": "alu", "achieved": round(total / secs * 1e-12, 3), "peak": round(peak, 2),
+            "unit": "TFLOP/s", "frac": round(t_roof / secs, 4),
+            "flops_per_step": int(round(total / steps))}
     return {"ms_per_step": round(secs / steps * 1e3, 5), "value": round(steps * C * 3 / secs, 1),
-            "unit": "DoF-updates/s", "outer_sweeps_per_cell": round(sw / (C * steps), 3),
-            "status": status}
+            "unit": "DoF-updates/s", "outer_sweeps_per_cell": round(sw, 3),
+            "kappa_applications_per_cell": round(kc, 3), "roofline": roof, "status": status}
 
 
 def c1_latency(reps=100, k=10):
@@ -407,17 +465,27 @@ def main():
         "roofline": roofline_entry(N, C, M, K, secs, sweeps, "fp64"),
         "status": status, "wall_s": round(wall, 4),
     }
-    out["roofline"]["traffic"] = profiled_traffic()
+    traffic = profiled_traffic()
+    out["roofline"]["traffic"] = traffic
     out["roofline"]["algorithmic_bytes_per_launch"] = 2 * dofs * 8
+    if traffic:
+        out["roofline"]["hbm_GBps_at_traffic"] = round(traffic / (secs / K) * 1e-9, 1)
+    u64 = run.u.cpu().numpy()
+    t64 = float(run.t.item())
     run.close()
 
     if not a.no_extras:
         r32 = DGRun(N, C, abi.FP32_PREDICTOR)
         r32.steps(Wm)
         s32, sw32 = r32.timed(K)
+        u32 = r32.u.cpu().numpy()
         out["fp32_predictor"] = {"value": round(K * dofs / s32, 1), "ms_per_step": round(s32 / K * 1e3, 5),
                                  "roofline": roofline_entry(N, C, M, K, s32, sw32, "fp32"),
-                                 "status": int(r32.st.item())}
+                                 "status": int(r32.st.item()),
+                                 "rel_l2_vs_fp64_after_same_steps": float(
+                                     f"{np.linalg.norm(u32 - u64) / np.linalg.norm(u64):.3e}"),
+                                 "rel_time_difference": float(f"{abs(float(r32.t.item()) - t64) / t64:.3e}")}
+        out["picard_sweeps_histogram"] = sweep_histogram(N, C)
         lat = np.array(r32.latency(30))
         r32.close()
         rl = DGRun(N, C, abi.FP64)

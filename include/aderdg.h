@@ -165,6 +165,16 @@ int aderdg_set_stream(aderdg_handle* h, void* hip_stream);
 int aderdg_sweep_count(aderdg_handle* h, int32_t k, int64_t* sweeps_out);
 
 /*
+ * aderdg_contraction_count -- total applications of the time operator kappa~
+ * (Sec. 1.2, the Picard update of Algorithm 1) summed over cells and steps for
+ * problem k since init: one per outer sweep for models without source or
+ * non-conservative terms, one per inner iteration otherwise (Algorithm 1,
+ * inner repeat).  Read back synchronously; counts algorithmic work.  Host
+ * output; E_INVAL on a null pointer or an index out of range.
+ */
+int aderdg_contraction_count(aderdg_handle* h, int32_t k, int64_t* count_out);
+
+/*
  * aderdg_operators -- host-only copy of the library's 1-D operator tables for
  * degree N (no device involved), for inspection: the GL nodes xi and weights w
  * (eq. gl_rule), k~ = Lambda^-1 Xi and kappa~ = Upsilon^-1 Lambda

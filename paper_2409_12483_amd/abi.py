@@ -26,8 +26,8 @@ SCHEME_DG, SCHEME_FV = 0, 1
 NVARS = {PDE_ADVECTION: 1, PDE_EULER: 3, PDE_EULER_REACT: 5, PDE_SWE: 3}
 
 EXPORTS = ["aderdg_init", "aderdg_predict", "aderdg_correct", "aderdg_step", "aderweno_step",
-           "aderdg_free", "aderdg_set_stream", "aderdg_sweep_count", "aderdg_operators",
-           "aderdg_last_error"]
+           "aderdg_free", "aderdg_set_stream", "aderdg_sweep_count", "aderdg_contraction_count",
+           "aderdg_operators", "aderdg_last_error"]
 
 
 class PdeDesc(ctypes.Structure):
@@ -70,6 +70,7 @@ def load(path=None):
     lib.aderdg_free.argtypes = [vp]
     lib.aderdg_set_stream.argtypes = [vp, vp]
     lib.aderdg_sweep_count.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    lib.aderdg_contraction_count.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.aderdg_operators.argtypes = [i32, ctypes.POINTER(dbl), i64]
     lib.aderdg_last_error.argtypes = []
     lib.aderdg_last_error.restype = ctypes.c_char_p
@@ -152,6 +153,12 @@ def aderdg_set_stream(h, stream):
 def aderdg_sweep_count(h, k):
     v = ctypes.c_int64()
     _check(load().aderdg_sweep_count(h, k, ctypes.byref(v)))
+    return v.value
+
+
+def aderdg_contraction_count(h, k):
+    v = ctypes.c_int64()
+    _check(load().aderdg_contraction_count(h, k, ctypes.byref(v)))
     return v.value
 
 

@@ -456,6 +456,20 @@ int aderdg_sweep_count(aderdg_handle* h, int32_t k, int64_t* sweeps_out) {
   return ADERDG_OK;
 }
 
+int aderdg_contraction_count(aderdg_handle* h, int32_t k, int64_t* count_out) {
+  if (!h || !count_out) return fail(ADERDG_E_INVAL, "null argument");
+  if (k < 0 || k >= h->nprob) return fail(ADERDG_E_INVAL, "problem index out of range");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "stream synchronize");
+  Slot slots[kSlots];
+  e = hipMemcpy(slots, h->clocks[k].contractions, sizeof(slots), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "contraction count read");
+  int64_t total = 0;
+  for (int i = 0; i < kSlots; ++i) total += (int64_t)slots[i].v;
+  *count_out = total;
+  return ADERDG_OK;
+}
+
 int aderdg_operators(int32_t N, double* out, int64_t cap) {
   OpTables t;
   if (!out || !build_op_tables(N, t) || N < 0) return fail(ADERDG_E_INVAL, "bad degree or buffer");

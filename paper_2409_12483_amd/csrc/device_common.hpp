@@ -288,6 +288,7 @@ struct ProbClock {
   unsigned long long pad2[12];
   Slot lam[3][kSlots];            // max signal speed (bit pattern of a non-negative double)
   Slot sweeps[kSlots];            // outer Picard sweeps summed over cells
+  Slot contractions[kSlots];      // kappa~ applications (outer sweeps + inner iterations) summed over cells
   StatusSlot stat[kSlots];        // most severe status code seen (min)
 };
 

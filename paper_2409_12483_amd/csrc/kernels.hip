@@ -117,25 +117,29 @@ __device__ __forceinline__ bool step_setup(const StepArgs& A, const ProbDev& P, 
 // waves (per-wave partials in LDS), one atomic each into slot (tile % kSlots).
 template <int WAVES>
 __device__ __forceinline__ void publish(ProbClock& clk, int buf, int64_t tile, int wave, int lane,
-                                        unsigned long long sw, double lam,
+                                        unsigned long long sw, unsigned long long cw, double lam,
                                         unsigned long long* sw_wave, double* lam_wave) {
   sw = wave_sum(sw);
+  cw = wave_sum(cw);
   lam = wave_max(lam);
   if (lane == 0) {
-    sw_wave[wave] = sw;
+    sw_wave[2 * wave] = sw;
+    sw_wave[2 * wave + 1] = cw;
     lam_wave[wave] = lam;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long S = 0;
+    unsigned long long S = 0, K = 0;
     double L = 0.0;
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) {
-      S += sw_wave[w];
+      S += sw_wave[2 * w];
+      K += sw_wave[2 * w + 1];
       L = dmax(L, lam_wave[w]);
     }
     const int slot = (int)(tile % kSlots);
     if (S) atomicAdd(&clk.sweeps[slot].v, S);
+    if (K) atomicAdd(&clk.contractions[slot].v, K);
     atomic_max_nonneg(&clk.lam[buf][slot].v, L);
   }
 }
@@ -182,7 +186,7 @@ dg_kernel(StepArgs A) {
   __shared__ TP red_all[WAVES * G::RED];
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
   __shared__ double lam_wave[WAVES];
-  __shared__ unsigned long long sw_wave[WAVES];
+  __shared__ unsigned long long sw_wave[2 * WAVES];
   __shared__ double bcast;
   // After the predictor, the first 2nM doubles of every cell's exchange block
   // hold its face traces: left [a][r], then right [a][r] (the right ones are
@@ -242,7 +246,7 @@ dg_kernel(StepArgs A) {
 
   // ---- predictor (or load of a given predictor) ----
   TP q[n][M];
-  int sweeps = 0;
+  int sweeps = 0, contractions = 0;
   bool failed = false;
   if constexpr (MODE == kCorrect) {
     const TP* qin = reinterpret_cast<const TP*>(A.q) + gc * (n * n * M) + a * (n * M);
@@ -260,7 +264,7 @@ dg_kernel(StepArgs A) {
     for (int r = 0; r < M; ++r) ucol[r] = TP(ucell[a * M + r]);
     const TP tol = TP(P.tol);
     Pred::run(q, ucol, a, xbp, red, TP(dt), TP(dtdx), xl, dx, c.t, pp, tol, max_iter,
-              sizeof(TP) == 4, active, sweeps, failed);
+              sizeof(TP) == 4, active, sweeps, contractions, failed);
   }
 
   if constexpr (MODE == kPredict) {
@@ -407,6 +411,7 @@ dg_kernel(StepArgs A) {
     if constexpr (MODE == kStep) {
       report_status(A.clocks[c.pid], c.tile, bad, failed && out_cell);
       const unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
+      const unsigned long long cw = (out_cell && a == 0) ? (unsigned long long)contractions : 0ull;
       double lam = 0.0;
       if (cfl_mode == 1) {
         if (out_cell) lam = PDE::speed(unew, pp);
@@ -436,7 +441,7 @@ dg_kernel(StepArgs A) {
           }
         }
       }
-      publish<WAVES>(A.clocks[c.pid], (A.step + 1) % 3, c.tile, wave, lane, sw, lam, sw_wave,
+      publish<WAVES>(A.clocks[c.pid], (A.step + 1) % 3, c.tile, wave, lane, sw, cw, lam, sw_wave,
                      lam_wave);
     } else {
       report_status(A.clocks[c.pid], c.tile, bad, false);
@@ -460,7 +465,7 @@ fv_kernel(StepArgs A) {
   __shared__ TP red_all[WAVES * G::RED];
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
   __shared__ double lam_wave[WAVES];
-  __shared__ unsigned long long sw_wave[WAVES];
+  __shared__ unsigned long long sw_wave[2 * WAVES];
   __shared__ double bcast;
 
   // After the predictor, every cell's exchange block holds its left traces
@@ -570,10 +575,10 @@ fv_kernel(StepArgs A) {
     for (int r = 0; r < M; ++r) q[l][r] = TP(xb[l * M + r]);
 #pragma unroll
   for (int r = 0; r < M; ++r) ucol[r] = TP(what[r]);
-  int sweeps = 0;
+  int sweeps = 0, contractions = 0;
   bool failed = false;
   Pred::run(q, ucol, a, xbp, red, TP(dt), TP(dtdx), xl, dx, c.t, pp, TP(P.tol), max_iter,
-            sizeof(TP) == 4, active, sweeps, failed);
+            sizeof(TP) == 4, active, sweeps, contractions, failed);
 
   // ---- FV corrector ----
   const double wa = c_ops[NW].w[a < n ? a : 0];
@@ -674,7 +679,9 @@ fv_kernel(StepArgs A) {
   }
   report_status(A.clocks[c.pid], c.tile, bad, failed && out_cell);
   const unsigned long long sw = (out_cell && a == 0) ? (unsigned long long)sweeps : 0ull;
-  publish<WAVES>(A.clocks[c.pid], (A.step + 1) % 3, c.tile, wave, lane, sw, lam, sw_wave, lam_wave);
+  const unsigned long long cw = (out_cell && a == 0) ? (unsigned long long)contractions : 0ull;
+  publish<WAVES>(A.clocks[c.pid], (A.step + 1) % 3, c.tile, wave, lane, sw, cw, lam, sw_wave,
+                 lam_wave);
 }
 
 // ------------------------------------------------------- lambda / clock ----

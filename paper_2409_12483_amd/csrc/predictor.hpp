@@ -210,9 +210,10 @@ struct Predictor {
   __device__ static void run(TP (&q)[n][M], const TP (&ucol)[M], int a, TP* xb, TP* red,
                              TP dt, TP dtdx, double xl, double dx, double t0, const PdeParams& pp,
                              TP tol, int max_iter, bool stagnation, bool active, int& sweeps,
-                             bool& failed) {
+                             int& contractions, bool& failed) {
     bool done = !active;
     sweeps = 0;
+    contractions = 0;   // kappa~ applications this cell needed (outer sweeps, or inner iterations)
     failed = false;
     TP eps_prev = TP(3.0e38);
     TP row[n * M];
@@ -256,6 +257,7 @@ struct Predictor {
           if (!__any(!idone)) break;
           residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
           TP ie, iqm;
+          if (!idone) ++contractions;
           time_contraction<false>(row, ucol, xb, a, active && !idone, dtdx, qi, kt, ie, iqm);
           cell_reduce(red, ie, iqm);
           if (!idone) {
@@ -286,6 +288,7 @@ struct Predictor {
       cell_reduce(red, e, qm);
       if (!done) {
         ++sweeps;
+        if constexpr (!kInner) ++contractions;
         const bool conv = e <= tol * dmax(TP(1), qm);
         const bool stag = stagnation && sweeps >= 2 && e >= eps_prev;
         eps_prev = e;

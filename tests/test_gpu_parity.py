@@ -327,3 +327,29 @@ def test_already_at_end_time_is_a_noop():
     (u,), t, dt, st, _ = run_steps([abi.pde_desc(abi.PDE_EULER)], [abi.config(2, 20)], [u0], 3,
                                    t0=np.array([0.5]), t_end=np.array([0.5]))
     assert np.array_equal(u, u0) and t[0] == 0.5 and dt[0] == 0.0 and st[0] == 0
+
+
+def test_contraction_count_matches_sweeps_and_inner_iterations():
+    """kappa~ applications: one per outer sweep without an inner loop (Euler),
+    at least one per outer sweep with it (shallow water, inner repeat of
+    Algorithm 1)."""
+    _say("contraction counts")
+    torch, dev = torch_dev()
+    cases = [(abi.PDE_EULER, W.euler_density_wave(300, 3, noise=1e-3), False),
+             (abi.PDE_SWE, W.swe_bump_nodal(300, 3), True)]
+    for pde, u0, inner in cases:
+        h = abi.aderdg_init([abi.pde_desc(pde)], [abi.config(3, 300)])
+        try:
+            u = tensor(u0)
+            t = tensor(np.zeros(1))
+            te = tensor(np.full(1, BIG))
+            dt = tensor(np.zeros(1))
+            st = torch.zeros(1, dtype=torch.int32, device=dev)
+            abi.aderdg_step(h, [u], t, te, dt, st, 4)
+            torch.cuda.synchronize()
+            sw = abi.aderdg_sweep_count(h, 0)
+            kc = abi.aderdg_contraction_count(h, 0)
+            assert int(st[0]) == 0 and sw >= 4 * 300
+            assert (kc > sw) if inner else (kc == sw), (pde, sw, kc)
+        finally:
+            abi.aderdg_free(h)
