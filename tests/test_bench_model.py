@@ -1,0 +1,36 @@
+"""The work model of the benchmark (CPU): the algorithmic flop counts per cell
+and step of the fused ADER-DG step reproduce the table of per-degree counts
+derived from the Kronecker-factored operators (N+1 Picard sweeps, Euler flux
+12 flops, Rusanov 48, signal speed 8), and the FV model is monotone in the
+measured work."""
+
+import bench
+
+# flops per cell-step for N = 1..9 with I = N+1 sweeps (predictor, corrector, CFL)
+TABLE = {1: 738, 2: 2299, 3: 5708, 4: 12117, 5: 22966, 6: 39983, 7: 65184, 8: 100873, 9: 149642}
+
+
+def test_dg_flop_model_matches_the_per_degree_table():
+    for N, want in TABLE.items():
+        pred, rest = bench.dg_flops_per_cell(N, 3, N + 1)
+        assert abs(pred + rest - want) <= 1, (N, pred + rest, want)
+
+
+def test_dg_flop_model_terms():
+    N, M = 5, 3
+    n = N + 1
+    pred1, rest = bench.dg_flops_per_cell(N, M, 1)
+    # one sweep: fluxes at n^2 nodes, two n x n contractions over n*M columns
+    # per time/space line, the update and the convergence check
+    assert pred1 == n * n * 12 + 2 * (2 * n ** 3 * M) + 2 * (2 * n * n * M)
+    pred0, rest0 = bench.dg_flops_per_cell(N, M, 0)
+    assert pred0 == 0 and rest0 == rest
+
+
+def test_fv_flop_model_grows_with_the_measured_work():
+    base = bench.fv_flops_per_cell(4, 3, 1.0, 1.0)
+    assert bench.fv_flops_per_cell(4, 3, 2.0, 1.0) > base
+    assert bench.fv_flops_per_cell(4, 3, 1.0, 2.0) > base
+    # the kappa~ application (2 n^3 M = 750 flops at n = 5) dominates its term
+    d = bench.fv_flops_per_cell(4, 3, 1.0, 2.0) - base
+    assert 750 < d < 2000
