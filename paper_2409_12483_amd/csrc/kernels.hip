@@ -119,12 +119,11 @@ template <int WAVES>
 __device__ __forceinline__ void publish(ProbClock& clk, int buf, int64_t tile, int wave, int lane,
                                         unsigned long long sw, unsigned long long cw, double lam,
                                         unsigned long long* sw_wave, double* lam_wave) {
-  sw = wave_sum(sw);
-  cw = wave_sum(cw);
+  // the two counters travel as one 64-bit sum (each stays far below 2^32 per wave)
+  const unsigned long long both = wave_sum(sw | (cw << 32));
   lam = wave_max(lam);
   if (lane == 0) {
-    sw_wave[2 * wave] = sw;
-    sw_wave[2 * wave + 1] = cw;
+    sw_wave[wave] = both;
     lam_wave[wave] = lam;
   }
   __syncthreads();
@@ -133,8 +132,8 @@ __device__ __forceinline__ void publish(ProbClock& clk, int buf, int64_t tile, i
     double L = 0.0;
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) {
-      S += sw_wave[2 * w];
-      K += sw_wave[2 * w + 1];
+      S += sw_wave[w] & 0xffffffffull;
+      K += sw_wave[w] >> 32;
       L = dmax(L, lam_wave[w]);
     }
     const int slot = (int)(tile % kSlots);
@@ -186,7 +185,7 @@ dg_kernel(StepArgs A) {
   __shared__ TP red_all[WAVES * G::RED];
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
   __shared__ double lam_wave[WAVES];
-  __shared__ unsigned long long sw_wave[2 * WAVES];
+  __shared__ unsigned long long sw_wave[WAVES];
   __shared__ double bcast;
   // After the predictor, the first 2nM doubles of every cell's exchange block
   // hold its face traces: left [a][r], then right [a][r] (the right ones are
@@ -465,7 +464,7 @@ fv_kernel(StepArgs A) {
   __shared__ TP red_all[WAVES * G::RED];
   __shared__ double jmp[PDE::kNcp ? PC * n * M : 1];
   __shared__ double lam_wave[WAVES];
-  __shared__ unsigned long long sw_wave[2 * WAVES];
+  __shared__ unsigned long long sw_wave[WAVES];
   __shared__ double bcast;
 
   // After the predictor, every cell's exchange block holds its left traces

@@ -212,8 +212,9 @@ struct Predictor {
                              TP tol, int max_iter, bool stagnation, bool active, int& sweeps,
                              int& contractions, bool& failed) {
     bool done = !active;
+    // outer sweeps; with an inner loop, its iterations (the kappa~ applications
+    // this cell needed) ride in the high 16 bits of the same register
     sweeps = 0;
-    contractions = 0;   // kappa~ applications this cell needed (outer sweeps, or inner iterations)
     failed = false;
     TP eps_prev = TP(3.0e38);
     TP row[n * M];
@@ -257,7 +258,7 @@ struct Predictor {
           if (!__any(!idone)) break;
           residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
           TP ie, iqm;
-          if (!idone) ++contractions;
+          if (!idone) sweeps += 1 << 16;
           time_contraction<false>(row, ucol, xb, a, active && !idone, dtdx, qi, kt, ie, iqm);
           cell_reduce(red, ie, iqm);
           if (!idone) {
@@ -288,9 +289,8 @@ struct Predictor {
       cell_reduce(red, e, qm);
       if (!done) {
         ++sweeps;
-        if constexpr (!kInner) ++contractions;
         const bool conv = e <= tol * dmax(TP(1), qm);
-        const bool stag = stagnation && sweeps >= 2 && e >= eps_prev;
+        const bool stag = stagnation && (sweeps & 0xffff) >= 2 && e >= eps_prev;
         eps_prev = e;
         if (conv || stag) done = true;
       }
@@ -311,6 +311,8 @@ struct Predictor {
       }
     }
     if (!done) failed = true;
+    contractions = kInner ? (sweeps >> 16) : sweeps;
+    sweeps &= 0xffff;
   }
 };
 
