@@ -27,6 +27,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -61,12 +62,21 @@ KERNEL_SOURCES = ("kernels.hip", "predictor.hpp", "device_common.hpp", "launch.h
 PROFILE = os.path.join(ROOT, "profiles", "dg_step_euler_n5_c1e5_fp64.md")
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed, so that a
+    comment edit does not count as a kernel change."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
-    """sha256 over the device sources of the step kernels (detects stale counter data)."""
+    """sha256 over the code of the step kernels' device sources (detects stale
+    counter data)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2409_12483_amd", "csrc", f), "rb") as fh:
-            h.update(f.encode() + b"\0" + fh.read())
+        with open(os.path.join(ROOT, "paper_2409_12483_amd", "csrc", f)) as fh:
+            h.update(f.encode() + b"\0" + _code_only(fh.read()).encode())
     return h.hexdigest()
 
 

@@ -166,7 +166,7 @@ int aderdg_sweep_count(aderdg_handle* h, int32_t k, int64_t* sweeps_out);
 
 /*
  * aderdg_contraction_count -- total applications of the time operator kappa~
- * (Sec. 1.2, the Picard update of Algorithm 1) summed over cells and steps for
+ * (Sec. 1.1, the Picard update of Algorithm 1) summed over cells and steps for
  * problem k since init: one per outer sweep for models without source or
  * non-conservative terms, one per inner iteration otherwise (Algorithm 1,
  * inner repeat).  Read back synchronously; counts algorithmic work.  Host

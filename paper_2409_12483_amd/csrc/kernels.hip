@@ -17,8 +17,9 @@
 //   face traces    in-lane (psi, psi~ contractions), staged in LDS;
 //   Riemann flux   per (face, time node) by the left cell's lane a;
 //   surface update per (cell, space node) in column layout, AoS store;
-//   epilogue       signal speed on the 2N+1 subcell averages of u^{n+1},
-//                  wave max + one 64-bit atomic max per wave (exact).
+//   epilogue       signal speed on the 2N+1 subcell averages of u^{n+1} and
+//                  the work counters, reduced over the workgroup into one
+//                  64-bit atomic per quantity on a clock slot (exact).
 #include "device_common.hpp"
 #include "launch.hpp"
 #include "predictor.hpp"

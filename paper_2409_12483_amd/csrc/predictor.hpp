@@ -17,8 +17,9 @@
 // iterate back.  No exchange ever leaves the wavefront, so a wave-level
 // fence replaces workgroup barriers.
 //
-// The operator coefficients k~ and kappa~ are wave-uniform scalar operands,
-// re-read from constant memory (scalar cache) in every sweep.
+// The operator coefficients k~ and kappa~ are wave-uniform scalar operands
+// from the constant tables: held in scalar registers across a sweep when
+// both fit the scalar budget, otherwise read where they are used.
 //
 // Stopping test (the paper leaves the norm open): per cell,
 // max|q_new - q_old| <= tol * max(1, max|q_new|), each cell stopping on its
@@ -27,9 +28,9 @@
 // depends on its own data only (not on which cells share its wavefront),
 // which keeps the face fluxes of recomputed halo cells bitwise identical
 // and the scheme exactly conservative.  With no source and no
-// non-conservative term the inner loop is one pass.  With `stagnation` (FP32 predictor) a loop also stops once its
-// increment stops decreasing, so that float round-off cannot spin it to the
-// iteration limit.
+// non-conservative term the inner loop is one pass.  With `stagnation`
+// (FP32 predictor) a loop also stops once its increment stops decreasing,
+// so that float round-off cannot spin it to the iteration limit.
 #pragma once
 
 #include "device_common.hpp"
