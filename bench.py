@@ -368,16 +368,19 @@ def c4_batched(nprob=256, k=10, reps=6):
     return out
 
 
-def c5_serving(rate, nreq, seed=0):
+def c5_serving(rate, nreq, seed=0, precision=None):
     """Continuous-batching service of a Poisson trace of solve requests
     (Euler / shallow-water DG 50/50, N uniform in 2..9, 1e3..2e5 cells
-    log-uniform, 50..500 steps), FP64, 200 GB device-memory budget, 256 slots."""
-    from paper_2409_12483_amd import serve
+    log-uniform, 50..500 steps), 200 GB device-memory budget, 256 slots;
+    FP64 unless another precision mode is given."""
+    from paper_2409_12483_amd import abi, serve
     from paper_2409_12483_amd import workloads as W
     trace = W.request_trace(nreq=nreq, rate=rate, seed=seed)
     reqs = serve.requests_from_trace(trace)
-    sch = serve.Scheduler(serve.GpuExecutor(), hbm_budget=200e9, max_active=256)
+    prec = abi.FP64 if precision is None else precision
+    sch = serve.Scheduler(serve.GpuExecutor(precision=prec), hbm_budget=200e9, max_active=256)
     m = sch.run(reqs)
+    m["precision"] = "fp64" if prec == abi.FP64 else "fp32_predictor"
     mean_dof = float(np.mean([r.dofs * r.steps for r in reqs]))
     m["rate_req_per_s"] = rate
     m["offered_dof_updates_per_s"] = round(rate * mean_dof, 1)
@@ -530,6 +533,8 @@ def main():
         out["c1_step_latency"] = c1_latency()
         out["c4_batched_256"] = c4_batched()
         out["c5_serving"] = [c5_serving(rate, 150) for rate in (25.0, 50.0, 100.0)]
+        out["c5_serving_fp32_predictor"] = [c5_serving(rate, 150, precision=abi.FP32_PREDICTOR)
+                                            for rate in (50.0, 100.0)]
     if a.c5_full:
         out["c5_serving_full"] = c5_serving(200.0, 2000)
     if not a.no_cpu_baseline:

@@ -89,3 +89,26 @@ def test_served_requests_equal_isolated_runs():
             assert np.array_equal(alone.u[0].cpu().numpy(), sch.states[r.id]), r.id
         finally:
             alone.close()
+
+
+def test_fp32_predictor_service_within_1e5_of_fp64():
+    """The FP32-predictor service: every request within 1e-5 relative L2 of
+    the same request advanced in FP64."""
+    print("[case] fp32 serving", flush=True)
+    torch, _ = torch_dev()
+    trace = W.request_trace(nreq=10, rate=400.0, seed=6, degrees=range(2, 7), cmin=100, cmax=600,
+                            smin=3, smax=20)
+    reqs = serve.requests_from_trace(trace)
+    sch = serve.Scheduler(serve.GpuExecutor(precision=abi.FP32_PREDICTOR), max_steps_per_tick=6,
+                          keep_states=True)
+    m = sch.run(reqs)
+    assert m["requests"] == len(reqs) and not sch.bad
+    for r in reqs:
+        ref = B.Batch([r.spec], cfl=serve.cfl_for(r.N))
+        try:
+            ref.step(r.steps)
+            torch.cuda.synchronize()
+            u64 = ref.u[0].cpu().numpy()
+            assert rel_l2(sch.states[r.id], u64) <= 1e-5, r.id
+        finally:
+            ref.close()
