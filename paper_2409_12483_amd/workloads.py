@@ -124,3 +124,33 @@ def request_trace(nreq=2000, rate=200.0, seed=0, degrees=range(2, 10), cmin=1_00
             "phase": float(rng.uniform(0.0, 2.0 * np.pi)),
         })
     return out
+
+
+def euler2d_sine_wave(cx, cy, N, amp=0.5, kx=1, ky=1, velocity=(1.0, 1.0), pressure=1.0, gamma=1.4,
+                      noise=0.0, seed=0, x0=0.0, x1=1.0, y0=0.0, y1=1.0):
+    """Nodal conserved state u[Cx, Cy, N+1, N+1, 4] of the 2-D sine wave.
+
+    rho = 1 + amp sin(2 pi (kx x + ky y)) (+ seeded uniform noise on the nodal
+    rho), velocity (u, v), pressure p, U = (rho, rho u, rho v, E).  The paper's
+    2-D accuracy and timing problem (Sec. 2.1) is amp = 0.5, kx = ky = 1,
+    velocity (1, 1), p = 1, gamma = 1.4 on the unit square; its exact solution
+    is the translate rho(x - u t, y - v t).  Node index order [x node][y node].
+    """
+    n = N + 1
+    xs = cell_points(cx, n, x0, x1)                     # [Cx, n]
+    ys = cell_points(cy, n, y0, y1)                     # [Cy, n]
+    X = xs[:, None, :, None]
+    Y = ys[None, :, None, :]
+    rho = 1.0 + amp * np.sin(2.0 * np.pi * (kx * X + ky * Y))
+    rho = np.broadcast_to(rho, (cx, cy, n, n)).copy()
+    if noise:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        rho = rho + rng.uniform(-noise, noise, size=rho.shape)
+    u = np.full_like(rho, velocity[0])
+    v = np.full_like(rho, velocity[1])
+    E = pressure / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return np.stack([rho, rho * u, rho * v, E], axis=-1)
+
+
+def euler2d_sine_wave_exact(x, y, t, amp=0.5, kx=1, ky=1, velocity=(1.0, 1.0)):
+    return 1.0 + amp * np.sin(2.0 * np.pi * (kx * (x - velocity[0] * t) + ky * (y - velocity[1] * t)))
