@@ -164,7 +164,7 @@ def correct2d(ops, pde, u, q, dt, dx, dy):
 
 def subcell_averages(ops, u):
     """(P (x) P) u: the (2N+1)^2 subcell averages of every cell (Sec. 1.4)."""
-    return np.einsum("si,tj,xyijr->xystr", ops.P, ops.P, u)
+    return np.einsum("si,tj,xyijr->xystr", ops.P, ops.P, u, optimize=True)
 
 
 def cfl_dt2d(ops, pde, u, dx, dy, cfl):
@@ -221,7 +221,7 @@ def dg2d_errors(ops, u, exact, extent=(0.0, 1.0, 0.0, 1.0), var=0, npts=25):
     dx, dy = (x1 - x0) / Cx, (y1 - y0) / Cy
     xq, wq = gauss_legendre_01(npts)
     phi = lagrange_eval(ops.xi, xq)                                   # [Q, n]
-    uh = np.einsum("pi,qj,xyij->xypq", phi, phi, u[..., var])
+    uh = np.einsum("pi,qj,xyij->xypq", phi, phi, u[..., var], optimize=True)
     X = x0 + dx * (np.arange(Cx)[:, None, None, None] + xq[None, None, :, None])
     Y = y0 + dy * (np.arange(Cy)[None, :, None, None] + xq[None, None, None, :])
     err = np.abs(uh - exact(X, Y))

@@ -1,4 +1,5 @@
-"""Thin ctypes binding of include/aderdg.h (argument marshalling only).
+"""Thin ctypes binding of include/aderdg.h and include/aderdg2d.h (argument
+marshalling only).
 
 Every entry point keeps its C name.  Buffers may be torch tensors on the HIP
 device (their data_ptr() is passed) or raw integer device addresses.  All
@@ -28,6 +29,8 @@ NVARS = {PDE_ADVECTION: 1, PDE_EULER: 3, PDE_EULER_REACT: 5, PDE_SWE: 3}
 EXPORTS = ["aderdg_init", "aderdg_predict", "aderdg_correct", "aderdg_step", "aderweno_step",
            "aderdg_free", "aderdg_set_stream", "aderdg_sweep_count", "aderdg_contraction_count",
            "aderdg_operators", "aderdg_last_error"]
+EXPORTS_2D = ["aderdg2d_init", "aderdg2d_predict", "aderdg2d_step", "aderdg2d_sweep_count",
+              "aderdg2d_free"]
 
 
 class PdeDesc(ctypes.Structure):
@@ -41,6 +44,16 @@ class Config(ctypes.Structure):
                 ("fixed_dt", ctypes.c_double), ("cfl_mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("picard_tol", ctypes.c_double),
                 ("picard_max_iter", ctypes.c_int32), ("scheme", ctypes.c_int32)]
+
+
+class Config2D(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("cells_x", ctypes.c_int64), ("cells_y", ctypes.c_int64),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+                ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_double),
+                ("picard_tol", ctypes.c_double), ("picard_max_iter", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class AderdgError(RuntimeError):
@@ -74,7 +87,12 @@ def load(path=None):
     lib.aderdg_operators.argtypes = [i32, ctypes.POINTER(dbl), i64]
     lib.aderdg_last_error.argtypes = []
     lib.aderdg_last_error.restype = ctypes.c_char_p
-    for name in EXPORTS[:-1]:
+    lib.aderdg2d_init.argtypes = [ctypes.POINTER(Config2D), vp, ctypes.POINTER(vp)]
+    lib.aderdg2d_predict.argtypes = [vp, vp, dbl, dbl, vp, vp]
+    lib.aderdg2d_step.argtypes = [vp, vp, vp, vp, vp, vp, i32]
+    lib.aderdg2d_sweep_count.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.aderdg2d_free.argtypes = [vp]
+    for name in EXPORTS[:-1] + EXPORTS_2D:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -186,3 +204,37 @@ def aderdg_operators(N):
 def aderdg_last_error():
     msg = load().aderdg_last_error()
     return msg.decode() if msg else ""
+
+
+# ------------------------------------------------------------------ 2-D ----
+def config2d(N, cells_x, cells_y, extent=(0.0, 1.0, 0.0, 1.0), gamma=1.4, cfl=0.4, fixed_dt=0.0,
+             precision=FP64, picard_tol=0.0, picard_max_iter=0):
+    x0, x1, y0, y1 = extent
+    return Config2D(N, precision, cells_x, cells_y, x0, x1, y0, y1, gamma, cfl, fixed_dt,
+                    picard_tol, picard_max_iter, 0)
+
+
+def aderdg2d_init(cfg, stream=None):
+    lib = load()
+    h = ctypes.c_void_p()
+    st = _current_stream() if stream is None else stream
+    _check(lib.aderdg2d_init(ctypes.byref(cfg), st, ctypes.byref(h)))
+    return h.value
+
+
+def aderdg2d_predict(h, u, t, dt, q_out, iters_out=None):
+    return _check(load().aderdg2d_predict(h, _ptr(u), t, dt, _ptr(q_out), _ptr(iters_out)))
+
+
+def aderdg2d_step(h, u, t, t_end, dt, status, nsteps):
+    return _check(load().aderdg2d_step(h, _ptr(u), _ptr(t), _ptr(t_end), _ptr(dt), _ptr(status), nsteps))
+
+
+def aderdg2d_sweep_count(h):
+    out = ctypes.c_int64()
+    _check(load().aderdg2d_sweep_count(h, ctypes.byref(out)))
+    return out.value
+
+
+def aderdg2d_free(h):
+    return _check(load().aderdg2d_free(h))

@@ -1,0 +1,700 @@
+// 2-D ADER-DG step for the Euler gas on a uniform periodic Cartesian mesh
+// (gfx950, wave64): the LST-DG predictor of Sec. 1.1 with the Kronecker
+// factors L^xi = kappa~ (x) k~ (x) I and L^eta = kappa~ (x) I (x) k~ (d = 2),
+// and the corrector of Sec. 1.2, eq. ader_dg_method_full, with the time step
+// of Sec. 1.5 (d = 2, signal speeds on the (2N+1)^2 subcell averages of
+// Sec. 1.4).
+//
+// Predictor kernel.  A workgroup owns CPB cells; each cell is served by
+// n^2 threads (n = N+1), and every thread plays three roles on the cell's
+// space-time tile q[a][i][j][r] (time node a, x node i, y node j, variable r):
+//   T role, thread (i, j):  owns the time line q[.][i][j] in registers;
+//   X role, thread (a, j):  contracts k~ along the x line q[a][.][j];
+//   Y role, thread (a, i):  contracts k~ along the y line q[a][i][.].
+// One Picard sweep: T threads store their lines into LDS (Q); X threads
+// evaluate the x fluxes on their lines and write k~ fx into R; Y threads
+// evaluate the y fluxes on their lines and add k~ fy into R; T threads read
+// their lines of R, apply kappa~ in registers and test convergence (cell
+// maxima by LDS integer max on order-preserving bit patterns).  Each
+// contraction runs from registers over a line the thread owns, so an LDS
+// word read feeds n multiply-adds.  A converged cell freezes while the
+// others of the workgroup go on; the loop ends when no cell is active.
+// The epilogue writes the face traces of every cell (x faces from the X
+// role, y faces from the Y role) and u + volume terms, both in FP64.
+//
+// Corrector kernel.  Rusanov fluxes through the four faces of every cell
+// from its own and its neighbours' traces (each face is evaluated by both
+// adjacent cells, identically), the surface update of u in place, the
+// admissibility test, and the signal-speed maxima of the new state on the
+// subcell averages for the next step's dt.
+#include "launch2d.hpp"
+
+namespace aderdg {
+
+__constant__ DevOps c2_ops[kDevMaxn];
+__constant__ DevOpsF c2_opsf[kDevMaxn];
+
+// ------------------------------------------------------------- model ----
+// Sec. 2, eq. system_of_equations with two space dimensions:
+// U = (rho, rho u, rho v, E), p = (gamma - 1) (E - (rho u u + rho v v) / 2).
+struct Euler2 {
+  static constexpr int M = 4;
+  template <class T> __device__ static void flux_x(const T* q, T* f, T gm1) {
+    const T ri = recip(q[0]);
+    const T u = q[1] * ri, v = q[2] * ri;
+    const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
+    f[0] = q[1];
+    f[1] = q[1] * u + p;
+    f[2] = q[1] * v;
+    f[3] = u * (q[3] + p);
+  }
+  template <class T> __device__ static void flux_y(const T* q, T* f, T gm1) {
+    const T ri = recip(q[0]);
+    const T u = q[1] * ri, v = q[2] * ri;
+    const T p = gm1 * (q[3] - T(0.5) * (q[1] * u + q[2] * v));
+    f[0] = q[2];
+    f[1] = q[2] * u;
+    f[2] = q[2] * v + p;
+    f[3] = v * (q[3] + p);
+  }
+  // |u| + c and |v| + c
+  __device__ static void speeds(const double* q, double gamma, double& sx, double& sy) {
+    const double ri = recip(q[0]);
+    const double u = q[1] * ri, v = q[2] * ri;
+    const double p = (gamma - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+    const double c = sqrt(gamma * p * ri);
+    sx = fabs(u) + c;
+    sy = fabs(v) + c;
+  }
+  __device__ static bool admissible(const double* q, double gamma) {
+    const double ri = recip(q[0]);
+    const double p = (gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) * ri);
+    return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) && q[0] > 0.0 &&
+           p > 0.0;
+  }
+};
+
+// Rusanov flux along x (dir 0) or y (dir 1), unscaled.
+template <int DIR>
+__device__ __forceinline__ void rusanov2(const double* qm, const double* qp, double* G, double gamma) {
+  double fm[4], fp[4], sxm, sym, sxp, syp;
+  if (DIR == 0) {
+    Euler2::flux_x(qm, fm, gamma - 1.0);
+    Euler2::flux_x(qp, fp, gamma - 1.0);
+  } else {
+    Euler2::flux_y(qm, fm, gamma - 1.0);
+    Euler2::flux_y(qp, fp, gamma - 1.0);
+  }
+  Euler2::speeds(qm, gamma, sxm, sym);
+  Euler2::speeds(qp, gamma, sxp, syp);
+  const double s = DIR == 0 ? fmax(sxm, sxp) : fmax(sym, syp);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) G[r] = 0.5 * (fm[r] + fp[r]) - 0.5 * s * (qp[r] - qm[r]);
+}
+
+template <int N, class TP> __device__ __forceinline__ TP ktil(int i, int j) {
+  if constexpr (sizeof(TP) == 8) return c2_ops[N].ktil[i][j];
+  else return c2_opsf[N].ktil[i][j];
+}
+template <int N, class TP> __device__ __forceinline__ TP kappa(int i, int j) {
+  if constexpr (sizeof(TP) == 8) return c2_ops[N].kappa[i][j];
+  else return c2_opsf[N].kappa[i][j];
+}
+
+// ------------------------------------------------------- time stepping ----
+// Step size of the current step (uniform over the workgroup) and, by
+// workgroup 0 of the predictor launch, the clock update: next time, last dt,
+// reset of the signal-speed buffer the step after next will fill, and carry
+// of the current maxima when the problem has already reached t_end.
+template <int N>
+__device__ __forceinline__ double step_dt2d(const Args2D& A, double& t, double* bcast, bool owner) {
+  if (A.mode == k2dPredict) {
+    t = A.t;
+    return A.dt;
+  }
+  Clock2D& clk = *A.clk;
+  const int s = A.step;
+  t = clk.t[s & 1];
+  double dt;
+  if (A.fixed_dt > 0.0) {
+    dt = A.fixed_dt;
+  } else {
+    if (threadIdx.x < 64) {
+      const int l = threadIdx.x & 31;
+      double v = __longlong_as_double(
+          (long long)(threadIdx.x < 32 ? clk.lamx[s % 3][l].v : clk.lamy[s % 3][l].v));
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+      if (l == 0) bcast[threadIdx.x >> 5] = v;
+    }
+    __syncthreads();
+    dt = A.cfl / (2.0 * (2 * N + 1)) * fmin(A.dx / bcast[0], A.dy / bcast[1]);
+  }
+  const double rem = A.t_end[0] - t;
+  if (dt > rem) dt = rem;
+  if (!(dt > 0.0)) dt = 0.0;
+  if (owner) {
+    if (threadIdx.x == 0) {
+      clk.t[(s + 1) & 1] = t + dt;
+      if (dt > 0.0) clk.dt_last = dt;
+    }
+    if (threadIdx.x < kSlots) {
+      clk.lamx[(s + 2) % 3][threadIdx.x].v = 0ull;
+      clk.lamy[(s + 2) % 3][threadIdx.x].v = 0ull;
+      if (dt == 0.0) {
+        clk.lamx[(s + 1) % 3][threadIdx.x].v = clk.lamx[s % 3][threadIdx.x].v;
+        clk.lamy[(s + 1) % 3][threadIdx.x].v = clk.lamy[s % 3][threadIdx.x].v;
+      }
+    }
+  }
+  return dt;
+}
+
+// ----------------------------------------------------------- predictor ----
+template <int N, class TP>
+struct Pred2Geo {
+  static constexpr int n = N + 1, L = n * n, M = 4;
+  static constexpr int CELL = n * n * n * M;           // tile elements of one cell
+  static constexpr bool kVbAlias = sizeof(TP) == 8;    // volume buffer reuses R in FP64
+  static constexpr int kPerCell = 2 * CELL * (int)sizeof(TP) + (kVbAlias ? 0 : 2 * L * M * 8);
+  static constexpr int kBudget = 159 * 1024;
+  static constexpr int CPB0 = 256 / L;
+  static constexpr int CPB = CPB0 * kPerCell <= kBudget ? CPB0 : kBudget / kPerCell;
+  static constexpr int NT = ((CPB * L + 63) / 64) * 64;
+  static_assert(CPB >= 1, "one cell tile must fit in LDS");
+};
+
+template <int N, class TP>
+__global__ void __launch_bounds__((Pred2Geo<N, TP>::NT))
+pred2d_kernel(Args2D A) {
+  using G = Pred2Geo<N, TP>;
+  constexpr int n = G::n, L = G::L, M = G::M, CPB = G::CPB, CELL = G::CELL;
+  using Bits = decltype(ord_bits(TP(0)));
+
+  __shared__ TP Qs[CPB * CELL];
+  __shared__ TP Rs[CPB * CELL];
+  __shared__ double Vsep[G::kVbAlias ? 1 : CPB * 2 * L * M];
+  __shared__ Bits red[2][CPB][2];
+  __shared__ double bcast[2];
+  __shared__ unsigned int swsum;
+
+  const int tid = threadIdx.x;
+  const int cl = tid / L, line = tid - cl * L;
+  const int hi = line / n, lo = line - hi * n;
+  const int64_t ncells = A.cx * A.cy;
+  const int64_t cell = (int64_t)blockIdx.x * CPB + cl;
+  const bool mine = cl < CPB && cell < ncells;
+
+  double t;
+  const double dt = step_dt2d<N>(A, t, bcast, blockIdx.x == 0);
+  if (!(dt > 0.0)) return;                                  // uniform: nothing to do this step
+  const double dtdx = dt / A.dx, dtdy = dt / A.dy;
+  const TP cxs = TP(dtdx), cys = TP(dtdy), gm1 = TP(A.gamma - 1.0);
+
+  if (tid < 4 * CPB) (&red[0][0][0])[tid] = 0;
+  if (tid == 0) swsum = 0u;
+
+  // T role: node (i, j) = (hi, lo); the initial guess is u on every time level
+  double u0[M];
+  TP q[n][M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) u0[r] = mine ? A.u[(cell * L + line) * M + r] : 1.0;
+#pragma unroll
+  for (int a = 0; a < n; ++a)
+#pragma unroll
+    for (int r = 0; r < M; ++r) q[a][r] = TP(u0[r]);
+
+  TP* const Qc = Qs + (mine ? cl : 0) * CELL;
+  TP* const Rc = Rs + (mine ? cl : 0) * CELL;
+  const TP tol = TP(A.tol);
+  bool active = mine, failed = false;
+  int sweeps = 0;
+
+  for (int it = 0;; ++it) {
+    if (active && sweeps >= A.max_iter) {
+      active = false;
+      failed = true;
+    }
+    if (active) {
+#pragma unroll
+      for (int a = 0; a < n; ++a)
+#pragma unroll
+        for (int r = 0; r < M; ++r) Qc[((a * n + hi) * n + lo) * M + r] = q[a][r];
+    }
+    if (!__syncthreads_or(active)) break;
+    if (active) {
+      // X role, line (a, j) = (hi, lo): R[a][i][j] = sum_i' k~[i][i'] (dt/dx) Fx(q[a][i'][j])
+      TP acc[n][M];
+#pragma unroll
+      for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc[i][r] = TP(0);
+#pragma unroll
+      for (int ip = 0; ip < n; ++ip) {
+        TP qq[M], f[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) qq[r] = Qc[((hi * n + ip) * n + lo) * M + r];
+        Euler2::flux_x(qq, f, gm1);
+#pragma unroll
+        for (int r = 0; r < M; ++r) f[r] *= cxs;
+#pragma unroll
+        for (int i = 0; i < n; ++i)
+#pragma unroll
+          for (int r = 0; r < M; ++r) acc[i][r] = fma(ktil<N, TP>(i, ip), f[r], acc[i][r]);
+      }
+#pragma unroll
+      for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int r = 0; r < M; ++r) Rc[((hi * n + i) * n + lo) * M + r] = acc[i][r];
+    }
+    __syncthreads();
+    if (active) {
+      // Y role, line (a, i) = (hi, lo): R[a][i][j] += sum_j' k~[j][j'] (dt/dy) Fy(q[a][i][j'])
+      TP acc[n][M];
+#pragma unroll
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc[j][r] = TP(0);
+#pragma unroll
+      for (int jp = 0; jp < n; ++jp) {
+        TP qq[M], f[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) qq[r] = Qc[((hi * n + lo) * n + jp) * M + r];
+        Euler2::flux_y(qq, f, gm1);
+#pragma unroll
+        for (int r = 0; r < M; ++r) f[r] *= cys;
+#pragma unroll
+        for (int j = 0; j < n; ++j)
+#pragma unroll
+          for (int r = 0; r < M; ++r) acc[j][r] = fma(ktil<N, TP>(j, jp), f[r], acc[j][r]);
+      }
+#pragma unroll
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          TP* p = &Rc[((hi * n + lo) * n + j) * M + r];
+          *p = *p + acc[j][r];
+        }
+    }
+    __syncthreads();
+    if (active) {
+      // T role: q_new[a] = u - sum_b kappa~[a][b] R[b][i][j]
+      TP rr[n][M];
+#pragma unroll
+      for (int b = 0; b < n; ++b)
+#pragma unroll
+        for (int r = 0; r < M; ++r) rr[b][r] = Rc[((b * n + hi) * n + lo) * M + r];
+      TP e = TP(0), qm = TP(0);
+#pragma unroll
+      for (int a = 0; a < n; ++a)
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          TP acc = TP(0);
+#pragma unroll
+          for (int b = 0; b < n; ++b) acc = fma(kappa<N, TP>(a, b), rr[b][r], acc);
+          const TP qn = TP(u0[r]) - acc;
+          e = max_abs(e, qn - q[a][r]);
+          qm = max_abs(qm, qn);
+          q[a][r] = qn;
+        }
+      atomicMax(&red[it & 1][cl][0], ord_bits(e));
+      atomicMax(&red[it & 1][cl][1], ord_bits(qm));
+      ++sweeps;
+    }
+    // the other parity's maxima were read before this sweep's first barrier
+    if (tid < 2 * CPB) (&red[(it + 1) & 1][0][0])[tid] = 0;
+    __syncthreads();
+    if (active) {
+      const TP E = from_bits(red[it & 1][cl][0]), Qm = from_bits(red[it & 1][cl][1]);
+      if (E <= tol * dmax(TP(1), Qm)) active = false;
+    }
+  }
+
+  // ---- epilogue: final tile into LDS for the traces
+  if (mine) {
+#pragma unroll
+    for (int a = 0; a < n; ++a)
+#pragma unroll
+      for (int r = 0; r < M; ++r) Qc[((a * n + hi) * n + lo) * M + r] = q[a][r];
+  }
+  __syncthreads();
+  if (mine) {
+    // x faces from the X role (a, j) = (hi, lo); y faces from the Y role (a, i) = (hi, lo)
+    double tw[M], te[M], ts[M], tn[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) tw[r] = te[r] = ts[r] = tn[r] = 0.0;
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      const double p0 = c2_ops[N].psi0[p], p1 = c2_ops[N].psi1[p];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        const double vx = (double)Qc[((hi * n + p) * n + lo) * M + r];
+        const double vy = (double)Qc[((hi * n + lo) * n + p) * M + r];
+        tw[r] = fma(p0, vx, tw[r]);
+        te[r] = fma(p1, vx, te[r]);
+        ts[r] = fma(p0, vy, ts[r]);
+        tn[r] = fma(p1, vy, tn[r]);
+      }
+    }
+    double* trc = A.tr + cell * (4 * L * M);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      trc[(0 * L + line) * M + r] = tw[r];
+      trc[(1 * L + line) * M + r] = te[r];
+      trc[(2 * L + line) * M + r] = ts[r];
+      trc[(3 * L + line) * M + r] = tn[r];
+    }
+    if (A.mode == k2dPredict) {
+      TP* qo = reinterpret_cast<TP*>(A.q_out) + cell * (n * L * M);
+#pragma unroll
+      for (int a = 0; a < n; ++a)
+#pragma unroll
+        for (int r = 0; r < M; ++r) qo[(a * L + line) * M + r] = q[a][r];
+      if (A.iters && line == 0) A.iters[cell] = sweeps;
+    }
+  }
+  // volume terms: time-integrated fluxes of the (promoted) predictor at every node
+  double* const Vb = G::kVbAlias ? reinterpret_cast<double*>(Rs) : Vsep;
+  double* const Vc = Vb + (mine ? cl : 0) * (2 * L * M);
+  if (mine) {
+    double fxb[M], fyb[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) fxb[r] = fyb[r] = 0.0;
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      double qd[M], f[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) qd[r] = (double)q[a][r];
+      const double wa = c2_ops[N].w[a];
+      Euler2::flux_x(qd, f, A.gamma - 1.0);
+#pragma unroll
+      for (int r = 0; r < M; ++r) fxb[r] = fma(wa, dtdx * f[r], fxb[r]);
+      Euler2::flux_y(qd, f, A.gamma - 1.0);
+#pragma unroll
+      for (int r = 0; r < M; ++r) fyb[r] = fma(wa, dtdy * f[r], fyb[r]);
+    }
+    // in FP64, Vb aliases R, last read before the loop's final barriers
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      Vc[line * M + r] = fxb[r];
+      Vc[(L + line) * M + r] = fyb[r];
+    }
+  }
+  __syncthreads();
+  if (mine) {
+    double vol[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) vol[r] = 0.0;
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      const double dx_ = c2_ops[N].Dw[hi][l], dy_ = c2_ops[N].Dw[lo][l];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        vol[r] = fma(dx_, Vc[(l * n + lo) * M + r], vol[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        vol[r] = fma(dy_, Vc[(L + hi * n + l) * M + r], vol[r]);
+      }
+    }
+    double* pc = A.part + (cell * L + line) * M;
+#pragma unroll
+    for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
+  }
+
+  // sweeps and status
+  if (mine && line == 0) atomicAdd(&swsum, (unsigned int)sweeps);
+  const bool any_fail = __any(failed);
+  __syncthreads();
+  if (A.mode == k2dStep) {
+    const int slot = (int)(blockIdx.x % kSlots);
+    if (tid == 0 && swsum) atomicAdd(&A.clk->sweeps[slot].v, (unsigned long long)swsum);
+    if ((tid & 63) == 0 && any_fail) atomicMin(&A.clk->stat[(slot + (tid >> 6)) % kSlots].v, -4);
+  }
+}
+
+// ----------------------------------------------------------- corrector ----
+template <int N>
+struct Corr2Geo {
+  static constexpr int n = N + 1, L = n * n, M = 4, Ns = 2 * N + 1;
+  static constexpr int CPB = 256 / L;
+  static constexpr int NT = 256;
+};
+
+// Signal-speed maxima over the (2N+1)^2 subcell averages (P (x) P) u of the
+// workgroup's cells; U holds u of each cell in LDS, V1 the x-projected
+// averages.  Returns this thread's maxima (to be reduced by the caller).
+template <int N>
+__device__ __forceinline__ void subcell_speeds(const double* U, double* V1, int ncl, double gamma,
+                                               double& lx, double& ly) {
+  using G = Corr2Geo<N>;
+  constexpr int n = G::n, L = G::L, M = G::M, Ns = G::Ns;
+  for (int w = threadIdx.x; w < ncl * Ns * n; w += G::NT) {
+    const int cl = w / (Ns * n), rem = w - cl * (Ns * n), s = rem / n, j = rem - s * n;
+    double v[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) v[r] = 0.0;
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      const double P = c2_ops[N].P[s][i];
+#pragma unroll
+      for (int r = 0; r < M; ++r) v[r] = fma(P, U[(cl * L + i * n + j) * M + r], v[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r) V1[((cl * Ns + s) * n + j) * M + r] = v[r];
+  }
+  __syncthreads();
+  lx = 0.0;
+  ly = 0.0;
+  for (int w = threadIdx.x; w < ncl * Ns * Ns; w += G::NT) {
+    const int cl = w / (Ns * Ns), rem = w - cl * (Ns * Ns), s = rem / Ns, tt = rem - s * Ns;
+    double v[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) v[r] = 0.0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      const double P = c2_ops[N].P[tt][j];
+#pragma unroll
+      for (int r = 0; r < M; ++r) v[r] = fma(P, V1[((cl * Ns + s) * n + j) * M + r], v[r]);
+    }
+    double sx, sy;
+    Euler2::speeds(v, gamma, sx, sy);
+    lx = fmax(lx, sx);
+    ly = fmax(ly, sy);
+  }
+}
+
+// Workgroup maxima of (lx, ly) into slot (block % kSlots) of lambda buffer buf.
+__device__ __forceinline__ void publish_lambda(Clock2D& clk, int buf, double lx, double ly,
+                                               double* part) {
+  lx = wave_max(lx);
+  ly = wave_max(ly);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    part[2 * wv] = lx;
+    part[2 * wv + 1] = ly;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double X = 0.0, Y = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      X = fmax(X, part[2 * w]);
+      Y = fmax(Y, part[2 * w + 1]);
+    }
+    const int slot = (int)(blockIdx.x % kSlots);
+    atomic_max_nonneg(&clk.lamx[buf][slot].v, X);
+    atomic_max_nonneg(&clk.lamy[buf][slot].v, Y);
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256)
+corr2d_kernel(Args2D A) {
+  using G = Corr2Geo<N>;
+  constexpr int n = G::n, L = G::L, M = G::M, Ns = G::Ns, CPB = G::CPB;
+  __shared__ double Gf[CPB * 4 * n * M];
+  __shared__ double U[CPB * L * M];
+  __shared__ double V1[CPB * Ns * n * M];
+  __shared__ double bcast[2];
+  __shared__ double part[8];
+
+  double t;
+  const double dt = step_dt2d<N>(A, t, bcast, false);
+  if (!(dt > 0.0)) return;
+  const double dtdx = dt / A.dx, dtdy = dt / A.dy;
+  const int64_t ncells = A.cx * A.cy;
+  const int64_t cell0 = (int64_t)blockIdx.x * CPB;
+  const int ncl = (int)((ncells - cell0) < CPB ? (ncells - cell0) : CPB);
+
+  // face fluxes, time-integrated: face 0 west, 1 east, 2 south, 3 north
+  for (int w = threadIdx.x; w < ncl * 4 * n; w += G::NT) {
+    const int cl = w / (4 * n), rem = w - cl * (4 * n), f = rem / n, k = rem - f * n;
+    const int64_t c = cell0 + cl;
+    const int64_t ix = c / A.cy, iy = c - ix * A.cy;
+    int64_t cm, cp;         // the cell on the minus side and on the plus side of the face
+    int fm, fp;             // the trace taken from each: east/west or north/south
+    if (f == 0) { cm = (ix == 0 ? A.cx - 1 : ix - 1) * A.cy + iy; cp = c; }
+    else if (f == 1) { cm = c; cp = (ix + 1 == A.cx ? 0 : ix + 1) * A.cy + iy; }
+    else if (f == 2) { cm = ix * A.cy + (iy == 0 ? A.cy - 1 : iy - 1); cp = c; }
+    else { cm = c; cp = ix * A.cy + (iy + 1 == A.cy ? 0 : iy + 1); }
+    fm = f < 2 ? 1 : 3;
+    fp = f < 2 ? 0 : 2;
+    const double sc = f < 2 ? dtdx : dtdy;
+    double acc[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) acc[r] = 0.0;
+    for (int a = 0; a < n; ++a) {
+      double qm[M], qp[M], Gr[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        qm[r] = A.tr[((cm * 4 + fm) * L + a * n + k) * M + r];
+        qp[r] = A.tr[((cp * 4 + fp) * L + a * n + k) * M + r];
+      }
+      if (f < 2) rusanov2<0>(qm, qp, Gr, A.gamma);
+      else rusanov2<1>(qm, qp, Gr, A.gamma);
+      const double wa = c2_ops[N].w[a];
+#pragma unroll
+      for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r) Gf[((cl * 4 + f) * n + k) * M + r] = acc[r];
+  }
+  __syncthreads();
+
+  // surface update of every node, in place
+  bool bad = false;
+  for (int w = threadIdx.x; w < ncl * L; w += G::NT) {
+    const int cl = w / L, line = w - cl * L, i = line / n, j = line - i * n;
+    const int64_t c = cell0 + cl;
+    const double* pc = A.part + (c * L + line) * M;
+    const double wix = c2_ops[N].winv[i], wiy = c2_ops[N].winv[j];
+    const double p0i = c2_ops[N].psi0[i], p1i = c2_ops[N].psi1[i];
+    const double p0j = c2_ops[N].psi0[j], p1j = c2_ops[N].psi1[j];
+    const double* Gc = Gf + cl * 4 * n * M;
+    double un[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const double sx = (p1i * Gc[(1 * n + j) * M + r] - p0i * Gc[(0 * n + j) * M + r]) * wix;
+      const double sy = (p1j * Gc[(3 * n + i) * M + r] - p0j * Gc[(2 * n + i) * M + r]) * wiy;
+      un[r] = pc[r] - sx - sy;
+      A.u[(c * L + line) * M + r] = un[r];
+      U[(cl * L + line) * M + r] = un[r];
+    }
+    bad |= !Euler2::admissible(un, A.gamma);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0)
+    atomicMin(&A.clk->stat[(blockIdx.x + (threadIdx.x >> 6)) % kSlots].v, -5);
+  __syncthreads();
+
+  double lx, ly;
+  subcell_speeds<N>(U, V1, ncl, A.gamma, lx, ly);
+  publish_lambda(*A.clk, (A.step + 1) % 3, lx, ly, part);
+}
+
+// Signal-speed maxima of the initial state into lambda buffer 0.
+template <int N>
+__global__ void __launch_bounds__(256)
+lambda2d_kernel(Args2D A) {
+  using G = Corr2Geo<N>;
+  constexpr int L = G::L, M = G::M, Ns = G::Ns, n = G::n, CPB = G::CPB;
+  __shared__ double U[CPB * L * M];
+  __shared__ double V1[CPB * Ns * n * M];
+  __shared__ double part[8];
+  const int64_t ncells = A.cx * A.cy;
+  const int64_t cell0 = (int64_t)blockIdx.x * CPB;
+  const int ncl = (int)((ncells - cell0) < CPB ? (ncells - cell0) : CPB);
+  for (int w = threadIdx.x; w < ncl * L * M; w += G::NT) U[w] = A.u[cell0 * L * M + w];
+  __syncthreads();
+  double lx, ly;
+  subcell_speeds<N>(U, V1, ncl, A.gamma, lx, ly);
+  publish_lambda(*A.clk, 0, lx, ly, part);
+}
+
+__global__ void clock2d_begin_kernel(Clock2D* clk, const double* t_user) {
+  const int i = threadIdx.x;
+  if (i == 0) {
+    clk->t[0] = t_user[0];
+    clk->t[1] = t_user[0];
+    clk->dt_last = 0.0;
+  }
+  if (i < kSlots) {
+    for (int b = 0; b < 3; ++b) {
+      clk->lamx[b][i].v = 0ull;
+      clk->lamy[b][i].v = 0ull;
+    }
+    clk->stat[i].v = 0;
+  }
+}
+
+__global__ void clock2d_end_kernel(const Clock2D* clk, double* t_user, double* dt_user,
+                                   int32_t* status_user, int parity) {
+  if (threadIdx.x != 0) return;
+  t_user[0] = clk->t[parity];
+  dt_user[0] = clk->dt_last;
+  int st = 0;
+  for (int i = 0; i < kSlots; ++i) st = min(st, clk->stat[i].v);
+  status_user[0] = st;
+}
+
+// -------------------------------------------------------------- dispatch ----
+template <class TP>
+static hipError_t launch_pred2d_p(int N, const Args2D& A, int64_t blocks, hipStream_t st) {
+  dim3 grid((unsigned)blocks);
+  switch (N) {
+#define ADERDG2_CASE(NN)                                                                      \
+  case NN:                                                                                    \
+    hipLaunchKernelGGL((pred2d_kernel<NN, TP>), grid, dim3(Pred2Geo<NN, TP>::NT), 0, st, A); \
+    break;
+    ADERDG2_CASE(1) ADERDG2_CASE(2) ADERDG2_CASE(3) ADERDG2_CASE(4) ADERDG2_CASE(5)
+    ADERDG2_CASE(6) ADERDG2_CASE(7) ADERDG2_CASE(8) ADERDG2_CASE(9)
+#undef ADERDG2_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <class TP> static int cpb_p(int N) {
+  switch (N) {
+    case 1: return Pred2Geo<1, TP>::CPB; case 2: return Pred2Geo<2, TP>::CPB;
+    case 3: return Pred2Geo<3, TP>::CPB; case 4: return Pred2Geo<4, TP>::CPB;
+    case 5: return Pred2Geo<5, TP>::CPB; case 6: return Pred2Geo<6, TP>::CPB;
+    case 7: return Pred2Geo<7, TP>::CPB; case 8: return Pred2Geo<8, TP>::CPB;
+    case 9: return Pred2Geo<9, TP>::CPB;
+    default: return 0;
+  }
+}
+
+int cells_per_block_2d(int N, int prec) { return prec ? cpb_p<float>(N) : cpb_p<double>(N); }
+int threads_per_block_2d(int N, int prec) {
+  const int L = (N + 1) * (N + 1), c = cells_per_block_2d(N, prec);
+  return ((c * L + 63) / 64) * 64;
+}
+int cells_per_block_corr2d(int N) { return 256 / ((N + 1) * (N + 1)); }
+
+hipError_t launch_pred2d(int N, int prec, const Args2D& A, int64_t blocks, hipStream_t st) {
+  return prec ? launch_pred2d_p<float>(N, A, blocks, st) : launch_pred2d_p<double>(N, A, blocks, st);
+}
+
+hipError_t launch_corr2d(int N, const Args2D& A, int64_t blocks, hipStream_t st) {
+  dim3 grid((unsigned)blocks), block(256);
+  switch (N) {
+#define ADERDG2_CASE(NN) case NN: hipLaunchKernelGGL((corr2d_kernel<NN>), grid, block, 0, st, A); break;
+    ADERDG2_CASE(1) ADERDG2_CASE(2) ADERDG2_CASE(3) ADERDG2_CASE(4) ADERDG2_CASE(5)
+    ADERDG2_CASE(6) ADERDG2_CASE(7) ADERDG2_CASE(8) ADERDG2_CASE(9)
+#undef ADERDG2_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda2d(int N, const Args2D& A, int64_t blocks, hipStream_t st) {
+  dim3 grid((unsigned)blocks), block(256);
+  switch (N) {
+#define ADERDG2_CASE(NN) case NN: hipLaunchKernelGGL((lambda2d_kernel<NN>), grid, block, 0, st, A); break;
+    ADERDG2_CASE(1) ADERDG2_CASE(2) ADERDG2_CASE(3) ADERDG2_CASE(4) ADERDG2_CASE(5)
+    ADERDG2_CASE(6) ADERDG2_CASE(7) ADERDG2_CASE(8) ADERDG2_CASE(9)
+#undef ADERDG2_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_clock2d_begin(Clock2D* clk, const double* t_user, hipStream_t st) {
+  hipLaunchKernelGGL(clock2d_begin_kernel, dim3(1), dim3(64), 0, st, clk, t_user);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock2d_end(const Clock2D* clk, double* t_user, double* dt_user,
+                              int32_t* status_user, int parity, hipStream_t st) {
+  hipLaunchKernelGGL(clock2d_end_kernel, dim3(1), dim3(64), 0, st, clk, t_user, dt_user,
+                     status_user, parity);
+  return hipGetLastError();
+}
+
+hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf) {
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c2_ops), ops, sizeof(DevOps) * kDevMaxn);
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c2_opsf), opsf, sizeof(DevOpsF) * kDevMaxn);
+}
+
+}  // namespace aderdg

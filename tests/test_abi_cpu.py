@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed).
 
-* libaderdg.so loads and exports every function declared in include/aderdg.h;
+* libaderdg.so loads and exports every function declared in include/aderdg.h
+  and include/aderdg2d.h;
 * the library's host operator tables (an independent C++ construction)
   agree with the oracle's;
 * argument validation returns ADERDG_E_INVAL before any device work.
@@ -18,15 +19,16 @@ from paper_2409_12483_amd import abi
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "aderdg.h")
+HEADER_2D = os.path.join(ROOT, "include", "aderdg2d.h")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(abi.LIBPATH),
                                 reason="libaderdg.so not built (run __graft_entry__.build())")
 
 
-def _declared_functions():
-    text = open(HEADER).read()
+def _declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(aderdg_\w+|aderweno_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(aderdg_\w+|aderweno_\w+|aderdg2d_\w+)\s*\(", text)))
 
 
 def test_header_declares_the_entry_points():
@@ -39,8 +41,12 @@ def test_header_declares_the_entry_points():
 
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(abi.LIBPATH)
-    for name in _declared_functions():
+    for name in _declared_functions() + _declared_functions(HEADER_2D):
         assert hasattr(lib, name), name
+
+
+def test_2d_header_declares_the_entry_points():
+    assert set(_declared_functions(HEADER_2D)) == set(abi.EXPORTS_2D)
 
 
 @pytest.mark.parametrize("N", range(0, 10))
@@ -108,3 +114,47 @@ def test_config_struct_layout_matches_header():
     assert abi.Config.ncells.offset == 8 and abi.Config.x0.offset == 16
     assert abi.Config.cfl_mode.offset == 48 and abi.Config.picard_tol.offset == 56
     assert ctypes.sizeof(abi.Config) == 72
+
+
+def _init2d(cfg):
+    lib = abi.load()
+    h = ctypes.c_void_p()
+    return lib.aderdg2d_init(ctypes.byref(cfg), None, ctypes.byref(h)), h
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda c: setattr(c, "N", 0), "N must"),
+    (lambda c: setattr(c, "N", 10), "N must"),
+    (lambda c: setattr(c, "precision", 3), "precision"),
+    (lambda c: setattr(c, "cells_x", 0), "cells_x"),
+    (lambda c: setattr(c, "cells_y", -2), "cells_x"),
+    (lambda c: (setattr(c, "cells_x", 1 << 16), setattr(c, "cells_y", 1 << 16)), "2^31"),
+    (lambda c: setattr(c, "y1", -1.0), "domain"),
+    (lambda c: setattr(c, "x1", float("inf")), "domain"),
+    (lambda c: setattr(c, "gamma", 0.9), "gamma"),
+    (lambda c: setattr(c, "cfl", 0.0), "cfl"),
+    (lambda c: setattr(c, "fixed_dt", -1.0), "fixed_dt"),
+    (lambda c: setattr(c, "picard_tol", float("nan")), "picard_tol"),
+])
+def test_invalid_2d_configs_are_rejected(mutate, needle):
+    c = abi.config2d(3, 8, 8)
+    mutate(c)
+    rc, h = _init2d(c)
+    assert rc == abi.ADERDG_E_INVAL
+    assert h.value is None
+    assert needle in abi.aderdg_last_error()
+
+
+def test_null_2d_arguments_are_rejected():
+    lib = abi.load()
+    assert lib.aderdg2d_init(None, None, None) == abi.ADERDG_E_INVAL
+    assert lib.aderdg2d_step(None, None, None, None, None, None, 1) == abi.ADERDG_E_INVAL
+    assert lib.aderdg2d_predict(None, None, 0.0, 0.1, None, None) == abi.ADERDG_E_INVAL
+    assert lib.aderdg2d_sweep_count(None, None) == abi.ADERDG_E_INVAL
+    assert lib.aderdg2d_free(None) == abi.ADERDG_OK
+
+
+def test_2d_config_struct_layout_matches_header():
+    assert abi.Config2D.cells_x.offset == 8 and abi.Config2D.x0.offset == 24
+    assert abi.Config2D.gamma.offset == 56 and abi.Config2D.picard_tol.offset == 80
+    assert abi.Config2D.picard_max_iter.offset == 88 and ctypes.sizeof(abi.Config2D) == 96

@@ -1,0 +1,165 @@
+"""2-D ADER-DG (Euler gas) on the GPU against the FP64 oracle, through the C ABI.
+
+* predictor alone: q of every cell and each cell's Picard sweep count;
+* fused steps: state, time and total sweeps after several CFL steps, for
+  every degree 1..9, on non-square meshes and domains whose cell counts leave
+  the last workgroup partly empty;
+* FP32-predictor mode within 1e-5 of the FP64 oracle;
+* edge cases: a single cell (its own neighbour on all four sides), one-cell
+  strips, zero steps, a fixed step, the last step clamped to t_end;
+* full size (512 x 512 cells, N = 5): a wave of period 8 cells equals, on
+  every cell, the oracle's 8 x 8 run repeated; a noisy state agrees with the
+  oracle on sampled 3 x 3 windows after one step.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import basis, dg2d
+from paper_2409_12483_amd import abi
+from paper_2409_12483_amd import workloads as W
+
+from gpu_util import BIG, rel_l2, torch_dev
+
+pytestmark = pytest.mark.gpu
+E2 = dg2d.Euler2D()
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def gpu_run(u0, N, nsteps, extent=(0.0, 1.0, 0.0, 1.0), cfl=0.4, fixed_dt=0.0, prec=abi.FP64,
+            t0=0.0, t_end=BIG):
+    torch, dev = torch_dev()
+    cx, cy = u0.shape[:2]
+    h = abi.aderdg2d_init(abi.config2d(N, cx, cy, extent=extent, cfl=cfl, fixed_dt=fixed_dt,
+                                       precision=prec))
+    try:
+        u = torch.tensor(np.ascontiguousarray(u0), dtype=torch.float64, device=dev)
+        t = torch.tensor([t0], dtype=torch.float64, device=dev)
+        te = torch.tensor([t_end], dtype=torch.float64, device=dev)
+        dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        abi.aderdg2d_step(h, u, t, te, dt, st, nsteps)
+        torch.cuda.synchronize()
+        return (u.cpu().numpy(), float(t[0]), float(dt[0]), int(st[0]), abi.aderdg2d_sweep_count(h))
+    finally:
+        abi.aderdg2d_free(h)
+
+
+@pytest.mark.parametrize("N,cx,cy", [(1, 9, 8), (3, 5, 7), (5, 4, 5), (9, 3, 2)])
+def test_predictor_matches_oracle(N, cx, cy):
+    _say("2d predictor", N, cx, cy)
+    torch, dev = torch_dev()
+    ops = basis.build_operators(N)
+    u0 = W.euler2d_sine_wave(cx, cy, N, noise=2e-2, seed=N, velocity=(0.8, -0.5))
+    dx, dy = 1.0 / cx, 0.9 / cy
+    dt = 0.3 * min(dx, dy) / (2 * (2 * N + 1)) / 2.5
+    qref, sw, _ = dg2d.predict2d(ops, E2, u0, dt, dx, dy)
+    h = abi.aderdg2d_init(abi.config2d(N, cx, cy, extent=(0.0, 1.0, 0.0, 0.9)))
+    try:
+        u = torch.tensor(u0, dtype=torch.float64, device=dev)
+        q = torch.zeros(qref.shape, dtype=torch.float64, device=dev)
+        it = torch.zeros(cx * cy, dtype=torch.int32, device=dev)
+        abi.aderdg2d_predict(h, u, 0.0, dt, q, it)
+        torch.cuda.synchronize()
+        assert rel_l2(q.cpu().numpy(), qref) <= 1e-12
+        assert np.array_equal(it.cpu().numpy(), sw.reshape(-1))
+    finally:
+        abi.aderdg2d_free(h)
+
+
+@pytest.mark.parametrize("N", range(1, 10))
+def test_fused_steps_match_oracle(N):
+    cx, cy = (7, 5) if N <= 4 else (6, 5) if N == 5 else (3, 5)
+    _say("2d steps", N, cx, cy)
+    ops = basis.build_operators(N)
+    ext = (0.0, 1.0, 0.0, 0.75)
+    u0 = W.euler2d_sine_wave(cx, cy, N, noise=1e-2, seed=10 + N, y1=0.75, velocity=(1.0, 0.6))
+    cfl = 0.3 if N >= 8 else 0.4
+    ref, t_ref, info = dg2d.dg2d_run(ops, E2, u0, extent=ext, cfl=cfl, nsteps=4)
+    u, t, dt, st, sweeps = gpu_run(u0, N, 4, extent=ext, cfl=cfl)
+    assert st == 0
+    assert rel_l2(u, ref) <= 1e-12
+    assert abs(t - t_ref) <= 1e-14 * t_ref
+    assert abs(dt - info["dts"][-1]) <= 1e-14 * dt
+    assert sweeps == sum(k * v for k, v in info["sweep_hist"].items())
+
+
+@pytest.mark.parametrize("N", [2, 5, 9])
+def test_fp32_predictor_within_1e5(N):
+    _say("2d fp32", N)
+    ops = basis.build_operators(N)
+    u0 = W.euler2d_sine_wave(6, 5, N, noise=1e-2, seed=3)
+    cfl = 0.3 if N >= 8 else 0.4
+    ref, t_ref, _ = dg2d.dg2d_run(ops, E2, u0, cfl=cfl, nsteps=3)
+    u, t, _, st, _ = gpu_run(u0, N, 3, cfl=cfl, prec=abi.FP32_PREDICTOR)
+    assert st == 0
+    assert 0.0 < rel_l2(u, ref) <= 1e-5
+    assert abs(t - t_ref) <= 1e-5 * t_ref
+
+
+@pytest.mark.parametrize("N,cx,cy", [(3, 1, 1), (4, 1, 6), (2, 5, 1)])
+def test_tiny_meshes(N, cx, cy):
+    _say("2d tiny mesh", N, cx, cy)
+    ops = basis.build_operators(N)
+    u0 = W.euler2d_sine_wave(cx, cy, N, amp=0.2, noise=1e-3, seed=1)
+    ref, t_ref, _ = dg2d.dg2d_run(ops, E2, u0, nsteps=3)
+    u, t, _, st, _ = gpu_run(u0, N, 3)
+    assert st == 0
+    assert rel_l2(u, ref) <= 1e-12
+    assert abs(t - t_ref) <= 1e-14 * t_ref
+
+
+def test_zero_steps_fixed_dt_and_clamp():
+    _say("2d zero steps / fixed dt / clamp")
+    N = 3
+    ops = basis.build_operators(N)
+    u0 = W.euler2d_sine_wave(6, 6, N, noise=1e-3, seed=2)
+    u, t, dt, st, sw = gpu_run(u0, N, 0, t0=0.25)
+    assert np.array_equal(u, u0) and t == 0.25 and dt == 0.0 and st == 0 and sw == 0
+    ref, _, _ = dg2d.dg2d_run(ops, E2, u0, fixed_dt=1e-3, nsteps=3)
+    u, t, dt, st, _ = gpu_run(u0, N, 3, fixed_dt=1e-3)
+    assert rel_l2(u, ref) <= 1e-12 and dt == 1e-3 and abs(t - 3e-3) <= 1e-17
+    # the CFL step is larger than 1e-3: the first step is clamped, the rest do nothing
+    ref, t_ref, _ = dg2d.dg2d_run(ops, E2, u0, t_end=1e-3, nsteps=5)
+    u, t, dt, st, _ = gpu_run(u0, N, 5, t_end=1e-3)
+    assert rel_l2(u, ref) <= 1e-12 and t == 1e-3 and t_ref == 1e-3 and dt == 1e-3
+
+
+def test_full_size_periodic_wave_equals_repeated_oracle():
+    N, C, per = 5, 512, 8
+    _say("2d full size tiled", N, C)
+    ops = basis.build_operators(N)
+    k = C // per
+    big = W.euler2d_sine_wave(C, C, N, kx=k, ky=k)
+    small = W.euler2d_sine_wave(per, per, N, kx=k, ky=k, x1=per / C, y1=per / C)
+    ref, t_ref, _ = dg2d.dg2d_run(ops, E2, small, extent=(0.0, per / C, 0.0, per / C), nsteps=3)
+    u, t, _, st, _ = gpu_run(big, N, 3)
+    assert st == 0
+    tiled = np.tile(ref, (k, k, 1, 1, 1))
+    assert rel_l2(u, tiled) <= 1e-12
+    assert np.abs(u - tiled).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(t - t_ref) <= 1e-14 * t_ref
+
+
+def test_full_size_sampled_windows():
+    N, C = 5, 512
+    _say("2d full size sampled", N, C)
+    ops = basis.build_operators(N)
+    u0 = W.euler2d_sine_wave(C, C, N, noise=1e-2, seed=7)
+    dx = dy = 1.0 / C
+    dt_ref = dg2d.cfl_dt2d(ops, E2, u0, dx, dy, 0.4)
+    u, t, dt, st, _ = gpu_run(u0, N, 1)
+    assert st == 0 and abs(dt - dt_ref) <= 1e-14 * dt_ref
+    rng = np.random.Generator(np.random.PCG64(11))
+    picks = rng.integers(0, C, size=(48, 2))
+    picks[0], picks[1] = (0, 0), (C - 1, C - 1)         # the periodic corners
+    for ix, iy in picks:
+        wx = (ix + np.arange(-1, 2)) % C
+        wy = (iy + np.arange(-1, 2)) % C
+        win = u0[np.ix_(wx, wy)]
+        q, _, _ = dg2d.predict2d(ops, E2, win, dt, dx, dy)
+        out = dg2d.correct2d(ops, E2, win, q, dt, dx, dy)
+        assert rel_l2(u[ix, iy], out[1, 1]) <= 1e-12, (ix, iy)
