@@ -8,14 +8,15 @@
 // Predictor kernel.  A workgroup owns CPB cells; each cell is served by
 // n^2 threads (n = N+1), and every thread plays three roles on the cell's
 // space-time tile q[a][i][j][r] (time node a, x node i, y node j, variable r):
-//   T role, thread (i, j):  owns the time line q[.][i][j] in registers;
+//   T role, thread (i, j):  updates the time line q[.][i][j];
 //   X role, thread (a, j):  contracts k~ along the x line q[a][.][j];
 //   Y role, thread (a, i):  contracts k~ along the y line q[a][i][.].
-// One Picard sweep: T threads store their lines into LDS (Q); X threads
-// evaluate the x fluxes on their lines and write k~ fx into R; Y threads
-// evaluate the y fluxes on their lines and add k~ fy into R; T threads read
-// their lines of R, apply kappa~ in registers and test convergence (cell
-// maxima by LDS integer max on order-preserving bit patterns).  Each
+// The tile q lives in LDS (Q).  One Picard sweep: X threads evaluate the x
+// fluxes on their lines and write k~ fx into R; Y threads evaluate the y
+// fluxes on their lines and add k~ fy into R; T threads read their lines of
+// R, apply kappa~ in registers, write q_new over their own time lines of Q
+// and test convergence (cell maxima by LDS integer max on order-preserving
+// bit patterns).  Each
 // contraction runs from registers over a line the thread owns, so an LDS
 // word read feeds n multiply-adds.  A converged cell freezes while the
 // others of the workgroup go on; the loop ends when no cell is active.
@@ -92,13 +93,23 @@ __device__ __forceinline__ void rusanov2(const double* qm, const double* qp, dou
   for (int r = 0; r < 4; ++r) G[r] = 0.5 * (fm[r] + fp[r]) - 0.5 * s * (qp[r] - qm[r]);
 }
 
-template <int N, class TP> __device__ __forceinline__ TP ktil(int i, int j) {
-  if constexpr (sizeof(TP) == 8) return c2_ops[N].ktil[i][j];
-  else return c2_opsf[N].ktil[i][j];
+// Operator coefficients in the constant address space.  launder() hides the
+// pointer from loop-invariant code motion: each sweep re-reads the column
+// or row it needs with scalar loads (scalar-cache hits) where it is used,
+// instead of holding both n x n operators in scalar registers across the
+// sweep loop, which would spill them into vector-register lanes.
+template <class T> using cptr = const __attribute__((address_space(4))) T*;
+template <class T> __device__ __forceinline__ cptr<T> launder(cptr<T> p) {
+  asm volatile("" : "+s"(p));
+  return p;
 }
-template <int N, class TP> __device__ __forceinline__ TP kappa(int i, int j) {
-  if constexpr (sizeof(TP) == 8) return c2_ops[N].kappa[i][j];
-  else return c2_opsf[N].kappa[i][j];
+template <int N, class TP> __device__ __forceinline__ cptr<TP> ktil_base() {
+  if constexpr (sizeof(TP) == 8) return (cptr<TP>)&c2_ops[N].ktil[0][0];
+  else return (cptr<TP>)&c2_opsf[N].ktil[0][0];
+}
+template <int N, class TP> __device__ __forceinline__ cptr<TP> kappa_base() {
+  if constexpr (sizeof(TP) == 8) return (cptr<TP>)&c2_ops[N].kappa[0][0];
+  else return (cptr<TP>)&c2_opsf[N].kappa[0][0];
 }
 
 // ------------------------------------------------------- time stepping ----
@@ -151,28 +162,84 @@ __device__ __forceinline__ double step_dt2d(const Args2D& A, double& t, double* 
 }
 
 // ----------------------------------------------------------- predictor ----
+// Cells per workgroup: as many n^2-thread cells as fill four waves, fewer
+// where the two LDS tiles of a cell would not leave room for a second
+// resident workgroup (the barriers of one workgroup are then overlapped by
+// another's work).
+// LDS tile layout.  The unit is 16 bytes: an FP32 node (its M = 4 values)
+// or half an FP64 node; FP64 tiles keep the two halves of every node in two
+// planes, so that every node access is one 16-byte LDS access per plane.
+// Node (a, i, j) of a cell sits at unit a*SA + i*n + j.  Each role may map
+// its lanes to its lines in either index order; the strides SA, the cell
+// stride and the orders below were chosen per n (with the cells per
+// workgroup) so that 8- and 16-lane groups of the three access patterns of
+// a sweep (X: lanes over (a, j); Y: lanes over (a, i); T: lanes over (i, j))
+// fall on distinct 16-byte bank groups as far as a linear layout allows;
+// the cells per workgroup fill whole wavefronts with few idle lanes while
+// leaving room for a second resident workgroup where the tiles allow.
+struct Layout2 {
+  int cpb;            // cells per workgroup
+  int SA, CELL;       // time-slice and cell strides in units
+  int oT, oX, oY;     // 1: the role's first line index runs fastest over lanes
+};
+constexpr Layout2 kLayout2[11] = {
+    {0, 0, 0, 0, 0, 0},        {0, 0, 0, 0, 0, 0},       {64, 5, 12, 0, 0, 0},
+    {14, 18, 57, 0, 1, 1},     {8, 19, 76, 0, 0, 1},     {5, 25, 137, 0, 0, 0},
+    {5, 41, 252, 0, 0, 1},     {3, 49, 353, 0, 0, 1},    {2, 65, 520, 0, 0, 1},
+    {3, 81, 729, 1, 0, 0},     {1, 105, 1050, 0, 0, 1}};
+
+#ifndef ADERDG2D_CPB_OVERRIDE
+#define ADERDG2D_CPB_OVERRIDE 0
+#endif
+
 template <int N, class TP>
 struct Pred2Geo {
   static constexpr int n = N + 1, L = n * n, M = 4;
-  static constexpr int CELL = n * n * n * M;           // tile elements of one cell
-  static constexpr bool kVbAlias = sizeof(TP) == 8;    // volume buffer reuses R in FP64
-  static constexpr int kPerCell = 2 * CELL * (int)sizeof(TP) + (kVbAlias ? 0 : 2 * L * M * 8);
-  static constexpr int kBudget = 159 * 1024;
-  static constexpr int CPB0 = 256 / L;
-  static constexpr int CPB = CPB0 * kPerCell <= kBudget ? CPB0 : kBudget / kPerCell;
+  static constexpr Layout2 lay = kLayout2[N + 1];
+  static constexpr int V = 16 / (int)sizeof(TP);       // elements per unit
+  static constexpr int P = M / V;                      // planes (2 in FP64, 1 in FP32)
+  static constexpr int CPB = ADERDG2D_CPB_OVERRIDE > 0 ? ADERDG2D_CPB_OVERRIDE : lay.cpb;
+  static constexpr int CELLE = lay.CELL * V;            // elements of one cell in one plane
+  static constexpr int PLANE = CPB * CELLE;            // elements between the planes
+  static constexpr int BUF = P * PLANE;                // elements of one tile buffer
+  static constexpr bool kVbAlias = BUF * (int)sizeof(TP) >= CPB * 2 * L * M * 8;
   static constexpr int NT = ((CPB * L + 63) / 64) * 64;
-  static_assert(CPB >= 1, "one cell tile must fit in LDS");
+  static_assert(2 * BUF * (int)sizeof(TP) + (kVbAlias ? 0 : CPB * 2 * L * M * 8) <= 159 * 1024,
+                "tiles must fit in LDS");
+  __device__ static constexpr int at(int a, int i, int j) { return (a * lay.SA + i * n + j) * V; }
 };
+
+// The four values of a node: one 16-byte LDS access per plane.
+template <int PLANE>
+__device__ __forceinline__ void ld4(const double* p, double* v) {
+  const double2 x = *reinterpret_cast<const double2*>(p);
+  const double2 y = *reinterpret_cast<const double2*>(p + PLANE);
+  v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+}
+template <int PLANE>
+__device__ __forceinline__ void ld4(const float* p, float* v) {
+  const float4 x = *reinterpret_cast<const float4*>(p);
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+template <int PLANE>
+__device__ __forceinline__ void st4(double* p, const double* v) {
+  *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+  *reinterpret_cast<double2*>(p + PLANE) = make_double2(v[2], v[3]);
+}
+template <int PLANE>
+__device__ __forceinline__ void st4(float* p, const float* v) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
 
 template <int N, class TP>
 __global__ void __launch_bounds__((Pred2Geo<N, TP>::NT))
 pred2d_kernel(Args2D A) {
   using G = Pred2Geo<N, TP>;
-  constexpr int n = G::n, L = G::L, M = G::M, CPB = G::CPB, CELL = G::CELL;
+  constexpr int n = G::n, L = G::L, M = G::M, CPB = G::CPB, PL = G::PLANE;
   using Bits = decltype(ord_bits(TP(0)));
 
-  __shared__ TP Qs[CPB * CELL];
-  __shared__ TP Rs[CPB * CELL];
+  __shared__ __align__(16) TP Qs[G::BUF];
+  __shared__ __align__(16) TP Rs[G::BUF];
   __shared__ double Vsep[G::kVbAlias ? 1 : CPB * 2 * L * M];
   __shared__ Bits red[2][CPB][2];
   __shared__ double bcast[2];
@@ -181,6 +248,11 @@ pred2d_kernel(Args2D A) {
   const int tid = threadIdx.x;
   const int cl = tid / L, line = tid - cl * L;
   const int hi = line / n, lo = line - hi * n;
+  // line indices of the three roles (lane order per the layout table)
+  const int ti = G::lay.oT ? lo : hi, tj = G::lay.oT ? hi : lo;      // T: node (i, j)
+  const int xa = G::lay.oX ? lo : hi, xj = G::lay.oX ? hi : lo;      // X: line (a, j)
+  const int ya = G::lay.oY ? lo : hi, yi = G::lay.oY ? hi : lo;      // Y: line (a, i)
+  const int node = ti * n + tj;
   const int64_t ncells = A.cx * A.cy;
   const int64_t cell = (int64_t)blockIdx.x * CPB + cl;
   const bool mine = cl < CPB && cell < ncells;
@@ -194,36 +266,30 @@ pred2d_kernel(Args2D A) {
   if (tid < 4 * CPB) (&red[0][0][0])[tid] = 0;
   if (tid == 0) swsum = 0u;
 
-  // T role: node (i, j) = (hi, lo); the initial guess is u on every time level
+  // The tile lives in LDS only.  T role: node (ti, tj); the initial guess is
+  // u on every time level.
+  TP* const Qc = Qs + (mine ? cl : 0) * G::CELLE;
+  TP* const Rc = Rs + (mine ? cl : 0) * G::CELLE;
   double u0[M];
-  TP q[n][M];
 #pragma unroll
-  for (int r = 0; r < M; ++r) u0[r] = mine ? A.u[(cell * L + line) * M + r] : 1.0;
+  for (int r = 0; r < M; ++r) u0[r] = mine ? A.u[(cell * L + node) * M + r] : 1.0;
+  if (mine) {
+    TP v[M];
 #pragma unroll
-  for (int a = 0; a < n; ++a)
+    for (int r = 0; r < M; ++r) v[r] = TP(u0[r]);
 #pragma unroll
-    for (int r = 0; r < M; ++r) q[a][r] = TP(u0[r]);
-
-  TP* const Qc = Qs + (mine ? cl : 0) * CELL;
-  TP* const Rc = Rs + (mine ? cl : 0) * CELL;
+    for (int a = 0; a < n; ++a) st4<PL>(Qc + G::at(a, ti, tj), v);
+  }
   const TP tol = TP(A.tol);
   bool active = mine, failed = false;
   int sweeps = 0;
 
   for (int it = 0;; ++it) {
-    if (active && sweeps >= A.max_iter) {
-      active = false;
-      failed = true;
-    }
-    if (active) {
-#pragma unroll
-      for (int a = 0; a < n; ++a)
-#pragma unroll
-        for (int r = 0; r < M; ++r) Qc[((a * n + hi) * n + lo) * M + r] = q[a][r];
-    }
+    // the tile of every active cell (initial guess or the last T role's
+    // update) is visible past this barrier
     if (!__syncthreads_or(active)) break;
     if (active) {
-      // X role, line (a, j) = (hi, lo): R[a][i][j] = sum_i' k~[i][i'] (dt/dx) Fx(q[a][i'][j])
+      // X role, line (a, j) = (xa, xj): R[a][i][j] = sum_i' k~[i][i'] (dt/dx) Fx(q[a][i'][j])
       TP acc[n][M];
 #pragma unroll
       for (int i = 0; i < n; ++i)
@@ -232,24 +298,22 @@ pred2d_kernel(Args2D A) {
 #pragma unroll
       for (int ip = 0; ip < n; ++ip) {
         TP qq[M], f[M];
-#pragma unroll
-        for (int r = 0; r < M; ++r) qq[r] = Qc[((hi * n + ip) * n + lo) * M + r];
+        ld4<PL>(Qc + G::at(xa, ip, xj), qq);
         Euler2::flux_x(qq, f, gm1);
 #pragma unroll
         for (int r = 0; r < M; ++r) f[r] *= cxs;
+        const cptr<TP> K = launder(ktil_base<N, TP>() + ip);        // column ip of k~
 #pragma unroll
         for (int i = 0; i < n; ++i)
 #pragma unroll
-          for (int r = 0; r < M; ++r) acc[i][r] = fma(ktil<N, TP>(i, ip), f[r], acc[i][r]);
+          for (int r = 0; r < M; ++r) acc[i][r] = fma(K[i * kDevMaxn], f[r], acc[i][r]);
       }
 #pragma unroll
-      for (int i = 0; i < n; ++i)
-#pragma unroll
-        for (int r = 0; r < M; ++r) Rc[((hi * n + i) * n + lo) * M + r] = acc[i][r];
+      for (int i = 0; i < n; ++i) st4<PL>(Rc + G::at(xa, i, xj), acc[i]);
     }
     __syncthreads();
     if (active) {
-      // Y role, line (a, i) = (hi, lo): R[a][i][j] += sum_j' k~[j][j'] (dt/dy) Fy(q[a][i][j'])
+      // Y role, line (a, i) = (ya, yi): R[a][i][j] += sum_j' k~[j][j'] (dt/dy) Fy(q[a][i][j'])
       TP acc[n][M];
 #pragma unroll
       for (int j = 0; j < n; ++j)
@@ -258,98 +322,125 @@ pred2d_kernel(Args2D A) {
 #pragma unroll
       for (int jp = 0; jp < n; ++jp) {
         TP qq[M], f[M];
-#pragma unroll
-        for (int r = 0; r < M; ++r) qq[r] = Qc[((hi * n + lo) * n + jp) * M + r];
+        ld4<PL>(Qc + G::at(ya, yi, jp), qq);
         Euler2::flux_y(qq, f, gm1);
 #pragma unroll
         for (int r = 0; r < M; ++r) f[r] *= cys;
+        const cptr<TP> K = launder(ktil_base<N, TP>() + jp);        // column jp of k~
 #pragma unroll
         for (int j = 0; j < n; ++j)
 #pragma unroll
-          for (int r = 0; r < M; ++r) acc[j][r] = fma(ktil<N, TP>(j, jp), f[r], acc[j][r]);
+          for (int r = 0; r < M; ++r) acc[j][r] = fma(K[j * kDevMaxn], f[r], acc[j][r]);
       }
 #pragma unroll
-      for (int j = 0; j < n; ++j)
+      for (int j = 0; j < n; ++j) {
+        TP v[M];
+        ld4<PL>(Rc + G::at(ya, yi, j), v);
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-          TP* p = &Rc[((hi * n + lo) * n + j) * M + r];
-          *p = *p + acc[j][r];
-        }
+        for (int r = 0; r < M; ++r) v[r] += acc[j][r];
+        st4<PL>(Rc + G::at(ya, yi, j), v);
+      }
     }
     __syncthreads();
+    TP e_ = TP(0), qm_ = TP(0);
     if (active) {
-      // T role: q_new[a] = u - sum_b kappa~[a][b] R[b][i][j]
+      // T role: q_new[a] = u - sum_b kappa~[a][b] R[b][i][j], written over the
+      // thread's own time line of the tile (no other thread reads it now)
       TP rr[n][M];
 #pragma unroll
-      for (int b = 0; b < n; ++b)
-#pragma unroll
-        for (int r = 0; r < M; ++r) rr[b][r] = Rc[((b * n + hi) * n + lo) * M + r];
+      for (int b = 0; b < n; ++b) ld4<PL>(Rc + G::at(b, ti, tj), rr[b]);
       TP e = TP(0), qm = TP(0);
 #pragma unroll
-      for (int a = 0; a < n; ++a)
+      for (int a = 0; a < n; ++a) {
+        TP qo[M], qn[M];
+        ld4<PL>(Qc + G::at(a, ti, tj), qo);
+        const cptr<TP> Kp = launder(kappa_base<N, TP>() + a * kDevMaxn);   // row a of kappa~
 #pragma unroll
         for (int r = 0; r < M; ++r) {
           TP acc = TP(0);
 #pragma unroll
-          for (int b = 0; b < n; ++b) acc = fma(kappa<N, TP>(a, b), rr[b][r], acc);
-          const TP qn = TP(u0[r]) - acc;
-          e = max_abs(e, qn - q[a][r]);
-          qm = max_abs(qm, qn);
-          q[a][r] = qn;
+          for (int b = 0; b < n; ++b) acc = fma(Kp[b], rr[b][r], acc);
+          qn[r] = TP(u0[r]) - acc;
+          e = max_abs(e, qn[r] - qo[r]);
+          qm = max_abs(qm, qn[r]);
         }
-      atomicMax(&red[it & 1][cl][0], ord_bits(e));
-      atomicMax(&red[it & 1][cl][1], ord_bits(qm));
+        st4<PL>(Qc + G::at(a, ti, tj), qn);
+      }
+      e_ = e;
+      qm_ = qm;
       ++sweeps;
+    }
+    {
+      // maxima along the thread's row of n lanes (same cell; rows start at
+      // multiples of n), within the wavefront, then one LDS
+      // atomic per row segment.  Every lane takes part in the shuffles
+      // (inactive lanes contribute zeros).
+      const int lane = tid & 63;
+#pragma unroll
+      for (int off = 1; off < n; off <<= 1) {
+        const TP e2 = __shfl_down(e_, off, 64), q2 = __shfl_down(qm_, off, 64);
+        if (lo + off < n && lane + off < 64) {
+          e_ = dmax(e_, e2);
+          qm_ = dmax(qm_, q2);
+        }
+      }
+      if (active && (lo == 0 || lane == 0)) {
+        atomicMax(&red[it & 1][cl][0], ord_bits(e_));
+        atomicMax(&red[it & 1][cl][1], ord_bits(qm_));
+      }
     }
     // the other parity's maxima were read before this sweep's first barrier
     if (tid < 2 * CPB) (&red[(it + 1) & 1][0][0])[tid] = 0;
     __syncthreads();
     if (active) {
       const TP E = from_bits(red[it & 1][cl][0]), Qm = from_bits(red[it & 1][cl][1]);
-      if (E <= tol * dmax(TP(1), Qm)) active = false;
+      if (E <= tol * dmax(TP(1), Qm)) {
+        active = false;
+      } else if (sweeps >= A.max_iter) {
+        active = false;
+        failed = true;
+      }
     }
   }
 
-  // ---- epilogue: final tile into LDS for the traces
+  // ---- epilogue (the loop's last barrier made every final tile visible)
   if (mine) {
-#pragma unroll
-    for (int a = 0; a < n; ++a)
-#pragma unroll
-      for (int r = 0; r < M; ++r) Qc[((a * n + hi) * n + lo) * M + r] = q[a][r];
-  }
-  __syncthreads();
-  if (mine) {
-    // x faces from the X role (a, j) = (hi, lo); y faces from the Y role (a, i) = (hi, lo)
+    // x faces from the X role's line (a, j), y faces from the Y role's line (a, i)
     double tw[M], te[M], ts[M], tn[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) tw[r] = te[r] = ts[r] = tn[r] = 0.0;
 #pragma unroll
     for (int p = 0; p < n; ++p) {
       const double p0 = c2_ops[N].psi0[p], p1 = c2_ops[N].psi1[p];
+      TP vx[M], vy[M];
+      ld4<PL>(Qc + G::at(xa, p, xj), vx);
+      ld4<PL>(Qc + G::at(ya, yi, p), vy);
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        const double vx = (double)Qc[((hi * n + p) * n + lo) * M + r];
-        const double vy = (double)Qc[((hi * n + lo) * n + p) * M + r];
-        tw[r] = fma(p0, vx, tw[r]);
-        te[r] = fma(p1, vx, te[r]);
-        ts[r] = fma(p0, vy, ts[r]);
-        tn[r] = fma(p1, vy, tn[r]);
+        tw[r] = fma(p0, (double)vx[r], tw[r]);
+        te[r] = fma(p1, (double)vx[r], te[r]);
+        ts[r] = fma(p0, (double)vy[r], ts[r]);
+        tn[r] = fma(p1, (double)vy[r], tn[r]);
       }
     }
     double* trc = A.tr + cell * (4 * L * M);
+    const int lx = xa * n + xj, ly = ya * n + yi;
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      trc[(0 * L + line) * M + r] = tw[r];
-      trc[(1 * L + line) * M + r] = te[r];
-      trc[(2 * L + line) * M + r] = ts[r];
-      trc[(3 * L + line) * M + r] = tn[r];
+      trc[(0 * L + lx) * M + r] = tw[r];
+      trc[(1 * L + lx) * M + r] = te[r];
+      trc[(2 * L + ly) * M + r] = ts[r];
+      trc[(3 * L + ly) * M + r] = tn[r];
     }
     if (A.mode == k2dPredict) {
       TP* qo = reinterpret_cast<TP*>(A.q_out) + cell * (n * L * M);
 #pragma unroll
-      for (int a = 0; a < n; ++a)
+      for (int a = 0; a < n; ++a) {
+        TP v[M];
+        ld4<PL>(Qc + G::at(a, ti, tj), v);
 #pragma unroll
-        for (int r = 0; r < M; ++r) qo[(a * L + line) * M + r] = q[a][r];
+        for (int r = 0; r < M; ++r) qo[(a * L + node) * M + r] = v[r];
+      }
       if (A.iters && line == 0) A.iters[cell] = sweeps;
     }
   }
@@ -363,8 +454,10 @@ pred2d_kernel(Args2D A) {
 #pragma unroll
     for (int a = 0; a < n; ++a) {
       double qd[M], f[M];
+      TP v[M];
+      ld4<PL>(Qc + G::at(a, ti, tj), v);
 #pragma unroll
-      for (int r = 0; r < M; ++r) qd[r] = (double)q[a][r];
+      for (int r = 0; r < M; ++r) qd[r] = (double)v[r];
       const double wa = c2_ops[N].w[a];
       Euler2::flux_x(qd, f, A.gamma - 1.0);
 #pragma unroll
@@ -376,8 +469,8 @@ pred2d_kernel(Args2D A) {
     // in FP64, Vb aliases R, last read before the loop's final barriers
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      Vc[line * M + r] = fxb[r];
-      Vc[(L + line) * M + r] = fyb[r];
+      Vc[node * M + r] = fxb[r];
+      Vc[(L + node) * M + r] = fyb[r];
     }
   }
   __syncthreads();
@@ -387,17 +480,13 @@ pred2d_kernel(Args2D A) {
     for (int r = 0; r < M; ++r) vol[r] = 0.0;
 #pragma unroll
     for (int l = 0; l < n; ++l) {
-      const double dx_ = c2_ops[N].Dw[hi][l], dy_ = c2_ops[N].Dw[lo][l];
+      const double dx_ = c2_ops[N].Dw[ti][l], dy_ = c2_ops[N].Dw[tj][l];
 #pragma unroll
-      for (int r = 0; r < M; ++r) {
-        vol[r] = fma(dx_, Vc[(l * n + lo) * M + r], vol[r]);
-      }
+      for (int r = 0; r < M; ++r) vol[r] = fma(dx_, Vc[(l * n + tj) * M + r], vol[r]);
 #pragma unroll
-      for (int r = 0; r < M; ++r) {
-        vol[r] = fma(dy_, Vc[(L + hi * n + l) * M + r], vol[r]);
-      }
+      for (int r = 0; r < M; ++r) vol[r] = fma(dy_, Vc[(L + ti * n + l) * M + r], vol[r]);
     }
-    double* pc = A.part + (cell * L + line) * M;
+    double* pc = A.part + (cell * L + node) * M;
 #pragma unroll
     for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
   }
