@@ -405,6 +405,152 @@ def roofline_entry(N, C, M, steps, seconds, sweeps, precision):
             "sweeps_per_cell": round(sweeps / (C * steps), 3)}
 
 
+FLUX2_FLOPS = 14          # one 2-D Euler flux (x or y) at a node, the reciprocal counted as one
+RIEMANN2_FLOPS = 70       # one 2-D Rusanov flux: two fluxes, two signal speeds, the combination
+
+
+def dg2d_flops_per_cell(N, sweeps_per_cell, M=4):
+    """Algorithmic flops of one 2-D step per cell (Kronecker-factored contractions):
+    predictor per sweep  2n^3 (F + M) (fluxes, scaled) + 3 * 2n^4 M (k~ along x, k~ along y,
+                         kappa~ along time) + 4 n^3 M (combine, update, convergence test)
+    epilogue             8 n^3 M (face traces) + 2n^3 F + 6 n^3 M + 4 n^3 M + n^2 M (volume terms)
+    corrector            2 n^2 (R + 3M) (each face once) + 6 n^2 M + 10 n^2 (update, admissibility)
+                         + 2 Ns n^2 M + 2 Ns^2 n M + 12 Ns^2 (subcell signal speeds, Ns = 2N+1)
+    Returns (predictor sweeps, the rest)."""
+    n, Ns = N + 1, 2 * N + 1
+    sweep = 2 * n ** 3 * (FLUX2_FLOPS + M) + 6 * n ** 4 * M + 4 * n ** 3 * M
+    epi = 8 * n ** 3 * M + 2 * n ** 3 * FLUX2_FLOPS + 10 * n ** 3 * M + n * n * M
+    corr = (2 * n * n * (RIEMANN2_FLOPS + 3 * M) + 6 * n * n * M + 10 * n * n
+            + 2 * Ns * n * n * M + 2 * Ns * Ns * n * M + 12 * Ns * Ns)
+    return sweeps_per_cell * sweep, epi + corr
+
+
+class DG2Run:
+    """The 2-D sine wave of Sec. 2.1 (Euler gas, rho = 1 + 0.5 sin(2 pi (x + y)),
+    velocity (1, 1), p = 1, gamma = 1.4, unit square, periodic) on C x C cells."""
+
+    def __init__(self, N, C, precision, cfl=None, kx=1, ky=1):
+        import torch
+        from paper_2409_12483_amd import abi
+        from paper_2409_12483_amd import workloads as W
+        self.abi, self.torch = abi, torch
+        dev = torch.device("cuda:0")
+        self.N, self.C = N, C
+        self.cfl = cfl if cfl is not None else (0.4 if N <= 7 else 0.3)
+        self.u = torch.tensor(W.euler2d_sine_wave(C, C, N, kx=kx, ky=ky), device=dev)
+        self.t = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.te = torch.full((1,), 1.0e300, dtype=torch.float64, device=dev)
+        self.dt = torch.zeros_like(self.t)
+        self.st = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.stream = torch.cuda.current_stream()
+        self.h = abi.aderdg2d_init(abi.config2d(N, C, C, cfl=self.cfl, precision=precision),
+                                   stream=self.stream.cuda_stream)
+
+    def steps(self, k):
+        self.abi.aderdg2d_step(self.h, self.u, self.t, self.te, self.dt, self.st, k)
+
+    def timed(self, k):
+        torch = self.torch
+        _sync()
+        s0 = self.abi.aderdg2d_sweep_count(self.h)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        self.steps(k)
+        e1.record(self.stream)
+        _sync()
+        return e0.elapsed_time(e1) * 1e-3, self.abi.aderdg2d_sweep_count(self.h) - s0
+
+    def close(self):
+        self.abi.aderdg2d_free(self.h)
+
+
+def dg2d_entry(N, C, precision, steps, warmup):
+    from paper_2409_12483_amd import abi
+    r = DG2Run(N, C, precision)
+    r.steps(warmup)
+    secs, sweeps = r.timed(steps)
+    status = int(r.st.item())
+    r.close()
+    cells = C * C
+    spc = sweeps / (cells * steps)
+    pred, rest = dg2d_flops_per_cell(N, spc)
+    total = (pred + rest) * cells * steps
+    if precision == abi.FP64:
+        peak = PEAK_FP64_VALU
+        t_roof = total / (PEAK_FP64_VALU * 1e12)
+    else:
+        t_roof = pred * cells * steps / (PEAK_FP32_VALU * 1e12) + rest * cells * steps / (PEAK_FP64_VALU * 1e12)
+        peak = total / t_roof * 1e-12
+    n = N + 1
+    return {"N": N, "cells": f"{C}x{C}", "cfl": 0.4 if N <= 7 else 0.3, "status": status,
+            "value": round(steps * cells * n * n * 4 / secs, 1), "unit": "DoF-updates/s",
+            "ms_per_step": round(secs / steps * 1e3, 5), "sweeps_per_cell": round(spc, 3),
+            "roofline": {"bound": "alu", "achieved": round(total / secs * 1e-12, 3), "peak": round(peak, 2),
+                         "unit": "TFLOP/s", "frac": round(t_roof / secs, 4),
+                         "flops_per_step": int(round(total / steps)),
+                         "kernels": "predictor + corrector launches of each step (HIP events around whole steps)"}}
+
+
+def dg2d_time_to_solution(N, C, precision=0, chunk=128):
+    """The paper's 2-D timing problem (Sec. 3, Table 10: the sine wave on C^2 cells,
+    t_final = 1): wall time of the whole run on the GPU, host loop included.
+    eager: aderdg2d_step calls sized to reach t_final; graph: replays of a HIP
+    graph holding one call of `chunk` steps (steps past t_final do nothing)."""
+    import torch
+    r = DG2Run(N, C, precision)
+    r.te.fill_(1.0)
+    _sync()
+    t0 = time.perf_counter()
+    r.steps(50)
+    _sync()
+    t_now, dt = float(r.t.item()), float(r.dt.item())
+    while t_now < 1.0:
+        r.steps(int(np.ceil((1.0 - t_now) / dt)) + 1)
+        _sync()
+        t_now = float(r.t.item())
+    eager = time.perf_counter() - t0
+    u_eager = r.u.clone()
+    st = int(r.st.item())
+    r.close()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g = DG2Run(N, C, precision)
+        g.te.fill_(1.0)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            g.steps(chunk)
+    _sync()
+    t0 = time.perf_counter()
+    replays = 0
+    while True:
+        graph.replay()
+        replays += 1
+        side.synchronize()
+        if float(g.t.item()) >= 1.0:
+            break
+    graphed = time.perf_counter() - t0
+    same = bool(torch.equal(g.u, u_eager))
+    st = min(st, int(g.st.item()))
+    g.close()
+    return {"N": N, "cells": f"{C}^2", "gpu_wall_s": round(eager, 5), "gpu_wall_s_graph": round(graphed, 5),
+            "graph_replays": replays, "graph_equals_eager": same, "steps_approx": int(round(1.0 / dt)),
+            "status": st}
+
+
+def dg2d_section(quick=False):
+    from paper_2409_12483_amd import abi
+    out = {"workload": "ADER-DG 2D Euler gamma=1.4, sine wave rho=1+0.5 sin(2 pi (x+y)), velocity (1,1), "
+                       "p=1, unit square, periodic, 512x512 cells, CFL 0.4, Rusanov"}
+    out["fp64"] = dg2d_entry(5, 512, abi.FP64, 20, 5)
+    out["fp32_predictor"] = dg2d_entry(5, 512, abi.FP32_PREDICTOR, 20, 5)
+    if quick:
+        return out
+    out["per_degree_fp64"] = [dg2d_entry(N, 512 if N <= 6 else 256, abi.FP64, 10, 3) for N in range(1, 10)]
+    out["paper_table10_time_to_solution"] = [dg2d_time_to_solution(N, C) for N in range(1, 10)
+                                             for C in (4, 8, 12, 16)]
+    return out
+
+
 def cpu_baseline(N, target_s=12.0):
     """The oracle, as is, on a bounded sample of the same workload."""
     from oracle import basis, dg
@@ -437,6 +583,8 @@ def main():
                     help="also serve the full 2000-request trace at 200 req/s")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 512 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--dg2d-only", action="store_true",
+                    help="only the 2-D workload (512x512 cells, N=5; for profiling the 2-D kernels)")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -456,6 +604,10 @@ def main():
         y.copy_(x)
         _sync()
         del x, y
+
+    if a.dg2d_only:
+        print(json.dumps({"dg2d_euler_sine_512x512": dg2d_section(quick=True)}))
+        return
 
     run = DGRun(N, C, abi.FP64)
     run.steps(Wm)
@@ -535,6 +687,7 @@ def main():
         out["c5_serving"] = [c5_serving(rate, 150) for rate in (25.0, 50.0, 100.0)]
         out["c5_serving_fp32_predictor"] = [c5_serving(rate, 150, precision=abi.FP32_PREDICTOR)
                                             for rate in (50.0, 100.0)]
+        out["dg2d_euler_sine_512x512"] = dg2d_section()
     if a.c5_full:
         out["c5_serving_full"] = c5_serving(200.0, 2000)
     if not a.no_cpu_baseline:

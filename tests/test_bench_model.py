@@ -34,3 +34,10 @@ def test_fv_flop_model_grows_with_the_measured_work():
     # the kappa~ application (2 n^3 M = 750 flops at n = 5) dominates its term
     d = bench.fv_flops_per_cell(4, 3, 1.0, 2.0) - base
     assert 750 < d < 2000
+
+
+def test_dg2d_flop_model_values():
+    """Regression values of the 2-D flop model at N = 5 (one sweep per cell)."""
+    pred, rest = bench.dg2d_flops_per_cell(5, 1.0)
+    assert pred == 2 * 216 * 18 + 6 * 1296 * 4 + 4 * 216 * 4 == 42336
+    assert rest == 21744 + 17556
