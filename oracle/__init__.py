@@ -14,7 +14,7 @@ or table it follows.  The paper is written for 3-D Cartesian meshes; here
 every formula is specialised to one space dimension (the eta and zeta
 directions are dropped, the multi-index p=(p0,p1,p2,p3) becomes
 (p0,p1) = (time node, space node)).  ``dg2d`` keeps two space dimensions
-(the zeta direction dropped) for the 2-D Euler gas.
+(the zeta direction dropped) and ``dg3d`` all three, for the Euler gas.
 
 Array conventions (AoS, variable index fastest, as in Sec. 1.1 "Using the
 BLAS interface"):
@@ -27,4 +27,4 @@ Functions whose result has no pin beyond oracle-vs-GPU parity say
 Riemann solver and the WENO constants (the paper defines neither).
 """
 
-from . import basis, pde, predictor, dg, dg2d, weno, fv, brute, pade, norms  # noqa: F401
+from . import basis, pde, predictor, dg, dg2d, dg3d, weno, fv, brute, pade, norms  # noqa: F401

@@ -154,3 +154,34 @@ def euler2d_sine_wave(cx, cy, N, amp=0.5, kx=1, ky=1, velocity=(1.0, 1.0), press
 
 def euler2d_sine_wave_exact(x, y, t, amp=0.5, kx=1, ky=1, velocity=(1.0, 1.0)):
     return 1.0 + amp * np.sin(2.0 * np.pi * (kx * (x - velocity[0] * t) + ky * (y - velocity[1] * t)))
+
+
+def euler3d_sine_wave(cx, cy, cz, N, amp=0.5, k=(1, 1, 1), velocity=(1.0, 1.0, 1.0), pressure=1.0,
+                      gamma=1.4, noise=0.0, seed=0, extent=(1.0, 1.0, 1.0)):
+    """Nodal conserved state u[Cx, Cy, Cz, N+1, N+1, N+1, 5] of the 3-D sine wave.
+
+    rho = 1 + amp sin(2 pi (kx x + ky y + kz z)) (+ seeded uniform noise on the
+    nodal rho), velocity (u, v, w), pressure p, U = (rho, rho u, rho v, rho w, E).
+    The paper's 3-D problem (Sec. 2.1) is amp = 0.5, k = (1, 1, 1), velocity
+    (1, 1, 1), p = 1, gamma = 1.4 on the unit cube.  Node order [x][y][z].
+    """
+    n = N + 1
+    xs = cell_points(cx, n, 0.0, extent[0])
+    ys = cell_points(cy, n, 0.0, extent[1])
+    zs = cell_points(cz, n, 0.0, extent[2])
+    X = xs[:, None, None, :, None, None]
+    Y = ys[None, :, None, None, :, None]
+    Z = zs[None, None, :, None, None, :]
+    rho = 1.0 + amp * np.sin(2.0 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z))
+    rho = np.broadcast_to(rho, (cx, cy, cz, n, n, n)).copy()
+    if noise:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        rho = rho + rng.uniform(-noise, noise, size=rho.shape)
+    vel = [np.full_like(rho, v) for v in velocity]
+    E = pressure / (gamma - 1.0) + 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2)
+    return np.stack([rho, rho * vel[0], rho * vel[1], rho * vel[2], E], axis=-1)
+
+
+def euler3d_sine_wave_exact(x, y, z, t, amp=0.5, k=(1, 1, 1), velocity=(1.0, 1.0, 1.0)):
+    return 1.0 + amp * np.sin(2.0 * np.pi * (k[0] * (x - velocity[0] * t) + k[1] * (y - velocity[1] * t)
+                                             + k[2] * (z - velocity[2] * t)))
