@@ -1,5 +1,5 @@
-"""Thin ctypes binding of include/aderdg.h and include/aderdg2d.h (argument
-marshalling only).
+"""Thin ctypes binding of include/aderdg.h, include/aderdg2d.h and
+include/aderdg3d.h (argument marshalling only).
 
 Every entry point keeps its C name.  Buffers may be torch tensors on the HIP
 device (their data_ptr() is passed) or raw integer device addresses.  All
@@ -31,6 +31,8 @@ EXPORTS = ["aderdg_init", "aderdg_predict", "aderdg_correct", "aderdg_step", "ad
            "aderdg_operators", "aderdg_last_error"]
 EXPORTS_2D = ["aderdg2d_init", "aderdg2d_predict", "aderdg2d_step", "aderdg2d_sweep_count",
               "aderdg2d_free"]
+EXPORTS_3D = ["aderdg3d_init", "aderdg3d_predict", "aderdg3d_step", "aderdg3d_sweep_count",
+              "aderdg3d_free"]
 
 
 class PdeDesc(ctypes.Structure):
@@ -51,6 +53,16 @@ class Config2D(ctypes.Structure):
                 ("cells_x", ctypes.c_int64), ("cells_y", ctypes.c_int64),
                 ("x0", ctypes.c_double), ("x1", ctypes.c_double),
                 ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_double),
+                ("picard_tol", ctypes.c_double), ("picard_max_iter", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class Config3D(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("cells_x", ctypes.c_int64), ("cells_y", ctypes.c_int64), ("cells_z", ctypes.c_int64),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double), ("z0", ctypes.c_double), ("z1", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_double),
                 ("picard_tol", ctypes.c_double), ("picard_max_iter", ctypes.c_int32),
                 ("pad", ctypes.c_int32)]
@@ -92,7 +104,12 @@ def load(path=None):
     lib.aderdg2d_step.argtypes = [vp, vp, vp, vp, vp, vp, i32]
     lib.aderdg2d_sweep_count.argtypes = [vp, ctypes.POINTER(i64)]
     lib.aderdg2d_free.argtypes = [vp]
-    for name in EXPORTS[:-1] + EXPORTS_2D:
+    lib.aderdg3d_init.argtypes = [ctypes.POINTER(Config3D), vp, ctypes.POINTER(vp)]
+    lib.aderdg3d_predict.argtypes = [vp, vp, dbl, dbl, vp, vp]
+    lib.aderdg3d_step.argtypes = [vp, vp, vp, vp, vp, vp, i32]
+    lib.aderdg3d_sweep_count.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.aderdg3d_free.argtypes = [vp]
+    for name in EXPORTS[:-1] + EXPORTS_2D + EXPORTS_3D:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -238,3 +255,38 @@ def aderdg2d_sweep_count(h):
 
 def aderdg2d_free(h):
     return _check(load().aderdg2d_free(h))
+
+
+# ------------------------------------------------------------------ 3-D ----
+def config3d(N, cells, extent=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.4, fixed_dt=0.0, precision=FP64,
+             picard_tol=0.0, picard_max_iter=0):
+    """cells: (cx, cy, cz); extent: (Lx, Ly, Lz) of the domain [0, Lx] x [0, Ly] x [0, Lz]."""
+    cx, cy, cz = cells
+    return Config3D(N, precision, cx, cy, cz, 0.0, extent[0], 0.0, extent[1], 0.0, extent[2],
+                    gamma, cfl, fixed_dt, picard_tol, picard_max_iter, 0)
+
+
+def aderdg3d_init(cfg, stream=None):
+    lib = load()
+    h = ctypes.c_void_p()
+    st = _current_stream() if stream is None else stream
+    _check(lib.aderdg3d_init(ctypes.byref(cfg), st, ctypes.byref(h)))
+    return h.value
+
+
+def aderdg3d_predict(h, u, t, dt, q_out, iters_out=None):
+    return _check(load().aderdg3d_predict(h, _ptr(u), t, dt, _ptr(q_out), _ptr(iters_out)))
+
+
+def aderdg3d_step(h, u, t, t_end, dt, status, nsteps):
+    return _check(load().aderdg3d_step(h, _ptr(u), _ptr(t), _ptr(t_end), _ptr(dt), _ptr(status), nsteps))
+
+
+def aderdg3d_sweep_count(h):
+    out = ctypes.c_int64()
+    _check(load().aderdg3d_sweep_count(h, ctypes.byref(out)))
+    return out.value
+
+
+def aderdg3d_free(h):
+    return _check(load().aderdg3d_free(h))

@@ -12,6 +12,7 @@
 // after a stream synchronisation).
 #include "../../include/aderdg.h"
 #include "../../include/aderdg2d.h"
+#include "../../include/aderdg3d.h"
 
 #include <hip/hip_runtime.h>
 
@@ -27,6 +28,7 @@
 
 #include "launch.hpp"
 #include "launch2d.hpp"
+#include "launch3d.hpp"
 #include "operators.hpp"
 
 using namespace aderdg;
@@ -101,6 +103,8 @@ int ensure_tables(int device) {
   if (e != hipSuccess) return fail_hip(e, "upload of operator tables");
   e = upload_tables_2d(ops, opsf);
   if (e != hipSuccess) return fail_hip(e, "upload of 2-D operator tables");
+  e = upload_tables_3d(ops, opsf);
+  if (e != hipSuccess) return fail_hip(e, "upload of 3-D operator tables");
   g_tables_devices.insert(device);
   return ADERDG_OK;
 }
@@ -638,6 +642,153 @@ int aderdg2d_free(aderdg2d_handle* h) {
   if (!h) return ADERDG_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
   release2d(h);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "stream synchronisation");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ 3-D ----
+struct aderdg3d_handle {
+  hipStream_t stream = nullptr;
+  aderdg3d_config cfg{};
+  int64_t cells = 0;
+  double* part = nullptr;
+  double* tr = nullptr;
+  Clock3D* clk = nullptr;
+};
+
+namespace {
+
+void release3d(aderdg3d_handle* h) {
+  if (h->part) hipFree(h->part);
+  if (h->tr) hipFree(h->tr);
+  if (h->clk) hipFree(h->clk);
+  delete h;
+}
+
+Args3D args3d(const aderdg3d_handle* h) {
+  const aderdg3d_config& c = h->cfg;
+  Args3D A{};
+  A.c[0] = c.cells_x;
+  A.c[1] = c.cells_y;
+  A.c[2] = c.cells_z;
+  A.h[0] = (c.x1 - c.x0) / (double)c.cells_x;
+  A.h[1] = (c.y1 - c.y0) / (double)c.cells_y;
+  A.h[2] = (c.z1 - c.z0) / (double)c.cells_z;
+  A.cfl = c.cfl;
+  A.fixed_dt = c.fixed_dt;
+  A.tol = c.picard_tol;
+  A.gamma = c.gamma;
+  A.max_iter = c.picard_max_iter;
+  A.clk = h->clk;
+  A.part = h->part;
+  A.tr = h->tr;
+  return A;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aderdg3d_init(const aderdg3d_config* cfg, void* hip_stream, aderdg3d_handle** out) {
+  g_last_error.clear();
+  if (!cfg || !out) return fail(ADERDG_E_INVAL, "null argument");
+  aderdg3d_config c = *cfg;
+  if (c.precision != ADERDG_FP64 && c.precision != ADERDG_FP32_PREDICTOR)
+    return fail(ADERDG_E_INVAL, "unknown precision");
+  if (c.N < 1 || !supported_3d(c.N, c.precision))
+    return fail(ADERDG_E_INVAL, "N must be in 1..5 (FP64) or 1..6 (FP32 predictor)");
+  if (c.cells_x < 1 || c.cells_y < 1 || c.cells_z < 1 || c.cells_x > INT32_MAX / c.cells_y ||
+      c.cells_x * c.cells_y > INT32_MAX / c.cells_z)
+    return fail(ADERDG_E_INVAL, "cells_x, cells_y, cells_z must be >= 1 with a product below 2^31");
+  const double ext[3] = {c.x1 - c.x0, c.y1 - c.y0, c.z1 - c.z0};
+  for (double e : ext)
+    if (!(e > 0.0) || !std::isfinite(e)) return fail(ADERDG_E_INVAL, "empty or non-finite domain");
+  if (!(c.gamma > 1.0) || !std::isfinite(c.gamma)) return fail(ADERDG_E_INVAL, "gamma must be > 1");
+  if (!(c.cfl > 0.0 && c.cfl <= 1.0)) return fail(ADERDG_E_INVAL, "cfl must be in (0, 1]");
+  if (!(c.fixed_dt >= 0.0) || !std::isfinite(c.fixed_dt)) return fail(ADERDG_E_INVAL, "fixed_dt must be >= 0");
+  if (!std::isfinite(c.picard_tol)) return fail(ADERDG_E_INVAL, "picard_tol must be finite");
+  if (c.picard_tol <= 0.0) c.picard_tol = c.precision == ADERDG_FP64 ? 1e-14 : 1e-6;
+  if (c.picard_max_iter <= 0) c.picard_max_iter = 64;
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  int rc = ensure_tables(device);
+  if (rc) return rc;
+  aderdg3d_handle* h = new aderdg3d_handle();
+  h->stream = (hipStream_t)hip_stream;
+  h->cfg = c;
+  h->cells = c.cells_x * c.cells_y * c.cells_z;
+  const int64_t L = (int64_t)(c.N + 1) * (c.N + 1) * (c.N + 1);
+  e = hipMalloc((void**)&h->part, sizeof(double) * h->cells * L * 5);
+  if (e == hipSuccess) e = hipMalloc((void**)&h->tr, sizeof(double) * h->cells * 6 * L * 5);
+  if (e != hipSuccess) { release3d(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
+  e = hipMalloc((void**)&h->clk, sizeof(Clock3D));
+  if (e != hipSuccess) { release3d(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }
+  e = hipMemset(h->clk, 0, sizeof(Clock3D));
+  if (e != hipSuccess) { release3d(h); return fail_hip(e, "clock init"); }
+  *out = h;
+  return ADERDG_OK;
+}
+
+int aderdg3d_predict(aderdg3d_handle* h, const double* u, double t, double dt, void* q_out,
+                     int32_t* iters_out) {
+  g_last_error.clear();
+  if (!h || !u || !q_out) return fail(ADERDG_E_INVAL, "null argument");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return fail(ADERDG_E_INVAL, "dt must be > 0 and finite");
+  Args3D A = args3d(h);
+  A.mode = k3dPredict;
+  A.t = t;
+  A.dt = dt;
+  A.u = const_cast<double*>(u);
+  A.q_out = q_out;
+  A.iters = iters_out;
+  const int cpb = cells_per_block_3d(h->cfg.N, h->cfg.precision);
+  hipError_t e = launch_pred3d(h->cfg.N, h->cfg.precision, A, (h->cells + cpb - 1) / cpb, h->stream);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "predictor launch");
+}
+
+int aderdg3d_step(aderdg3d_handle* h, double* u, double* t, const double* t_end, double* dt,
+                  int32_t* status, int32_t nsteps) {
+  g_last_error.clear();
+  if (!h || !u || !t || !t_end || !dt || !status) return fail(ADERDG_E_INVAL, "null argument");
+  if (nsteps < 0) return fail(ADERDG_E_INVAL, "nsteps must be >= 0");
+  Args3D A = args3d(h);
+  A.mode = k3dStep;
+  A.u = u;
+  A.t_end = t_end;
+  const int N = h->cfg.N;
+  const int cpb = cells_per_block_3d(N, h->cfg.precision), cpb2 = cells_per_block_corr3d(N);
+  const int64_t blocks = (h->cells + cpb - 1) / cpb, blocks2 = (h->cells + cpb2 - 1) / cpb2;
+  hipError_t e = launch_clock3d_begin(h->clk, t, h->stream);
+  if (e == hipSuccess && h->cfg.fixed_dt <= 0.0) e = launch_lambda3d(N, A, blocks2, h->stream);
+  for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+    A.step = s;
+    e = launch_pred3d(N, h->cfg.precision, A, blocks, h->stream);
+    if (e == hipSuccess) e = launch_corr3d(N, A, blocks2, h->stream);
+  }
+  if (e == hipSuccess) e = launch_clock3d_end(h->clk, t, dt, status, nsteps & 1, h->stream);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "3-D step launch");
+}
+
+int aderdg3d_sweep_count(aderdg3d_handle* h, int64_t* sweeps_out) {
+  g_last_error.clear();
+  if (!h || !sweeps_out) return fail(ADERDG_E_INVAL, "null argument");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "stream synchronisation");
+  Slot slots[kSlots];
+  e = hipMemcpy(slots, h->clk->sweeps, sizeof(slots), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "sweep count read");
+  int64_t total = 0;
+  for (int i = 0; i < kSlots; ++i) total += (int64_t)slots[i].v;
+  *sweeps_out = total;
+  return ADERDG_OK;
+}
+
+int aderdg3d_free(aderdg3d_handle* h) {
+  if (!h) return ADERDG_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  release3d(h);
   return e == hipSuccess ? ADERDG_OK : fail_hip(e, "stream synchronisation");
 }
 

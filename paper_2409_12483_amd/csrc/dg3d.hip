@@ -1,0 +1,752 @@
+// 3-D ADER-DG step for the Euler gas on a uniform periodic Cartesian mesh
+// (gfx950, wave64): the LST-DG predictor of Sec. 1.1 with the Kronecker
+// factors kappa~ (x) k~ along x, y and z, and the corrector of Sec. 1.2,
+// eq. ader_dg_method_full, with the time step of Sec. 1.5 (d = 3, signal
+// speeds on the (2N+1)^3 subcell averages of Sec. 1.4).
+//
+// The design is that of the 2-D step with a fourth role.  Each cell is
+// served by n^3 threads; its space-time tile q[a][i][j][k][r] lives in LDS
+// (Q), with a second tile R for the contracted fluxes.  A thread's line index
+// (h2, h1, h0) reads as
+//   X role: the x line (a, j, k)      Y role: the y line (a, i, k)
+//   Z role: the z line (a, i, j)      T role: the time line of node (i, j, k)
+// One Picard sweep: X writes k~ fx into R, Y and Z add k~ fy and k~ fz, T
+// applies kappa~ from registers, writes q_new over its own time line of Q and
+// tests convergence.  Every contraction runs from registers over a line the
+// thread owns.  Two tiles of n^4 M values must fit in LDS: N <= 5 in FP64,
+// N <= 6 in the FP32-predictor mode.  The epilogue writes the six face traces
+// and u + volume terms in FP64; the corrector kernel evaluates the Rusanov
+// fluxes through the six faces, updates u in place and reduces the subcell
+// signal speeds for the next step.
+#include "launch3d.hpp"
+
+namespace aderdg {
+
+__constant__ DevOps c3_ops[kDevMaxn];
+__constant__ DevOpsF c3_opsf[kDevMaxn];
+
+// Sec. 2, eq. system_of_equations in three dimensions:
+// U = (rho, rho u, rho v, rho w, E), p = (gamma - 1) (E - rho |v|^2 / 2).
+struct Euler3 {
+  static constexpr int M = 5;
+  template <int D, class T> __device__ static void flux(const T* q, T* f, T gm1) {
+    const T ri = recip(q[0]);
+    const T u = q[1] * ri, v = q[2] * ri, w = q[3] * ri;
+    const T p = gm1 * (q[4] - T(0.5) * (q[1] * u + q[2] * v + q[3] * w));
+    const T m = q[1 + D];
+    const T vd = D == 0 ? u : (D == 1 ? v : w);
+    f[0] = m;
+    f[1] = m * u;
+    f[2] = m * v;
+    f[3] = m * w;
+    f[1 + D] += p;
+    f[4] = vd * (q[4] + p);
+  }
+  template <int D> __device__ static double speed(const double* q, double gamma) {
+    const double ri = recip(q[0]);
+    const double u = q[1] * ri, v = q[2] * ri, w = q[3] * ri;
+    const double p = (gamma - 1.0) * (q[4] - 0.5 * (q[1] * u + q[2] * v + q[3] * w));
+    return fabs(D == 0 ? u : (D == 1 ? v : w)) + sqrt(gamma * p * ri);
+  }
+  __device__ static void speeds(const double* q, double gamma, double* s) {
+    const double ri = recip(q[0]);
+    const double u = q[1] * ri, v = q[2] * ri, w = q[3] * ri;
+    const double p = (gamma - 1.0) * (q[4] - 0.5 * (q[1] * u + q[2] * v + q[3] * w));
+    const double c = sqrt(gamma * p * ri);
+    s[0] = fabs(u) + c;
+    s[1] = fabs(v) + c;
+    s[2] = fabs(w) + c;
+  }
+  __device__ static bool admissible(const double* q, double gamma) {
+    const double ri = recip(q[0]);
+    const double p = (gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) * ri);
+    return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) && isfinite(q[4]) &&
+           q[0] > 0.0 && p > 0.0;
+  }
+};
+
+template <int D>
+__device__ __forceinline__ void rusanov3(const double* qm, const double* qp, double* G, double gamma) {
+  double fm[5], fp[5];
+  Euler3::flux<D>(qm, fm, gamma - 1.0);
+  Euler3::flux<D>(qp, fp, gamma - 1.0);
+  const double s = fmax(Euler3::speed<D>(qm, gamma), Euler3::speed<D>(qp, gamma));
+#pragma unroll
+  for (int r = 0; r < 5; ++r) G[r] = 0.5 * (fm[r] + fp[r]) - 0.5 * s * (qp[r] - qm[r]);
+}
+
+// Operator coefficients re-read where used (see the 2-D kernels): the
+// laundered pointer keeps them out of loop-invariant code motion.
+template <class T> using cptr3 = const __attribute__((address_space(4))) T*;
+template <class T> __device__ __forceinline__ cptr3<T> launder3(cptr3<T> p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+template <int N, class TP> __device__ __forceinline__ cptr3<TP> ktil3() {
+  if constexpr (sizeof(TP) == 8) return (cptr3<TP>)&c3_ops[N].ktil[0][0];
+  else return (cptr3<TP>)&c3_opsf[N].ktil[0][0];
+}
+template <int N, class TP> __device__ __forceinline__ cptr3<TP> kappa3() {
+  if constexpr (sizeof(TP) == 8) return (cptr3<TP>)&c3_ops[N].kappa[0][0];
+  else return (cptr3<TP>)&c3_opsf[N].kappa[0][0];
+}
+
+// Step size of the current step and, by workgroup 0 of the predictor, the
+// clock update (as in the 2-D step).
+template <int N>
+__device__ __forceinline__ double step_dt3d(const Args3D& A, double* bcast, bool owner) {
+  if (A.mode == k3dPredict) return A.dt;
+  Clock3D& clk = *A.clk;
+  const int s = A.step;
+  const double t = clk.t[s & 1];
+  double dt;
+  if (A.fixed_dt > 0.0) {
+    dt = A.fixed_dt;
+  } else {
+    if (threadIdx.x < 64) {             // wave 0 (every workgroup has one)
+      const int l = threadIdx.x & 31;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double v = __longlong_as_double((long long)clk.lam[d][s % 3][l].v);
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+        if (threadIdx.x == 0) bcast[d] = v;
+      }
+    }
+    __syncthreads();
+    dt = A.cfl / (3.0 * (2 * N + 1)) *
+         fmin(fmin(A.h[0] / bcast[0], A.h[1] / bcast[1]), A.h[2] / bcast[2]);
+  }
+  const double rem = A.t_end[0] - t;
+  if (dt > rem) dt = rem;
+  if (!(dt > 0.0)) dt = 0.0;
+  if (owner) {
+    if (threadIdx.x == 0) {
+      clk.t[(s + 1) & 1] = t + dt;
+      if (dt > 0.0) clk.dt_last = dt;
+    }
+    if (threadIdx.x < kSlots) {
+      for (int d = 0; d < 3; ++d) {
+        clk.lam[d][(s + 2) % 3][threadIdx.x].v = 0ull;
+        if (dt == 0.0) clk.lam[d][(s + 1) % 3][threadIdx.x].v = clk.lam[d][s % 3][threadIdx.x].v;
+      }
+    }
+  }
+  return dt;
+}
+
+// ----------------------------------------------------------- predictor ----
+template <int N, class TP>
+struct Pred3Geo {
+  static constexpr int n = N + 1, L = n * n * n, M = 5;
+  static constexpr int TILE = n * L * M;                 // elements of one tile
+  static constexpr int CPB = L >= 64 ? 1 : 256 / L;      // whole wavefronts, few idle lanes
+  static constexpr int NT = ((CPB * L + 63) / 64) * 64;
+  static constexpr int VB = CPB * 3 * L * M;             // doubles of the volume buffer
+  static constexpr bool kVbAlias = CPB * TILE * (int)sizeof(TP) >= VB * 8;
+  static constexpr int kBytes = 2 * CPB * TILE * (int)sizeof(TP) + (kVbAlias ? 0 : VB * 8);
+  __device__ static constexpr int at(int a, int i, int j, int k) { return (((a * n + i) * n + j) * n + k) * M; }
+};
+
+template <int N, class TP>
+struct Fits3 {
+  static constexpr bool value = Pred3Geo<N, TP>::kBytes <= 159 * 1024;
+};
+
+template <int N, class TP>
+__global__ void __launch_bounds__((Pred3Geo<N, TP>::NT))
+pred3d_kernel(Args3D A) {
+  using G = Pred3Geo<N, TP>;
+  constexpr int n = G::n, L = G::L, M = G::M, CPB = G::CPB;
+  using Bits = decltype(ord_bits(TP(0)));
+
+  __shared__ TP Qs[CPB * G::TILE];
+  __shared__ TP Rs[CPB * G::TILE];
+  __shared__ double Vsep[G::kVbAlias ? 1 : G::VB];
+  __shared__ Bits red[2][CPB][2];
+  __shared__ double bcast[3];
+  __shared__ unsigned int swsum;
+
+  const int tid = threadIdx.x;
+  const int cl = tid / L, line = tid - cl * L;
+  const int h2 = line / (n * n), h1 = (line / n) % n, h0 = line % n;
+  const int64_t ncells = A.c[0] * A.c[1] * A.c[2];
+  const int64_t cell = (int64_t)blockIdx.x * CPB + cl;
+  const bool mine = cl < CPB && cell < ncells;
+
+  const double dt = step_dt3d<N>(A, bcast, blockIdx.x == 0);
+  if (!(dt > 0.0)) return;
+  const TP c0 = TP(dt / A.h[0]), c1 = TP(dt / A.h[1]), c2 = TP(dt / A.h[2]), gm1 = TP(A.gamma - 1.0);
+
+  if (tid < 4 * CPB) (&red[0][0][0])[tid] = 0;
+  if (tid == 0) swsum = 0u;
+
+  TP* const Qc = Qs + (mine ? cl : 0) * G::TILE;
+  TP* const Rc = Rs + (mine ? cl : 0) * G::TILE;
+  // T role: node (i, j, k) = (h2, h1, h0)
+  double u0[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) u0[r] = mine ? A.u[(cell * L + line) * M + r] : 1.0;
+  if (mine) {
+#pragma unroll
+    for (int a = 0; a < n; ++a)
+#pragma unroll
+      for (int r = 0; r < M; ++r) Qc[G::at(a, h2, h1, h0) + r] = TP(u0[r]);
+  }
+  const TP tol = TP(A.tol);
+  bool active = mine, failed = false;
+  int sweeps = 0;
+
+  for (int it = 0;; ++it) {
+    if (!__syncthreads_or(active)) break;
+    if (active) {
+      // X role, line (a, j, k): R = k~ (dt/dx) Fx along i
+      TP acc[n][M];
+#pragma unroll
+      for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc[i][r] = TP(0);
+#pragma unroll
+      for (int ip = 0; ip < n; ++ip) {
+        TP qq[M], f[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, ip, h1, h0) + r];
+        Euler3::flux<0>(qq, f, gm1);
+        const cptr3<TP> K = launder3(ktil3<N, TP>() + ip);
+#pragma unroll
+        for (int i = 0; i < n; ++i)
+#pragma unroll
+          for (int r = 0; r < M; ++r) acc[i][r] = fma(K[i * kDevMaxn], c0 * f[r], acc[i][r]);
+      }
+#pragma unroll
+      for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int r = 0; r < M; ++r) Rc[G::at(h2, i, h1, h0) + r] = acc[i][r];
+    }
+    __syncthreads();
+    if (active) {
+      // Y role, line (a, i, k): R += k~ (dt/dy) Fy along j
+      TP acc[n][M];
+#pragma unroll
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc[j][r] = TP(0);
+#pragma unroll
+      for (int jp = 0; jp < n; ++jp) {
+        TP qq[M], f[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, jp, h0) + r];
+        Euler3::flux<1>(qq, f, gm1);
+        const cptr3<TP> K = launder3(ktil3<N, TP>() + jp);
+#pragma unroll
+        for (int j = 0; j < n; ++j)
+#pragma unroll
+          for (int r = 0; r < M; ++r) acc[j][r] = fma(K[j * kDevMaxn], c1 * f[r], acc[j][r]);
+      }
+#pragma unroll
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, j, h0) + r] += acc[j][r];
+    }
+    __syncthreads();
+    if (active) {
+      // Z role, line (a, i, j): R += k~ (dt/dz) Fz along k
+      TP acc[n][M];
+#pragma unroll
+      for (int k = 0; k < n; ++k)
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc[k][r] = TP(0);
+#pragma unroll
+      for (int kp = 0; kp < n; ++kp) {
+        TP qq[M], f[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, h0, kp) + r];
+        Euler3::flux<2>(qq, f, gm1);
+        const cptr3<TP> K = launder3(ktil3<N, TP>() + kp);
+#pragma unroll
+        for (int k = 0; k < n; ++k)
+#pragma unroll
+          for (int r = 0; r < M; ++r) acc[k][r] = fma(K[k * kDevMaxn], c2 * f[r], acc[k][r]);
+      }
+#pragma unroll
+      for (int k = 0; k < n; ++k)
+#pragma unroll
+        for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, h0, k) + r] += acc[k][r];
+    }
+    __syncthreads();
+    TP e_ = TP(0), qm_ = TP(0);
+    if (active) {
+      // T role: q_new[a] = u - sum_b kappa~[a][b] R[b][i][j][k] over the own time line
+      TP rr[n][M];
+#pragma unroll
+      for (int b = 0; b < n; ++b)
+#pragma unroll
+        for (int r = 0; r < M; ++r) rr[b][r] = Rc[G::at(b, h2, h1, h0) + r];
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        const cptr3<TP> Kp = launder3(kappa3<N, TP>() + a * kDevMaxn);
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          TP acc = TP(0);
+#pragma unroll
+          for (int b = 0; b < n; ++b) acc = fma(Kp[b], rr[b][r], acc);
+          const TP qn = TP(u0[r]) - acc;
+          TP* p = &Qc[G::at(a, h2, h1, h0) + r];
+          e_ = max_abs(e_, qn - *p);
+          qm_ = max_abs(qm_, qn);
+          *p = qn;
+        }
+      }
+      ++sweeps;
+    }
+    {
+      // cell maxima: one cell per workgroup -> whole-wavefront reduction;
+      // otherwise along rows of n lanes (rows start at multiples of n).  All
+      // lanes take part in the shuffles; inactive lanes contribute zeros.
+      const int lane = tid & 63;
+      bool head;
+      if (CPB == 1) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          e_ = dmax(e_, __shfl_xor(e_, off, 64));
+          qm_ = dmax(qm_, __shfl_xor(qm_, off, 64));
+        }
+        head = lane == 0;
+      } else {
+#pragma unroll
+        for (int off = 1; off < n; off <<= 1) {
+          const TP e2 = __shfl_down(e_, off, 64), q2 = __shfl_down(qm_, off, 64);
+          if (h0 + off < n && lane + off < 64) {
+            e_ = dmax(e_, e2);
+            qm_ = dmax(qm_, q2);
+          }
+        }
+        head = h0 == 0 || lane == 0;
+      }
+      if (active && head) {
+        atomicMax(&red[it & 1][cl][0], ord_bits(e_));
+        atomicMax(&red[it & 1][cl][1], ord_bits(qm_));
+      }
+    }
+    if (tid < 2 * CPB) (&red[(it + 1) & 1][0][0])[tid] = 0;
+    __syncthreads();
+    if (active) {
+      const TP E = from_bits(red[it & 1][cl][0]), Qm = from_bits(red[it & 1][cl][1]);
+      if (E <= tol * dmax(TP(1), Qm)) {
+        active = false;
+      } else if (sweeps >= A.max_iter) {
+        active = false;
+        failed = true;
+      }
+    }
+  }
+
+  // ---- epilogue: traces from the X, Y, Z roles' lines (line index = (a, s, t))
+  if (mine) {
+    double tm[3][M], tp[3][M];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int r = 0; r < M; ++r) tm[d][r] = tp[d][r] = 0.0;
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      const double p0 = c3_ops[N].psi0[p], p1 = c3_ops[N].psi1[p];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        const double vx = (double)Qc[G::at(h2, p, h1, h0) + r];
+        const double vy = (double)Qc[G::at(h2, h1, p, h0) + r];
+        const double vz = (double)Qc[G::at(h2, h1, h0, p) + r];
+        tm[0][r] = fma(p0, vx, tm[0][r]);
+        tp[0][r] = fma(p1, vx, tp[0][r]);
+        tm[1][r] = fma(p0, vy, tm[1][r]);
+        tp[1][r] = fma(p1, vy, tp[1][r]);
+        tm[2][r] = fma(p0, vz, tm[2][r]);
+        tp[2][r] = fma(p1, vz, tp[2][r]);
+      }
+    }
+    double* trc = A.tr + cell * (6 * L * M);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        trc[((2 * d) * L + line) * M + r] = tm[d][r];
+        trc[((2 * d + 1) * L + line) * M + r] = tp[d][r];
+      }
+    if (A.mode == k3dPredict) {
+      TP* qo = reinterpret_cast<TP*>(A.q_out) + cell * (n * L * M);
+#pragma unroll
+      for (int a = 0; a < n; ++a)
+#pragma unroll
+        for (int r = 0; r < M; ++r) qo[(a * L + line) * M + r] = Qc[G::at(a, h2, h1, h0) + r];
+      if (A.iters && line == 0) A.iters[cell] = sweeps;
+    }
+  }
+  // volume terms from the time-integrated fluxes of the (promoted) predictor
+  double* const Vb = G::kVbAlias ? reinterpret_cast<double*>(Rs) : Vsep;
+  double* const Vc = Vb + (mine ? cl : 0) * (3 * L * M);
+  if (mine) {
+    double fb[3][M];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int r = 0; r < M; ++r) fb[d][r] = 0.0;
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      double qd[M], f[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) qd[r] = (double)Qc[G::at(a, h2, h1, h0) + r];
+      const double wa = c3_ops[N].w[a];
+      Euler3::flux<0>(qd, f, A.gamma - 1.0);
+#pragma unroll
+      for (int r = 0; r < M; ++r) fb[0][r] = fma(wa, (dt / A.h[0]) * f[r], fb[0][r]);
+      Euler3::flux<1>(qd, f, A.gamma - 1.0);
+#pragma unroll
+      for (int r = 0; r < M; ++r) fb[1][r] = fma(wa, (dt / A.h[1]) * f[r], fb[1][r]);
+      Euler3::flux<2>(qd, f, A.gamma - 1.0);
+#pragma unroll
+      for (int r = 0; r < M; ++r) fb[2][r] = fma(wa, (dt / A.h[2]) * f[r], fb[2][r]);
+    }
+    // in the aliased case Vb overlays R, last read before the loop's final barriers
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int r = 0; r < M; ++r) Vc[(d * L + line) * M + r] = fb[d][r];
+  }
+  __syncthreads();
+  if (mine) {
+    double vol[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) vol[r] = 0.0;
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      const double dx_ = c3_ops[N].Dw[h2][l], dy_ = c3_ops[N].Dw[h1][l], dz_ = c3_ops[N].Dw[h0][l];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        vol[r] = fma(dx_, Vc[(0 * L + (l * n + h1) * n + h0) * M + r], vol[r]);
+        vol[r] = fma(dy_, Vc[(1 * L + (h2 * n + l) * n + h0) * M + r], vol[r]);
+        vol[r] = fma(dz_, Vc[(2 * L + (h2 * n + h1) * n + l) * M + r], vol[r]);
+      }
+    }
+    double* pc = A.part + (cell * L + line) * M;
+#pragma unroll
+    for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
+  }
+
+  if (mine && line == 0) atomicAdd(&swsum, (unsigned int)sweeps);
+  const bool any_fail = __any(failed);
+  __syncthreads();
+  if (A.mode == k3dStep) {
+    const int slot = (int)(blockIdx.x % kSlots);
+    if (tid == 0 && swsum) atomicAdd(&A.clk->sweeps[slot].v, (unsigned long long)swsum);
+    if ((tid & 63) == 0 && any_fail) atomicMin(&A.clk->stat[(slot + (tid >> 6)) % kSlots].v, -4);
+  }
+}
+
+// ----------------------------------------------------------- corrector ----
+template <int N>
+struct Corr3Geo {
+  static constexpr int n = N + 1, L = n * n * n, M = 5, Ns = 2 * N + 1;
+  static constexpr int CPB = L >= 256 ? 1 : 256 / L;
+  static constexpr int NT = 256;
+};
+
+// Signal-speed maxima per direction over the (2N+1)^3 subcell averages
+// (P (x) P (x) P) u of the workgroup's cells (u in LDS U), by three
+// one-direction projections through LDS (V1, V2).
+template <int N>
+__device__ __forceinline__ void subcell_speeds3(const double* U, double* V1, double* V2, int ncl,
+                                                double gamma, double* lam) {
+  using G = Corr3Geo<N>;
+  constexpr int n = G::n, L = G::L, M = G::M, Ns = G::Ns;
+  for (int w = threadIdx.x; w < ncl * Ns * n * n; w += G::NT) {
+    const int cl = w / (Ns * n * n), rem = w - cl * (Ns * n * n), s = rem / (n * n), jk = rem - s * (n * n);
+    double v[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) v[r] = 0.0;
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      const double P = c3_ops[N].P[s][i];
+#pragma unroll
+      for (int r = 0; r < M; ++r) v[r] = fma(P, U[(cl * L + i * n * n + jk) * M + r], v[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r) V1[((cl * Ns + s) * n * n + jk) * M + r] = v[r];
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < ncl * Ns * Ns * n; w += G::NT) {
+    const int cl = w / (Ns * Ns * n), rem = w - cl * (Ns * Ns * n);
+    const int s = rem / (Ns * n), t = (rem / n) % Ns, k = rem % n;
+    double v[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) v[r] = 0.0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      const double P = c3_ops[N].P[t][j];
+#pragma unroll
+      for (int r = 0; r < M; ++r) v[r] = fma(P, V1[((cl * Ns + s) * n * n + j * n + k) * M + r], v[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r) V2[(((cl * Ns + s) * Ns + t) * n + k) * M + r] = v[r];
+  }
+  __syncthreads();
+  lam[0] = lam[1] = lam[2] = 0.0;
+  for (int w = threadIdx.x; w < ncl * Ns * Ns * Ns; w += G::NT) {
+    const int cl = w / (Ns * Ns * Ns), rem = w - cl * (Ns * Ns * Ns);
+    const int st = rem / Ns, z = rem % Ns;
+    double v[M], sp[3];
+#pragma unroll
+    for (int r = 0; r < M; ++r) v[r] = 0.0;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      const double P = c3_ops[N].P[z][k];
+#pragma unroll
+      for (int r = 0; r < M; ++r) v[r] = fma(P, V2[((cl * Ns * Ns + st) * n + k) * M + r], v[r]);
+    }
+    Euler3::speeds(v, gamma, sp);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lam[d] = fmax(lam[d], sp[d]);
+  }
+}
+
+__device__ __forceinline__ void publish_lambda3(Clock3D& clk, int buf, double* lam, double* part) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) lam[d] = wave_max(lam[d]);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int d = 0; d < 3; ++d) part[3 * wv + d] = lam[d];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int slot = (int)(blockIdx.x % kSlots);
+    for (int d = 0; d < 3; ++d) {
+      double X = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) X = fmax(X, part[3 * w + d]);
+      atomic_max_nonneg(&clk.lam[d][buf][slot].v, X);
+    }
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256)
+corr3d_kernel(Args3D A) {
+  using G = Corr3Geo<N>;
+  constexpr int n = G::n, L = G::L, M = G::M, Ns = G::Ns, CPB = G::CPB, F = n * n;
+  __shared__ double Gf[CPB * 6 * F * M];
+  __shared__ double U[CPB * L * M];
+  __shared__ double V1[CPB * Ns * F * M];
+  __shared__ double V2[CPB * Ns * Ns * n * M];
+  __shared__ double bcast[3];
+  __shared__ double part[12];
+
+  const double dt = step_dt3d<N>(A, bcast, false);
+  if (!(dt > 0.0)) return;
+  const int64_t ncells = A.c[0] * A.c[1] * A.c[2];
+  const int64_t cell0 = (int64_t)blockIdx.x * CPB;
+  const int ncl = (int)((ncells - cell0) < CPB ? (ncells - cell0) : CPB);
+
+  // fluxes through the faces, time-integrated: face 2d = minus side, 2d+1 = plus side of direction d
+  for (int w = threadIdx.x; w < ncl * 6 * F; w += G::NT) {
+    const int cl = w / (6 * F), rem = w - cl * (6 * F), f = rem / F, st = rem - f * F;
+    const int d = f >> 1;
+    const int64_t c = cell0 + cl;
+    int64_t idx[3] = {c / (A.c[1] * A.c[2]), (c / A.c[2]) % A.c[1], c % A.c[2]};
+    int64_t nb[3] = {idx[0], idx[1], idx[2]};
+    if (f & 1) nb[d] = (nb[d] + 1 == A.c[d]) ? 0 : nb[d] + 1;
+    else nb[d] = (nb[d] == 0) ? A.c[d] - 1 : nb[d] - 1;
+    const int64_t other = (nb[0] * A.c[1] + nb[1]) * A.c[2] + nb[2];
+    const int64_t cm = (f & 1) ? c : other, cp = (f & 1) ? other : c;
+    const double sc = dt / A.h[d];
+    double acc[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) acc[r] = 0.0;
+    for (int a = 0; a < n; ++a) {
+      double qm[M], qp[M], Gr[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        qm[r] = A.tr[((cm * 6 + 2 * d + 1) * L + a * F + st) * M + r];
+        qp[r] = A.tr[((cp * 6 + 2 * d) * L + a * F + st) * M + r];
+      }
+      if (d == 0) rusanov3<0>(qm, qp, Gr, A.gamma);
+      else if (d == 1) rusanov3<1>(qm, qp, Gr, A.gamma);
+      else rusanov3<2>(qm, qp, Gr, A.gamma);
+      const double wa = c3_ops[N].w[a];
+#pragma unroll
+      for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r) Gf[((cl * 6 + f) * F + st) * M + r] = acc[r];
+  }
+  __syncthreads();
+
+  bool bad = false;
+  for (int w = threadIdx.x; w < ncl * L; w += G::NT) {
+    const int cl = w / L, line = w - cl * L;
+    const int i = line / F, j = (line / n) % n, k = line % n;
+    const int64_t c = cell0 + cl;
+    const double* pc = A.part + (c * L + line) * M;
+    const double* Gc = Gf + cl * 6 * F * M;
+    const double* ps0 = c3_ops[N].psi0;
+    const double* ps1 = c3_ops[N].psi1;
+    const double* wi = c3_ops[N].winv;
+    double un[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const double sx = (ps1[i] * Gc[(1 * F + j * n + k) * M + r] - ps0[i] * Gc[(0 * F + j * n + k) * M + r]) * wi[i];
+      const double sy = (ps1[j] * Gc[(3 * F + i * n + k) * M + r] - ps0[j] * Gc[(2 * F + i * n + k) * M + r]) * wi[j];
+      const double sz = (ps1[k] * Gc[(5 * F + i * n + j) * M + r] - ps0[k] * Gc[(4 * F + i * n + j) * M + r]) * wi[k];
+      un[r] = pc[r] - sx - sy - sz;
+      A.u[(c * L + line) * M + r] = un[r];
+      U[(cl * L + line) * M + r] = un[r];
+    }
+    bad |= !Euler3::admissible(un, A.gamma);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0)
+    atomicMin(&A.clk->stat[(blockIdx.x + (threadIdx.x >> 6)) % kSlots].v, -5);
+  __syncthreads();
+  double lam[3];
+  subcell_speeds3<N>(U, V1, V2, ncl, A.gamma, lam);
+  publish_lambda3(*A.clk, (A.step + 1) % 3, lam, part);
+}
+
+template <int N>
+__global__ void __launch_bounds__(256)
+lambda3d_kernel(Args3D A) {
+  using G = Corr3Geo<N>;
+  constexpr int n = G::n, L = G::L, M = G::M, Ns = G::Ns, CPB = G::CPB, F = n * n;
+  __shared__ double U[CPB * L * M];
+  __shared__ double V1[CPB * Ns * F * M];
+  __shared__ double V2[CPB * Ns * Ns * n * M];
+  __shared__ double part[12];
+  const int64_t ncells = A.c[0] * A.c[1] * A.c[2];
+  const int64_t cell0 = (int64_t)blockIdx.x * CPB;
+  const int ncl = (int)((ncells - cell0) < CPB ? (ncells - cell0) : CPB);
+  for (int w = threadIdx.x; w < ncl * L * M; w += G::NT) U[w] = A.u[cell0 * L * M + w];
+  __syncthreads();
+  double lam[3];
+  subcell_speeds3<N>(U, V1, V2, ncl, A.gamma, lam);
+  publish_lambda3(*A.clk, 0, lam, part);
+}
+
+__global__ void clock3d_begin_kernel(Clock3D* clk, const double* t_user) {
+  const int i = threadIdx.x;
+  if (i == 0) {
+    clk->t[0] = t_user[0];
+    clk->t[1] = t_user[0];
+    clk->dt_last = 0.0;
+  }
+  if (i < kSlots) {
+    for (int d = 0; d < 3; ++d)
+      for (int b = 0; b < 3; ++b) clk->lam[d][b][i].v = 0ull;
+    clk->stat[i].v = 0;
+  }
+}
+
+__global__ void clock3d_end_kernel(const Clock3D* clk, double* t_user, double* dt_user,
+                                   int32_t* status_user, int parity) {
+  if (threadIdx.x != 0) return;
+  t_user[0] = clk->t[parity];
+  dt_user[0] = clk->dt_last;
+  int st = 0;
+  for (int i = 0; i < kSlots; ++i) st = min(st, clk->stat[i].v);
+  status_user[0] = st;
+}
+
+// -------------------------------------------------------------- dispatch ----
+template <int N, class TP>
+static hipError_t pred3d_one(const Args3D& A, int64_t blocks, hipStream_t st) {
+  if constexpr (Fits3<N, TP>::value) {
+    hipLaunchKernelGGL((pred3d_kernel<N, TP>), dim3((unsigned)blocks), dim3(Pred3Geo<N, TP>::NT), 0,
+                       st, A);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <class TP>
+static hipError_t launch_pred3d_p(int N, const Args3D& A, int64_t blocks, hipStream_t st) {
+  switch (N) {
+    case 1: return pred3d_one<1, TP>(A, blocks, st);
+    case 2: return pred3d_one<2, TP>(A, blocks, st);
+    case 3: return pred3d_one<3, TP>(A, blocks, st);
+    case 4: return pred3d_one<4, TP>(A, blocks, st);
+    case 5: return pred3d_one<5, TP>(A, blocks, st);
+    case 6: return pred3d_one<6, TP>(A, blocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class TP> static bool fits_p(int N) {
+  switch (N) {
+    case 1: return Fits3<1, TP>::value;
+    case 2: return Fits3<2, TP>::value;
+    case 3: return Fits3<3, TP>::value;
+    case 4: return Fits3<4, TP>::value;
+    case 5: return Fits3<5, TP>::value;
+    case 6: return Fits3<6, TP>::value;
+    default: return false;
+  }
+}
+template <class TP> static int cpb3_p(int N) {
+  switch (N) {
+    case 1: return Pred3Geo<1, TP>::CPB;
+    case 2: return Pred3Geo<2, TP>::CPB;
+    case 3: return Pred3Geo<3, TP>::CPB;
+    case 4: return Pred3Geo<4, TP>::CPB;
+    case 5: return Pred3Geo<5, TP>::CPB;
+    case 6: return Pred3Geo<6, TP>::CPB;
+    default: return 0;
+  }
+}
+
+bool supported_3d(int N, int prec) { return prec ? fits_p<float>(N) : fits_p<double>(N); }
+int cells_per_block_3d(int N, int prec) { return prec ? cpb3_p<float>(N) : cpb3_p<double>(N); }
+int cells_per_block_corr3d(int N) {
+  const int L = (N + 1) * (N + 1) * (N + 1);
+  return L >= 256 ? 1 : 256 / L;
+}
+
+hipError_t launch_pred3d(int N, int prec, const Args3D& A, int64_t blocks, hipStream_t st) {
+  return prec ? launch_pred3d_p<float>(N, A, blocks, st) : launch_pred3d_p<double>(N, A, blocks, st);
+}
+
+hipError_t launch_corr3d(int N, const Args3D& A, int64_t blocks, hipStream_t st) {
+  dim3 grid((unsigned)blocks), block(256);
+  switch (N) {
+#define ADERDG3_CASE(NN) case NN: hipLaunchKernelGGL((corr3d_kernel<NN>), grid, block, 0, st, A); break;
+    ADERDG3_CASE(1) ADERDG3_CASE(2) ADERDG3_CASE(3) ADERDG3_CASE(4) ADERDG3_CASE(5) ADERDG3_CASE(6)
+#undef ADERDG3_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda3d(int N, const Args3D& A, int64_t blocks, hipStream_t st) {
+  dim3 grid((unsigned)blocks), block(256);
+  switch (N) {
+#define ADERDG3_CASE(NN) case NN: hipLaunchKernelGGL((lambda3d_kernel<NN>), grid, block, 0, st, A); break;
+    ADERDG3_CASE(1) ADERDG3_CASE(2) ADERDG3_CASE(3) ADERDG3_CASE(4) ADERDG3_CASE(5) ADERDG3_CASE(6)
+#undef ADERDG3_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_clock3d_begin(Clock3D* clk, const double* t_user, hipStream_t st) {
+  hipLaunchKernelGGL(clock3d_begin_kernel, dim3(1), dim3(64), 0, st, clk, t_user);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock3d_end(const Clock3D* clk, double* t_user, double* dt_user,
+                              int32_t* status_user, int parity, hipStream_t st) {
+  hipLaunchKernelGGL(clock3d_end_kernel, dim3(1), dim3(64), 0, st, clk, t_user, dt_user,
+                     status_user, parity);
+  return hipGetLastError();
+}
+
+hipError_t upload_tables_3d(const DevOps* ops, const DevOpsF* opsf) {
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c3_ops), ops, sizeof(DevOps) * kDevMaxn);
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c3_opsf), opsf, sizeof(DevOpsF) * kDevMaxn);
+}
+
+}  // namespace aderdg

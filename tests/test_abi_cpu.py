@@ -1,7 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed).
 
-* libaderdg.so loads and exports every function declared in include/aderdg.h
-  and include/aderdg2d.h;
+* libaderdg.so loads and exports every function declared in include/aderdg.h,
+  include/aderdg2d.h and include/aderdg3d.h;
 * the library's host operator tables (an independent C++ construction)
   agree with the oracle's;
 * argument validation returns ADERDG_E_INVAL before any device work.
@@ -20,6 +20,7 @@ from paper_2409_12483_amd import abi
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "aderdg.h")
 HEADER_2D = os.path.join(ROOT, "include", "aderdg2d.h")
+HEADER_3D = os.path.join(ROOT, "include", "aderdg3d.h")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(abi.LIBPATH),
                                 reason="libaderdg.so not built (run __graft_entry__.build())")
@@ -28,7 +29,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(abi.LIBPATH),
 def _declared_functions(header=HEADER):
     text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(aderdg_\w+|aderweno_\w+|aderdg2d_\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(aderdg_\w+|aderweno_\w+|aderdg[23]d_\w+)\s*\(", text)))
 
 
 def test_header_declares_the_entry_points():
@@ -41,7 +42,7 @@ def test_header_declares_the_entry_points():
 
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(abi.LIBPATH)
-    for name in _declared_functions() + _declared_functions(HEADER_2D):
+    for name in _declared_functions() + _declared_functions(HEADER_2D) + _declared_functions(HEADER_3D):
         assert hasattr(lib, name), name
 
 
@@ -158,3 +159,43 @@ def test_2d_config_struct_layout_matches_header():
     assert abi.Config2D.cells_x.offset == 8 and abi.Config2D.x0.offset == 24
     assert abi.Config2D.gamma.offset == 56 and abi.Config2D.picard_tol.offset == 80
     assert abi.Config2D.picard_max_iter.offset == 88 and ctypes.sizeof(abi.Config2D) == 96
+
+
+def test_3d_header_declares_the_entry_points():
+    assert set(_declared_functions(HEADER_3D)) == set(abi.EXPORTS_3D)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda c: setattr(c, "N", 0), "N must"),
+    (lambda c: setattr(c, "N", 6), "N must"),
+    (lambda c: (setattr(c, "N", 7), setattr(c, "precision", abi.FP32_PREDICTOR)), "N must"),
+    (lambda c: setattr(c, "precision", 2), "precision"),
+    (lambda c: setattr(c, "cells_z", 0), "cells_x"),
+    (lambda c: (setattr(c, "cells_x", 2048), setattr(c, "cells_y", 2048), setattr(c, "cells_z", 1024)), "2^31"),
+    (lambda c: setattr(c, "z1", -1.0), "domain"),
+    (lambda c: setattr(c, "gamma", 1.0), "gamma"),
+    (lambda c: setattr(c, "cfl", 2.0), "cfl"),
+    (lambda c: setattr(c, "fixed_dt", float("nan")), "fixed_dt"),
+])
+def test_invalid_3d_configs_are_rejected(mutate, needle):
+    c = abi.config3d(3, (4, 4, 4))
+    mutate(c)
+    h = ctypes.c_void_p()
+    rc = abi.load().aderdg3d_init(ctypes.byref(c), None, ctypes.byref(h))
+    assert rc == abi.ADERDG_E_INVAL and h.value is None
+    assert needle in abi.aderdg_last_error()
+
+
+def test_null_3d_arguments_are_rejected():
+    lib = abi.load()
+    assert lib.aderdg3d_init(None, None, None) == abi.ADERDG_E_INVAL
+    assert lib.aderdg3d_step(None, None, None, None, None, None, 1) == abi.ADERDG_E_INVAL
+    assert lib.aderdg3d_predict(None, None, 0.0, 0.1, None, None) == abi.ADERDG_E_INVAL
+    assert lib.aderdg3d_sweep_count(None, None) == abi.ADERDG_E_INVAL
+    assert lib.aderdg3d_free(None) == abi.ADERDG_OK
+
+
+def test_3d_config_struct_layout_matches_header():
+    assert abi.Config3D.cells_z.offset == 24 and abi.Config3D.x0.offset == 32
+    assert abi.Config3D.gamma.offset == 80 and abi.Config3D.picard_max_iter.offset == 112
+    assert ctypes.sizeof(abi.Config3D) == 120
