@@ -551,6 +551,127 @@ def dg2d_section(quick=False):
     return out
 
 
+FLUX3_FLOPS = 18          # one 3-D Euler flux at a node, the reciprocal counted as one
+RIEMANN3_FLOPS = 80       # one 3-D Rusanov flux
+
+
+def dg3d_flops_per_cell(N, sweeps_per_cell, M=5):
+    """Algorithmic flops of one 3-D step per cell:
+    predictor per sweep  3n^4 (F + M) (fluxes, scaled) + 4 * 2n^5 M (k~ along x, y, z and
+                         kappa~ along time) + 5 n^4 M (combine, update, test)
+    epilogue             12 n^4 M (six face traces) + 3n^4 F + 9 n^4 M + 6 n^4 M + n^3 M
+    corrector            3 n^3 (R + 3M) (each face once) + 8 n^3 M + 10 n^3
+                         + 2 Ns n^3 M + 2 Ns^2 n^2 M + 2 Ns^3 n M + 14 Ns^3 (subcell speeds)
+    Returns (predictor sweeps, the rest)."""
+    n, Ns = N + 1, 2 * N + 1
+    sweep = 3 * n ** 4 * (FLUX3_FLOPS + M) + 8 * n ** 5 * M + 5 * n ** 4 * M
+    epi = 12 * n ** 4 * M + 3 * n ** 4 * FLUX3_FLOPS + 15 * n ** 4 * M + n ** 3 * M
+    corr = (3 * n ** 3 * (RIEMANN3_FLOPS + 3 * M) + 8 * n ** 3 * M + 10 * n ** 3
+            + 2 * Ns * n ** 3 * M + 2 * Ns * Ns * n * n * M + 2 * Ns ** 3 * n * M + 14 * Ns ** 3)
+    return sweeps_per_cell * sweep, epi + corr
+
+
+class DG3Run:
+    """The 3-D sine wave of Sec. 2.1 (rho = 1 + 0.5 sin(2 pi (x + y + z)),
+    velocity (1, 1, 1), p = 1, gamma = 1.4, unit cube, periodic) on C^3 cells."""
+
+    def __init__(self, N, C, precision, cfl=0.4):
+        import torch
+        from paper_2409_12483_amd import abi
+        from paper_2409_12483_amd import workloads as W
+        self.abi, self.torch = abi, torch
+        dev = torch.device("cuda:0")
+        self.u = torch.tensor(W.euler3d_sine_wave(C, C, C, N), device=dev)
+        self.t = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.te = torch.full((1,), 1.0e300, dtype=torch.float64, device=dev)
+        self.dt = torch.zeros_like(self.t)
+        self.st = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.stream = torch.cuda.current_stream()
+        self.h = abi.aderdg3d_init(abi.config3d(N, (C, C, C), cfl=cfl, precision=precision),
+                                   stream=self.stream.cuda_stream)
+
+    def steps(self, k):
+        self.abi.aderdg3d_step(self.h, self.u, self.t, self.te, self.dt, self.st, k)
+
+    def timed(self, k):
+        torch = self.torch
+        _sync()
+        s0 = self.abi.aderdg3d_sweep_count(self.h)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        self.steps(k)
+        e1.record(self.stream)
+        _sync()
+        return e0.elapsed_time(e1) * 1e-3, self.abi.aderdg3d_sweep_count(self.h) - s0
+
+    def close(self):
+        self.abi.aderdg3d_free(self.h)
+
+
+def dg3d_entry(N, C, precision, steps, warmup):
+    from paper_2409_12483_amd import abi
+    r = DG3Run(N, C, precision)
+    r.steps(warmup)
+    secs, sweeps = r.timed(steps)
+    status = int(r.st.item())
+    r.close()
+    cells = C ** 3
+    spc = sweeps / (cells * steps)
+    pred, rest = dg3d_flops_per_cell(N, spc)
+    total = (pred + rest) * cells * steps
+    if precision == abi.FP64:
+        peak = PEAK_FP64_VALU
+        t_roof = total / (PEAK_FP64_VALU * 1e12)
+    else:
+        t_roof = pred * cells * steps / (PEAK_FP32_VALU * 1e12) + rest * cells * steps / (PEAK_FP64_VALU * 1e12)
+        peak = total / t_roof * 1e-12
+    n = N + 1
+    return {"N": N, "cells": f"{C}^3", "precision": "fp64" if precision == abi.FP64 else "fp32_predictor",
+            "status": status, "value": round(steps * cells * n ** 3 * 5 / secs, 1), "unit": "DoF-updates/s",
+            "ms_per_step": round(secs / steps * 1e3, 5), "sweeps_per_cell": round(spc, 3),
+            "roofline": {"bound": "alu", "achieved": round(total / secs * 1e-12, 3), "peak": round(peak, 2),
+                         "unit": "TFLOP/s", "frac": round(t_roof / secs, 4),
+                         "flops_per_step": int(round(total / steps))}}
+
+
+def dg3d_time_to_solution(N, C, precision=0):
+    """The paper's 3-D timing problem (Sec. 3, Table 11: the sine wave on C^3
+    cells, t_final = 1): wall time of the whole run on the GPU, host loop included."""
+    r = DG3Run(N, C, precision)
+    r.te.fill_(1.0)
+    _sync()
+    t0 = time.perf_counter()
+    r.steps(20)
+    _sync()
+    t_now, dt = float(r.t.item()), float(r.dt.item())
+    while t_now < 1.0:
+        r.steps(int(np.ceil((1.0 - t_now) / dt)) + 1)
+        _sync()
+        t_now = float(r.t.item())
+    el = time.perf_counter() - t0
+    st = int(r.st.item())
+    r.close()
+    return {"N": N, "cells": f"{C}^3", "gpu_wall_s": round(el, 5), "steps_approx": int(round(1.0 / dt)),
+            "status": st}
+
+
+def dg3d_section(quick=False):
+    from paper_2409_12483_amd import abi
+    out = {"workload": "ADER-DG 3D Euler gamma=1.4, sine wave rho=1+0.5 sin(2 pi (x+y+z)), velocity (1,1,1), "
+                       "p=1, unit cube, periodic, CFL 0.4, Rusanov"}
+    out["n3_64c_fp64"] = dg3d_entry(3, 64, abi.FP64, 10, 3)
+    out["n5_40c_fp64"] = dg3d_entry(5, 40, abi.FP64, 10, 3)
+    out["n5_40c_fp32_predictor"] = dg3d_entry(5, 40, abi.FP32_PREDICTOR, 10, 3)
+    if quick:
+        return out
+    sizes = {1: 96, 2: 72, 3: 64, 4: 48, 5: 40}
+    out["per_degree_fp64"] = [dg3d_entry(N, C, abi.FP64, 10, 3) for N, C in sizes.items()]
+    out["n6_32c_fp32_predictor"] = dg3d_entry(6, 32, abi.FP32_PREDICTOR, 10, 3)
+    out["paper_table11_time_to_solution"] = [dg3d_time_to_solution(N, C) for N in range(1, 6)
+                                             for C in (4, 5, 6, 7)]
+    return out
+
+
 def cpu_baseline(N, target_s=12.0):
     """The oracle, as is, on a bounded sample of the same workload."""
     from oracle import basis, dg
@@ -585,6 +706,8 @@ def main():
                     help="first run a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--dg2d-only", action="store_true",
                     help="only the 2-D workload (512x512 cells, N=5; for profiling the 2-D kernels)")
+    ap.add_argument("--dg3d-only", action="store_true",
+                    help="only the 3-D workloads (N=3 on 64^3 and N=5 on 40^3 cells; for profiling)")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -607,6 +730,9 @@ def main():
 
     if a.dg2d_only:
         print(json.dumps({"dg2d_euler_sine_512x512": dg2d_section(quick=True)}))
+        return
+    if a.dg3d_only:
+        print(json.dumps({"dg3d_euler_sine": dg3d_section(quick=True)}))
         return
 
     run = DGRun(N, C, abi.FP64)
@@ -688,6 +814,7 @@ def main():
         out["c5_serving_fp32_predictor"] = [c5_serving(rate, 150, precision=abi.FP32_PREDICTOR)
                                             for rate in (50.0, 100.0)]
         out["dg2d_euler_sine_512x512"] = dg2d_section()
+        out["dg3d_euler_sine"] = dg3d_section()
     if a.c5_full:
         out["c5_serving_full"] = c5_serving(200.0, 2000)
     if not a.no_cpu_baseline:

@@ -41,3 +41,10 @@ def test_dg2d_flop_model_values():
     pred, rest = bench.dg2d_flops_per_cell(5, 1.0)
     assert pred == 2 * 216 * 18 + 6 * 1296 * 4 + 4 * 216 * 4 == 42336
     assert rest == 21744 + 17556
+
+
+def test_dg3d_flop_model_values():
+    """Regression values of the 3-D flop model at N = 3 (one sweep per cell)."""
+    pred, rest = bench.dg3d_flops_per_cell(3, 1.0)
+    assert pred == 3 * 256 * 23 + 8 * 1024 * 5 + 5 * 256 * 5 == 65024
+    assert rest > 0
