@@ -136,16 +136,26 @@ __device__ __forceinline__ double step_dt3d(const Args3D& A, double* bcast, bool
 }
 
 // ----------------------------------------------------------- predictor ----
+// Tile strides: a node's M = 5 values are contiguous; the j-line, i-line and
+// time-slice strides carry small pads (per n, in elements) chosen by a
+// bank-model search so that the four access patterns of a sweep (lanes over
+// (a, j, k), (a, i, k), (a, i, j) and (i, j, k)) spread over the LDS banks.
+constexpr int kPad3[8][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0},
+                             {0, 3, 4}, {0, 0, 0}, {0, 0, 0}, {0, 0, 2}};
+
 template <int N, class TP>
 struct Pred3Geo {
   static constexpr int n = N + 1, L = n * n * n, M = 5;
-  static constexpr int TILE = n * L * M;                 // elements of one tile
+  static constexpr int SJ = n * M + kPad3[N + 1][0];
+  static constexpr int SI = n * SJ + kPad3[N + 1][1];
+  static constexpr int SA = n * SI + kPad3[N + 1][2];
+  static constexpr int TILE = n * SA;                    // elements of one tile
   static constexpr int CPB = L >= 64 ? 1 : 256 / L;      // whole wavefronts, few idle lanes
   static constexpr int NT = ((CPB * L + 63) / 64) * 64;
   static constexpr int VB = CPB * 3 * L * M;             // doubles of the volume buffer
   static constexpr bool kVbAlias = CPB * TILE * (int)sizeof(TP) >= VB * 8;
   static constexpr int kBytes = 2 * CPB * TILE * (int)sizeof(TP) + (kVbAlias ? 0 : VB * 8);
-  __device__ static constexpr int at(int a, int i, int j, int k) { return (((a * n + i) * n + j) * n + k) * M; }
+  __device__ static constexpr int at(int a, int i, int j, int k) { return a * SA + i * SI + j * SJ + k * M; }
 };
 
 template <int N, class TP>
