@@ -273,12 +273,16 @@ pred2d_kernel(Args2D A) {
   double u0[M];
 #pragma unroll
   for (int r = 0; r < M; ++r) u0[r] = mine ? A.u[(cell * L + node) * M + r] : 1.0;
+  // the T role also keeps its time line in registers (the old values for the
+  // convergence test without re-reading them from the tile)
+  TP qt[n][M];
+#pragma unroll
+  for (int a = 0; a < n; ++a)
+#pragma unroll
+    for (int r = 0; r < M; ++r) qt[a][r] = TP(u0[r]);
   if (mine) {
-    TP v[M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) v[r] = TP(u0[r]);
-#pragma unroll
-    for (int a = 0; a < n; ++a) st4<PL>(Qc + G::at(a, ti, tj), v);
+    for (int a = 0; a < n; ++a) st4<PL>(Qc + G::at(a, ti, tj), qt[a]);
   }
   const TP tol = TP(A.tol);
   bool active = mine, failed = false;
@@ -344,27 +348,27 @@ pred2d_kernel(Args2D A) {
     __syncthreads();
     TP e_ = TP(0), qm_ = TP(0);
     if (active) {
-      // T role: q_new[a] = u - sum_b kappa~[a][b] R[b][i][j], written over the
-      // thread's own time line of the tile (no other thread reads it now)
+      // T role: q_new[a] = u - sum_b kappa~[a][b] R[b][i][j], kept in registers
+      // and written over the thread's own time line of the tile (no other
+      // thread reads it now)
       TP rr[n][M];
 #pragma unroll
       for (int b = 0; b < n; ++b) ld4<PL>(Rc + G::at(b, ti, tj), rr[b]);
       TP e = TP(0), qm = TP(0);
 #pragma unroll
       for (int a = 0; a < n; ++a) {
-        TP qo[M], qn[M];
-        ld4<PL>(Qc + G::at(a, ti, tj), qo);
         const cptr<TP> Kp = launder(kappa_base<N, TP>() + a * kDevMaxn);   // row a of kappa~
 #pragma unroll
         for (int r = 0; r < M; ++r) {
           TP acc = TP(0);
 #pragma unroll
           for (int b = 0; b < n; ++b) acc = fma(Kp[b], rr[b][r], acc);
-          qn[r] = TP(u0[r]) - acc;
-          e = max_abs(e, qn[r] - qo[r]);
-          qm = max_abs(qm, qn[r]);
+          const TP qn = TP(u0[r]) - acc;
+          e = max_abs(e, qn - qt[a][r]);
+          qm = max_abs(qm, qn);
+          qt[a][r] = qn;
         }
-        st4<PL>(Qc + G::at(a, ti, tj), qn);
+        st4<PL>(Qc + G::at(a, ti, tj), qt[a]);
       }
       e_ = e;
       qm_ = qm;
