@@ -53,9 +53,9 @@ typedef struct aderdg2d_handle aderdg2d_handle;
 /*
  * aderdg2d_init -- create a 2-D problem.  cfg is copied.  hip_stream: a
  * hipStream_t (NULL = default stream).  Allocates library-owned device
- * memory: the face traces and u + volume terms of every cell (5 (N+1)^2 4
- * doubles per cell) and a clock.  Errors: E_INVAL (*out untouched), E_NOMEM,
- * E_DEVICE.
+ * memory: per cell u + volume terms ((N+1)^2 4 doubles) and the four face
+ * traces (4 (N+1)^2 4 values in the predictor precision), and a clock.
+ * Errors: E_INVAL (*out untouched), E_NOMEM, E_DEVICE.
  */
 int aderdg2d_init(const aderdg2d_config* cfg, void* hip_stream, aderdg2d_handle** out);
 

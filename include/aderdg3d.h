@@ -45,9 +45,9 @@ typedef struct aderdg3d_handle aderdg3d_handle;
 
 /*
  * aderdg3d_init -- create a 3-D problem (cfg copied; hip_stream NULL = default
- * stream).  Allocates 7 (N+1)^3 5 doubles of scratch per cell (six face traces
- * and u + volume terms) and a device clock.  E_INVAL (*out untouched),
- * E_NOMEM, E_DEVICE.
+ * stream).  Allocates per cell u + volume terms ((N+1)^3 5 doubles) and the
+ * six face traces (6 (N+1)^3 5 values in the predictor precision), and a
+ * device clock.  E_INVAL (*out untouched), E_NOMEM, E_DEVICE.
  */
 int aderdg3d_init(const aderdg3d_config* cfg, void* hip_stream, aderdg3d_handle** out);
 

@@ -510,7 +510,7 @@ struct aderdg2d_handle {
   aderdg2d_config cfg{};
   int64_t cells = 0;
   double* part = nullptr;
-  double* tr = nullptr;
+  void* tr = nullptr;
   Clock2D* clk = nullptr;
 };
 
@@ -573,7 +573,8 @@ int aderdg2d_init(const aderdg2d_config* cfg, void* hip_stream, aderdg2d_handle*
   h->cells = c.cells_x * c.cells_y;
   const int64_t L = (int64_t)(c.N + 1) * (c.N + 1);
   e = hipMalloc((void**)&h->part, sizeof(double) * h->cells * L * 4);
-  if (e == hipSuccess) e = hipMalloc((void**)&h->tr, sizeof(double) * h->cells * 4 * L * 4);
+  const size_t tr_elem = c.precision == ADERDG_FP64 ? sizeof(double) : sizeof(float);
+  if (e == hipSuccess) e = hipMalloc(&h->tr, tr_elem * h->cells * 4 * L * 4);
   if (e != hipSuccess) { release2d(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
   e = hipMalloc((void**)&h->clk, sizeof(Clock2D));
   if (e != hipSuccess) { release2d(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }
@@ -618,7 +619,7 @@ int aderdg2d_step(aderdg2d_handle* h, double* u, double* t, const double* t_end,
   for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
     A.step = s;
     e = launch_pred2d(N, h->cfg.precision, A, blocks, h->stream);
-    if (e == hipSuccess) e = launch_corr2d(N, A, blocks2, h->stream);
+    if (e == hipSuccess) e = launch_corr2d(N, h->cfg.precision, A, blocks2, h->stream);
   }
   if (e == hipSuccess) e = launch_clock2d_end(h->clk, t, dt, status, nsteps & 1, h->stream);
   return e == hipSuccess ? ADERDG_OK : fail_hip(e, "2-D step launch");
@@ -653,7 +654,7 @@ struct aderdg3d_handle {
   aderdg3d_config cfg{};
   int64_t cells = 0;
   double* part = nullptr;
-  double* tr = nullptr;
+  void* tr = nullptr;
   Clock3D* clk = nullptr;
 };
 
@@ -721,7 +722,8 @@ int aderdg3d_init(const aderdg3d_config* cfg, void* hip_stream, aderdg3d_handle*
   h->cells = c.cells_x * c.cells_y * c.cells_z;
   const int64_t L = (int64_t)(c.N + 1) * (c.N + 1) * (c.N + 1);
   e = hipMalloc((void**)&h->part, sizeof(double) * h->cells * L * 5);
-  if (e == hipSuccess) e = hipMalloc((void**)&h->tr, sizeof(double) * h->cells * 6 * L * 5);
+  const size_t tr_elem = c.precision == ADERDG_FP64 ? sizeof(double) : sizeof(float);
+  if (e == hipSuccess) e = hipMalloc(&h->tr, tr_elem * h->cells * 6 * L * 5);
   if (e != hipSuccess) { release3d(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
   e = hipMalloc((void**)&h->clk, sizeof(Clock3D));
   if (e != hipSuccess) { release3d(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }
@@ -765,7 +767,7 @@ int aderdg3d_step(aderdg3d_handle* h, double* u, double* t, const double* t_end,
   for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
     A.step = s;
     e = launch_pred3d(N, h->cfg.precision, A, blocks, h->stream);
-    if (e == hipSuccess) e = launch_corr3d(N, A, blocks2, h->stream);
+    if (e == hipSuccess) e = launch_corr3d(N, h->cfg.precision, A, blocks2, h->stream);
   }
   if (e == hipSuccess) e = launch_clock3d_end(h->clk, t, dt, status, nsteps & 1, h->stream);
   return e == hipSuccess ? ADERDG_OK : fail_hip(e, "3-D step launch");

@@ -21,7 +21,8 @@
 // word read feeds n multiply-adds.  A converged cell freezes while the
 // others of the workgroup go on; the loop ends when no cell is active.
 // The epilogue writes the face traces of every cell (x faces from the X
-// role, y faces from the Y role) and u + volume terms, both in FP64.
+// role, y faces from the Y role; summed in FP64, stored in the predictor
+// precision) and u + volume terms in FP64.
 //
 // Corrector kernel.  Rusanov fluxes through the four faces of every cell
 // from its own and its neighbours' traces (each face is evaluated by both
@@ -427,14 +428,14 @@ pred2d_kernel(Args2D A) {
         tn[r] = fma(p1, (double)vy[r], tn[r]);
       }
     }
-    double* trc = A.tr + cell * (4 * L * M);
+    TP* trc = reinterpret_cast<TP*>(A.tr) + cell * (4 * L * M);
     const int lx = xa * n + xj, ly = ya * n + yi;
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      trc[(0 * L + lx) * M + r] = tw[r];
-      trc[(1 * L + lx) * M + r] = te[r];
-      trc[(2 * L + ly) * M + r] = ts[r];
-      trc[(3 * L + ly) * M + r] = tn[r];
+      trc[(0 * L + lx) * M + r] = TP(tw[r]);
+      trc[(1 * L + lx) * M + r] = TP(te[r]);
+      trc[(2 * L + ly) * M + r] = TP(ts[r]);
+      trc[(3 * L + ly) * M + r] = TP(tn[r]);
     }
     if (A.mode == k2dPredict) {
       TP* qo = reinterpret_cast<TP*>(A.q_out) + cell * (n * L * M);
@@ -580,7 +581,7 @@ __device__ __forceinline__ void publish_lambda(Clock2D& clk, int buf, double lx,
   }
 }
 
-template <int N>
+template <int N, class TP>
 __global__ void __launch_bounds__(256)
 corr2d_kernel(Args2D A) {
   using G = Corr2Geo<N>;
@@ -620,8 +621,8 @@ corr2d_kernel(Args2D A) {
       double qm[M], qp[M], Gr[M];
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        qm[r] = A.tr[((cm * 4 + fm) * L + a * n + k) * M + r];
-        qp[r] = A.tr[((cp * 4 + fp) * L + a * n + k) * M + r];
+        qm[r] = (double)reinterpret_cast<const TP*>(A.tr)[((cm * 4 + fm) * L + a * n + k) * M + r];
+        qp[r] = (double)reinterpret_cast<const TP*>(A.tr)[((cp * 4 + fp) * L + a * n + k) * M + r];
       }
       if (f < 2) rusanov2<0>(qm, qp, Gr, A.gamma);
       else rusanov2<1>(qm, qp, Gr, A.gamma);
@@ -748,16 +749,21 @@ hipError_t launch_pred2d(int N, int prec, const Args2D& A, int64_t blocks, hipSt
   return prec ? launch_pred2d_p<float>(N, A, blocks, st) : launch_pred2d_p<double>(N, A, blocks, st);
 }
 
-hipError_t launch_corr2d(int N, const Args2D& A, int64_t blocks, hipStream_t st) {
+template <class TP>
+static hipError_t launch_corr2d_p(int N, const Args2D& A, int64_t blocks, hipStream_t st) {
   dim3 grid((unsigned)blocks), block(256);
   switch (N) {
-#define ADERDG2_CASE(NN) case NN: hipLaunchKernelGGL((corr2d_kernel<NN>), grid, block, 0, st, A); break;
+#define ADERDG2_CASE(NN) case NN: hipLaunchKernelGGL((corr2d_kernel<NN, TP>), grid, block, 0, st, A); break;
     ADERDG2_CASE(1) ADERDG2_CASE(2) ADERDG2_CASE(3) ADERDG2_CASE(4) ADERDG2_CASE(5)
     ADERDG2_CASE(6) ADERDG2_CASE(7) ADERDG2_CASE(8) ADERDG2_CASE(9)
 #undef ADERDG2_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_corr2d(int N, int prec, const Args2D& A, int64_t blocks, hipStream_t st) {
+  return prec ? launch_corr2d_p<float>(N, A, blocks, st) : launch_corr2d_p<double>(N, A, blocks, st);
 }
 
 hipError_t launch_lambda2d(int N, const Args2D& A, int64_t blocks, hipStream_t st) {

@@ -15,7 +15,7 @@
 // tests convergence.  Every contraction runs from registers over a line the
 // thread owns.  Two tiles of n^4 M values must fit in LDS: N <= 5 in FP64,
 // N <= 6 in the FP32-predictor mode.  The epilogue writes the six face traces
-// and u + volume terms in FP64; the corrector kernel evaluates the Rusanov
+// (in the predictor precision) and u + volume terms (FP64); the corrector kernel evaluates the Rusanov
 // fluxes through the six faces, updates u in place and reduces the subcell
 // signal speeds for the next step.
 #include "launch3d.hpp"
@@ -374,13 +374,13 @@ pred3d_kernel(Args3D A) {
         tp[2][r] = fma(p1, vz, tp[2][r]);
       }
     }
-    double* trc = A.tr + cell * (6 * L * M);
+    TP* trc = reinterpret_cast<TP*>(A.tr) + cell * (6 * L * M);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        trc[((2 * d) * L + line) * M + r] = tm[d][r];
-        trc[((2 * d + 1) * L + line) * M + r] = tp[d][r];
+        trc[((2 * d) * L + line) * M + r] = TP(tm[d][r]);
+        trc[((2 * d + 1) * L + line) * M + r] = TP(tp[d][r]);
       }
     if (A.mode == k3dPredict) {
       TP* qo = reinterpret_cast<TP*>(A.q_out) + cell * (n * L * M);
@@ -535,7 +535,7 @@ __device__ __forceinline__ void publish_lambda3(Clock3D& clk, int buf, double* l
   }
 }
 
-template <int N>
+template <int N, class TP>
 __global__ void __launch_bounds__(256)
 corr3d_kernel(Args3D A) {
   using G = Corr3Geo<N>;
@@ -572,8 +572,8 @@ corr3d_kernel(Args3D A) {
       double qm[M], qp[M], Gr[M];
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        qm[r] = A.tr[((cm * 6 + 2 * d + 1) * L + a * F + st) * M + r];
-        qp[r] = A.tr[((cp * 6 + 2 * d) * L + a * F + st) * M + r];
+        qm[r] = (double)reinterpret_cast<const TP*>(A.tr)[((cm * 6 + 2 * d + 1) * L + a * F + st) * M + r];
+        qp[r] = (double)reinterpret_cast<const TP*>(A.tr)[((cp * 6 + 2 * d) * L + a * F + st) * M + r];
       }
       if (d == 0) rusanov3<0>(qm, qp, Gr, A.gamma);
       else if (d == 1) rusanov3<1>(qm, qp, Gr, A.gamma);
@@ -719,15 +719,20 @@ hipError_t launch_pred3d(int N, int prec, const Args3D& A, int64_t blocks, hipSt
   return prec ? launch_pred3d_p<float>(N, A, blocks, st) : launch_pred3d_p<double>(N, A, blocks, st);
 }
 
-hipError_t launch_corr3d(int N, const Args3D& A, int64_t blocks, hipStream_t st) {
+template <class TP>
+static hipError_t launch_corr3d_p(int N, const Args3D& A, int64_t blocks, hipStream_t st) {
   dim3 grid((unsigned)blocks), block(256);
   switch (N) {
-#define ADERDG3_CASE(NN) case NN: hipLaunchKernelGGL((corr3d_kernel<NN>), grid, block, 0, st, A); break;
+#define ADERDG3_CASE(NN) case NN: hipLaunchKernelGGL((corr3d_kernel<NN, TP>), grid, block, 0, st, A); break;
     ADERDG3_CASE(1) ADERDG3_CASE(2) ADERDG3_CASE(3) ADERDG3_CASE(4) ADERDG3_CASE(5) ADERDG3_CASE(6)
 #undef ADERDG3_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_corr3d(int N, int prec, const Args3D& A, int64_t blocks, hipStream_t st) {
+  return prec ? launch_corr3d_p<float>(N, A, blocks, st) : launch_corr3d_p<double>(N, A, blocks, st);
 }
 
 hipError_t launch_lambda3d(int N, const Args3D& A, int64_t blocks, hipStream_t st) {

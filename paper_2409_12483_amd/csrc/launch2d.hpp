@@ -40,7 +40,8 @@ struct Args2D {
   const double* t_end;     // device, one value
   double* u;               // state [cells][n][n][4] (the corrector updates it in place)
   double* part;            // scratch [cells][n][n][4]: u + volume terms
-  double* tr;              // scratch [cells][4 faces][n time][n face nodes][4]: face traces
+  void* tr;                // scratch [cells][4 faces][n time][n face nodes][4]: face traces, in the
+                           // predictor precision (FP64, or FP32 in the FP32-predictor mode)
   void* q_out;             // predictor mode: q [cells][n][n][n][4] in the predictor precision
   int32_t* iters;          // predictor mode: sweeps per cell (may be null)
 };
@@ -48,7 +49,7 @@ struct Args2D {
 int cells_per_block_2d(int N, int prec);
 int threads_per_block_2d(int N, int prec);
 hipError_t launch_pred2d(int N, int prec, const Args2D& A, int64_t blocks, hipStream_t st);
-hipError_t launch_corr2d(int N, const Args2D& A, int64_t blocks, hipStream_t st);
+hipError_t launch_corr2d(int N, int prec, const Args2D& A, int64_t blocks, hipStream_t st);
 hipError_t launch_lambda2d(int N, const Args2D& A, int64_t blocks, hipStream_t st);
 int cells_per_block_corr2d(int N);
 hipError_t launch_clock2d_begin(Clock2D* clk, const double* t_user, hipStream_t st);

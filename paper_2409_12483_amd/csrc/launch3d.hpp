@@ -33,7 +33,7 @@ struct Args3D {
   const double* t_end;     // device, one value
   double* u;               // state [cells][n][n][n][5], updated in place by the corrector
   double* part;            // scratch [cells][n][n][n][5]: u + volume terms
-  double* tr;              // scratch [cells][6 faces][n time][n][n][5]
+  void* tr;                // scratch [cells][6 faces][n time][n][n][5], predictor precision
   void* q_out;             // predictor mode: q [cells][n][n][n][n][5] in the predictor precision
   int32_t* iters;          // predictor mode: sweeps per cell (may be null)
 };
@@ -42,7 +42,7 @@ bool supported_3d(int N, int prec);
 int cells_per_block_3d(int N, int prec);
 int cells_per_block_corr3d(int N);
 hipError_t launch_pred3d(int N, int prec, const Args3D& A, int64_t blocks, hipStream_t st);
-hipError_t launch_corr3d(int N, const Args3D& A, int64_t blocks, hipStream_t st);
+hipError_t launch_corr3d(int N, int prec, const Args3D& A, int64_t blocks, hipStream_t st);
 hipError_t launch_lambda3d(int N, const Args3D& A, int64_t blocks, hipStream_t st);
 hipError_t launch_clock3d_begin(Clock3D* clk, const double* t_user, hipStream_t st);
 hipError_t launch_clock3d_end(const Clock3D* clk, double* t_user, double* dt_user,
