@@ -461,11 +461,13 @@ struct Corr3Geo {
 };
 
 // Signal-speed maxima per direction over the (2N+1)^3 subcell averages
-// (P (x) P (x) P) u of the workgroup's cells (u in LDS U), by three
-// one-direction projections through LDS (V1, V2).
+// (P (x) P (x) P) u of the workgroup's cells (u in LDS U): the x projection
+// V1 goes through LDS; then one thread per (cell, s, t) forms the y-projected
+// line sum_j P[t][j] V1[s][j][.] in registers and runs along z.  Keeping the
+// second projection out of LDS leaves room for more resident workgroups.
 template <int N>
-__device__ __forceinline__ void subcell_speeds3(const double* U, double* V1, double* V2, int ncl,
-                                                double gamma, double* lam) {
+__device__ __forceinline__ void subcell_speeds3(const double* U, double* V1, int ncl, double gamma,
+                                                double* lam) {
   using G = Corr3Geo<N>;
   constexpr int n = G::n, L = G::L, M = G::M, Ns = G::Ns;
   for (int w = threadIdx.x; w < ncl * Ns * n * n; w += G::NT) {
@@ -483,38 +485,34 @@ __device__ __forceinline__ void subcell_speeds3(const double* U, double* V1, dou
     for (int r = 0; r < M; ++r) V1[((cl * Ns + s) * n * n + jk) * M + r] = v[r];
   }
   __syncthreads();
-  for (int w = threadIdx.x; w < ncl * Ns * Ns * n; w += G::NT) {
-    const int cl = w / (Ns * Ns * n), rem = w - cl * (Ns * Ns * n);
-    const int s = rem / (Ns * n), t = (rem / n) % Ns, k = rem % n;
-    double v[M];
+  lam[0] = lam[1] = lam[2] = 0.0;
+  for (int w = threadIdx.x; w < ncl * Ns * Ns; w += G::NT) {
+    const int cl = w / (Ns * Ns), rem = w - cl * (Ns * Ns), s = rem / Ns, t = rem - s * Ns;
+    double v2[n][M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) v[r] = 0.0;
+    for (int k = 0; k < n; ++k)
+#pragma unroll
+      for (int r = 0; r < M; ++r) v2[k][r] = 0.0;
 #pragma unroll
     for (int j = 0; j < n; ++j) {
       const double P = c3_ops[N].P[t][j];
 #pragma unroll
-      for (int r = 0; r < M; ++r) v[r] = fma(P, V1[((cl * Ns + s) * n * n + j * n + k) * M + r], v[r]);
+      for (int k = 0; k < n; ++k)
+#pragma unroll
+        for (int r = 0; r < M; ++r) v2[k][r] = fma(P, V1[((cl * Ns + s) * n * n + j * n + k) * M + r], v2[k][r]);
     }
+    for (int z = 0; z < Ns; ++z) {
+      double v[M], sp[3];
 #pragma unroll
-    for (int r = 0; r < M; ++r) V2[(((cl * Ns + s) * Ns + t) * n + k) * M + r] = v[r];
-  }
-  __syncthreads();
-  lam[0] = lam[1] = lam[2] = 0.0;
-  for (int w = threadIdx.x; w < ncl * Ns * Ns * Ns; w += G::NT) {
-    const int cl = w / (Ns * Ns * Ns), rem = w - cl * (Ns * Ns * Ns);
-    const int st = rem / Ns, z = rem % Ns;
-    double v[M], sp[3];
+      for (int r = 0; r < M; ++r) {
+        v[r] = 0.0;
 #pragma unroll
-    for (int r = 0; r < M; ++r) v[r] = 0.0;
+        for (int k = 0; k < n; ++k) v[r] = fma(c3_ops[N].P[z][k], v2[k][r], v[r]);
+      }
+      Euler3::speeds(v, gamma, sp);
 #pragma unroll
-    for (int k = 0; k < n; ++k) {
-      const double P = c3_ops[N].P[z][k];
-#pragma unroll
-      for (int r = 0; r < M; ++r) v[r] = fma(P, V2[((cl * Ns * Ns + st) * n + k) * M + r], v[r]);
+      for (int d = 0; d < 3; ++d) lam[d] = fmax(lam[d], sp[d]);
     }
-    Euler3::speeds(v, gamma, sp);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) lam[d] = fmax(lam[d], sp[d]);
   }
 }
 
@@ -543,7 +541,6 @@ corr3d_kernel(Args3D A) {
   __shared__ double Gf[CPB * 6 * F * M];
   __shared__ double U[CPB * L * M];
   __shared__ double V1[CPB * Ns * F * M];
-  __shared__ double V2[CPB * Ns * Ns * n * M];
   __shared__ double bcast[3];
   __shared__ double part[12];
 
@@ -613,7 +610,7 @@ corr3d_kernel(Args3D A) {
     atomicMin(&A.clk->stat[(blockIdx.x + (threadIdx.x >> 6)) % kSlots].v, -5);
   __syncthreads();
   double lam[3];
-  subcell_speeds3<N>(U, V1, V2, ncl, A.gamma, lam);
+  subcell_speeds3<N>(U, V1, ncl, A.gamma, lam);
   publish_lambda3(*A.clk, (A.step + 1) % 3, lam, part);
 }
 
@@ -624,7 +621,6 @@ lambda3d_kernel(Args3D A) {
   constexpr int n = G::n, L = G::L, M = G::M, Ns = G::Ns, CPB = G::CPB, F = n * n;
   __shared__ double U[CPB * L * M];
   __shared__ double V1[CPB * Ns * F * M];
-  __shared__ double V2[CPB * Ns * Ns * n * M];
   __shared__ double part[12];
   const int64_t ncells = A.c[0] * A.c[1] * A.c[2];
   const int64_t cell0 = (int64_t)blockIdx.x * CPB;
@@ -632,7 +628,7 @@ lambda3d_kernel(Args3D A) {
   for (int w = threadIdx.x; w < ncl * L * M; w += G::NT) U[w] = A.u[cell0 * L * M + w];
   __syncthreads();
   double lam[3];
-  subcell_speeds3<N>(U, V1, V2, ncl, A.gamma, lam);
+  subcell_speeds3<N>(U, V1, ncl, A.gamma, lam);
   publish_lambda3(*A.clk, 0, lam, part);
 }
 
