@@ -537,6 +537,46 @@ def dg2d_time_to_solution(N, C, precision=0, chunk=128):
             "status": st}
 
 
+def oracle_rate(run, dofs_per_step, target_s=6.0, max_steps=40):
+    """The oracle, as is, stepped on a bounded sample for about target_s seconds:
+    DoF-updates/s on one host thread."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < target_s and steps < max_steps:
+            run()
+            steps += 1
+        el = time.perf_counter() - t0
+    return round(steps * dofs_per_step / el, 1), steps
+
+
+def dg2d_cpu_baseline(N=5, C=32):
+    from oracle import basis, dg2d
+    from paper_2409_12483_amd import workloads as W
+    ops, pde = basis.build_operators(N), dg2d.Euler2D()
+    state = {"u": W.euler2d_sine_wave(C, C, N)}
+
+    def one():
+        state["u"], _, _ = dg2d.dg2d_run(ops, pde, state["u"], nsteps=1)
+    v, steps = oracle_rate(one, C * C * (N + 1) ** 2 * 4)
+    return {"value": v, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"the same sine wave on {C}x{C} cells, N={N}, {steps} steps, NumPy FP64, single thread"}
+
+
+def dg3d_cpu_baseline(N=3, C=8):
+    from oracle import basis, dg3d
+    from paper_2409_12483_amd import workloads as W
+    ops, pde = basis.build_operators(N), dg3d.Euler3D()
+    state = {"u": W.euler3d_sine_wave(C, C, C, N)}
+
+    def one():
+        state["u"], _, _ = dg3d.dg3d_run(ops, pde, state["u"], nsteps=1)
+    v, steps = oracle_rate(one, C ** 3 * (N + 1) ** 3 * 5)
+    return {"value": v, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"the same sine wave on {C}^3 cells, N={N}, {steps} steps, NumPy FP64, single thread"}
+
+
 def dg2d_section(quick=False):
     from paper_2409_12483_amd import abi
     out = {"workload": "ADER-DG 2D Euler gamma=1.4, sine wave rho=1+0.5 sin(2 pi (x+y)), velocity (1,1), "
@@ -548,6 +588,7 @@ def dg2d_section(quick=False):
     out["per_degree_fp64"] = [dg2d_entry(N, 512 if N <= 6 else 256, abi.FP64, 10, 3) for N in range(1, 10)]
     out["paper_table10_time_to_solution"] = [dg2d_time_to_solution(N, C) for N in range(1, 10)
                                              for C in (4, 8, 12, 16)]
+    out["cpu_baseline_n5"] = dg2d_cpu_baseline()
     return out
 
 
@@ -669,6 +710,7 @@ def dg3d_section(quick=False):
     out["n6_32c_fp32_predictor"] = dg3d_entry(6, 32, abi.FP32_PREDICTOR, 10, 3)
     out["paper_table11_time_to_solution"] = [dg3d_time_to_solution(N, C) for N in range(1, 6)
                                              for C in (4, 5, 6, 7)]
+    out["cpu_baseline_n3"] = dg3d_cpu_baseline()
     return out
 
 
@@ -680,12 +722,14 @@ def cpu_baseline(N, target_s=12.0):
     ops = basis.build_operators(N)
     C = 20_000
     u = W.euler_density_wave(C, N, noise=1e-3, seed=0)
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < target_s and steps < 50:
-        u, _, _ = dg.dg_run(ops, OP.Euler(), u, 0.0, 1.0, cfl=0.4, nsteps=1)
-        steps += 1
-    el = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < target_s and steps < 50:
+            u, _, _ = dg.dg_run(ops, OP.Euler(), u, 0.0, 1.0, cfl=0.4, nsteps=1)
+            steps += 1
+        el = time.perf_counter() - t0
     return {"value": round(steps * C * (N + 1) * 3 / el, 1), "unit": "DoF-updates/s",
             "cores": 1, "kind": "oracle",
             "sample": f"{C} cells of the same mesh family (dx = 1/{C}), {steps} steps, NumPy FP64, single thread"}
