@@ -6,7 +6,8 @@
   workgroup partly empty;
 * edge cases: a single cell (its own neighbour on all six sides), one-cell
   slabs, zero steps, a fixed step, the last step clamped to t_end;
-* full size (48^3 cells, N = 3): a wave of period 4 cells equals, on every
+* full size (48^3 and 64^3 cells at N = 3, 40^3 at N = 5 in FP64 and with the
+  FP32 predictor): a wave of period 4 cells equals, on every
   cell, the oracle's 4^3 run repeated.
 """
 
@@ -124,16 +125,27 @@ def test_zero_steps_fixed_dt_and_clamp():
     assert rel_l2(u, ref) <= 1e-12 and t == 1e-3 and t_ref == 1e-3 and dt == 1e-3
 
 
-def test_full_size_periodic_wave_equals_repeated_oracle():
-    N, C, per = 3, 48, 4
-    _say("3d full size tiled", N, C)
+@pytest.mark.parametrize("N,C,prec", [(3, 48, abi.FP64), (3, 64, abi.FP64), (5, 40, abi.FP64),
+                                       (5, 40, abi.FP32_PREDICTOR)])
+def test_full_size_periodic_wave_equals_repeated_oracle(N, C, prec):
+    """The mesh sizes, degrees, precisions and CFL number of the timed 3-D
+    runs, with a wave of period 4 cells: every 4^3 block of the GPU result
+    equals the oracle's run on one block, and the sweep total is k^3 times the
+    oracle's (FP64)."""
+    per = 4
+    _say("3d full size tiled", N, C, prec)
     ops = basis.build_operators(N)
     k = C // per
     big = W.euler3d_sine_wave(C, C, C, N, k=(k, k, k))
     small = W.euler3d_sine_wave(per, per, per, N, k=(k, k, k), extent=(per / C,) * 3)
-    ref, t_ref, _ = dg3d.dg3d_run(ops, E3, small, extent=(per / C,) * 3, nsteps=2)
-    u, t, _, st, _ = gpu_run(big, N, 2)
+    ref, t_ref, info = dg3d.dg3d_run(ops, E3, small, extent=(per / C,) * 3, nsteps=2)
+    u, t, _, st, sweeps = gpu_run(big, N, 2, prec=prec)
     assert st == 0
     tiled = np.tile(ref, (k, k, k, 1, 1, 1, 1))
-    assert np.abs(u - tiled).max() <= 1e-12 * np.abs(ref).max()
-    assert abs(t - t_ref) <= 1e-14 * t_ref
+    if prec == abi.FP64:
+        assert np.abs(u - tiled).max() <= 1e-12 * np.abs(ref).max()
+        assert abs(t - t_ref) <= 1e-14 * t_ref
+        assert sweeps == k ** 3 * sum(c * v for c, v in info["sweep_hist"].items())
+    else:
+        assert 0.0 < rel_l2(u, tiled) <= 1e-5
+        assert abs(t - t_ref) <= 1e-5 * t_ref
