@@ -538,11 +538,14 @@ __global__ void __launch_bounds__(256)
 corr3d_kernel(Args3D A) {
   using G = Corr3Geo<N>;
   constexpr int n = G::n, L = G::L, M = G::M, Ns = G::Ns, CPB = G::CPB, F = n * n;
-  __shared__ double Gf[CPB * 6 * F * M];
+  // the face fluxes Gf are dead once the nodes are updated (a barrier later),
+  // so the x projection V1 of the subcell averages reuses their LDS
+  __shared__ double GV[CPB * (6 > Ns ? 6 : Ns) * F * M];
   __shared__ double U[CPB * L * M];
-  __shared__ double V1[CPB * Ns * F * M];
   __shared__ double bcast[3];
   __shared__ double part[12];
+  double* const Gf = GV;
+  double* const V1 = GV;
 
   const double dt = step_dt3d<N>(A, bcast, false);
   if (!(dt > 0.0)) return;
