@@ -154,7 +154,10 @@ struct Pred3Geo {
   static constexpr int NT = ((CPB * L + 63) / 64) * 64;
   static constexpr int VB = CPB * 3 * L * M;             // doubles of the volume buffer
   static constexpr bool kVbAlias = CPB * TILE * (int)sizeof(TP) >= VB * 8;
-  static constexpr int kBytes = 2 * CPB * TILE * (int)sizeof(TP) + (kVbAlias ? 0 : VB * 8);
+  // too large for R alone but not for Q and R together (both dead once the
+  // fluxes of the volume terms are in registers): overlay both, one barrier more
+  static constexpr bool kVbOverQR = !kVbAlias && 2 * CPB * TILE * (int)sizeof(TP) >= VB * 8;
+  static constexpr int kBytes = 2 * CPB * TILE * (int)sizeof(TP) + (kVbAlias || kVbOverQR ? 0 : VB * 8);
   __device__ static constexpr int at(int a, int i, int j, int k) { return a * SA + i * SI + j * SJ + k * M; }
 };
 
@@ -170,9 +173,13 @@ pred3d_kernel(Args3D A) {
   constexpr int n = G::n, L = G::L, M = G::M, CPB = G::CPB;
   using Bits = decltype(ord_bits(TP(0)));
 
-  __shared__ TP Qs[CPB * G::TILE];
-  __shared__ TP Rs[CPB * G::TILE];
-  __shared__ double Vsep[G::kVbAlias ? 1 : G::VB];
+  constexpr bool kQR = G::kVbOverQR;
+  __shared__ __align__(16) TP QR[kQR ? 2 * CPB * G::TILE : 1];
+  __shared__ TP Qsep[kQR ? 1 : CPB * G::TILE];
+  __shared__ TP Rsep[kQR ? 1 : CPB * G::TILE];
+  __shared__ double Vsep[G::kVbAlias || kQR ? 1 : G::VB];
+  TP* const Qs = kQR ? QR : Qsep;
+  TP* const Rs = kQR ? QR + CPB * G::TILE : Rsep;
   __shared__ Bits red[2][CPB][2];
   __shared__ double bcast[3];
   __shared__ unsigned int swsum;
@@ -392,14 +399,14 @@ pred3d_kernel(Args3D A) {
     }
   }
   // volume terms from the time-integrated fluxes of the (promoted) predictor
-  double* const Vb = G::kVbAlias ? reinterpret_cast<double*>(Rs) : Vsep;
+  double* const Vb = G::kVbAlias ? reinterpret_cast<double*>(Rs) : kQR ? reinterpret_cast<double*>(QR) : Vsep;
   double* const Vc = Vb + (mine ? cl : 0) * (3 * L * M);
+  double fb[3][M];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int r = 0; r < M; ++r) fb[d][r] = 0.0;
   if (mine) {
-    double fb[3][M];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int r = 0; r < M; ++r) fb[d][r] = 0.0;
 #pragma unroll
     for (int a = 0; a < n; ++a) {
       double qd[M], f[M];
@@ -416,7 +423,11 @@ pred3d_kernel(Args3D A) {
 #pragma unroll
       for (int r = 0; r < M; ++r) fb[2][r] = fma(wa, (dt / A.h[2]) * f[r], fb[2][r]);
     }
-    // in the aliased case Vb overlays R, last read before the loop's final barriers
+  }
+  // Vb overlays R (last read before the loop's final barriers), or Q and R:
+  // then every read of Q above must be done before the first store
+  if constexpr (kQR) __syncthreads();
+  if (mine) {
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll

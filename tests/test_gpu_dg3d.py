@@ -85,7 +85,7 @@ def test_fused_steps_match_oracle(N):
     assert sweeps == sum(k * v for k, v in info["sweep_hist"].items())
 
 
-@pytest.mark.parametrize("N", [2, 5, 6])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6])
 def test_fp32_predictor_within_1e5(N):
     _say("3d fp32", N)
     ops = basis.build_operators(N)
