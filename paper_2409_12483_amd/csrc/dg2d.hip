@@ -175,7 +175,10 @@ __device__ __forceinline__ double step_dt2d(const Args2D& A, double& t, double* 
 // stride and the orders below were chosen per n (with the cells per
 // workgroup) so that 8- and 16-lane groups of the three access patterns of
 // a sweep (X: lanes over (a, j); Y: lanes over (a, i); T: lanes over (i, j))
-// fall on distinct 16-byte bank groups as far as a linear layout allows.
+// fall on distinct 16-byte bank groups as far as a linear layout allows;
+// at n = 3 and n = 5 the tiles are unpadded instead, since the padding cost
+// resident workgroups (3 -> 6 and 3 -> 4 per CU) worth more than the
+// conflicts it removed (measured: -11 % per step at both in FP64).
 // Cells per workgroup: whole wavefronts with few idle lanes and room for a
 // second resident workgroup up to N = 5; one cell (one or two wavefronts)
 // from N = 6 on, where many small workgroups per CU hide latency better than
@@ -187,7 +190,7 @@ struct Layout2 {
 };
 constexpr Layout2 kLayout2[11] = {
     {0, 0, 0, 0, 0, 0},        {0, 0, 0, 0, 0, 0},       {64, 5, 12, 0, 0, 0},
-    {14, 18, 57, 0, 1, 1},     {8, 19, 76, 0, 0, 1},     {5, 25, 137, 0, 0, 0},
+    {14, 9, 27, 0, 1, 1},      {8, 19, 76, 0, 0, 1},     {5, 25, 125, 0, 0, 0},
     {5, 41, 252, 0, 0, 1},     {1, 49, 353, 0, 0, 1},    {1, 65, 520, 0, 0, 1},
     {3, 81, 729, 1, 0, 0},     {1, 105, 1050, 0, 0, 1}};
 
