@@ -150,7 +150,9 @@ struct Pred3Geo {
   static constexpr int SI = n * SJ + kPad3[N + 1][1];
   static constexpr int SA = n * SI + kPad3[N + 1][2];
   static constexpr int TILE = n * SA;                    // elements of one tile
-  static constexpr int CPB = L >= 64 ? 1 : 256 / L;      // whole wavefronts, few idle lanes
+  // whole wavefronts with few idle lanes; in FP64 at N = 1, 2 fewer cells, so
+  // that more workgroups (and more cells in all) fit in the LDS of a CU
+  static constexpr int CPB = L >= 64 ? 1 : sizeof(TP) == 8 && N <= 2 ? (N == 1 ? 16 : 4) : 256 / L;
   static constexpr int NT = ((CPB * L + 63) / 64) * 64;
   static constexpr int VB = CPB * 3 * L * M;             // doubles of the volume buffer
   static constexpr bool kVbAlias = CPB * TILE * (int)sizeof(TP) >= VB * 8;
