@@ -45,6 +45,7 @@ def fv_run(ops, pde, v, x0, x1, cfl=0.4, t_end=np.inf, nsteps=None, t0=0.0,
     t = float(t0)
     steps = 0
     sweep_hist = {}
+    dts = []
     any_failed = False
     while (nsteps is None or steps < nsteps) and t < t_end:
         dt = fixed_dt if fixed_dt else fv_dt(pde, v, dx, cfl)
@@ -56,5 +57,6 @@ def fv_run(ops, pde, v, x0, x1, cfl=0.4, t_end=np.inf, nsteps=None, t0=0.0,
         for s, c in zip(*np.unique(sweeps, return_counts=True)):
             sweep_hist[int(s)] = sweep_hist.get(int(s), 0) + int(c)
         t += dt
+        dts.append(dt)
         steps += 1
-    return v, t, {"steps": steps, "sweep_hist": sweep_hist, "failed": any_failed}
+    return v, t, {"steps": steps, "dts": dts, "sweep_hist": sweep_hist, "failed": any_failed}

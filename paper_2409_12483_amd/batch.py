@@ -48,6 +48,12 @@ class Batch:
         self.t_end = torch.full((n,), 1.0e300, dtype=torch.float64, device=dev)
         self.dt = torch.zeros(n, dtype=torch.float64, device=dev)
         self.status = torch.zeros(n, dtype=torch.int32, device=dev)
+        # most severe status seen by each problem over all calls (the library
+        # reports the status of the last call only)
+        self.sticky = torch.zeros(n, dtype=torch.int32, device=dev)
+        # the buffers above were filled on the current stream; the handle's
+        # stream must not run ahead of those fills
+        self.stream.wait_stream(torch.cuda.current_stream())
         descs = [abi.pde_desc(_PDE[s["pde"]]) for s in self.specs]
         cfgs = [abi.config(s["N"], s["ncells"], precision=precision, cfl=cfl) for s in self.specs]
         self.h = abi.aderdg_init(descs, cfgs, stream=self.stream.cuda_stream)
@@ -62,6 +68,7 @@ class Batch:
         """Enqueue nsteps steps of every problem (asynchronous)."""
         with self.torch.cuda.stream(self.stream):
             abi.aderdg_step(self.h, self.u, self.t, self.t_end, self.dt, self.status, nsteps)
+            self.torch.minimum(self.sticky, self.status, out=self.sticky)
 
     def capture(self, nsteps):
         """Capture an advance of nsteps steps into a HIP graph.  The state
@@ -72,6 +79,7 @@ class Batch:
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=self.stream):
             abi.aderdg_step(self.h, self.u, self.t, self.t_end, self.dt, self.status, nsteps)
+            torch.minimum(self.sticky, self.status, out=self.sticky)
         self.graph, self.graph_steps = g, nsteps
 
     def replay(self):

@@ -96,7 +96,8 @@ class GpuExecutor:
         self.stream.synchronize()
 
     def status(self, cohort):
-        return cohort.status.cpu().numpy()
+        """Most severe status of each problem over every call so far."""
+        return cohort.sticky.cpu().numpy()
 
     def state(self, cohort, i):
         return cohort.u[i].cpu().numpy()

@@ -185,3 +185,33 @@ def euler3d_sine_wave(cx, cy, cz, N, amp=0.5, k=(1, 1, 1), velocity=(1.0, 1.0, 1
 def euler3d_sine_wave_exact(x, y, z, t, amp=0.5, k=(1, 1, 1), velocity=(1.0, 1.0, 1.0)):
     return 1.0 + amp * np.sin(2.0 * np.pi * (k[0] * (x - velocity[0] * t) + k[1] * (y - velocity[1] * t)
                                              + k[2] * (z - velocity[2] * t)))
+
+
+def swe_lake_at_rest_nodal(ncells, N, kind="linear", x0=0.0, x1=1.0, amp=0.2, seed=0):
+    """Shallow water at rest over a bathymetry, nodal (h, hu, b): u[C, N+1, 3].
+
+    h + b = 1 and hu = 0 everywhere.  kind = "linear": b is continuous and
+    piecewise linear between seeded edge values (kinks at the cell edges);
+    kind = "step": b is constant in every cell (seeded values), so it jumps
+    at every edge.  Periodic: the edge value at x1 equals the one at x0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xs = cell_points(ncells, N + 1, x0, x1)
+    if kind == "linear":
+        edges = 0.1 + amp * rng.uniform(0.0, 1.0, ncells)           # b at the left edge of each cell
+        left, right = edges, np.roll(edges, -1)
+        xi, _ = gl_points_01(N + 1)
+        b = left[:, None] + (right - left)[:, None] * xi[None, :]
+    elif kind == "step":
+        b = np.broadcast_to((0.1 + amp * rng.uniform(0.0, 1.0, ncells))[:, None], xs.shape).copy()
+    else:
+        raise ValueError(kind)
+    return np.stack([1.0 - b, np.zeros_like(b), b], axis=-1)
+
+
+def swe_lake_at_rest_averages(ncells, x0=0.0, x1=1.0, npts=16):
+    """Cell averages of the lake at rest over the Gaussian bump of the shallow-water
+    workload: b = 0.2 exp(-100 (x - 0.5)^2), h = 1 - b, hu = 0: v[C, 3]."""
+    xs = cell_points(ncells, npts, x0, x1)
+    _, w = gl_points_01(npts)
+    b = 0.2 * np.exp(-100.0 * (xs - 0.5) ** 2)
+    return np.stack([(1.0 - b) @ w, np.zeros(ncells), b @ w], axis=-1)

@@ -48,3 +48,16 @@ def test_dg3d_flop_model_values():
     pred, rest = bench.dg3d_flops_per_cell(3, 1.0)
     assert pred == 3 * 256 * 23 + 8 * 1024 * 5 + 5 * 256 * 5 == 65024
     assert rest > 0
+
+
+def test_roofline_bound_is_hbm_at_n1_and_alu_at_n5():
+    """The fused step's time bound: algorithmic bytes (2 n M 8 per cell) at
+    8 TB/s against algorithmic flops at the FP64 VALU peak; N = 1 sits below
+    the ridge point (about 7.7 flop/B against 9.8), N = 5 far above."""
+    C, K = 100_000, 10
+    lo = bench.roofline_entry(1, C, 3, K, 1e-3, 2 * C * K, "fp64")
+    assert lo["bound"] == "hbm" and lo["unit"] == "GB/s"
+    assert lo["algorithmic_bytes_per_launch"] == 2 * 2 * 3 * 8 * C
+    hi = bench.roofline_entry(5, C, 3, K, 1e-3, 6 * C * K, "fp64")
+    assert hi["bound"] == "alu" and hi["peak"] == bench.PEAK_FP64_VALU
+    assert abs(hi["frac"] - hi["achieved"] / hi["peak"]) <= 1e-3

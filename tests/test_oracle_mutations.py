@@ -12,7 +12,7 @@ import copy
 import numpy as np
 import pytest
 
-from oracle import basis, brute, dg, pade, predictor
+from oracle import basis, brute, dg, fv, pade, predictor
 from oracle import pde as P
 from paper_2409_12483_amd import workloads as W
 
@@ -128,3 +128,86 @@ def test_planted_missing_source_in_corrector_is_caught(monkeypatch):
     monkeypatch.setattr(dg, "volume_source_terms",
                         lambda ops, pde, q, dt, dx, x_left, t0: np.zeros((q.shape[0], ops.n, q.shape[-1])))
     assert not _all_pins_pass(basis.build_operators(N))
+
+
+# ------------------------------------------------------------ shallow water ----
+# Quick versions of the pins in test_oracle_swe.py: the DG lake at rest over a
+# piecewise-linear bathymetry, the first step over a step bathymetry (momentum
+# stays zero), the FV lake at rest at fifth order, and the FV time step of a
+# uniform state.  The shallow-water mistakes below must each break one of them.
+
+def _swe_pin_dg_linear_lake():
+    swe = P.ShallowWater()
+    u = W.swe_lake_at_rest_nodal(8, 2, kind="linear")
+    u1, _, _ = dg.dg_run(basis.build_operators(2), swe, u, 0.0, 1.0, cfl=0.4, nsteps=10)
+    return np.abs(u1[..., 1]).max() <= 1e-13
+
+
+def _swe_pin_dg_step_lake():
+    swe = P.ShallowWater()
+    u = W.swe_lake_at_rest_nodal(8, 1, kind="step")
+    u1, _, _ = dg.dg_run(basis.build_operators(1), swe, u, 0.0, 1.0, cfl=0.4, nsteps=1)
+    return np.abs(u1[..., 1]).max() <= 1e-14
+
+
+def _swe_pin_fv_lake_order():
+    swe = P.ShallowWater()
+    ops = basis.build_operators(4)
+    errs = []
+    for C in (64, 128):
+        v = W.swe_lake_at_rest_averages(C)
+        v1, _, _ = fv.fv_run(ops, swe, v, 0.0, 1.0, cfl=0.4, t_end=0.02)
+        errs.append(np.abs(v1[:, 1]).max())
+    return np.isfinite(errs).all() and np.log2(errs[0] / errs[1]) >= 4.5 and errs[1] <= 3e-6
+
+
+def _swe_pin_fv_dt():
+    swe = P.ShallowWater()
+    v = np.tile([1.3, 0.39, 0.2], (20, 1))
+    _, _, info = fv.fv_run(basis.build_operators(4), swe, v, 0.0, 1.0, cfl=0.4, nsteps=1)
+    expect = 0.4 * 0.05 / (0.3 + np.sqrt(9.81 * 1.3))
+    return abs(info["dts"][0] - expect) <= 1e-15 * expect
+
+
+SWE_PINS = [_swe_pin_dg_linear_lake, _swe_pin_dg_step_lake, _swe_pin_fv_lake_order, _swe_pin_fv_dt]
+
+
+def _all_swe_pins_pass():
+    with np.errstate(all="ignore"):
+        return all(pin() for pin in SWE_PINS)
+
+
+def test_unmutated_oracle_passes_every_shallow_water_pin():
+    assert _all_swe_pins_pass()
+
+
+def test_planted_sign_error_in_volume_non_conservative_term_is_caught(monkeypatch):
+    # the corrector's volume term with + (dt/dx) B(q) dq instead of - (shared by DG and FV)
+    def wrong(ops, pde, q, dt, dx, x_left, t0):
+        sb = np.zeros_like(q)
+        if pde.has_ncp:
+            dq = np.einsum("lj,cajr->calr", ops.ktil, q)
+            sb = sb + (dt / dx) * pde.ncp(q, dq)
+        return np.einsum("a,cakr->ckr", ops.w, sb)
+    monkeypatch.setattr(dg, "volume_source_terms", wrong)
+    monkeypatch.setattr(fv, "volume_source_terms", wrong)
+    assert not _all_swe_pins_pass()
+
+
+def test_planted_doubled_non_conservative_product_is_caught(monkeypatch):
+    orig = P.ShallowWater.ncp
+    monkeypatch.setattr(P.ShallowWater, "ncp", lambda self, Q, dQ: 2.0 * orig(self, Q, dQ))
+    assert not _all_swe_pins_pass()
+
+
+@pytest.mark.parametrize("factor", [-1.0, 0.0, 2.0])
+def test_planted_wrong_path_conservative_jump_is_caught(monkeypatch, factor):
+    orig = P.ShallowWater.ncp_jump
+    monkeypatch.setattr(P.ShallowWater, "ncp_jump", lambda self, a, b: factor * orig(self, a, b))
+    assert not _all_swe_pins_pass()
+
+
+def test_planted_halved_finite_volume_time_step_is_caught(monkeypatch):
+    orig = fv.fv_dt
+    monkeypatch.setattr(fv, "fv_dt", lambda pde, v, dx, cfl: 0.5 * orig(pde, v, dx, cfl))
+    assert not _all_swe_pins_pass()
