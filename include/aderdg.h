@@ -149,6 +149,28 @@ int aderdg_step(aderdg_handle* h, double* const* u, double* t, const double* t_e
 int aderweno_step(aderdg_handle* h, double* const* v, double* t, const double* t_end, double* dt,
                   int32_t* status, int32_t nsteps);
 
+/*
+ * aderdg_step_noalloc -- aderdg_step / aderweno_step for ONE problem without a
+ * handle and without any device allocation, for callers that cannot allocate
+ * (code under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  pde, cfg: the problem (host structs, as for aderdg_init; cfg->scheme
+ * selects the DG or the FV step).  u: device state (DG [ncells][N+1][M], FV
+ * [ncells][M], fp64, in/out).  t, t_end, dt, status: device arrays of one
+ * element each, as for aderdg_step.  hip_stream: the stream to enqueue on (NULL =
+ * default).  Same kernels and results as aderdg_step on a one-problem handle.
+ * The library-owned memory the step needs (the state's ping-pong copy, the
+ * problem clock and descriptors) lives in a static device array of 64 MiB per
+ * device, held until the process ends: the state may hold at most
+ * (64 MiB - 64 KiB) / 8 = 8 380 416 doubles, otherwise E_INVAL before anything
+ * is enqueued.  Every call on a device shares that array, so calls that
+ * overlap on one device (different streams or threads) race; calls in stream
+ * order are safe.  No host synchronisation; the enqueued work holds no memset
+ * node and is capturable.
+ */
+int aderdg_step_noalloc(const aderdg_pde_desc* pde, const aderdg_config* cfg, double* u, double* t,
+                        const double* t_end, double* dt, int32_t* status, int32_t nsteps,
+                        void* hip_stream);
+
 /* aderdg_free -- release the handle (synchronises its stream first).  NULL is accepted. */
 int aderdg_free(aderdg_handle* h);
 
@@ -173,6 +195,20 @@ int aderdg_sweep_count(aderdg_handle* h, int32_t k, int64_t* sweeps_out);
  * output; E_INVAL on a null pointer or an index out of range.
  */
 int aderdg_contraction_count(aderdg_handle* h, int32_t k, int64_t* count_out);
+
+/*
+ * aderdg_conserved_totals -- the conserved totals of problem k's state u
+ * (device, the problem's layout): out[r] = dx sum_i sum_k w_k u_i[k][r] for DG
+ * (the exact integral of the nodal polynomial over the mesh, with the GL
+ * weights of eq. gl_rule), dx sum_i v_i[r] for FV.  The corrector of Sec. 1.2
+ * (eq. ader_dg_method_full) changes them only by round-off for conservation
+ * laws (interface terms telescope over a periodic mesh), so their drift over a
+ * run measures conservation.  totals_out: device fp64 [M].  Two kernels on the
+ * handle's stream with a fixed summation order (bitwise reproducible); no host
+ * synchronisation.  Uses the handle's partial-sum buffer, so calls on one
+ * handle are stream-ordered.  E_INVAL on a null pointer or a bad index.
+ */
+int aderdg_conserved_totals(aderdg_handle* h, int32_t k, const double* u, double* totals_out);
 
 /*
  * aderdg_operators -- host-only copy of the library's 1-D operator tables for

@@ -28,7 +28,7 @@ NVARS = {PDE_ADVECTION: 1, PDE_EULER: 3, PDE_EULER_REACT: 5, PDE_SWE: 3}
 
 EXPORTS = ["aderdg_init", "aderdg_predict", "aderdg_correct", "aderdg_step", "aderweno_step",
            "aderdg_free", "aderdg_set_stream", "aderdg_sweep_count", "aderdg_contraction_count",
-           "aderdg_operators", "aderdg_last_error"]
+           "aderdg_operators", "aderdg_conserved_totals", "aderdg_step_noalloc", "aderdg_last_error"]
 EXPORTS_2D = ["aderdg2d_init", "aderdg2d_predict", "aderdg2d_step", "aderdg2d_sweep_count",
               "aderdg2d_free"]
 EXPORTS_3D = ["aderdg3d_init", "aderdg3d_predict", "aderdg3d_step", "aderdg3d_sweep_count",
@@ -97,6 +97,9 @@ def load(path=None):
     lib.aderdg_sweep_count.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.aderdg_contraction_count.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.aderdg_operators.argtypes = [i32, ctypes.POINTER(dbl), i64]
+    lib.aderdg_conserved_totals.argtypes = [vp, i32, vp, vp]
+    lib.aderdg_step_noalloc.argtypes = [ctypes.POINTER(PdeDesc), ctypes.POINTER(Config), vp, vp, vp,
+                                        vp, vp, i32, vp]
     lib.aderdg_last_error.argtypes = []
     lib.aderdg_last_error.restype = ctypes.c_char_p
     lib.aderdg2d_init.argtypes = [ctypes.POINTER(Config2D), vp, ctypes.POINTER(vp)]
@@ -177,6 +180,14 @@ def aderweno_step(h, v, t, t_end, dt, status, nsteps):
     return _check(load().aderweno_step(h, _ptr_array(v), _ptr(t), _ptr(t_end), _ptr(dt), _ptr(status), nsteps))
 
 
+def aderdg_step_noalloc(pde, cfg, u, t, t_end, dt, status, nsteps, stream=None):
+    """One problem, no handle, no device allocation (library-resident scratch).
+    stream: HIP stream handle (default: torch's current)."""
+    s = _current_stream() if stream is None else stream
+    return _check(load().aderdg_step_noalloc(ctypes.byref(pde), ctypes.byref(cfg), _ptr(u), _ptr(t),
+                                             _ptr(t_end), _ptr(dt), _ptr(status), nsteps, s))
+
+
 def aderdg_free(h):
     return _check(load().aderdg_free(h))
 
@@ -195,6 +206,11 @@ def aderdg_contraction_count(h, k):
     v = ctypes.c_int64()
     _check(load().aderdg_contraction_count(h, k, ctypes.byref(v)))
     return v.value
+
+
+def aderdg_conserved_totals(h, k, u, out):
+    """Enqueue the conserved totals of problem k's state u into the device array out [M]."""
+    return _check(load().aderdg_conserved_totals(h, k, _ptr(u), _ptr(out)))
 
 
 def aderdg_operators(N):

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libaderdg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("ADERDG_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "dg2d.hip", "dg3d.hip", "abi.cpp", "operators.cpp"]
+SOURCES = ["kernels.hip", "dg2d.hip", "dg3d.hip", "noalloc.hip", "abi.cpp", "operators.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -134,6 +134,7 @@ struct aderdg_handle {
   std::vector<ProbDev> single_host;    // per-problem descriptor for the standalone kernels
   ProbDev* single_dev = nullptr;
   ProbClock* clocks = nullptr;
+  double* partials = nullptr;          // conserved-totals partial sums (largest problem)
   std::vector<Group> groups;
 };
 
@@ -149,6 +150,7 @@ void release(aderdg_handle* h) {
   }
   if (h->single_dev) (void)hipFree(h->single_dev);
   if (h->clocks) (void)hipFree(h->clocks);
+  if (h->partials) (void)hipFree(h->partials);
   delete h;
 }
 
@@ -182,13 +184,11 @@ int validate(const aderdg_pde_desc& p, const aderdg_config& c, int k) {
   return ADERDG_OK;
 }
 
-ProbDev make_probdev(const aderdg_handle* h, int k) {
-  const aderdg_pde_desc& p = h->pdes[k];
-  const aderdg_config& c = h->cfgs[k];
+ProbDev probdev_of(const aderdg_pde_desc& p, const aderdg_config& c, int k, double* scratch) {
   ProbDev d;
   std::memset(&d, 0, sizeof(d));
   d.state[0] = nullptr;
-  d.state[1] = h->scratch[k];
+  d.state[1] = scratch;
   d.ncells = c.ncells;
   d.x0 = c.x0;
   d.dx = (c.x1 - c.x0) / (double)c.ncells;
@@ -203,6 +203,10 @@ ProbDev make_probdev(const aderdg_handle* h, int k) {
   d.pp.omega = p.omega;
   d.pp.a = p.adv_speed;
   return d;
+}
+
+ProbDev make_probdev(const aderdg_handle* h, int k) {
+  return probdev_of(h->pdes[k], h->cfgs[k], k, h->scratch[k]);
 }
 
 int upload_group(aderdg_handle* h, Group& g) {
@@ -321,6 +325,13 @@ int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t 
     e = hipMalloc((void**)&h->scratch[k], sizeof(double) * h->elems[k]);
     if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
   }
+  int64_t nparts = 1;
+  for (int k = 0; k < nprob; ++k) {
+    const int64_t p = totals_partials(cfgs[k].ncells) * pdes[k].nvars;
+    if (p > nparts) nparts = p;
+  }
+  e = hipMalloc((void**)&h->partials, sizeof(double) * nparts);
+  if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "partials allocation"); }
   e = hipMalloc((void**)&h->clocks, sizeof(ProbClock) * nprob);
   if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }
   e = hipMemset(h->clocks, 0, sizeof(ProbClock) * nprob);
@@ -450,6 +461,74 @@ int aderdg_free(aderdg_handle* h) {
   return ADERDG_OK;
 }
 
+int aderdg_step_noalloc(const aderdg_pde_desc* pde, const aderdg_config* cfg, double* u, double* t,
+                        const double* t_end, double* dt, int32_t* status, int32_t nsteps,
+                        void* hip_stream) {
+  g_last_error.clear();
+  if (!pde || !cfg || !u || !t || !t_end || !dt || !status) return fail(ADERDG_E_INVAL, "null argument");
+  if (nsteps < 0) return fail(ADERDG_E_INVAL, "nsteps must be >= 0");
+  int rc = validate(*pde, *cfg, 0);
+  if (rc) return rc;
+  const bool is_dg = cfg->scheme == ADERDG_SCHEME_DG;
+  const int64_t per_cell = is_dg ? (int64_t)(cfg->N + 1) * pde->nvars : pde->nvars;
+  const int64_t elems = per_cell * cfg->ncells;
+  if (elems > (int64_t)kNoallocMaxElems)
+    return fail(ADERDG_E_INVAL, "state of " + std::to_string(elems) + " doubles exceeds the " +
+                                    std::to_string(kNoallocMaxElems) +
+                                    " doubles of the static scratch (64 MiB per device)");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  rc = ensure_tables(device);
+  if (rc) return rc;
+  void* base = nullptr;
+  e = noalloc_scratch(device, &base);
+  if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress of the static scratch");
+  unsigned char* b = static_cast<unsigned char*>(base);
+  double* copy = reinterpret_cast<double*>(b + kNoallocState);
+  ProbDev d = probdev_of(*pde, *cfg, 0, copy);
+  d.state[0] = u;
+  const int64_t tile = is_dg ? dg_tile_cells(cfg->N, true) : fv_tile_cells(cfg->N);
+  d.tile_begin = 0;
+  d.tiles = (cfg->ncells + tile - 1) / tile;
+  ProbDev l = d;
+  l.tiles = (cfg->ncells + 255) / 256;
+  if (d.tiles >= ((int64_t)1 << 31)) return fail(ADERDG_E_INVAL, "grid too large");
+  e = launch_noalloc_setup(d, l, base, st);
+  if (e != hipSuccess) return fail_hip(e, "descriptor kernel");
+  ProbClock* clk = reinterpret_cast<ProbClock*>(b + kNoallocClock);
+  e = launch_clock_begin(clk, t, 1, st);
+  if (e != hipSuccess) return fail_hip(e, "clock kernel");
+  if (nsteps > 0 && !(cfg->fixed_dt > 0.0)) {
+    StepArgs A{};
+    A.probs = reinterpret_cast<const ProbDev*>(b + kNoallocLamDesc);
+    A.nprob = 1;
+    A.clocks = clk;
+    A.t_end = t_end;
+    e = launch_lambda(pde->pde, cfg->N, is_dg, A, l.tiles, st);
+    if (e != hipSuccess) return fail_hip(e, "lambda kernel");
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    StepArgs A{};
+    A.probs = reinterpret_cast<const ProbDev*>(b + kNoallocStepDesc);
+    A.nprob = 1;
+    A.clocks = clk;
+    A.t_end = t_end;
+    A.step = s;
+    e = is_dg ? launch_dg(pde->pde, cfg->N, cfg->precision, 2, A, d.tiles, st)
+              : launch_fv(pde->pde, cfg->N, cfg->precision, A, d.tiles, st);
+    if (e != hipSuccess) return fail_hip(e, "step kernel");
+  }
+  e = launch_clock_end(clk, t, dt, status, 1, nsteps & 1, st);
+  if (e != hipSuccess) return fail_hip(e, "clock kernel");
+  if (nsteps & 1) {
+    e = launch_copy(copy, u, elems, st);
+    if (e != hipSuccess) return fail_hip(e, "copy kernel");
+  }
+  return ADERDG_OK;
+}
+
 int aderdg_sweep_count(aderdg_handle* h, int32_t k, int64_t* sweeps_out) {
   if (!h || !sweeps_out) return fail(ADERDG_E_INVAL, "null argument");
   if (k < 0 || k >= h->nprob) return fail(ADERDG_E_INVAL, "problem index out of range");
@@ -476,6 +555,18 @@ int aderdg_contraction_count(aderdg_handle* h, int32_t k, int64_t* count_out) {
   for (int i = 0; i < kSlots; ++i) total += (int64_t)slots[i].v;
   *count_out = total;
   return ADERDG_OK;
+}
+
+int aderdg_conserved_totals(aderdg_handle* h, int32_t k, const double* u, double* totals_out) {
+  g_last_error.clear();
+  if (!h || !u || !totals_out) return fail(ADERDG_E_INVAL, "null argument");
+  if (k < 0 || k >= h->nprob) return fail(ADERDG_E_INVAL, "problem index out of range");
+  const aderdg_config& c = h->cfgs[k];
+  const bool is_dg = c.scheme == ADERDG_SCHEME_DG;
+  const double dx = (c.x1 - c.x0) / (double)c.ncells;
+  hipError_t e = launch_totals(u, c.ncells, is_dg ? c.N : 0, is_dg ? c.N + 1 : 1, h->pdes[k].nvars, dx,
+                               h->partials, totals_out, h->stream);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "totals kernels");
 }
 
 int aderdg_operators(int32_t N, double* out, int64_t cap) {

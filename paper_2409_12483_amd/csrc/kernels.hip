@@ -742,6 +742,69 @@ lambda_kernel(StepArgs A) {
   }
 }
 
+// ------------------------------------------------- conserved totals ----
+// dx * sum_i sum_k w_k u_i[k][r] per variable r (DG; FV: dx * sum_i v_i[r]),
+// the quantity the corrector's telescoping face terms keep constant
+// (Sec. 1.2).  Two passes with a fixed association order, so the result is
+// bitwise reproducible: every workgroup sums a fixed range of kTotCellsPerBlock
+// cells (thread i takes cells i, i + 256, ...; then a fixed LDS tree), the
+// second pass sums the per-workgroup partials the same way.
+constexpr int kTotThreads = 256;
+
+__device__ __forceinline__ void tree_sum(double (&acc)[kTotMaxVars], int M, double* lds) {
+  for (int r = 0; r < M; ++r) lds[r * kTotThreads + threadIdx.x] = acc[r];
+  __syncthreads();
+  for (int off = kTotThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int r = 0; r < M; ++r)
+        lds[r * kTotThreads + threadIdx.x] += lds[r * kTotThreads + threadIdx.x + off];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kTotThreads)
+totals_partial_kernel(const double* __restrict__ u, int64_t ncells, int N, int nodes, int M,
+                      double* __restrict__ partials) {
+  __shared__ double lds[kTotMaxVars * kTotThreads];
+  double acc[kTotMaxVars] = {};
+  const int64_t c0 = (int64_t)blockIdx.x * kTotCellsPerBlock;
+  for (int j = threadIdx.x; j < kTotCellsPerBlock; j += kTotThreads) {
+    const int64_t c = c0 + j;
+    if (c >= ncells) break;
+    const double* uc = u + c * nodes * M;
+    for (int k = 0; k < nodes; ++k) {
+      const double w = nodes > 1 ? c_ops[N].w[k] : 1.0;
+      for (int r = 0; r < M; ++r) acc[r] = fma(w, uc[k * M + r], acc[r]);
+    }
+  }
+  tree_sum(acc, M, lds);
+  if (threadIdx.x == 0)
+    for (int r = 0; r < M; ++r) partials[(int64_t)blockIdx.x * M + r] = lds[r * kTotThreads];
+}
+
+__global__ void __launch_bounds__(kTotThreads)
+totals_final_kernel(const double* __restrict__ partials, int64_t nparts, int M, double dx,
+                    double* __restrict__ out) {
+  __shared__ double lds[kTotMaxVars * kTotThreads];
+  double acc[kTotMaxVars] = {};
+  for (int64_t b = threadIdx.x; b < nparts; b += kTotThreads)
+    for (int r = 0; r < M; ++r) acc[r] += partials[b * M + r];
+  tree_sum(acc, M, lds);
+  if ((int)threadIdx.x < M) out[threadIdx.x] = dx * lds[threadIdx.x * kTotThreads];
+}
+
+hipError_t launch_totals(const double* u, int64_t ncells, int N, int nodes, int M, double dx,
+                         double* partials, double* out, hipStream_t st) {
+  if (M < 1 || M > kTotMaxVars || N < 0 || N >= kDevMaxn) return hipErrorInvalidValue;
+  const int64_t nb = totals_partials(ncells);
+  hipLaunchKernelGGL(totals_partial_kernel, dim3((unsigned)nb), dim3(kTotThreads), 0, st, u, ncells,
+                     N, nodes, M, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(kTotThreads), 0, st, partials, nb, M, dx, out);
+  return hipGetLastError();
+}
+
 __global__ void clock_begin_kernel(ProbClock* clocks, const double* t_user, int nprob) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprob) return;

@@ -38,7 +38,29 @@ hipError_t launch_clock_end(const ProbClock* clocks, double* t_user, double* dt_
 hipError_t launch_status_reset(ProbClock* clocks, int p, hipStream_t st);
 hipError_t launch_copy(const double* src, double* dst, int64_t count, hipStream_t st);
 hipError_t upload_tables(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno);
+// Conserved totals (two deterministic passes; partials: totals_partials(ncells) * M doubles).
+constexpr int kTotMaxVars = 5;
+constexpr int kTotCellsPerBlock = 4096;
+inline int64_t totals_partials(int64_t ncells) {
+  const int64_t nb = (ncells + kTotCellsPerBlock - 1) / kTotCellsPerBlock;
+  return nb > 0 ? nb : 1;
+}
+hipError_t launch_totals(const double* u, int64_t ncells, int N, int nodes, int M, double dx,
+                         double* partials, double* out, hipStream_t st);
 int64_t dg_tile_cells(int N, bool halo);
 int64_t fv_tile_cells(int NW);
+
+// Static scratch of the allocation-free step entry point (noalloc.hip):
+// descriptors, one problem clock, then the ping-pong state.
+constexpr size_t kNoallocBytes = size_t(64) << 20;                 // 64 MiB per device
+constexpr size_t kNoallocStepDesc = 0;                             // ProbDev of the step kernel
+constexpr size_t kNoallocLamDesc = 256;                            // ProbDev of the lambda kernel
+constexpr size_t kNoallocClock = 1024;                             // ProbClock
+constexpr size_t kNoallocState = size_t(64) << 10;                 // state copy, 8-byte elements
+constexpr size_t kNoallocMaxElems = (kNoallocBytes - kNoallocState) / sizeof(double);
+static_assert(sizeof(ProbDev) <= 256, "descriptor slot");
+static_assert(kNoallocClock + sizeof(ProbClock) <= kNoallocState, "clock slot");
+hipError_t noalloc_scratch(int device, void** out);
+hipError_t launch_noalloc_setup(const ProbDev& step, const ProbDev& lam, void* base, hipStream_t st);
 
 }  // namespace aderdg

@@ -199,3 +199,19 @@ def test_3d_config_struct_layout_matches_header():
     assert abi.Config3D.cells_z.offset == 24 and abi.Config3D.x0.offset == 32
     assert abi.Config3D.gamma.offset == 80 and abi.Config3D.picard_max_iter.offset == 112
     assert ctypes.sizeof(abi.Config3D) == 120
+
+
+def test_noalloc_step_rejects_a_state_beyond_its_static_scratch():
+    """The allocation-free entry point checks its size limit on the host, before
+    any device call: (64 MiB - 64 KiB) / 8 doubles of state."""
+    lib = abi.load()
+    limit = ((64 << 20) - (64 << 10)) // 8
+    dummy = ctypes.c_void_p(8)          # never dereferenced: the call fails before device work
+    for N, C in [(5, limit // 18 + 1), (1, limit // 6 + 1)]:
+        rc = lib.aderdg_step_noalloc(ctypes.byref(abi.pde_desc(abi.PDE_EULER)), ctypes.byref(abi.config(N, C)),
+                                     dummy, dummy, dummy, dummy, dummy, 1, None)
+        assert rc == abi.ADERDG_E_INVAL
+        assert "static scratch" in abi.aderdg_last_error()
+    rc = lib.aderdg_step_noalloc(ctypes.byref(abi.pde_desc(abi.PDE_EULER)), ctypes.byref(abi.config(2, 10)),
+                                 dummy, dummy, dummy, dummy, dummy, -1, None)
+    assert rc == abi.ADERDG_E_INVAL

@@ -1,0 +1,72 @@
+"""GPU: the allocation-free step entry point against the handle-based one.
+
+aderdg_step_noalloc keeps the state's ping-pong copy, the problem clock and
+the descriptors in a static device array instead of allocating them; it runs
+the same kernels as aderdg_step, so its results must equal those of a
+one-problem handle bit for bit.  Two calls in a row on the same device (the
+array keeps the previous call's contents), the second with a smaller
+problem, for the DG and the FV step; odd and even step counts.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2409_12483_amd import abi
+from paper_2409_12483_amd import workloads as W
+
+from gpu_util import BIG, tensor, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _handle_run(desc, cfg, u0, nsteps, fv):
+    torch, dev = torch_dev()
+    h = abi.aderdg_init([desc], [cfg])
+    try:
+        u = tensor(u0)
+        t = tensor(np.zeros(1))
+        te = tensor(np.full(1, BIG))
+        dt = tensor(np.zeros(1))
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        (abi.aderweno_step if fv else abi.aderdg_step)(h, [u], t, te, dt, st, nsteps)
+        torch.cuda.synchronize()
+        return u.cpu().numpy(), t.cpu().numpy(), dt.cpu().numpy(), st.cpu().numpy()
+    finally:
+        abi.aderdg_free(h)
+
+
+def _noalloc_run(desc, cfg, u0, nsteps):
+    torch, dev = torch_dev()
+    u = tensor(u0)
+    t = tensor(np.zeros(1))
+    te = tensor(np.full(1, BIG))
+    dt = tensor(np.zeros(1))
+    st = torch.full((1,), 7, dtype=torch.int32, device=dev)
+    abi.aderdg_step_noalloc(desc, cfg, u, t, te, dt, st, nsteps)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), t.cpu().numpy(), dt.cpu().numpy(), st.cpu().numpy()
+
+
+CASES = [
+    # (label, pde, config, initial state, steps): the second of each pair is smaller
+    ("dg big", abi.PDE_EULER, lambda: abi.config(5, 20_000), lambda: W.euler_density_wave(20_000, 5, noise=1e-3), 7),
+    ("dg small", abi.PDE_EULER, lambda: abi.config(3, 333), lambda: W.euler_density_wave(333, 3, k=2), 4),
+    ("fv big", abi.PDE_SWE, lambda: abi.config(4, 50_000, scheme=abi.SCHEME_FV), lambda: W.swe_bump_averages(50_000), 5),
+    ("fv small", abi.PDE_SWE, lambda: abi.config(4, 101, scheme=abi.SCHEME_FV, precision=abi.FP32_PREDICTOR),
+     lambda: W.swe_bump_averages(101), 6),
+]
+
+
+@pytest.mark.parametrize("first,second", [(0, 1), (2, 3)])
+def test_noalloc_step_equals_handle_step_twice_in_a_row(first, second):
+    for i in (first, second):
+        label, pde, cfg, init, ns = CASES[i]
+        print("[case] noalloc", label, flush=True)
+        fv = "fv" in label
+        desc = abi.pde_desc(pde)
+        u0 = init()
+        want = _handle_run(desc, cfg(), u0, ns, fv)
+        got = _noalloc_run(desc, cfg(), u0, ns)
+        for w, g in zip(want, got):
+            assert np.array_equal(w, g), label
+        assert got[3][0] == 0 and got[1][0] > 0
