@@ -529,6 +529,10 @@ fv_kernel(StepArgs A) {
   // ---- WENO reconstruction at node a (reading of eq. weno_reconstr) ----
   // Stencils outermost: the oscillation-indicator form of one stencil (wave-
   // uniform, scalar registers) is live for all M variables, then released.
+  // The indicator is a quadratic form that vanishes on constants, so it is
+  // evaluated on the averages minus the cell's own: on nearly constant data
+  // the form of the raw averages would cancel to round-off of |v|^2, which
+  // the weights' (sigma + eps)^-8 would amplify.
   double what[M];
   {
     const int base = (active ? pc : 0) + NW;   // vb index of this cell
@@ -539,16 +543,20 @@ fv_kernel(StepArgs A) {
       const cptr<double> S = opaque((cptr<double>)&c_weno[wi].S[s][0][0]);
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        double v[n];
+        double v[n], d[n];
+        const double vc = vb[base * M + r];
 #pragma unroll
-        for (int i = 0; i < n; ++i) v[i] = vb[(base + off + i) * M + r];
+        for (int i = 0; i < n; ++i) {
+          v[i] = vb[(base + off + i) * M + r];
+          d[i] = v[i] - vc;
+        }
         double sig = 0.0, val = 0.0;
 #pragma unroll
         for (int i = 0; i < n; ++i) {
           double si = 0.0;
 #pragma unroll
-          for (int j = 0; j < n; ++j) si += S[i * kWenoMaxn + j] * v[j];
-          sig += v[i] * si;
+          for (int j = 0; j < n; ++j) si += S[i * kWenoMaxn + j] * d[j];
+          sig += d[i] * si;
           val += c_weno[wi].R[s][a < n ? a : 0][i] * v[i];
         }
         const double e = sig + 1.0e-14;
