@@ -17,10 +17,14 @@
  *     cuda:0), contiguous, 8-byte aligned at least; the caller owns them.
  *     The library owns only its operator tables, internal ping-pong state
  *     buffers and per-problem clocks, allocated in aderdg_init and released
- *     in aderdg_free.
+ *     in aderdg_free, both stream-ordered on the handle's stream
+ *     (hipMallocAsync / hipFreeAsync; the problem tables are written by
+ *     kernels, not copied from host memory).
  *   - All work is enqueued on the handle's HIP stream (the one given at init,
  *     NULL = default stream) and is asynchronous: no call synchronises the
- *     host, except aderdg_init (it uploads tables) and aderdg_free.
+ *     host, except the counter read-backs (aderdg_sweep_count,
+ *     aderdg_contraction_count) and the first aderdg_init on a device, which
+ *     builds and uploads the operator tables.
  *   - A handle is used by one host thread at a time.
  *
  * Layouts (array-of-structures, variable index fastest: Sec. 1.1, the AoS
@@ -171,7 +175,8 @@ int aderdg_step_noalloc(const aderdg_pde_desc* pde, const aderdg_config* cfg, do
                         const double* t_end, double* dt, int32_t* status, int32_t nsteps,
                         void* hip_stream);
 
-/* aderdg_free -- release the handle (synchronises its stream first).  NULL is accepted. */
+/* aderdg_free -- release the handle: its device memory is freed in stream order after the
+ * work already enqueued on its stream (no host synchronisation).  NULL is accepted. */
 int aderdg_free(aderdg_handle* h);
 
 /*

@@ -43,32 +43,41 @@ class Batch:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         n = len(self.specs)
         init = states if states is not None else [initial_state(s) for s in self.specs]
-        self.u = [torch.tensor(np.ascontiguousarray(x), device=dev) for x in init]
-        self.t = torch.zeros(n, dtype=torch.float64, device=dev)
-        self.t_end = torch.full((n,), 1.0e300, dtype=torch.float64, device=dev)
-        self.dt = torch.zeros(n, dtype=torch.float64, device=dev)
-        self.status = torch.zeros(n, dtype=torch.int32, device=dev)
-        # most severe status seen by each problem over all calls (the library
-        # reports the status of the last call only)
-        self.sticky = torch.zeros(n, dtype=torch.int32, device=dev)
-        # the buffers above were filled on the current stream; the handle's
-        # stream must not run ahead of those fills
-        self.stream.wait_stream(torch.cuda.current_stream())
+        # the batch's buffers are allocated and filled on the batch's own
+        # stream, so that the handle's work is ordered after the fills and
+        # the memory is recycled in that stream's order when the batch is freed
+        with torch.cuda.stream(self.stream):
+            self.u = [torch.tensor(np.ascontiguousarray(x), device=dev) for x in init]
+            self.t = torch.zeros(n, dtype=torch.float64, device=dev)
+            self.t_end = torch.full((n,), 1.0e300, dtype=torch.float64, device=dev)
+            self.dt = torch.zeros(n, dtype=torch.float64, device=dev)
+            self.status = torch.zeros(n, dtype=torch.int32, device=dev)
+            # most severe status seen by each problem over all calls (the
+            # library reports the status of the last call only)
+            self.sticky = torch.zeros(n, dtype=torch.int32, device=dev)
         descs = [abi.pde_desc(_PDE[s["pde"]]) for s in self.specs]
         cfgs = [abi.config(s["N"], s["ncells"], precision=precision, cfl=cfl) for s in self.specs]
         self.h = abi.aderdg_init(descs, cfgs, stream=self.stream.cuda_stream)
         self.graph = None
         self.graph_steps = 0
+        self.event = None
 
     @property
     def dofs(self):
         return sum(s["ncells"] * (s["N"] + 1) * 3 for s in self.specs)
 
     def step(self, nsteps):
-        """Enqueue nsteps steps of every problem (asynchronous)."""
+        """Enqueue nsteps steps of every problem (asynchronous); an event
+        recorded after them tells when they are done (see ready())."""
         with self.torch.cuda.stream(self.stream):
             abi.aderdg_step(self.h, self.u, self.t, self.t_end, self.dt, self.status, nsteps)
             self.torch.minimum(self.sticky, self.status, out=self.sticky)
+            self.event = self.torch.cuda.Event()
+            self.event.record(self.stream)
+
+    def ready(self):
+        """True once the last enqueued advance has finished (non-blocking)."""
+        return self.event is None or self.event.query()
 
     def capture(self, nsteps):
         """Capture an advance of nsteps steps into a HIP graph.  The state

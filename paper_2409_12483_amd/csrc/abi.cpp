@@ -140,17 +140,20 @@ struct aderdg_handle {
 
 namespace {
 
+// Stream-ordered release: every buffer goes back to the device's memory pool
+// after the work already enqueued on the handle's stream; the host is not
+// synchronised.
 void release(aderdg_handle* h) {
   if (!h) return;
-  if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
-  for (double* p : h->scratch) if (p) (void)hipFree(p);
+  hipStream_t st = h->stream;
+  for (double* p : h->scratch) if (p) (void)hipFreeAsync(p, st);
   for (Group& g : h->groups) {
-    if (g.dev) (void)hipFree(g.dev);
-    if (g.lam_dev) (void)hipFree(g.lam_dev);
+    if (g.dev) (void)hipFreeAsync(g.dev, st);
+    if (g.lam_dev) (void)hipFreeAsync(g.lam_dev, st);
   }
-  if (h->single_dev) (void)hipFree(h->single_dev);
-  if (h->clocks) (void)hipFree(h->clocks);
-  if (h->partials) (void)hipFree(h->partials);
+  if (h->single_dev) (void)hipFreeAsync(h->single_dev, st);
+  if (h->clocks) (void)hipFreeAsync(h->clocks, st);
+  if (h->partials) (void)hipFreeAsync(h->partials, st);
   delete h;
 }
 
@@ -210,33 +213,32 @@ ProbDev make_probdev(const aderdg_handle* h, int k) {
 }
 
 int upload_group(aderdg_handle* h, Group& g) {
-  hipError_t e = hipMemcpy(g.dev, g.host.data(), sizeof(ProbDev) * g.host.size(), hipMemcpyHostToDevice);
+  hipError_t e = launch_write_probs(g.host.data(), (int)g.host.size(), g.dev, h->stream);
   if (e != hipSuccess) return fail_hip(e, "upload of problem table");
-  e = hipMemcpy(g.lam_dev, g.lam_host.data(), sizeof(ProbDev) * g.lam_host.size(), hipMemcpyHostToDevice);
+  e = launch_write_probs(g.lam_host.data(), (int)g.lam_host.size(), g.lam_dev, h->stream);
   if (e != hipSuccess) return fail_hip(e, "upload of problem table");
   return ADERDG_OK;
 }
 
-// Point the group's tables at the caller's state buffers; re-upload on change.
+// Point the group's tables at the caller's state buffers: when they changed,
+// the new pointers are written by a small kernel in stream order (no host
+// synchronisation; under stream capture the write is part of the graph).
 int bind_states(aderdg_handle* h, Group& g, double* const* u) {
   bool changed = false;
   for (size_t i = 0; i < g.pids.size(); ++i) {
     double* p = u[g.pids[i]];
     if (!p) return fail(ADERDG_E_INVAL, "null state pointer for problem " + std::to_string(g.pids[i]));
-    if (g.host[i].state[0] != p) {
-      g.host[i].state[0] = p;
-      g.lam_host[i].state[0] = p;
-      changed = true;
-    }
+    if (g.host[i].state[0] != p) changed = true;
   }
   if (!changed) return ADERDG_OK;
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  (void)hipStreamIsCapturing(h->stream, &cs);
-  if (cs != hipStreamCaptureStatusNone)
-    return fail(ADERDG_E_INVAL, "state pointers changed during stream capture; call once eagerly first");
-  hipError_t e = hipStreamSynchronize(h->stream);
-  if (e != hipSuccess) return fail_hip(e, "stream synchronize");
-  return upload_group(h, g);
+  std::vector<double*> ptrs(g.pids.size());
+  for (size_t i = 0; i < g.pids.size(); ++i) {
+    ptrs[i] = u[g.pids[i]];
+    g.host[i].state[0] = ptrs[i];
+    g.lam_host[i].state[0] = ptrs[i];
+  }
+  hipError_t e = launch_write_state_ptrs(ptrs.data(), (int)ptrs.size(), g.dev, g.lam_dev, h->stream);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "state pointer kernel");
 }
 
 int run_steps(aderdg_handle* h, int scheme, double* const* u, double* t, const double* t_end,
@@ -318,11 +320,13 @@ int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t 
   h->cfgs.assign(cfgs, cfgs + nprob);
   h->scratch.assign(nprob, nullptr);
   h->elems.assign(nprob, 0);
+  // every allocation and table write is stream-ordered on the handle's stream
+  hipStream_t st = h->stream;
   for (int k = 0; k < nprob; ++k) {
     const aderdg_config& c = cfgs[k];
     const int64_t per_cell = c.scheme == ADERDG_SCHEME_DG ? (int64_t)(c.N + 1) * pdes[k].nvars : pdes[k].nvars;
     h->elems[k] = per_cell * c.ncells;
-    e = hipMalloc((void**)&h->scratch[k], sizeof(double) * h->elems[k]);
+    e = hipMallocAsync((void**)&h->scratch[k], sizeof(double) * h->elems[k], st);
     if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
   }
   int64_t nparts = 1;
@@ -330,17 +334,17 @@ int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t 
     const int64_t p = totals_partials(cfgs[k].ncells) * pdes[k].nvars;
     if (p > nparts) nparts = p;
   }
-  e = hipMalloc((void**)&h->partials, sizeof(double) * nparts);
+  e = hipMallocAsync((void**)&h->partials, sizeof(double) * nparts, st);
   if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "partials allocation"); }
-  e = hipMalloc((void**)&h->clocks, sizeof(ProbClock) * nprob);
+  e = hipMallocAsync((void**)&h->clocks, sizeof(ProbClock) * nprob, st);
   if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }
-  e = hipMemset(h->clocks, 0, sizeof(ProbClock) * nprob);
+  e = launch_zero(h->clocks, sizeof(ProbClock) * nprob, st);
   if (e != hipSuccess) { release(h); return fail_hip(e, "clock init"); }
   // standalone descriptors
   for (int k = 0; k < nprob; ++k) h->single_host.push_back(make_probdev(h, k));
-  e = hipMalloc((void**)&h->single_dev, sizeof(ProbDev) * nprob);
+  e = hipMallocAsync((void**)&h->single_dev, sizeof(ProbDev) * nprob, st);
   if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "table allocation"); }
-  e = hipMemcpy(h->single_dev, h->single_host.data(), sizeof(ProbDev) * nprob, hipMemcpyHostToDevice);
+  e = launch_write_probs(h->single_host.data(), nprob, h->single_dev, st);
   if (e != hipSuccess) { release(h); return fail_hip(e, "table upload"); }
   // launch groups
   std::map<std::tuple<int, int, int, int>, int> index;
@@ -378,10 +382,13 @@ int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t 
     g.blocks = b;
     g.lam_blocks = lb;
     if (b >= ((int64_t)1 << 31)) { release(h); return fail(ADERDG_E_INVAL, "grid too large"); }
-    e = hipMalloc((void**)&g.dev, sizeof(ProbDev) * g.host.size());
+    e = hipMallocAsync((void**)&g.dev, sizeof(ProbDev) * g.host.size(), st);
     if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "table allocation"); }
-    e = hipMalloc((void**)&g.lam_dev, sizeof(ProbDev) * g.lam_host.size());
+    e = hipMallocAsync((void**)&g.lam_dev, sizeof(ProbDev) * g.lam_host.size(), st);
     if (e != hipSuccess) { release(h); return fail(ADERDG_E_NOMEM, "table allocation"); }
+    // state pointers are bound by the first step call
+    rc = upload_group(h, g);
+    if (rc) { release(h); return rc; }
   }
   *out = h;
   return ADERDG_OK;

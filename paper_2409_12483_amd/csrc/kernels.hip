@@ -32,6 +32,11 @@ __constant__ DevWeno c_weno[2];  // WENO degree 2 and 4
 
 enum Mode { kPredict = 0, kCorrect = 1, kStep = 2 };
 
+#ifndef ADERDG_FP32_MFMA
+#define ADERDG_FP32_MFMA 0
+#endif
+constexpr bool kFp32Mfma = ADERDG_FP32_MFMA;
+
 // Geometry of a workgroup for degree N and M variables.  Each cell owns an
 // LDS exchange block: rows of RSD doubles, CBD doubles per block (padded
 // against bank conflicts); in FP32-predictor mode the predictor addresses
@@ -180,7 +185,7 @@ dg_kernel(StepArgs A) {
   constexpr bool HALO = MODE != kPredict;
   using G = Geo<N, PDE::M, WAVES, HALO>;
   constexpr int n = G::n, M = PDE::M, CPW = G::CPW, PC = G::PC;
-  using Pred = Predictor<N, PDE, TP>;
+  using Pred = Predictor<N, PDE, TP, sizeof(TP) == 4 && kFp32Mfma>;
 
   __shared__ double xb_all[WAVES * G::XB];
   __shared__ TP red_all[WAVES * G::RED];
@@ -457,7 +462,7 @@ fv_kernel(StepArgs A) {
   using G = Geo<NW, PDE::M, WAVES, true>;
   constexpr int n = G::n, M = PDE::M, CPW = G::CPW, PC = G::PC;
   constexpr int NV = PC + 2 * NW;   // cell averages staged: predictor cells + WENO reach
-  using Pred = Predictor<NW, PDE, TP>;
+  using Pred = Predictor<NW, PDE, TP, sizeof(TP) == 4 && kFp32Mfma>;
   constexpr int wi = NW / 2 - 1;    // c_weno index
 
   __shared__ double vb[NV * M];
@@ -810,6 +815,66 @@ hipError_t launch_totals(const double* u, int64_t ncells, int N, int nodes, int 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(kTotThreads), 0, st, partials, nb, M, dx, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ stream-ordered setup ----
+// Problem tables and state pointers travel as kernel arguments, so a handle
+// is set up and re-pointed in stream order: no host copy, no host sync, and
+// nothing the caller's graph capture could not record.
+__global__ void write_probs_kernel(ProbChunk c, ProbDev* dst) {
+  const int i = threadIdx.x;
+  if (i < c.n) dst[c.first + i] = c.d[i];
+}
+
+__global__ void write_state_ptrs_kernel(PtrChunk c, ProbDev* dst, ProbDev* dst2) {
+  const int i = threadIdx.x;
+  if (i < c.n) {
+    dst[c.first + i].state[0] = c.p[i];
+    if (dst2) dst2[c.first + i].state[0] = c.p[i];
+  }
+}
+
+__global__ void zero_words_kernel(unsigned long long* p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+hipError_t launch_write_probs(const ProbDev* src, int count, ProbDev* dst, hipStream_t st) {
+  for (int first = 0; first < count; first += kProbChunk) {
+    ProbChunk c{};
+    c.first = first;
+    c.n = count - first < kProbChunk ? count - first : kProbChunk;
+    for (int i = 0; i < c.n; ++i) c.d[i] = src[first + i];
+    hipLaunchKernelGGL(write_probs_kernel, dim3(1), dim3(kProbChunk), 0, st, c, dst);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_write_state_ptrs(double* const* ptrs, int count, ProbDev* dst, ProbDev* dst2,
+                                   hipStream_t st) {
+  for (int first = 0; first < count; first += kPtrChunk) {
+    PtrChunk c{};
+    c.first = first;
+    c.n = count - first < kPtrChunk ? count - first : kPtrChunk;
+    for (int i = 0; i < c.n; ++i) c.p[i] = ptrs[first + i];
+    hipLaunchKernelGGL(write_state_ptrs_kernel, dim3(1), dim3(kPtrChunk), 0, st, c, dst, dst2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const int64_t words = (int64_t)(bytes / 8);
+  int64_t blocks = (words + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<unsigned long long*>(p), words);
   return hipGetLastError();
 }
 

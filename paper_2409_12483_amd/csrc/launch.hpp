@@ -36,6 +36,21 @@ hipError_t launch_clock_begin(ProbClock* clocks, const double* t_user, int nprob
 hipError_t launch_clock_end(const ProbClock* clocks, double* t_user, double* dt_user,
                             int32_t* status_user, int nprob, int parity, hipStream_t st);
 hipError_t launch_status_reset(ProbClock* clocks, int p, hipStream_t st);
+// Stream-ordered table set-up (kernel arguments carry the data).
+constexpr int kProbChunk = 8;
+constexpr int kPtrChunk = 32;
+struct ProbChunk {
+  ProbDev d[kProbChunk];
+  int32_t n, first;
+};
+struct PtrChunk {
+  double* p[kPtrChunk];
+  int32_t n, first;
+};
+hipError_t launch_write_probs(const ProbDev* src, int count, ProbDev* dst, hipStream_t st);
+hipError_t launch_write_state_ptrs(double* const* ptrs, int count, ProbDev* dst, ProbDev* dst2,
+                                   hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_copy(const double* src, double* dst, int64_t count, hipStream_t st);
 hipError_t upload_tables(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno);
 // Conserved totals (two deterministic passes; partials: totals_partials(ncells) * M doubles).

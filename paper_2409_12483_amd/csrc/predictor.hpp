@@ -59,10 +59,60 @@ template <int N> struct OpSrc<N, float> {
   __device__ static cptr<float> Kap() { return (cptr<float>)&c_opsf[N].kappa[0][0]; }
 };
 
-template <int N, class PDE, class TP>
+// MFMA contraction (FP32 predictor): v_mfma_f32_4x4x1f32 treats the wave as
+// 16 blocks of 4 lanes and forms, per block, the outer product of a 4-row
+// column held by the block's lanes (A: lane 4k+i gives row i) with a 4-column
+// row (B: lane 4k+j gives column j), accumulated into the 4x4 block (lane
+// 4k+j holds column j, rows 0..3).  With the operator rows as A (row
+// rb*4 + lane%4, the same in every block) and each lane's own value as B,
+// every lane gets rows rb*4..rb*4+3 of operator x (its own column): the
+// contraction along the index the lane already owns, with no data movement.
+// Issued on the matrix pipe, it runs beside the VALU's point-wise work.
+typedef float mf_v4 __attribute__((ext_vector_type(4)));
+
+template <int n, int M, int NRB>
+__device__ __forceinline__ void mfma_apply(const float (&A)[NRB][n], const float (&B)[n][M],
+                                           const float* c0, float (&out)[n][M]) {
+#pragma unroll
+  for (int r = 0; r < M; ++r)
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+      const float init = c0 ? c0[r] : 0.0f;
+      mf_v4 acc = {init, init, init, init};
+#pragma unroll
+      for (int j = 0; j < n; ++j) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(A[rb][j], B[j][r], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (rb * 4 + v < n) out[rb * 4 + v][r] = acc[v];
+    }
+}
+
+template <int N, class PDE, class TP, bool MF = false>
 struct Predictor {
+  static_assert(!MF || sizeof(TP) == 4, "the MFMA contractions are FP32");
   static constexpr int n = N + 1;
   static constexpr int M = PDE::M;
+  static constexpr int NRB = (n + 3) / 4;   // 4-row blocks of an operator (MFMA path)
+  // Per-lane operator rows for the MFMA path: row rb*4 + lane%4 of k~ and of
+  // -(dt/dx) kappa~ (zero past n).
+  struct MfOps {
+    TP k[MF ? NRB : 1][MF ? n : 1];
+    TP kap[MF ? NRB : 1][MF ? n : 1];
+  };
+  __device__ static void mf_init(MfOps& mo, TP dtdx) {
+    if constexpr (MF) {
+      const int q4 = threadIdx.x & 3;
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) {
+        const int row = rb * 4 + q4;
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+          mo.k[rb][j] = row < n ? c_opsf[N].ktil[row < n ? row : 0][j] : TP(0);
+          mo.kap[rb][j] = row < n ? -dtdx * c_opsf[N].kappa[row < n ? row : 0][j] : TP(0);
+        }
+      }
+    }
+  }
   static constexpr int RS = LdsLayout<n, M, sizeof(TP)>::RS;   // row stride of the exchange block
   static constexpr bool kInner = PDE::kSource || PDE::kNcp;
   // k~ is held in scalar registers across a sweep only while it fits beside
@@ -152,12 +202,44 @@ struct Predictor {
   template <bool RELOAD_K>
   __device__ static void time_contraction(const TP* rowres, const TP (&ucol)[M], TP* xb, int a,
                                           bool write, TP dtdx, TP (&q)[n][M], TP (&kt)[n][n],
-                                          TP& e, TP& qm) {
+                                          const MfOps& mo, TP& e, TP& qm) {
     if (write) {
 #pragma unroll
       for (int l = 0; l < n; ++l)
 #pragma unroll
         for (int r = 0; r < M; ++r) xb[a * RS + l * M + r] = rowres[l * M + r];
+    }
+    if constexpr (MF) {
+      wave_sync();
+      TP col[n][M], qn[n][M];
+#pragma unroll
+      for (int b = 0; b < n; ++b)
+#pragma unroll
+        for (int r = 0; r < M; ++r) col[b][r] = xb[b * RS + a * M + r];
+      mfma_apply<n, M, NRB>(mo.kap, col, ucol, qn);
+      if (write) {
+#pragma unroll
+        for (int a2 = 0; a2 < n; ++a2)
+#pragma unroll
+          for (int r = 0; r < M; ++r) xb[a2 * RS + a * M + r] = qn[a2][r];
+      }
+      wave_sync();
+#pragma unroll
+      for (int l = 0; l < n; ++l)
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          const TP v = xb[a * RS + l * M + r];
+          const TP d = v - q[l][r];
+          if (l == 0 && r == 0) {
+            e = dabs(d);
+            qm = dabs(v);
+          } else {
+            e = max_abs(e, d);
+            qm = max_abs(qm, v);
+          }
+          q[l][r] = v;
+        }
+      return;
     }
     // kappa~ is fetched before the fence (when it fits the scalar budget):
     // its latency then overlaps the transpose
@@ -220,14 +302,22 @@ struct Predictor {
     TP eps_prev = TP(3.0e38);
     TP row[n * M];
     TP kt[n][n];
-    load_k(kt);
+    MfOps mo;
+    mf_init(mo, dtdx);
+    if constexpr (!MF) load_k(kt);
     reinterpret_cast<Bits*>(red)[0] = 0;   // the cell's reduction words start cleared
     reinterpret_cast<Bits*>(red)[1] = 0;
     // one outer sweep
     auto sweep = [&]() __attribute__((always_inline)) {
-      if constexpr (kInner) load_k(kt);
+      if constexpr (kInner && !MF) load_k(kt);
       // Algorithm 2: fluxes at every node of the row, then k~ along space.
       TP KF[n][M];
+      if constexpr (MF) {
+        TP f[n][M];
+#pragma unroll
+        for (int j = 0; j < n; ++j) PDE::flux(q[j], f[j], pp);
+        mfma_apply<n, M, NRB>(mo.k, f, nullptr, KF);
+      } else {
       const cptr<TP> Kc = opaque(OpSrc<N, TP>::K());
       auto kc = [&](int l, int j) -> TP { return kPreloadK ? kt[l][j] : Kc[l * kDevMaxn + j]; };
 #pragma unroll
@@ -241,10 +331,11 @@ struct Predictor {
             KF[l][r] = j == 0 ? kc(l, 0) * f[r] : KF[l][r] + kc(l, j) * f[r];
         }
       }
+      }
       TP e, qm;
       if constexpr (!kInner) {
         residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp);
-        time_contraction<true>(row, ucol, xb, a, active && !done, dtdx, q, kt, e, qm);
+        time_contraction<true>(row, ucol, xb, a, active && !done, dtdx, q, kt, mo, e, qm);
       } else {
         // inner loop over source / non-conservative terms (Algorithm 1, inner repeat)
         TP qi[n][M];
@@ -260,7 +351,7 @@ struct Predictor {
           residual_row(qi, KF, row, a, dt, dtdx, xl, dx, t0, pp);
           TP ie, iqm;
           if (!idone) sweeps += 1 << 16;
-          time_contraction<false>(row, ucol, xb, a, active && !idone, dtdx, qi, kt, ie, iqm);
+          time_contraction<false>(row, ucol, xb, a, active && !idone, dtdx, qi, kt, mo, ie, iqm);
           cell_reduce(red, ie, iqm);
           if (!idone) {
             const bool conv = ie <= tol * dmax(TP(1), iqm);

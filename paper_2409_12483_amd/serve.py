@@ -3,20 +3,28 @@
 Requests (PDE, degree N, cells, number of steps) arrive over time.  The
 scheduler admits them first-come first-served while two budgets hold: device
 memory (each request holds its state and the library's ping-pong copy) and a
-slot limit on concurrently active requests.  Requests admitted in the same
-tick with the same (PDE, N) form a cohort, i.e. one library handle and one
-kernel launch per step for all of them.  Every tick advances every active
-cohort by the smallest number of steps any of its unfinished requests still
-needs (capped), then retires the requests that have run all their steps
-(their end time is frozen, so they no longer advance) and frees a cohort
-once all its requests are done.  A request's numbers never depend on the
-other requests of its cohort or tick: each problem of a launch reads only
-its own state and clock.
+slot limit on concurrently active requests.  Requests admitted together with
+the same (PDE, N) form a cohort, i.e. one library handle and one kernel
+launch per step for all of them.
+
+There is no global tick.  Every cohort runs on one of a few device streams
+and advances in chunks: a chunk is the smallest number of steps any of its
+unfinished requests still needs (capped), enqueued with an event behind it.
+The loop polls the events without blocking; when a cohort's chunk is done it
+retires the requests that have run all their steps (their end time is
+frozen, so they stop advancing), frees the cohort once all its requests are
+done (stream-ordered: no host synchronisation), and enqueues the next chunk.
+New arrivals are admitted as soon as slots and memory free up, and their
+cohorts start at once on the streams, overlapping the cohorts already
+running.  A request's numbers never depend on the other requests of its
+cohort or on the other cohorts: each problem of a launch reads only its own
+state and clock.
 
 The scheduler talks to an executor (``GpuExecutor`` here; tests use a CPU
 stand-in with the same methods):
-    create(specs) -> cohort      step(cohort, n)      freeze(cohort, idx)
-    sync()                       state(cohort, i)     free(cohort)
+    create(specs) -> cohort      step(cohort, n)      ready(cohort)
+    freeze(cohort, idx)          status(cohort)       state(cohort, i)
+    free(cohort)                 wait(timeout)
 """
 
 import time
@@ -60,6 +68,7 @@ class Cohort:
     requests: list
     handle: object
     remaining: list = field(default_factory=list)
+    inflight: int = 0        # steps of the chunk on the device (0: none)
 
     def active(self):
         return [i for i, r in enumerate(self.remaining) if r > 0]
@@ -72,44 +81,61 @@ def cfl_for(N):
 
 
 class GpuExecutor:
-    """Cohorts as library handles on one HIP stream."""
+    """Cohorts as library handles spread over a few device streams (default
+    priority; a new cohort takes the stream with the fewest live cohorts)."""
 
-    def __init__(self, precision=None, stream=None):
+    def __init__(self, precision=None, streams=4, poll_s=2e-4):
         import torch
         from . import abi
         self.torch = torch
         self.precision = abi.FP64 if precision is None else precision
-        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.streams = [torch.cuda.Stream() for _ in range(max(1, int(streams)))]
+        self.load = [0] * len(self.streams)
+        self.poll_s = poll_s
 
     def create(self, specs):
         cfls = {cfl_for(s["N"]) for s in specs}
         assert len(cfls) == 1, "a cohort shares one degree"
-        return B.Batch(specs, precision=self.precision, stream=self.stream, cfl=cfls.pop())
+        k = min(range(len(self.streams)), key=lambda i: self.load[i])
+        self.load[k] += 1
+        b = B.Batch(specs, precision=self.precision, stream=self.streams[k], cfl=cfls.pop())
+        b.slot = k
+        return b
 
     def step(self, cohort, n):
         cohort.step(n)
 
+    def ready(self, cohort):
+        return cohort.ready()
+
+    def wait(self, timeout):
+        time.sleep(max(0.0, min(timeout, self.poll_s)))
+
     def freeze(self, cohort, idx):
         cohort.freeze(idx)
 
-    def sync(self):
-        self.stream.synchronize()
-
     def status(self, cohort):
-        """Most severe status of each problem over every call so far."""
+        """Most severe status of each problem over every call so far (read
+        after the cohort's last event completed)."""
         return cohort.sticky.cpu().numpy()
 
     def state(self, cohort, i):
         return cohort.u[i].cpu().numpy()
 
     def free(self, cohort):
+        self.load[cohort.slot] -= 1
         cohort.close()
 
 
 class Scheduler:
     def __init__(self, executor, hbm_budget=200e9, max_active=256, max_steps_per_tick=50,
-                 clock=time.perf_counter, keep_states=False):
+                 clock=time.perf_counter, keep_states=False, admit_window=2e-3, idle_cohorts=2):
         self.ex = executor
+        # arrivals wait at most admit_window seconds to be admitted together
+        # (one cohort, one launch per step), and are admitted at once while
+        # fewer than idle_cohorts cohorts are running
+        self.window = float(admit_window)
+        self.idle = int(idle_cohorts)
         self.budget = float(hbm_budget)
         self.max_active = int(max_active)
         self.cap = int(max_steps_per_tick)
@@ -122,9 +148,14 @@ class Scheduler:
         self.finished = []
         self.states = {}
         self.bad = {}
-        self.ticks = 0
+        self.ticks = 0           # chunks enqueued
+        self.max_inflight = 0    # most cohorts with work on the device at once
 
     # -- admission -------------------------------------------------------
+    def head_fits(self):
+        r = self.queue[0]
+        return self.nactive + 1 <= self.max_active and self.used + r.nbytes <= self.budget
+
     def submit(self, req):
         if req.nbytes > self.budget:
             raise ValueError(f"request {req.id} needs {req.nbytes} bytes, over the whole budget")
@@ -149,19 +180,32 @@ class Scheduler:
             self.cohorts.append(Cohort(reqs, h, [r.steps for r in reqs]))
         return took
 
-    # -- one tick: advance every cohort, retire finished requests --------
-    def advance(self):
-        plan = []
+    # -- chunks: enqueue, and retire when done -----------------------------
+    def launch(self):
+        """Enqueue the next chunk of every cohort that has none in flight."""
         for c in self.cohorts:
+            if c.inflight:
+                continue
             act = c.active()
             n = min(min(c.remaining[i] for i in act), self.cap)
             self.ex.step(c.handle, n)
-            plan.append((c, act, n))
-        self.ex.sync()
-        now = self.clock()
-        self.ticks += 1
+            c.inflight = n
+            self.ticks += 1
+        self.max_inflight = max(self.max_inflight, sum(1 for c in self.cohorts if c.inflight))
+
+    def complete(self):
+        """Retire the requests of every cohort whose chunk has finished.
+        Returns the number of cohorts that made progress."""
+        done_cohorts = 0
         keep = []
-        for c, act, n in plan:
+        for c in self.cohorts:
+            if not c.inflight or not self.ex.ready(c.handle):
+                keep.append(c)
+                continue
+            done_cohorts += 1
+            now = self.clock()
+            n, c.inflight = c.inflight, 0
+            act = c.active()
             done_idx = []
             for i in act:
                 c.remaining[i] -= n
@@ -188,9 +232,10 @@ class Scheduler:
                     self.used -= r.nbytes
                     self.nactive -= 1
         self.cohorts = keep
+        return done_cohorts
 
     # -- the service loop over an arrival trace --------------------------
-    def run(self, requests, sleep=time.sleep):
+    def run(self, requests):
         """Serve requests (arrival times in seconds from the start); returns metrics."""
         pending = sorted(requests, key=lambda r: r.arrival)
         t0 = self.clock()
@@ -203,15 +248,24 @@ class Scheduler:
                 while j < len(pending) and pending[j].arrival <= now:
                     self.submit(pending[j])
                     j += 1
-                self.admit(now)
-                if self.cohorts:
-                    self.advance()
-                elif j < len(pending):
-                    sleep(max(0.0, pending[j].arrival - self.clock()))
+                if self.queue and (len(self.cohorts) < self.idle
+                                   or now >= self.queue[0].arrival + self.window):
+                    self.admit(now)
+                self.launch()
+                if not self.complete():
+                    # sleep until the next arrival, the queue head's admission
+                    # deadline (if it fits), or a chunk finishing
+                    wake = [pending[j].arrival] if j < len(pending) else []
+                    if self.queue and self.head_fits():
+                        wake.append(self.queue[0].arrival + self.window)
+                    t = min(wake) - self.clock() if wake else 1.0
+                    self.ex.wait(min(max(0.0, t), 1.0))
             makespan = self.clock()
         finally:
             self.clock = base
-        return summarize(self.finished, makespan, self.ticks)
+        out = summarize(self.finished, makespan, self.ticks)
+        out["max_cohorts_in_flight"] = self.max_inflight
+        return out
 
 
 def summarize(finished, makespan, ticks):

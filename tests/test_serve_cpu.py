@@ -21,20 +21,27 @@ class VirtualClock:
 
 
 class FakeExecutor:
-    """Counts the steps each problem is advanced by; time advances with work."""
+    """Counts the steps each problem is advanced by; a chunk occupies one of
+    `streams` simulated device streams for work / rate seconds of the
+    virtual clock, and chunks on different streams overlap."""
 
-    def __init__(self, clock, dof_rate=1e9):
+    def __init__(self, clock, dof_rate=1e9, streams=4, fail=None):
         self.clock = clock
         self.rate = dof_rate
+        self.busy = [0.0] * streams
+        self.load = [0] * streams
         self.live = []
         self.max_live_problems = 0
         self.max_live_bytes = 0
-        self.pending_work = 0.0
         self.created = []
+        self.fail = dict(fail or {})      # (cohort index, problem, chunk) -> status planted there
 
     def create(self, specs):
+        k = min(range(len(self.busy)), key=lambda i: self.load[i])
+        self.load[k] += 1
         c = {"specs": list(specs), "steps": [0] * len(specs), "frozen": [False] * len(specs),
-             "freed": False}
+             "freed": False, "slot": k, "done_at": 0.0, "chunks": 0,
+             "sticky": np.zeros(len(specs), dtype=np.int32), "index": len(self.created)}
         self.live.append(c)
         self.created.append(c)
         self.max_live_problems = max(self.max_live_problems, sum(len(x["specs"]) for x in self.live))
@@ -44,27 +51,40 @@ class FakeExecutor:
 
     def step(self, c, n):
         assert n >= 1 and not c["freed"]
+        work = 0.0
         for i, s in enumerate(c["specs"]):
             if not c["frozen"][i]:
                 c["steps"][i] += n
-                self.pending_work += s["ncells"] * (s["N"] + 1) * 3 * n
+                work += s["ncells"] * (s["N"] + 1) * 3 * n
+                st = self.fail.get((c["index"], i, c["chunks"]), 0)
+                c["sticky"][i] = min(c["sticky"][i], st)
+        k = c["slot"]
+        start = max(self.clock.t, self.busy[k])
+        self.busy[k] = start + work / self.rate
+        c["done_at"] = self.busy[k]
+        c["chunks"] += 1
+
+    def ready(self, c):
+        return self.clock.t >= c["done_at"]
+
+    def wait(self, timeout):
+        later = [c["done_at"] for c in self.live if c["done_at"] > self.clock.t]
+        step = min([timeout] + [t - self.clock.t for t in later])
+        self.clock.t += max(step, 0.0)
 
     def freeze(self, c, idx):
         for i in idx:
             c["frozen"][i] = True
 
-    def sync(self):
-        self.clock.t += self.pending_work / self.rate
-        self.pending_work = 0.0
-
     def status(self, c):
-        return np.zeros(len(c["specs"]), dtype=np.int32)
+        return c["sticky"].copy()
 
     def state(self, c, i):
         return np.array([c["steps"][i]])
 
     def free(self, c):
         c["freed"] = True
+        self.load[c["slot"]] -= 1
         self.live.remove(c)
 
 
@@ -73,11 +93,11 @@ def _trace(n=60, rate=50.0, seed=1):
                                                      cmax=20000, smin=5, smax=60))
 
 
-def _run(reqs, **kw):
+def _run(reqs, fail=None, streams=4, **kw):
     clk = VirtualClock()
-    ex = FakeExecutor(clk)
+    ex = FakeExecutor(clk, streams=streams, fail=fail)
     sch = serve.Scheduler(ex, clock=clk, keep_states=True, **kw)
-    m = sch.run(reqs, sleep=clk.sleep)
+    m = sch.run(reqs)
     return sch, ex, m
 
 
@@ -118,7 +138,7 @@ def test_cohorts_group_same_pde_and_degree():
     sch, ex, _ = _run(reqs)
     for c in ex.created:
         assert len({(s["pde"], s["N"]) for s in c["specs"]}) == 1
-    # a burst is admitted in few ticks, so several cohorts hold more than one request
+    # a burst is admitted in few passes, so several cohorts hold more than one request
     assert max(len(c["specs"]) for c in ex.created) > 1
 
 
@@ -135,3 +155,23 @@ def test_latency_summary_is_consistent():
     assert m["latency_ms"]["p50"] <= m["latency_ms"]["p99"]
     assert m["queue_ms"]["p50"] >= 0.0
     assert m["dof_updates_per_s"] > 0
+
+
+def test_cohorts_overlap_on_the_streams():
+    """Arrivals admitted while other cohorts run start at once: several
+    cohorts have work on the (simulated) device at the same time."""
+    reqs = _trace(n=60, rate=400.0)
+    sch, ex, m = _run(reqs, streams=4)
+    assert m["max_cohorts_in_flight"] >= 2
+    one = _trace(n=60, rate=400.0)
+    _, _, m1 = _run(one, streams=1)
+    # overlapping streams finish the same trace sooner than one stream
+    assert m["makespan_s"] < m1["makespan_s"]
+
+
+def test_status_of_an_earlier_chunk_is_not_lost():
+    """A problem that reported an error in a chunk before its last one is still
+    reported when it finishes (the executor's status is sticky)."""
+    reqs = [serve.Request(id=i, arrival=0.0, pde="euler", N=3, ncells=2000, steps=40) for i in range(3)]
+    sch, _, _ = _run(reqs, fail={(0, 1, 0): -4}, max_steps_per_tick=10)
+    assert sch.bad == {1: -4}
