@@ -85,6 +85,10 @@ def load(path=None):
     p = path or LIBPATH
     if not os.path.exists(p):
         raise FileNotFoundError(f"{p} not built; run `python -m paper_2409_12483_amd.build`")
+    # PyTorch provides the device memory and streams the library works on;
+    # load it (and the HIP runtime it brings) before the library, so that one
+    # runtime serves both
+    import torch  # noqa: F401
     lib = ctypes.CDLL(p)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.aderdg_init.argtypes = [ctypes.POINTER(PdeDesc), ctypes.POINTER(Config), i32, vp, ctypes.POINTER(vp)]

@@ -98,8 +98,11 @@ class Batch:
     def freeze(self, idx):
         """Stop advancing problems idx (their end time becomes their time)."""
         if len(idx):
-            ii = self.torch.tensor(list(idx), device=self.t.device)
+            # the index tensor is made on the batch's stream too: its copy is
+            # then ordered before the kernels that read it, and its memory is
+            # not recycled before they have run
             with self.torch.cuda.stream(self.stream):
+                ii = self.torch.tensor(list(idx), device=self.t.device)
                 self.t_end.index_copy_(0, ii, self.t.index_select(0, ii))
 
     def sweeps(self, k):

@@ -128,9 +128,13 @@ class GpuExecutor:
 
 
 class Scheduler:
-    def __init__(self, executor, hbm_budget=200e9, max_active=256, max_steps_per_tick=50,
-                 clock=time.perf_counter, keep_states=False, admit_window=2e-3, idle_cohorts=2):
+    def __init__(self, executor, hbm_budget=200e9, max_active=256, max_steps_per_tick=500,
+                 clock=time.perf_counter, keep_states=False, admit_window=2e-3, idle_cohorts=2,
+                 chunk_dof_steps=1e8):
         self.ex = executor
+        # a chunk holds about chunk_dof_steps DoF-updates (a few milliseconds
+        # of device time), so that no cohort holds its stream for long
+        self.chunk_work = float(chunk_dof_steps)
         # arrivals wait at most admit_window seconds to be admitted together
         # (one cohort, one launch per step), and are admitted at once while
         # fewer than idle_cohorts cohorts are running
@@ -187,7 +191,8 @@ class Scheduler:
             if c.inflight:
                 continue
             act = c.active()
-            n = min(min(c.remaining[i] for i in act), self.cap)
+            work = sum(c.requests[i].dofs for i in act)
+            n = min(min(c.remaining[i] for i in act), self.cap, max(1, int(self.chunk_work // work)))
             self.ex.step(c.handle, n)
             c.inflight = n
             self.ticks += 1
