@@ -28,6 +28,7 @@ stand-in with the same methods):
 """
 
 import time
+from collections import deque
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -67,8 +68,8 @@ class Request:
 class Cohort:
     requests: list
     handle: object
-    remaining: list = field(default_factory=list)
-    inflight: int = 0        # steps of the chunk on the device (0: none)
+    remaining: list = field(default_factory=list)   # steps not yet enqueued, per request
+    chunks: deque = field(default_factory=deque)    # (event, steps, advanced, finishing) in flight
 
     def active(self):
         return [i for i, r in enumerate(self.remaining) if r > 0]
@@ -103,10 +104,12 @@ class GpuExecutor:
         return b
 
     def step(self, cohort, n):
+        """Enqueue n steps; returns the event that marks their end."""
         cohort.step(n)
+        return cohort.event
 
-    def ready(self, cohort):
-        return cohort.ready()
+    def ready(self, event):
+        return event.query()
 
     def wait(self, timeout):
         time.sleep(max(0.0, min(timeout, self.poll_s)))
@@ -130,8 +133,9 @@ class GpuExecutor:
 class Scheduler:
     def __init__(self, executor, hbm_budget=200e9, max_active=256, max_steps_per_tick=500,
                  clock=time.perf_counter, keep_states=False, admit_window=2e-3, idle_cohorts=2,
-                 chunk_dof_steps=1e8):
+                 chunk_dof_steps=1e8, depth=2):
         self.ex = executor
+        self.depth = max(1, int(depth))      # chunks in flight per cohort
         # a chunk holds about chunk_dof_steps DoF-updates (a few milliseconds
         # of device time), so that no cohort holds its stream for long
         self.chunk_work = float(chunk_dof_steps)
@@ -186,50 +190,51 @@ class Scheduler:
 
     # -- chunks: enqueue, and retire when done -----------------------------
     def launch(self):
-        """Enqueue the next chunk of every cohort that has none in flight."""
+        """Keep `depth` chunks in flight per cohort.  The requests a chunk
+        finishes are frozen right behind it in stream order, so the next chunk
+        can be enqueued before the host has seen the first one end."""
         for c in self.cohorts:
-            if c.inflight:
-                continue
-            act = c.active()
-            work = sum(c.requests[i].dofs for i in act)
-            n = min(min(c.remaining[i] for i in act), self.cap, max(1, int(self.chunk_work // work)))
-            self.ex.step(c.handle, n)
-            c.inflight = n
-            self.ticks += 1
-        self.max_inflight = max(self.max_inflight, sum(1 for c in self.cohorts if c.inflight))
+            while len(c.chunks) < self.depth:
+                act = c.active()
+                if not act:
+                    break
+                work = sum(c.requests[i].dofs for i in act)
+                n = min(min(c.remaining[i] for i in act), self.cap, max(1, int(self.chunk_work // work)))
+                ev = self.ex.step(c.handle, n)
+                fin = []
+                for i in act:
+                    c.remaining[i] -= n
+                    if c.remaining[i] == 0:
+                        fin.append(i)
+                if fin and len(fin) < len(act):
+                    self.ex.freeze(c.handle, fin)
+                c.chunks.append((ev, n, act, fin))
+                self.ticks += 1
+        self.max_inflight = max(self.max_inflight, sum(1 for c in self.cohorts if c.chunks))
 
     def complete(self):
-        """Retire the requests of every cohort whose chunk has finished.
-        Returns the number of cohorts that made progress."""
-        done_cohorts = 0
+        """Retire the requests of the chunks that have finished, free the
+        cohorts that are done.  Returns the number of chunks retired."""
+        retired = 0
         keep = []
         for c in self.cohorts:
-            if not c.inflight or not self.ex.ready(c.handle):
-                keep.append(c)
-                continue
-            done_cohorts += 1
-            now = self.clock()
-            n, c.inflight = c.inflight, 0
-            act = c.active()
-            done_idx = []
-            for i in act:
-                c.remaining[i] -= n
-                c.requests[i].steps_done += n
-                if c.remaining[i] == 0:
-                    done_idx.append(i)
-            if done_idx:
-                st = self.ex.status(c.handle)
-                for i in done_idx:
-                    r = c.requests[i]
-                    r.done = now
-                    self.finished.append(r)
-                    if st[i] != 0:
-                        self.bad[r.id] = int(st[i])
-                    if self.keep:
-                        self.states[r.id] = self.ex.state(c.handle, i)
-                if len(done_idx) < len(act):
-                    self.ex.freeze(c.handle, done_idx)
-            if c.active():
+            while c.chunks and self.ex.ready(c.chunks[0][0]):
+                _, n, act, fin = c.chunks.popleft()
+                retired += 1
+                now = self.clock()
+                for i in act:
+                    c.requests[i].steps_done += n
+                if fin:
+                    st = self.ex.status(c.handle)
+                    for i in fin:
+                        r = c.requests[i]
+                        r.done = now
+                        self.finished.append(r)
+                        if st[i] != 0:
+                            self.bad[r.id] = int(st[i])
+                        if self.keep:
+                            self.states[r.id] = self.ex.state(c.handle, i)
+            if c.chunks or c.active():
                 keep.append(c)
             else:
                 self.ex.free(c.handle)
@@ -237,7 +242,7 @@ class Scheduler:
                     self.used -= r.nbytes
                     self.nactive -= 1
         self.cohorts = keep
-        return done_cohorts
+        return retired
 
     # -- the service loop over an arrival trace --------------------------
     def run(self, requests):

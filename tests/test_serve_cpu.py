@@ -63,9 +63,10 @@ class FakeExecutor:
         self.busy[k] = start + work / self.rate
         c["done_at"] = self.busy[k]
         c["chunks"] += 1
+        return c["done_at"]
 
-    def ready(self, c):
-        return self.clock.t >= c["done_at"]
+    def ready(self, done_at):
+        return self.clock.t >= done_at
 
     def wait(self, timeout):
         later = [c["done_at"] for c in self.live if c["done_at"] > self.clock.t]
