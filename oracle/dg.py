@@ -94,9 +94,9 @@ def dg_correct(ops, pde, u, q, dt, dx, x_left, t0):
     return u + vol - surf - jump + sb
 
 
-def dg_step(ops, pde, u, t, dt, dx, x_left, tol=1e-14, max_iter=64):
+def dg_step(ops, pde, u, t, dt, dx, x_left, tol=1e-14, max_iter=64, inner="picard"):
     """One full ADER-DG step: predictor then corrector."""
-    q, sweeps, failed = predict(ops, pde, u, dt, dx, x_left, t, tol, max_iter)
+    q, sweeps, failed = predict(ops, pde, u, dt, dx, x_left, t, tol, max_iter, inner)
     return dg_correct(ops, pde, u, q, dt, dx, x_left, t), sweeps, failed
 
 
@@ -106,7 +106,7 @@ def conserved_totals(ops, u, dx):
 
 
 def dg_run(ops, pde, u, x0, x1, cfl=0.4, t_end=np.inf, nsteps=None, t0=0.0,
-           fixed_dt=None, cfl_mode="subcell", tol=1e-14, max_iter=64):
+           fixed_dt=None, cfl_mode="subcell", tol=1e-14, max_iter=64, inner="picard"):
     """Advance until t_end or for nsteps steps.  Returns (u, t, info)."""
     u = np.array(u, dtype=np.float64, copy=True)
     C = u.shape[0]
@@ -122,7 +122,7 @@ def dg_run(ops, pde, u, x0, x1, cfl=0.4, t_end=np.inf, nsteps=None, t0=0.0,
         dt = min(dt, t_end - t)
         if dt <= 0:
             break
-        u, sweeps, failed = dg_step(ops, pde, u, t, dt, dx, x_left, tol, max_iter)
+        u, sweeps, failed = dg_step(ops, pde, u, t, dt, dx, x_left, tol, max_iter, inner)
         any_failed |= bool(failed.any())
         for s, c in zip(*np.unique(sweeps, return_counts=True)):
             sweep_hist[int(s)] = sweep_hist.get(int(s), 0) + int(c)

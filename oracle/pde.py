@@ -74,6 +74,13 @@ class EulerReact(Euler):
         S[..., 4] = -self.omega ** 2 * Q[..., 3]
         return S
 
+    def source_jacobian(self, Q, x, t):
+        """dS/dQ at every point: [..., M, M] (row = component of S)."""
+        J = np.zeros(Q.shape + (self.M,))
+        J[..., 3, 4] = 1.0
+        J[..., 4, 3] = -self.omega ** 2
+        return J
+
     def max_speed(self, Q):
         return super().max_speed(Q[..., :3])
 

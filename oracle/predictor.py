@@ -32,15 +32,41 @@ def _cellmax(a):
     return np.abs(a).reshape(a.shape[0], -1).max(axis=1)
 
 
-def predict(ops, pde, u, dt, dx, x_left, t0, tol=1e-14, max_iter=64):
+def _newton_update(ops, pde, qi, qp, x, ts, dt):
+    """One Newton step for the inner system G(q) = q - P(q) = 0, P the Picard
+    map with the flux terms frozen (source terms only, which act point-wise,
+    so the system splits into one per space node): the Jacobian is
+    I - dt (kappa~ (x) I_M) blockdiag_b(dS/dq(q[b, l])), of size nM per node.
+    qi: current inner iterate, qp = P(qi); returns the next iterate."""
+    C, n, _, M = qi.shape
+    Js = pde.source_jacobian(qi, x, ts[None, :, None])                  # [C, b, l, M, M]
+    Jm = np.einsum("ab,cblrs->clarbs", ops.kappa, Js)                    # [C, l, a, r, b, s]
+    Jm = np.eye(n * M)[None, None] - dt * Jm.reshape(C, n, n * M, n * M)
+    G = np.transpose(qi - qp, (0, 2, 1, 3)).reshape(C, n, n * M)        # [C, l, (a, r)]
+    delta = np.linalg.solve(Jm, -G[..., None])[..., 0]
+    return qi + np.transpose(delta.reshape(C, n, n, M), (0, 2, 1, 3))
+
+
+def predict(ops, pde, u, dt, dx, x_left, t0, tol=1e-14, max_iter=64, inner="picard"):
     """Space-time predictor for every cell.
 
     u       : [C, n, M] DG nodal coefficients at t0
     dt, dx  : time step and cell width (uniform mesh)
     x_left  : [C] left edge of each cell (source-term coordinates)
+    inner   : "picard" (the nested Picard iteration of eq.
+              lst_dg_predictor_nested_picards) or "newton": the inner
+              iterations on the source terms by Newton's method, which Sec. 1.1
+              recommends for stiff sources (models with a source and no
+              non-conservative term)
     returns (q [C, n, n, M] indexed [cell, time node, space node, var],
              outer sweep counts [C], not-converged flags [C])
     """
+    if inner not in ("picard", "newton"):
+        raise ValueError(inner)
+    newton = inner == "newton"
+    if newton and (pde.has_ncp or not pde.has_source):
+        raise ValueError("Newton inner iterations need a model with a source and no "
+                         "non-conservative term")
     u = np.asarray(u, dtype=np.float64)
     C, n, M = u.shape
     assert n == ops.n and M == pde.M
@@ -78,6 +104,8 @@ def predict(ops, pde, u, dt, dx, x_left, t0, tol=1e-14, max_iter=64):
                 rhs = rhs - dtdx * pde.ncp(qi, dq)
             # kappa~ along the time index, added onto q_init (Algorithm 1, kappa_kernel)
             qn = q_init[active[inner_active]] + np.einsum("ab,cblr->calr", ops.kappa, rhs)
+            if newton:
+                qn = _newton_update(ops, pde, qi, qn, xs[active[inner_active]][:, None, :], ts, dt)
             eps_in = _cellmax(qn - qi)
             q_int[inner_active] = qn
             if not iterative_inner:

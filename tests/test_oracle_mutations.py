@@ -211,3 +211,27 @@ def test_planted_halved_finite_volume_time_step_is_caught(monkeypatch):
     orig = fv.fv_dt
     monkeypatch.setattr(fv, "fv_dt", lambda pde, v, dx, cfl: 0.5 * orig(pde, v, dx, cfl))
     assert not _all_swe_pins_pass()
+
+
+# ------------------------------------------------------- Newton inner loop ----
+def _newton_pade_pin():
+    ops = basis.build_operators(2)
+    pr = P.EulerReact(omega=1.0)
+    u = W.euler_react_uniform(1, 2)
+    dt = 2 * np.pi
+    q, _, failed = predictor.predict(ops, pr, u, dt, 1000.0, np.array([0.0]), 0.0, inner="newton")
+    u1 = dg.dg_correct(ops, pr, u, q, dt, 1000.0, np.array([0.0]), 0.0)
+    closed = pade.oscillator_trajectory(2, 1)[-1]
+    return (not failed.any()) and np.abs(u1[0, :, 3:] - closed).max() <= 1e-13
+
+
+def test_unmutated_newton_passes_its_pin():
+    assert _newton_pade_pin()
+
+
+@pytest.mark.parametrize("mutate", [lambda J: -J, lambda J: np.swapaxes(J, -1, -2), lambda J: 0.5 * J])
+def test_planted_wrong_source_jacobian_is_caught(monkeypatch, mutate):
+    orig = P.EulerReact.source_jacobian
+    monkeypatch.setattr(P.EulerReact, "source_jacobian", lambda self, Q, x, t: mutate(orig(self, Q, x, t)))
+    with np.errstate(all="ignore"):
+        assert not _newton_pade_pin()
