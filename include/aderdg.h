@@ -65,6 +65,12 @@ enum aderdg_prec { ADERDG_FP64 = 0, ADERDG_FP32_PREDICTOR = 1 };
 enum aderdg_bc { ADERDG_BC_PERIODIC = 0 };
 enum aderdg_cfl_mode { ADERDG_CFL_SUBCELL = 0, ADERDG_CFL_NODAL = 1 };
 enum aderdg_scheme { ADERDG_SCHEME_DG = 0, ADERDG_SCHEME_FV = 1 };
+/* Inner iterations of the predictor (Sec. 1.1, eq. lst_dg_predictor_nested_picards):
+ * Picard (the paper's choice), or Newton's method, which Sec. 1.1 recommends for stiff
+ * source terms.  Newton is available for DG problems of the models with a linear source
+ * (ADERDG_PDE_EULER_REACT): its Jacobian is then constant and the inverse is formed once
+ * per step. */
+enum aderdg_inner { ADERDG_INNER_PICARD = 0, ADERDG_INNER_NEWTON = 1 };
 
 typedef struct {
   int32_t pde;        /* enum aderdg_pde */
@@ -85,8 +91,10 @@ typedef struct {
   int32_t cfl_mode;        /* enum aderdg_cfl_mode (DG only) */
   int32_t precision;       /* enum aderdg_prec */
   double picard_tol;       /* <= 0: 1e-14 (FP64) or 1e-6 (FP32 predictor) */
-  int32_t picard_max_iter; /* <= 0: 64 */
+  int32_t picard_max_iter; /* <= 0: 64 (bounds the inner Newton iterations too) */
   int32_t scheme;          /* enum aderdg_scheme: which step function serves this problem */
+  int32_t inner;           /* enum aderdg_inner (default 0: Picard) */
+  int32_t reserved;        /* must be 0 */
 } aderdg_config;
 
 typedef struct aderdg_handle aderdg_handle;

@@ -24,6 +24,7 @@ FP64, FP32_PREDICTOR = 0, 1
 BC_PERIODIC = 0
 CFL_SUBCELL, CFL_NODAL = 0, 1
 SCHEME_DG, SCHEME_FV = 0, 1
+INNER_PICARD, INNER_NEWTON = 0, 1
 NVARS = {PDE_ADVECTION: 1, PDE_EULER: 3, PDE_EULER_REACT: 5, PDE_SWE: 3}
 
 EXPORTS = ["aderdg_init", "aderdg_predict", "aderdg_correct", "aderdg_step", "aderweno_step",
@@ -45,7 +46,8 @@ class Config(ctypes.Structure):
                 ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("fixed_dt", ctypes.c_double), ("cfl_mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("picard_tol", ctypes.c_double),
-                ("picard_max_iter", ctypes.c_int32), ("scheme", ctypes.c_int32)]
+                ("picard_max_iter", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("inner", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Config2D(ctypes.Structure):
@@ -146,9 +148,9 @@ def pde_desc(pde, gamma=1.4, g=9.81, omega=1.0, adv_speed=1.0):
 
 
 def config(N, ncells, x0=0.0, x1=1.0, cfl=0.4, fixed_dt=0.0, cfl_mode=CFL_SUBCELL,
-           precision=FP64, picard_tol=0.0, picard_max_iter=0, scheme=SCHEME_DG):
+           precision=FP64, picard_tol=0.0, picard_max_iter=0, scheme=SCHEME_DG, inner=INNER_PICARD):
     return Config(N, BC_PERIODIC, ncells, x0, x1, cfl, fixed_dt, cfl_mode, precision,
-                  picard_tol, picard_max_iter, scheme)
+                  picard_tol, picard_max_iter, scheme, inner, 0)
 
 
 def aderdg_init(pdes, cfgs, stream=None):

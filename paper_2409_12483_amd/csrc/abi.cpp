@@ -110,7 +110,7 @@ int ensure_tables(int device) {
 }
 
 struct Group {
-  int scheme, pde, N, prec;
+  int scheme, pde, N, prec, inner;
   std::vector<int> pids;
   std::vector<ProbDev> host;
   ProbDev* dev = nullptr;
@@ -184,6 +184,10 @@ int validate(const aderdg_pde_desc& p, const aderdg_config& c, int k) {
   if (c.precision != ADERDG_FP64 && c.precision != ADERDG_FP32_PREDICTOR) return bad("unknown precision");
   if (!std::isfinite(c.picard_tol)) return bad("non-finite picard_tol");
   if (c.picard_max_iter > 100000) return bad("picard_max_iter too large");
+  if (c.inner != ADERDG_INNER_PICARD && c.inner != ADERDG_INNER_NEWTON) return bad("unknown inner solver");
+  if (c.inner == ADERDG_INNER_NEWTON && (c.scheme != ADERDG_SCHEME_DG || p.pde != ADERDG_PDE_EULER_REACT))
+    return bad("Newton inner iterations serve DG problems of the model with a linear source (EULER_REACT)");
+  if (c.reserved != 0) return bad("reserved must be 0");
   return ADERDG_OK;
 }
 
@@ -275,7 +279,8 @@ int run_steps(aderdg_handle* h, int scheme, double* const* u, double* t, const d
       A.clocks = h->clocks;
       A.t_end = t_end;
       A.step = s;
-      e = scheme == ADERDG_SCHEME_DG ? launch_dg(g->pde, g->N, g->prec, 2, A, g->blocks, h->stream)
+      e = scheme == ADERDG_SCHEME_DG ? launch_dg(g->pde, g->N, g->prec, 2, A, g->blocks, h->stream,
+                                                 g->inner == ADERDG_INNER_NEWTON)
                                       : launch_fv(g->pde, g->N, g->prec, A, g->blocks, h->stream);
       if (e != hipSuccess) return fail_hip(e, "step kernel");
     }
@@ -347,9 +352,9 @@ int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t 
   e = launch_write_probs(h->single_host.data(), nprob, h->single_dev, st);
   if (e != hipSuccess) { release(h); return fail_hip(e, "table upload"); }
   // launch groups
-  std::map<std::tuple<int, int, int, int>, int> index;
+  std::map<std::tuple<int, int, int, int, int>, int> index;
   for (int k = 0; k < nprob; ++k) {
-    auto key = std::make_tuple(cfgs[k].scheme, pdes[k].pde, cfgs[k].N, cfgs[k].precision);
+    auto key = std::make_tuple(cfgs[k].scheme, pdes[k].pde, cfgs[k].N, cfgs[k].precision, cfgs[k].inner);
     auto it = index.find(key);
     if (it == index.end()) {
       Group g;
@@ -357,6 +362,7 @@ int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t 
       g.pde = pdes[k].pde;
       g.N = cfgs[k].N;
       g.prec = cfgs[k].precision;
+      g.inner = cfgs[k].inner;
       index[key] = (int)h->groups.size();
       h->groups.push_back(g);
       it = index.find(key);
@@ -425,7 +431,8 @@ int aderdg_predict(aderdg_handle* h, int32_t k, const double* u, double t, doubl
   A.t = t;
   A.dt = dt;
   const int64_t tile = dg_tile_cells(c.N, false);
-  hipError_t e = launch_dg(h->pdes[k].pde, c.N, c.precision, 0, A, (c.ncells + tile - 1) / tile, h->stream);
+  hipError_t e = launch_dg(h->pdes[k].pde, c.N, c.precision, 0, A, (c.ncells + tile - 1) / tile, h->stream,
+                           c.inner == ADERDG_INNER_NEWTON);
   if (e != hipSuccess) return fail_hip(e, "predictor kernel");
   return ADERDG_OK;
 }
@@ -523,7 +530,7 @@ int aderdg_step_noalloc(const aderdg_pde_desc* pde, const aderdg_config* cfg, do
     A.clocks = clk;
     A.t_end = t_end;
     A.step = s;
-    e = is_dg ? launch_dg(pde->pde, cfg->N, cfg->precision, 2, A, d.tiles, st)
+    e = is_dg ? launch_dg(pde->pde, cfg->N, cfg->precision, 2, A, d.tiles, st, cfg->inner == ADERDG_INNER_NEWTON)
               : launch_fv(pde->pde, cfg->N, cfg->precision, A, d.tiles, st);
     if (e != hipSuccess) return fail_hip(e, "step kernel");
   }

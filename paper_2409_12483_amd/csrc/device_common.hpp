@@ -107,6 +107,7 @@ __device__ __forceinline__ float recip(float x) {
 struct Advection {
   static constexpr int M = 1;
   static constexpr bool kSource = false, kNcp = false;
+  static constexpr int kSrcVars = 0;
   template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
     f[0] = T(p.a) * q[0];
   }
@@ -118,6 +119,7 @@ struct Advection {
 struct Euler {  // Sec. 2, eq. system_of_equations in 1-D: (rho, rho u, E)
   static constexpr int M = 3;
   static constexpr bool kSource = false, kNcp = false;
+  static constexpr int kSrcVars = 0;
   template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
     const T u = q[1] * recip(q[0]);
     const T pr = T(p.gamma - 1.0) * (q[2] - T(0.5) * q[1] * u);
@@ -156,6 +158,13 @@ struct EulerReact {  // Sec. 2.1, eq. pdes_2_comps in 1-D: (rho, rho u, E, rho c
     s[3] = q[4];
     s[4] = -T(p.omega * p.omega) * q[3];
   }
+  // The source is linear: its Jacobian is constant and non-zero only among
+  // the variables src_var(0..kSrcVars-1) = (rho c1, rho c2).
+  static constexpr int kSrcVars = 2;
+  __device__ static constexpr int src_var(int k) { return 3 + k; }
+  __device__ static double src_jac(int k, int k2, const PdeParams& p) {
+    return k == 0 ? (k2 == 1 ? 1.0 : 0.0) : (k2 == 0 ? -p.omega * p.omega : 0.0);
+  }
   template <class T> __device__ static T speed(const T* q, const PdeParams& p) {
     return Euler::speed(q, p);
   }
@@ -168,6 +177,7 @@ struct EulerReact {  // Sec. 2.1, eq. pdes_2_comps in 1-D: (rho, rho u, E, rho c
 struct ShallowWater {  // (h, hu, b); B(Q) dQ/dx = (0, g h db/dx, 0)
   static constexpr int M = 3;
   static constexpr bool kSource = false, kNcp = true;
+  static constexpr int kSrcVars = 0;
   template <class T> __device__ static void flux(const T* q, T* f, const PdeParams& p) {
     const T u = q[1] * recip(q[0]);
     f[0] = q[1];

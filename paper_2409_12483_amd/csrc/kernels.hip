@@ -178,14 +178,16 @@ struct DgOccupancy {
   static constexpr int value = (PDE::kSource || PDE::kNcp || N > 5) ? 1 : 4;
 };
 
-template <int N, class PDE, class TP, int WAVES, int MODE>
+template <int N, class PDE, class TP, int WAVES, int MODE, bool NEWTON = false>
 __global__ void __launch_bounds__(WAVES * 64)
 __attribute__((amdgpu_waves_per_eu(DgOccupancy<N, PDE>::value)))
 dg_kernel(StepArgs A) {
   constexpr bool HALO = MODE != kPredict;
   using G = Geo<N, PDE::M, WAVES, HALO>;
   constexpr int n = G::n, M = PDE::M, CPW = G::CPW, PC = G::PC;
-  using Pred = Predictor<N, PDE, TP, sizeof(TP) == 4 && kFp32Mfma>;
+  using Pred = Predictor<N, PDE, TP, sizeof(TP) == 4 && kFp32Mfma, NEWTON>;
+  // inverse Jacobian of the Newton inner iterations (augmented rows)
+  __shared__ double jinv[NEWTON ? NewtonDims<N, PDE>::kSize : 1];
 
   __shared__ double xb_all[WAVES * G::XB];
   __shared__ TP red_all[WAVES * G::RED];
@@ -268,8 +270,12 @@ dg_kernel(StepArgs A) {
 #pragma unroll
     for (int r = 0; r < M; ++r) ucol[r] = TP(ucell[a * M + r]);
     const TP tol = TP(P.tol);
+    if constexpr (NEWTON) {
+      newton_prepare<N, PDE>(jinv, dt, pp);
+      __syncthreads();
+    }
     Pred::run(q, ucol, a, xbp, red, TP(dt), TP(dtdx), xl, dx, c.t, pp, tol, max_iter,
-              sizeof(TP) == 4, active, sweeps, contractions, failed);
+              sizeof(TP) == 4, active, sweeps, contractions, failed, jinv);
   }
 
   if constexpr (MODE == kPredict) {
@@ -913,21 +919,21 @@ __global__ void copy_kernel(const double* __restrict__ src, double* __restrict__
 }
 
 // -------------------------------------------------------------- dispatch ----
-template <int N, class PDE, class TP, int WAVES>
+template <int N, class PDE, class TP, int WAVES, bool NEWTON>
 static hipError_t launch_dg_t(int mode, const StepArgs& A, int64_t blocks, hipStream_t st) {
   dim3 grid((unsigned)blocks), block(WAVES * 64);
   switch (mode) {
-    case kPredict: hipLaunchKernelGGL((dg_kernel<N, PDE, TP, WAVES, kPredict>), grid, block, 0, st, A); break;
+    case kPredict: hipLaunchKernelGGL((dg_kernel<N, PDE, TP, WAVES, kPredict, NEWTON>), grid, block, 0, st, A); break;
     case kCorrect: hipLaunchKernelGGL((dg_kernel<N, PDE, TP, WAVES, kCorrect>), grid, block, 0, st, A); break;
-    default: hipLaunchKernelGGL((dg_kernel<N, PDE, TP, WAVES, kStep>), grid, block, 0, st, A); break;
+    default: hipLaunchKernelGGL((dg_kernel<N, PDE, TP, WAVES, kStep, NEWTON>), grid, block, 0, st, A); break;
   }
   return hipGetLastError();
 }
 
-template <class PDE, class TP>
+template <class PDE, class TP, bool NEWTON>
 static hipError_t launch_dg_n(int N, int mode, const StepArgs& A, int64_t blocks, hipStream_t st) {
   switch (N) {
-#define ADERDG_CASE(NN) case NN: return launch_dg_t<NN, PDE, TP, kDgWaves>(mode, A, blocks, st);
+#define ADERDG_CASE(NN) case NN: return launch_dg_t<NN, PDE, TP, kDgWaves, NEWTON>(mode, A, blocks, st);
     ADERDG_CASE(1) ADERDG_CASE(2) ADERDG_CASE(3) ADERDG_CASE(4) ADERDG_CASE(5)
     ADERDG_CASE(6) ADERDG_CASE(7) ADERDG_CASE(8) ADERDG_CASE(9)
 #undef ADERDG_CASE
@@ -935,15 +941,20 @@ static hipError_t launch_dg_n(int N, int mode, const StepArgs& A, int64_t blocks
   }
 }
 
-template <class PDE>
+template <class PDE, bool NEWTON = false>
 static hipError_t launch_dg_p(int N, int prec, int mode, const StepArgs& A, int64_t blocks,
                               hipStream_t st) {
-  return prec == 1 ? launch_dg_n<PDE, float>(N, mode, A, blocks, st)
-                   : launch_dg_n<PDE, double>(N, mode, A, blocks, st);
+  return prec == 1 ? launch_dg_n<PDE, float, NEWTON>(N, mode, A, blocks, st)
+                   : launch_dg_n<PDE, double, NEWTON>(N, mode, A, blocks, st);
 }
 
 hipError_t launch_dg(int pde, int N, int prec, int mode, const StepArgs& A, int64_t blocks,
-                     hipStream_t st) {
+                     hipStream_t st, bool newton) {
+  if (newton) {
+    // Newton inner iterations are compiled for the model with a linear source
+    if (pde != 2) return hipErrorInvalidValue;
+    return launch_dg_p<EulerReact, true>(N, prec, mode, A, blocks, st);
+  }
   switch (pde) {
     case 0: return launch_dg_p<Advection>(N, prec, mode, A, blocks, st);
     case 1: return launch_dg_p<Euler>(N, prec, mode, A, blocks, st);

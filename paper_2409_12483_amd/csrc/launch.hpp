@@ -29,7 +29,7 @@ struct StepArgs {
 };
 
 hipError_t launch_dg(int pde, int N, int prec, int mode, const StepArgs& A, int64_t blocks,
-                     hipStream_t st);
+                     hipStream_t st, bool newton = false);
 hipError_t launch_fv(int pde, int NW, int prec, const StepArgs& A, int64_t blocks, hipStream_t st);
 hipError_t launch_lambda(int pde, int N, bool dg, const StepArgs& A, int64_t blocks, hipStream_t st);
 hipError_t launch_clock_begin(ProbClock* clocks, const double* t_user, int nprob, hipStream_t st);

@@ -87,9 +87,85 @@ __device__ __forceinline__ void mfma_apply(const float (&A)[NRB][n], const float
     }
 }
 
-template <int N, class PDE, class TP, bool MF = false>
+// Newton inner iterations (Sec. 1.1: for stiff source terms the inner
+// process of eq. lst_dg_predictor_nested_picards can use Newton's method).
+// For a model whose source is linear, the Jacobian of the inner system
+// G(q) = q - P(q) (P: the Picard map with the flux terms frozen) is the same
+// for every space node: I - dt (kappa~ (x) A) on the variables the source
+// couples (A = dS/dq there), the identity elsewhere.  Its inverse, of size
+// L = n * kSrcVars, is formed once per workgroup and step in LDS by the first
+// wavefront (Gauss-Jordan with partial pivoting) and read as wave-uniform
+// operands.  `aug` holds L rows of 2L doubles; the inverse is its right half.
+template <int N, class PDE>
+struct NewtonDims {
+  static constexpr int n = N + 1;
+  static constexpr int L = n * PDE::kSrcVars;
+  static constexpr int W = 2 * L;                // row stride of the augmented matrix
+  static constexpr int kSize = L > 0 ? L * W : 1;
+};
+
+template <int N, class PDE>
+__device__ void newton_prepare(double* aug, double dt, const PdeParams& pp) {
+  using D = NewtonDims<N, PDE>;
+  constexpr int n = D::n, KS = PDE::kSrcVars, L = D::L, W = D::W;
+  static_assert(L > 0 && W <= 64, "one wavefront spans the augmented rows");
+  if (threadIdx.x >= 64) return;
+  const int j = threadIdx.x;          // column of the augmented matrix
+  if (j < W) {
+    for (int i = 0; i < L; ++i) {
+      double v;
+      if (j < L) {
+        const int a = i / KS, k = i % KS, b = j / KS, k2 = j % KS;
+        v = (i == j ? 1.0 : 0.0) - dt * c_ops[N].kappa[a][b] * PDE::src_jac(k, k2, pp);
+      } else {
+        v = (j - L == i) ? 1.0 : 0.0;
+      }
+      aug[i * W + j] = v;
+    }
+  }
+  wave_sync();
+  for (int c = 0; c < L; ++c) {
+    // pivot: the largest |aug[r][c]| over r >= c (lane r), ties to the lowest row
+    double mag = -1.0;
+    int row = c;
+    if (j >= c && j < L) {
+      mag = fabs(aug[j * W + c]);
+      row = j;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double om = __shfl_xor(mag, off, 64);
+      const int orow = __shfl_xor(row, off, 64);
+      if (om > mag || (om == mag && orow < row)) {
+        mag = om;
+        row = orow;
+      }
+    }
+    if (row != c && j < W) {
+      const double t = aug[c * W + j];
+      aug[c * W + j] = aug[row * W + j];
+      aug[row * W + j] = t;
+    }
+    wave_sync();
+    const double inv = 1.0 / aug[c * W + c];
+    wave_sync();
+    if (j < W) aug[c * W + j] *= inv;
+    wave_sync();
+    for (int r = 0; r < L; ++r) {
+      if (r == c) continue;
+      const double f = aug[r * W + c];
+      wave_sync();
+      if (j < W) aug[r * W + j] -= f * aug[c * W + j];
+      wave_sync();
+    }
+  }
+}
+
+template <int N, class PDE, class TP, bool MF = false, bool NEWTON = false>
 struct Predictor {
   static_assert(!MF || sizeof(TP) == 4, "the MFMA contractions are FP32");
+  static_assert(!NEWTON || (PDE::kSource && !PDE::kNcp && PDE::kSrcVars > 0),
+                "Newton inner iterations serve models with a linear source only");
   static constexpr int n = N + 1;
   static constexpr int M = PDE::M;
   static constexpr int NRB = (n + 3) / 4;   // 4-row blocks of an operator (MFMA path)
@@ -288,12 +364,134 @@ struct Predictor {
       }
   }
 
+  // Inner iterations by Newton's method, in the column role: lane a holds the
+  // space node a of its cell for every time level (KF and the iterate are
+  // transposed once through the cell's LDS block), evaluates the point-wise
+  // source and the Picard map P on its column, and applies the inverse
+  // Jacobian to the source variables: q <- q + J^-1 (P(q) - q) there, P(q)
+  // elsewhere.  On exit q holds row a of the converged inner iterate and
+  // e, qm the lane's share of the outer norms (against the row on entry).
+  __device__ static void newton_inner(const TP (&KF)[n][M], TP (&q)[n][M], const TP (&ucol)[M],
+                                      TP* xb, TP* red, int a, bool write, TP dt, TP dtdx, double xl,
+                                      double dx, double t0, const PdeParams& pp, TP tol,
+                                      int max_iter, bool stagnation, const double* jinv,
+                                      int& sweeps, bool& failed, TP& e, TP& qm) {
+    using D = NewtonDims<N, PDE>;
+    constexpr int KS = PDE::kSrcVars, L = D::L, W = D::W;
+    TP kfc[n][M], qc[n][M];
+    if (write) {
+#pragma unroll
+      for (int l = 0; l < n; ++l)
+#pragma unroll
+        for (int r = 0; r < M; ++r) xb[a * RS + l * M + r] = KF[l][r];
+    }
+    wave_sync();
+#pragma unroll
+    for (int b = 0; b < n; ++b)
+#pragma unroll
+      for (int r = 0; r < M; ++r) kfc[b][r] = xb[b * RS + a * M + r];
+    wave_sync();
+    if (write) {
+#pragma unroll
+      for (int l = 0; l < n; ++l)
+#pragma unroll
+        for (int r = 0; r < M; ++r) xb[a * RS + l * M + r] = q[l][r];
+    }
+    wave_sync();
+#pragma unroll
+    for (int b = 0; b < n; ++b)
+#pragma unroll
+      for (int r = 0; r < M; ++r) qc[b][r] = xb[b * RS + a * M + r];
+    const TP xa = TP(xl + dx * c_ops[N].xi[a < n ? a : 0]);
+    const cptr<TP> Kp = opaque(OpSrc<N, TP>::Kap());
+    bool idone = !write;
+    TP ieps_prev = TP(3.0e38);
+    for (int m = 0; m < max_iter; ++m) {
+      if (!__any(!idone)) break;
+      // Picard map on the column
+      TP R[n][M];
+#pragma unroll
+      for (int b = 0; b < n; ++b) {
+        TP sv[M];
+        PDE::source(qc[b], xa, TP(t0 + (double)dt * c_ops[N].xi[b]), sv, pp);
+#pragma unroll
+        for (int r = 0; r < M; ++r) R[b][r] = kfc[b][r] - TP(dx) * sv[r];
+      }
+      TP qp[n][M];
+#pragma unroll
+      for (int a2 = 0; a2 < n; ++a2)
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          TP acc = Kp[a2 * kDevMaxn] * R[0][r];
+#pragma unroll
+          for (int b = 1; b < n; ++b) acc += Kp[a2 * kDevMaxn + b] * R[b][r];
+          qp[a2][r] = ucol[r] - dtdx * acc;
+        }
+      // Newton correction on the source variables
+      TP dlt[L];
+#pragma unroll
+      for (int b = 0; b < n; ++b)
+#pragma unroll
+        for (int k = 0; k < KS; ++k) dlt[b * KS + k] = qp[b][PDE::src_var(k)] - qc[b][PDE::src_var(k)];
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        TP acc = TP(0);
+#pragma unroll
+        for (int j2 = 0; j2 < L; ++j2) acc += TP(jinv[i * W + L + j2]) * dlt[j2];
+        const int a2 = i / KS, v = PDE::src_var(i % KS);
+        qp[a2][v] = qc[a2][v] + acc;
+      }
+      TP ie = TP(0), iqm = TP(0);
+#pragma unroll
+      for (int b = 0; b < n; ++b)
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          ie = max_abs(ie, qp[b][r] - qc[b][r]);
+          iqm = max_abs(iqm, qp[b][r]);
+          if (!idone) qc[b][r] = qp[b][r];
+        }
+      if (!idone) sweeps += 1 << 16;
+      cell_reduce(red, ie, iqm);
+      if (!idone) {
+        const bool conv = ie <= tol * dmax(TP(1), iqm);
+        const bool stag = stagnation && m >= 1 && ie >= ieps_prev;
+        ieps_prev = ie;
+        if (conv || stag) idone = true;
+      }
+    }
+    if (!idone) failed = true;
+    // back to rows, with the outer norms
+    wave_sync();
+    if (write) {
+#pragma unroll
+      for (int b = 0; b < n; ++b)
+#pragma unroll
+        for (int r = 0; r < M; ++r) xb[b * RS + a * M + r] = qc[b][r];
+    }
+    wave_sync();
+#pragma unroll
+    for (int l = 0; l < n; ++l)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        const TP v = xb[a * RS + l * M + r];
+        const TP d = v - q[l][r];
+        if (l == 0 && r == 0) {
+          e = dabs(d);
+          qm = dabs(v);
+        } else {
+          e = max_abs(e, d);
+          qm = max_abs(qm, v);
+        }
+        q[l][r] = v;
+      }
+  }
+
   // q: row a of the initial guess on entry (broadcast of the initial data),
   // the converged row on exit.  ucol: initial data at space node a.
   __device__ static void run(TP (&q)[n][M], const TP (&ucol)[M], int a, TP* xb, TP* red,
                              TP dt, TP dtdx, double xl, double dx, double t0, const PdeParams& pp,
                              TP tol, int max_iter, bool stagnation, bool active, int& sweeps,
-                             int& contractions, bool& failed) {
+                             int& contractions, bool& failed, const double* jinv = nullptr) {
     bool done = !active;
     // outer sweeps; with an inner loop, its iterations (the kappa~ applications
     // this cell needed) ride in the high 16 bits of the same register
@@ -336,6 +534,9 @@ struct Predictor {
       if constexpr (!kInner) {
         residual_row(q, KF, row, a, dt, dtdx, xl, dx, t0, pp);
         time_contraction<true>(row, ucol, xb, a, active && !done, dtdx, q, kt, mo, e, qm);
+      } else if constexpr (NEWTON) {
+        newton_inner(KF, q, ucol, xb, red, a, active && !done, dt, dtdx, xl, dx, t0, pp, tol, max_iter,
+                     stagnation, jinv, sweeps, failed, e, qm);
       } else {
         // inner loop over source / non-conservative terms (Algorithm 1, inner repeat)
         TP qi[n][M];

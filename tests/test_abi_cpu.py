@@ -109,12 +109,32 @@ def test_null_arguments_are_rejected():
         abi.aderdg_operators(10)
 
 
-def test_config_struct_layout_matches_header():
-    # field offsets of the ctypes mirror follow the C declaration order and alignment
-    assert ctypes.sizeof(abi.PdeDesc) == 40
-    assert abi.Config.ncells.offset == 8 and abi.Config.x0.offset == 16
-    assert abi.Config.cfl_mode.offset == 48 and abi.Config.picard_tol.offset == 56
-    assert ctypes.sizeof(abi.Config) == 72
+def test_config_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors of the C structs have the header's size and field
+    offsets: a C program compiled against include/aderdg.h prints them."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {"aderdg_pde_desc": (abi.PdeDesc, [f for f, _ in abi.PdeDesc._fields_]),
+              "aderdg_config": (abi.Config, [f for f, _ in abi.Config._fields_])}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "aderdg.h"', "int main(void) {"]
+    for st, (_, names) in fields.items():
+        lines.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
+        for f in names:
+            lines.append(f'  printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st, (cls, names) in fields.items():
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for f in names:
+            assert got[(st, f)] == getattr(cls, f).offset, (st, f)
 
 
 def _init2d(cfg):
@@ -215,3 +235,11 @@ def test_noalloc_step_rejects_a_state_beyond_its_static_scratch():
     rc = lib.aderdg_step_noalloc(ctypes.byref(abi.pde_desc(abi.PDE_EULER)), ctypes.byref(abi.config(2, 10)),
                                  dummy, dummy, dummy, dummy, dummy, -1, None)
     assert rc == abi.ADERDG_E_INVAL
+
+
+@pytest.mark.parametrize("pde,scheme", [(abi.PDE_EULER, abi.SCHEME_DG), (abi.PDE_SWE, abi.SCHEME_DG),
+                                        (abi.PDE_EULER_REACT, abi.SCHEME_FV)])
+def test_newton_inner_solver_only_for_dg_with_a_linear_source(pde, scheme):
+    rc, _ = _init(abi.pde_desc(pde), abi.config(4, 20, scheme=scheme, inner=abi.INNER_NEWTON))
+    assert rc == abi.ADERDG_E_INVAL
+    assert "Newton" in abi.aderdg_last_error()
