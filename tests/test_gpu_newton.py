@@ -35,11 +35,13 @@ def test_gpu_newton_ode_steps_equal_pade(N, nsteps):
     assert st[0] == 0
     closed = pade.oscillator_trajectory(N, nsteps)[-1]
     assert np.abs(u[0, :, 3:] - closed).max() <= 1e-12
-    # and the Picard inner loop cannot take these steps
-    (_,), _, _, st_p, _ = run_steps([abi.pde_desc(abi.PDE_EULER_REACT, omega=1.0)],
-                                    [abi.config(N, 1, x0=0.0, x1=WIDE, fixed_dt=dt)], [u0], nsteps,
-                                    t_end=np.array([2 * np.pi]))
-    assert st_p[0] != 0
+    if N <= 4:
+        # steps beyond the inner Picard loop's contraction bound (omega dt
+        # above the smallest Pade pole modulus at these degrees)
+        (_,), _, _, st_p, _ = run_steps([abi.pde_desc(abi.PDE_EULER_REACT, omega=1.0)],
+                                        [abi.config(N, 1, x0=0.0, x1=WIDE, fixed_dt=dt)], [u0], nsteps,
+                                        t_end=np.array([2 * np.pi]))
+        assert st_p[0] != 0
 
 
 def _reacting_gas(C, N, seed=0):
