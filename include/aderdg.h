@@ -183,6 +183,44 @@ int aderdg_step_noalloc(const aderdg_pde_desc* pde, const aderdg_config* cfg, do
                         const double* t_end, double* dt, int32_t* status, int32_t nsteps,
                         void* hip_stream);
 
+/*
+ * aderdg_user_init -- a handle for ONE DG problem of a user-defined model,
+ * compiled at run time.  The paper builds its kernels once per parameter set
+ * at run time (Sec. 1.1, the JIT gemm kernels; Sec. 3); here the whole fused
+ * step (predictor, Sec. 1.1, and corrector, Sec. 1.2) is compiled with hipRTC
+ * for gfx950 once per (model source, N, precision) and cached for the process.
+ *   model_source  C++ text of a struct `UserPDE` with the interface of the
+ *                 built-in models (the form of Sec. 1, eq. pde_src):
+ *                   static constexpr int M;  bool kSource, kNcp;  int kSrcVars (0);
+ *                   template <class T> __device__ static void flux(const T* q, T* f, const PdeParams&);
+ *                   template <class T> __device__ static T speed(const T* q, const PdeParams&);
+ *                   __device__ static bool admissible(const double* q, const PdeParams&);
+ *                   __device__ static constexpr double diss(int r);     (Rusanov dissipation mask)
+ *                   with kSource: template <class T> __device__ static void
+ *                                   source(const T* q, T x, T t, T* s, const PdeParams&);
+ *                   with kNcp: ncp(q, dq, b, pp) = B(q) dq and jump(qm, qp, j, pp) = B~ (qp - qm).
+ *                 The library's device helpers (recip, dabs, dmax, PdeParams) are in scope.
+ *   nvars         M of the model (1..5; checked against UserPDE::M at compile time).
+ *   params        4 doubles handed to the model as PdeParams {gamma, g, omega, a}.
+ *   cfg           as for aderdg_init (scheme DG, Picard inner iterations).
+ * The handle then serves aderdg_predict, aderdg_correct, aderdg_step (problem 0),
+ * aderdg_conserved_totals, the counters and aderdg_free like any other.
+ * Errors: E_INVAL (bad arguments, or the model does not compile: the compiler's
+ * log is in aderdg_last_error()), E_DEVICE (module loading), E_NOMEM.
+ * The first call per (model, N, precision) compiles (about a second or two)
+ * and synchronises the host; later calls reuse the module.
+ */
+int aderdg_user_init(const char* model_source, int32_t nvars, const double* params,
+                     const aderdg_config* cfg, void* hip_stream, aderdg_handle** out);
+
+/*
+ * aderdg_user_compile_check -- compile a user model as aderdg_user_init would, without a
+ * device (host only).  log (may be NULL): receives the compiler's messages, at most cap
+ * bytes including the terminating zero.  Returns 0 if it compiles, E_INVAL otherwise.
+ */
+int aderdg_user_compile_check(const char* model_source, int32_t nvars, int32_t N, int32_t precision,
+                              char* log, int64_t cap);
+
 /* aderdg_free -- release the handle: its device memory is freed in stream order after the
  * work already enqueued on its stream (no host synchronisation).  NULL is accepted. */
 int aderdg_free(aderdg_handle* h);

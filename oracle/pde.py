@@ -153,6 +153,28 @@ class Advection:
         return np.ones(1)
 
 
+class Burgers:
+    """Inviscid Burgers equation dq/dt + d(q^2/2)/dx = 0 (scalar).  Not one of
+    the paper's models: it is the test model of the runtime-compiled user
+    models (a flux that is not compiled into the library)."""
+
+    M = 1
+    has_source = False
+    has_ncp = False
+
+    def flux(self, Q):
+        return 0.5 * Q * Q
+
+    def max_speed(self, Q):
+        return np.abs(Q[..., 0])
+
+    def admissible(self, Q):
+        return np.isfinite(Q).all(axis=-1)
+
+    def dissipation_mask(self):
+        return np.ones(1)
+
+
 def rusanov(pde, qm, qp):
     """Rusanov (local Lax-Friedrichs) flux F^(qm, qp), unscaled.
 

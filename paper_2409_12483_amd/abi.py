@@ -29,7 +29,8 @@ NVARS = {PDE_ADVECTION: 1, PDE_EULER: 3, PDE_EULER_REACT: 5, PDE_SWE: 3}
 
 EXPORTS = ["aderdg_init", "aderdg_predict", "aderdg_correct", "aderdg_step", "aderweno_step",
            "aderdg_free", "aderdg_set_stream", "aderdg_sweep_count", "aderdg_contraction_count",
-           "aderdg_operators", "aderdg_conserved_totals", "aderdg_step_noalloc", "aderdg_last_error"]
+           "aderdg_operators", "aderdg_conserved_totals", "aderdg_step_noalloc", "aderdg_user_init",
+           "aderdg_user_compile_check", "aderdg_last_error"]
 EXPORTS_2D = ["aderdg2d_init", "aderdg2d_predict", "aderdg2d_step", "aderdg2d_sweep_count",
               "aderdg2d_free"]
 EXPORTS_3D = ["aderdg3d_init", "aderdg3d_predict", "aderdg3d_step", "aderdg3d_sweep_count",
@@ -104,6 +105,9 @@ def load(path=None):
     lib.aderdg_contraction_count.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.aderdg_operators.argtypes = [i32, ctypes.POINTER(dbl), i64]
     lib.aderdg_conserved_totals.argtypes = [vp, i32, vp, vp]
+    lib.aderdg_user_init.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(dbl), ctypes.POINTER(Config), vp,
+                                     ctypes.POINTER(vp)]
+    lib.aderdg_user_compile_check.argtypes = [ctypes.c_char_p, i32, i32, i32, ctypes.c_char_p, i64]
     lib.aderdg_step_noalloc.argtypes = [ctypes.POINTER(PdeDesc), ctypes.POINTER(Config), vp, vp, vp,
                                         vp, vp, i32, vp]
     lib.aderdg_last_error.argtypes = []
@@ -212,6 +216,23 @@ def aderdg_contraction_count(h, k):
     v = ctypes.c_int64()
     _check(load().aderdg_contraction_count(h, k, ctypes.byref(v)))
     return v.value
+
+
+def aderdg_user_init(model_source, nvars, cfg, params=(1.4, 9.81, 1.0, 1.0), stream=None):
+    """Handle of one DG problem of a runtime-compiled user model (see include/aderdg.h)."""
+    lib = load()
+    h = ctypes.c_void_p()
+    p = (ctypes.c_double * 4)(*params)
+    s = _current_stream() if stream is None else stream
+    _check(lib.aderdg_user_init(model_source.encode(), nvars, p, ctypes.byref(cfg), s, ctypes.byref(h)))
+    return h.value
+
+
+def aderdg_user_compile_check(model_source, nvars, N, precision=FP64):
+    """(ok, compiler log) for a user model, compiled on the host only."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    rc = load().aderdg_user_compile_check(model_source.encode(), nvars, N, precision, buf, len(buf))
+    return rc == ADERDG_OK, buf.value.decode(errors="replace")
 
 
 def aderdg_conserved_totals(h, k, u, out):

@@ -30,11 +30,13 @@
 #include "launch2d.hpp"
 #include "launch3d.hpp"
 #include "operators.hpp"
+#include "rtc.hpp"
 
 using namespace aderdg;
 
 namespace {
 
+constexpr int kPdeUser = 100;   // pde code of a runtime-compiled user model
 thread_local std::string g_last_error;
 
 int fail(int code, const std::string& msg) {
@@ -59,14 +61,19 @@ int model_nvars(int pde) {
 std::mutex g_tables_mutex;
 std::set<int> g_tables_devices;
 
+// Host copies of the device operator tables (also used to fill the tables of
+// runtime-compiled modules).
+DevOps g_host_ops[kDevMaxn];
+DevOpsF g_host_opsf[kDevMaxn];
+
 int ensure_tables(int device) {
   std::lock_guard<std::mutex> lock(g_tables_mutex);
   if (g_tables_devices.count(device)) return ADERDG_OK;
-  static DevOps ops[kDevMaxn];
-  static DevOpsF opsf[kDevMaxn];
+  DevOps* ops = g_host_ops;
+  DevOpsF* opsf = g_host_opsf;
   static DevWeno weno[2];
-  std::memset(ops, 0, sizeof(ops));
-  std::memset(opsf, 0, sizeof(opsf));
+  std::memset(g_host_ops, 0, sizeof(g_host_ops));
+  std::memset(g_host_opsf, 0, sizeof(g_host_opsf));
   std::memset(weno, 0, sizeof(weno));
   for (int N = 0; N < kDevMaxn; ++N) {
     OpTables t;
@@ -111,6 +118,7 @@ int ensure_tables(int device) {
 
 struct Group {
   int scheme, pde, N, prec, inner;
+  const RtcModule* rtc = nullptr;   // runtime-compiled user model (else a compiled-in one)
   std::vector<int> pids;
   std::vector<ProbDev> host;
   ProbDev* dev = nullptr;
@@ -135,6 +143,7 @@ struct aderdg_handle {
   ProbDev* single_dev = nullptr;
   ProbClock* clocks = nullptr;
   double* partials = nullptr;          // conserved-totals partial sums (largest problem)
+  const RtcModule* rtc = nullptr;      // user model of a handle made by aderdg_user_init
   std::vector<Group> groups;
 };
 
@@ -163,9 +172,12 @@ int validate(const aderdg_pde_desc& p, const aderdg_config& c, int k) {
     std::snprintf(buf, sizeof(buf), "problem %d: %s", k, what);
     return fail(ADERDG_E_INVAL, buf);
   };
-  const int M = model_nvars(p.pde);
+  const int M = p.pde == kPdeUser ? p.nvars : model_nvars(p.pde);
   if (M < 0) return bad("unknown pde");
+  if (p.pde == kPdeUser && (M < 1 || M > kTotMaxVars)) return bad("a user model needs 1 <= nvars <= 5");
   if (p.nvars != M) return bad("nvars does not match the model");
+  if (p.pde == kPdeUser && c.scheme != ADERDG_SCHEME_DG) return bad("user models run the DG scheme");
+  if (p.pde == kPdeUser && c.inner != ADERDG_INNER_PICARD) return bad("user models use Picard inner iterations");
   if ((p.pde == ADERDG_PDE_EULER || p.pde == ADERDG_PDE_EULER_REACT) && !(p.gamma > 1.0))
     return bad("gamma must be > 1");
   if (p.pde == ADERDG_PDE_SWE && !(p.g > 0.0)) return bad("g must be > 0");
@@ -267,7 +279,8 @@ int run_steps(aderdg_handle* h, int scheme, double* const* u, double* t, const d
       A.nprob = (int)g->pids.size();
       A.clocks = h->clocks;
       A.t_end = t_end;
-      e = launch_lambda(g->pde, g->N, scheme == ADERDG_SCHEME_DG, A, g->lam_blocks, h->stream);
+      e = g->rtc ? rtc_launch(g->rtc->lambda, A, g->lam_blocks, 256, h->stream)
+                 : launch_lambda(g->pde, g->N, scheme == ADERDG_SCHEME_DG, A, g->lam_blocks, h->stream);
       if (e != hipSuccess) return fail_hip(e, "lambda kernel");
     }
   }
@@ -279,9 +292,12 @@ int run_steps(aderdg_handle* h, int scheme, double* const* u, double* t, const d
       A.clocks = h->clocks;
       A.t_end = t_end;
       A.step = s;
-      e = scheme == ADERDG_SCHEME_DG ? launch_dg(g->pde, g->N, g->prec, 2, A, g->blocks, h->stream,
-                                                 g->inner == ADERDG_INNER_NEWTON)
-                                      : launch_fv(g->pde, g->N, g->prec, A, g->blocks, h->stream);
+      if (g->rtc)
+        e = rtc_launch(g->rtc->dg[2], A, g->blocks, kRtcWaves * 64, h->stream);
+      else
+        e = scheme == ADERDG_SCHEME_DG ? launch_dg(g->pde, g->N, g->prec, 2, A, g->blocks, h->stream,
+                                                   g->inner == ADERDG_INNER_NEWTON)
+                                        : launch_fv(g->pde, g->N, g->prec, A, g->blocks, h->stream);
       if (e != hipSuccess) return fail_hip(e, "step kernel");
     }
   }
@@ -298,16 +314,12 @@ int run_steps(aderdg_handle* h, int scheme, double* const* u, double* t, const d
   return ADERDG_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t nprob,
-                void* hip_stream, aderdg_handle** out) {
-  g_last_error.clear();
+int init_handle(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t nprob, void* hip_stream,
+                aderdg_handle** out, const std::string* user_model) {
   if (!pdes || !cfgs || !out) return fail(ADERDG_E_INVAL, "null argument");
   if (nprob < 1) return fail(ADERDG_E_INVAL, "nprob must be >= 1");
   for (int k = 0; k < nprob; ++k) {
+    if ((pdes[k].pde == kPdeUser) != (user_model != nullptr)) return fail(ADERDG_E_INVAL, "unknown pde");
     int rc = validate(pdes[k], cfgs[k], k);
     if (rc) return rc;
   }
@@ -316,8 +328,17 @@ int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t 
   if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
   int rc = ensure_tables(device);
   if (rc) return rc;
+  const RtcModule* rtc = nullptr;
+  if (user_model) {
+    std::string log;
+    const int r = rtc_module(*user_model, pdes[0].nvars, cfgs[0].N, cfgs[0].precision, device, g_host_ops,
+                             g_host_opsf, &rtc, &log);
+    if (r == -1) return fail(ADERDG_E_INVAL, "user model does not compile:\n" + log);
+    if (r) return fail(ADERDG_E_DEVICE, log);
+  }
 
   aderdg_handle* h = new aderdg_handle();
+  h->rtc = rtc;
   h->stream = (hipStream_t)hip_stream;
   h->device = device;
   h->nprob = nprob;
@@ -395,9 +416,52 @@ int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t 
     // state pointers are bound by the first step call
     rc = upload_group(h, g);
     if (rc) { release(h); return rc; }
+    g.rtc = rtc;
   }
   *out = h;
   return ADERDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aderdg_init(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t nprob,
+                void* hip_stream, aderdg_handle** out) {
+  g_last_error.clear();
+  return init_handle(pdes, cfgs, nprob, hip_stream, out, nullptr);
+}
+
+int aderdg_user_init(const char* model_source, int32_t nvars, const double* params,
+                     const aderdg_config* cfg, void* hip_stream, aderdg_handle** out) {
+  g_last_error.clear();
+  if (!model_source || !params || !cfg || !out) return fail(ADERDG_E_INVAL, "null argument");
+  aderdg_pde_desc d{};
+  d.pde = kPdeUser;
+  d.nvars = nvars;
+  d.gamma = params[0];
+  d.g = params[1];
+  d.omega = params[2];
+  d.adv_speed = params[3];
+  const std::string model(model_source);
+  return init_handle(&d, cfg, 1, hip_stream, out, &model);
+}
+
+int aderdg_user_compile_check(const char* model_source, int32_t nvars, int32_t N, int32_t precision,
+                              char* log, int64_t cap) {
+  g_last_error.clear();
+  if (!model_source) return fail(ADERDG_E_INVAL, "null argument");
+  if (N < 1 || N > kMaxN) return fail(ADERDG_E_INVAL, "N must be in 1..9");
+  if (precision != ADERDG_FP64 && precision != ADERDG_FP32_PREDICTOR) return fail(ADERDG_E_INVAL, "unknown precision");
+  if (nvars < 1 || nvars > kTotMaxVars) return fail(ADERDG_E_INVAL, "a user model needs 1 <= nvars <= 5");
+  std::string text;
+  const int r = rtc_compile_check(model_source, nvars, N, precision, &text);
+  if (log && cap > 0) {
+    const size_t n = text.size() < (size_t)(cap - 1) ? text.size() : (size_t)(cap - 1);
+    std::memcpy(log, text.data(), n);
+    log[n] = '\0';
+  }
+  return r ? fail(ADERDG_E_INVAL, "user model does not compile") : ADERDG_OK;
 }
 
 int aderdg_set_stream(aderdg_handle* h, void* hip_stream) {
@@ -431,8 +495,9 @@ int aderdg_predict(aderdg_handle* h, int32_t k, const double* u, double t, doubl
   A.t = t;
   A.dt = dt;
   const int64_t tile = dg_tile_cells(c.N, false);
-  hipError_t e = launch_dg(h->pdes[k].pde, c.N, c.precision, 0, A, (c.ncells + tile - 1) / tile, h->stream,
-                           c.inner == ADERDG_INNER_NEWTON);
+  hipError_t e = h->rtc ? rtc_launch(h->rtc->dg[0], A, (c.ncells + tile - 1) / tile, kRtcWaves * 64, h->stream)
+                        : launch_dg(h->pdes[k].pde, c.N, c.precision, 0, A, (c.ncells + tile - 1) / tile,
+                                    h->stream, c.inner == ADERDG_INNER_NEWTON);
   if (e != hipSuccess) return fail_hip(e, "predictor kernel");
   return ADERDG_OK;
 }
@@ -455,7 +520,9 @@ int aderdg_correct(aderdg_handle* h, int32_t k, const double* u, const void* q, 
   A.t = t;
   A.dt = dt;
   const int64_t tile = dg_tile_cells(c.N, true);
-  hipError_t e = launch_dg(h->pdes[k].pde, c.N, c.precision, 1, A, (c.ncells + tile - 1) / tile, h->stream);
+  hipError_t e = h->rtc ? rtc_launch(h->rtc->dg[1], A, (c.ncells + tile - 1) / tile, kRtcWaves * 64, h->stream)
+                        : launch_dg(h->pdes[k].pde, c.N, c.precision, 1, A, (c.ncells + tile - 1) / tile,
+                                    h->stream);
   if (e != hipSuccess) return fail_hip(e, "corrector kernel");
   return ADERDG_OK;
 }

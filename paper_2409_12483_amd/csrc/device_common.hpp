@@ -302,6 +302,23 @@ struct ProbClock {
   StatusSlot stat[kSlots];        // most severe status code seen (min)
 };
 
+// Kernel arguments (passed by value).
+struct StepArgs {
+  const ProbDev* probs;   // problems of the launch group (device)
+  int32_t nprob;
+  int32_t k;              // standalone modes: index into probs
+  ProbClock* clocks;      // per-problem clocks of the handle (device)
+  const double* t_end;    // caller's t_end array (device), indexed by ProbDev::pid
+  int32_t step;           // step index within the current call (ping-pong / clock parity)
+  int32_t pad;
+  // standalone predictor / corrector
+  const double* u_in;
+  double* u_out;
+  void* q;
+  int32_t* iters;
+  double t, dt;
+};
+
 __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, double v) {
   // non-negative doubles order like their bit patterns
   atomicMax(addr, (unsigned long long)__double_as_longlong(v));

@@ -11,23 +11,6 @@ namespace aderdg {
 constexpr int kDgWaves = 4;   // wavefronts per DG workgroup
 constexpr int kFvWaves = 4;   // wavefronts per FV workgroup
 
-// Kernel arguments (passed by value).
-struct StepArgs {
-  const ProbDev* probs;   // problems of the launch group (device)
-  int32_t nprob;
-  int32_t k;              // standalone modes: index into probs
-  ProbClock* clocks;      // per-problem clocks of the handle (device)
-  const double* t_end;    // caller's t_end array (device), indexed by ProbDev::pid
-  int32_t step;           // step index within the current call (ping-pong / clock parity)
-  int32_t pad;
-  // standalone predictor / corrector
-  const double* u_in;
-  double* u_out;
-  void* q;
-  int32_t* iters;
-  double t, dt;
-};
-
 hipError_t launch_dg(int pde, int N, int prec, int mode, const StepArgs& A, int64_t blocks,
                      hipStream_t st, bool newton = false);
 hipError_t launch_fv(int pde, int NW, int prec, const StepArgs& A, int64_t blocks, hipStream_t st);
