@@ -26,14 +26,26 @@ def fv_dt(pde, v, dx, cfl):
     return cfl * dx / float(pde.max_speed(v).max())
 
 
-def fv_step(ops, pde, v, t, dt, dx, x_left, tol=1e-14, max_iter=64):
+def _fv_update(ops, pde, v, t, dt, dx, x_left, tol, max_iter):
     w_hat = reconstruct(v, ops)
     q, sweeps, failed = predict(ops, pde, w_hat, dt, dx, x_left, t, tol, max_iter)
     Gbar, Jbar = interface_terms(ops, pde, q, dt, dx)
     sb = volume_source_terms(ops, pde, q, dt, dx, x_left, t)      # [C, n, M]
     vol = np.einsum("k,ckr->cr", ops.w, sb)                       # w over space nodes
     v_new = v - (Gbar - np.roll(Gbar, 1, axis=0)) - (Jbar + np.roll(Jbar, 1, axis=0)) + vol
+    return v_new, sweeps, failed, Gbar
+
+
+def fv_step(ops, pde, v, t, dt, dx, x_left, tol=1e-14, max_iter=64):
+    v_new, sweeps, failed, _ = _fv_update(ops, pde, v, t, dt, dx, x_left, tol, max_iter)
     return v_new, sweeps, failed
+
+
+def fv_step_terms(ops, pde, v, t, dt, dx, x_left, tol=1e-14, max_iter=64):
+    """fv_step's new averages and its time-integrated flux through the right
+    face of every cell (for the subcell limiter's face bookkeeping)."""
+    v_new, _, _, Gbar = _fv_update(ops, pde, v, t, dt, dx, x_left, tol, max_iter)
+    return v_new, Gbar
 
 
 def fv_run(ops, pde, v, x0, x1, cfl=0.4, t_end=np.inf, nsteps=None, t0=0.0,

@@ -215,3 +215,23 @@ def swe_lake_at_rest_averages(ncells, x0=0.0, x1=1.0, npts=16):
     _, w = gl_points_01(npts)
     b = 0.2 * np.exp(-100.0 * (xs - 0.5) ** 2)
     return np.stack([(1.0 - b) @ w, np.zeros(ncells), b @ w], axis=-1)
+
+
+# Table 9 (Sec. 2.2): primitive states (rho, u, p) left and right of the initial
+# discontinuity at x_c = 0.5 of the four classical Riemann tests (Sod, Lax,
+# two shocks, two rarefactions); gamma = 1.4, free outflow, t_final = 0.15.
+RIEMANN_TESTS = {
+    1: ((1.000, 0.000, 1.000), (0.125, 0.000, 0.100)),
+    2: ((0.445, 0.698, 3.528), (0.500, 0.000, 0.571)),
+    3: ((1.000, 1.000, 1.000), (1.000, -1.000, 1.000)),
+    4: ((1.000, -1.000, 1.000), (1.000, 1.000, 1.000)),
+}
+
+
+def riemann_nodal(ncells, N, test, x0=0.0, x1=1.0, xc=0.5, gamma=1.4):
+    """Conserved nodal data [C, N+1, 3] of a Table 9 Riemann problem: the left
+    state at nodes x <= x_c, the right state elsewhere."""
+    (rl, ul, pl), (rr, ur, pr) = RIEMANN_TESTS[test]
+    xs = cell_points(ncells, N + 1, x0, x1)
+    left = xs <= xc
+    return _euler_conserved(np.where(left, rl, rr), np.where(left, ul, ur), np.where(left, pl, pr), gamma)

@@ -1,0 +1,169 @@
+"""Pins of the oracle's a posteriori subcell limiter (Sec. 1.4, Sec. 1.6) and of
+its exact Riemann solver (the reference solution of the tests of Sec. 2.2).
+
+* R P = 1 and P R != 1 for N_s = 2N+1 (Sec. 1.4); P R is the orthogonal
+  projection onto the range of P, so it keeps the mean of any subcell data.
+* The detectors of Sec. 1.6 on hand-made candidates: a negative density
+  (PAD), a value outside [min - delta, max + delta] over the cell and its
+  neighbours (NAD), and one inside the delta window.
+* Smooth periodic data trigger no limiting: the limited run equals the plain
+  ADER-DG run.
+* The exact Riemann solver: the textbook star states of the Sod problem, the
+  symmetry of the two-shock and two-rarefaction tests, and the
+  Rankine-Hugoniot conditions across its shocks.
+* The four Riemann problems of Table 9 with free outflow: the solution stays
+  admissible, mass, momentum and energy change only through the boundary
+  fluxes (so every face carries one flux, also between a limited and an
+  unlimited cell), and the L1 density error against the exact solution falls
+  under mesh refinement.
+* Test 4 (two rarefactions): at the final time no cell is troubled (Sec. 2.2
+  states that the limiter is not active there).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import basis, dg, limiter, riemann
+from oracle import pde as P
+from paper_2409_12483_amd import workloads as W
+
+GAMMA = 1.4
+T_END = 0.15
+
+
+@pytest.mark.parametrize("N", [1, 2, 5, 9])
+def test_R_left_inverse_of_P_and_PR_a_mean_preserving_projection(N):
+    ops = basis.build_operators(N)
+    R = limiter.subcell_R(ops)
+    assert R.shape == (N + 1, 2 * N + 1)
+    assert np.abs(R @ ops.P - np.eye(N + 1)).max() <= 1e-11
+    PR = ops.P @ R
+    assert np.abs(PR - np.eye(2 * N + 1)).max() > 1e-2            # N_s > N+1: not invertible
+    assert np.abs(PR @ PR - PR).max() <= 1e-11
+    assert np.abs(PR - PR.T).max() <= 1e-11
+    v = np.random.default_rng(N).standard_normal(2 * N + 1)
+    assert abs((PR @ v).mean() - v.mean()) <= 1e-13
+
+
+def _uniform_cells(C, N, rho=1.0, u=0.0, p=1.0):
+    return W._euler_conserved(np.full((C, N + 1), rho), np.full((C, N + 1), u), np.full((C, N + 1), p), GAMMA)
+
+
+def test_detectors_on_hand_made_candidates():
+    N, C = 2, 5
+    ops = basis.build_operators(N)
+    e = P.Euler()
+    u = _uniform_cells(C, N)
+    v = limiter.subcell_averages(ops, u)
+    assert not limiter.troubled_cells(ops, e, v, u, "periodic").any()
+    cand = u.copy()
+    cand[1, :, 0] += 0.5e-4                                         # inside delta_0 = 1e-4
+    cand[3, :, 0] += 3e-4                                           # outside
+    bad = limiter.troubled_cells(ops, e, v, cand, "periodic")
+    assert bad.tolist() == [False, False, False, True, False]
+    cand = u.copy()
+    cand[2, :, 0] = -0.1                                            # negative density (PAD)
+    cand[2, :, 2] = 10.0
+    assert limiter.troubled_cells(ops, e, v, cand, "transmissive").tolist() == [False, False, True, False, False]
+    # a ramp: the window of cell 2 spans cells 1..3, delta = 1e-3 of its range
+    ramp = _uniform_cells(C, N, rho=1.0)
+    ramp[..., 0] = 1.0 + 0.1 * np.arange(C)[:, None]
+    vr = limiter.subcell_averages(ops, ramp)
+    cand = ramp.copy()
+    cand[2, :, 0] = 1.3 + 0.5e-3 * 0.2                              # max + delta / 2
+    assert not limiter.troubled_cells(ops, e, vr, cand, "transmissive")[2]
+    cand[2, :, 0] = 1.3 + 2e-3 * 0.2                                # max + 2 delta
+    assert limiter.troubled_cells(ops, e, vr, cand, "transmissive")[2]
+
+
+def test_smooth_periodic_flow_is_never_limited():
+    N, C = 3, 12
+    ops = basis.build_operators(N)
+    e = P.Euler()
+    u0 = W.euler_density_wave(C, N)
+    ul, _, info = limiter.limited_run(ops, e, u0, 0.0, 1.0, cfl=0.4, nsteps=20)
+    assert sum(info["troubled"]) == 0
+    ud, _, _ = dg.dg_run(ops, e, u0, 0.0, 1.0, cfl=0.4, nsteps=20)
+    assert np.abs(ul - ud).max() <= 1e-13
+
+
+def test_exact_riemann_solver():
+    ps, us = riemann.star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    assert abs(ps - 0.30313) < 5e-6 and abs(us - 0.92745) < 5e-6   # Sod: the textbook star state
+    for k in (3, 4):
+        L, R = W.RIEMANN_TESTS[k]
+        ps, us = riemann.star_state(L, R)
+        assert abs(us) <= 1e-14                                     # symmetric data
+        assert (ps > 1.0) == (k == 3)
+    # Rankine-Hugoniot across the right shock of Sod and both shocks of test 3
+    for L, R in (W.RIEMANN_TESTS[1], W.RIEMANN_TESTS[3]):
+        ps, us = riemann.star_state(L, R)
+        rr, ur, pr = R
+        rs = riemann.sample(L, R, us + 1e-9)[0]
+        s = (rs * us - rr * ur) / (rs - rr)                         # shock speed from mass
+        cons = lambda r, u, p: np.array([r, r * u, p / (GAMMA - 1) + 0.5 * r * u * u])
+        flux = lambda r, u, p: np.array([r * u, r * u * u + p, u * (p / (GAMMA - 1) + 0.5 * r * u * u + p)])
+        jump = flux(rs, us, ps) - flux(rr, ur, pr) - s * (cons(rs, us, ps) - cons(rr, ur, pr))
+        assert np.abs(jump).max() <= 1e-10
+        assert riemann.sample(L, R, s + 1e-6) == pytest.approx(R)   # the shock is where the sampler puts it
+
+
+def _run(test, N, C, bc="transmissive", t_end=T_END):
+    ops = basis.build_operators(N)
+    with np.errstate(all="ignore"):
+        u, t, info = limiter.limited_run(ops, P.Euler(), W.riemann_nodal(C, N, test), 0.0, 1.0, cfl=0.4,
+                                         t_end=t_end, bc=bc, dims=2)
+    return ops, u, t, info
+
+
+def _l1_density(ops, u, test, t):
+    L, R = W.RIEMANN_TESTS[test]
+    C, n, _ = u.shape
+    exact = riemann.density(L, R, W.cell_points(C, n), t)
+    return np.einsum("k,ck->c", ops.w, np.abs(u[..., 0] - exact)).mean()
+
+
+def _totals(ops, u, C):
+    return np.einsum("k,ckm->m", ops.w, u) / C
+
+
+def _boundary_flux(state):
+    r, u, p = state
+    return np.array([r * u, r * u * u + p, u * (p / (GAMMA - 1) + 0.5 * r * u * u + p)])
+
+
+@pytest.mark.parametrize("test", [1, 2, 3, 4])
+def test_riemann_problems_admissible_conservative_and_converging(test):
+    N = 2
+    errs = []
+    for C in (25, 50):
+        ops, u, t, info = _run(test, N, C)
+        assert t == pytest.approx(T_END, abs=1e-14)
+        assert P.Euler().admissible(u).all()
+        assert max(info["troubled"]) > 0
+        # no physical wave reaches the boundary before t_end, so the totals
+        # change at the rate of the initial states' fluxes; the scheme's own
+        # tiny signals do reach the outflow faces, hence the loose bound
+        L, R = W.RIEMANN_TESTS[test]
+        u0 = W.riemann_nodal(C, N, test)
+        expect = _totals(ops, u0, C) + t * (_boundary_flux(L) - _boundary_flux(R))
+        assert (np.abs(_totals(ops, u, C) - expect) <= 1e-5 * (1 + np.abs(expect))).all()
+        errs.append(_l1_density(ops, u, test, t))
+    assert errs[1] < 0.6 * errs[0]
+
+
+@pytest.mark.parametrize("test", [1, 2, 3])
+def test_limited_steps_conserve_exactly_on_a_periodic_mesh(test):
+    """Periodic data with two jumps (x = 0.5 and x = 0): the totals stay at
+    their initial values to rounding, through steps with limited cells beside
+    unlimited ones (a face with two fluxes would show here)."""
+    ops, u, _, info = _run(test, 2, 20, bc="periodic", t_end=0.05)
+    assert min(info["troubled"]) > 0
+    u0 = W.riemann_nodal(20, 2, test)
+    assert np.abs(_totals(ops, u, 20) - _totals(ops, u0, 20)).max() <= 1e-13
+
+
+def test_two_rarefactions_leave_no_troubled_cell_at_the_final_time():
+    _, _, _, info = _run(4, 5, 50)
+    assert info["troubled"][-1] == 0
+    assert info["troubled"][0] > 0              # the initial jump of the velocity is limited

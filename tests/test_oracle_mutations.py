@@ -12,7 +12,7 @@ import copy
 import numpy as np
 import pytest
 
-from oracle import basis, brute, dg, fv, pade, predictor
+from oracle import basis, brute, dg, fv, limiter, pade, predictor
 from oracle import pde as P
 from paper_2409_12483_amd import workloads as W
 
@@ -235,3 +235,56 @@ def test_planted_wrong_source_jacobian_is_caught(monkeypatch, mutate):
     monkeypatch.setattr(P.EulerReact, "source_jacobian", lambda self, Q, x, t: mutate(orig(self, Q, x, t)))
     with np.errstate(all="ignore"):
         assert not _newton_pade_pin()
+
+
+# the subcell limiter: R P = 1, exact conservation through limited steps on a
+# periodic mesh, and no limiting of smooth flow
+
+
+def _lim_pin_left_inverse():
+    ops = basis.build_operators(N)
+    return np.abs(limiter.subcell_R(ops) @ ops.P - np.eye(N + 1)).max() <= 1e-11
+
+
+def _lim_pin_conservation():
+    ops = basis.build_operators(N)
+    u0 = W.riemann_nodal(10, N, 1)
+    with np.errstate(all="ignore"):
+        u, _, info = limiter.limited_run(ops, P.Euler(), u0, 0.0, 1.0, cfl=0.4, nsteps=8, dims=2)
+    tot = lambda a: np.einsum("k,ckm->m", ops.w, a)
+    return min(info["troubled"]) > 0 and np.abs(tot(u) - tot(u0)).max() <= 1e-13
+
+
+def _lim_pin_smooth():
+    ops = basis.build_operators(N)
+    _, _, info = limiter.limited_run(ops, P.Euler(), W.euler_density_wave(16, N), 0.0, 1.0, cfl=0.4, nsteps=6)
+    return sum(info["troubled"]) == 0
+
+
+def _all_limiter_pins_pass():
+    return _lim_pin_left_inverse() and _lim_pin_conservation() and _lim_pin_smooth()
+
+
+def test_unmutated_limiter_passes_its_pins():
+    assert _all_limiter_pins_pass()
+
+
+def test_planted_transposed_reconstruction_is_caught(monkeypatch):
+    monkeypatch.setattr(limiter, "subcell_R", lambda ops: ops.P.T * (N + 1) / (2 * N + 1))
+    assert not _all_limiter_pins_pass()
+
+
+def test_planted_face_shift_in_subgrid_fluxes_is_caught(monkeypatch):
+    orig = limiter.fv_subgrid
+
+    def shifted(*a, **k):
+        v, g = orig(*a, **k)
+        return v, np.roll(g, 1, axis=0)
+    monkeypatch.setattr(limiter, "fv_subgrid", shifted)
+    assert not _all_limiter_pins_pass()
+
+
+def test_planted_missing_nad_tolerance_is_caught(monkeypatch):
+    monkeypatch.setattr(limiter, "DELTA0", 0.0)
+    monkeypatch.setattr(limiter, "EPS0", 0.0)
+    assert not _all_limiter_pins_pass()
