@@ -266,9 +266,10 @@ int aderdg_conserved_totals(aderdg_handle* h, int32_t k, const double* u, double
  * degree N (no device involved), for inspection: the GL nodes xi and weights w
  * (eq. gl_rule), k~ = Lambda^-1 Xi and kappa~ = Upsilon^-1 Lambda
  * (eq. m_and_kappa_matrices and the definitions after it), D~_kl = w_l
- * D^phi_kl, psi = phi(0), psi~ = phi(1) (Sec. 1.2) and the subcell
- * projection P (Sec. 1.4), concatenated in that order: n, n, n*n, n*n, n*n,
- * n, n, (2N+1)*n doubles (n = N+1).  cap = capacity of out in doubles;
+ * D^phi_kl, psi = phi(0), psi~ = phi(1) (Sec. 1.2), the subcell
+ * projection P and the reconstruction R = (P^T P)^-1 P^T (Sec. 1.4, eq.
+ * p_operator and eq. r_operator), concatenated in that order: n, n, n*n,
+ * n*n, n*n, n, n, (2N+1)*n, n*(2N+1) doubles (n = N+1).  cap = capacity of out in doubles;
  * returns the number written, or E_INVAL.
  */
 int aderdg_operators(int32_t N, double* out, int64_t cap);

@@ -1,5 +1,5 @@
-"""Thin ctypes binding of include/aderdg.h, include/aderdg2d.h and
-include/aderdg3d.h (argument marshalling only).
+"""Thin ctypes binding of include/aderdg.h, include/aderdg2d.h,
+include/aderdg3d.h and include/aderdg_lim.h (argument marshalling only).
 
 Every entry point keeps its C name.  Buffers may be torch tensors on the HIP
 device (their data_ptr() is passed) or raw integer device addresses.  All
@@ -35,6 +35,9 @@ EXPORTS_2D = ["aderdg2d_init", "aderdg2d_predict", "aderdg2d_step", "aderdg2d_sw
               "aderdg2d_free"]
 EXPORTS_3D = ["aderdg3d_init", "aderdg3d_predict", "aderdg3d_step", "aderdg3d_sweep_count",
               "aderdg3d_free"]
+EXPORTS_LIM = ["aderdg_lim_init", "aderdg_lim_project", "aderdg_lim_step", "aderdg_lim_counters",
+               "aderdg_lim_free"]
+LIM_PERIODIC, LIM_TRANSMISSIVE = 0, 1
 
 
 class PdeDesc(ctypes.Structure):
@@ -69,6 +72,13 @@ class Config3D(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_double),
                 ("picard_tol", ctypes.c_double), ("picard_max_iter", ctypes.c_int32),
                 ("pad", ctypes.c_int32)]
+
+
+class LimConfig(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("bc", ctypes.c_int32), ("ncells", ctypes.c_int64),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("dims", ctypes.c_int32), ("picard_max_iter", ctypes.c_int32),
+                ("picard_tol", ctypes.c_double)]
 
 
 class AderdgError(RuntimeError):
@@ -122,7 +132,12 @@ def load(path=None):
     lib.aderdg3d_step.argtypes = [vp, vp, vp, vp, vp, vp, i32]
     lib.aderdg3d_sweep_count.argtypes = [vp, ctypes.POINTER(i64)]
     lib.aderdg3d_free.argtypes = [vp]
-    for name in EXPORTS[:-1] + EXPORTS_2D + EXPORTS_3D:
+    lib.aderdg_lim_init.argtypes = [ctypes.POINTER(LimConfig), vp, ctypes.POINTER(vp)]
+    lib.aderdg_lim_project.argtypes = [vp, vp, vp]
+    lib.aderdg_lim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32]
+    lib.aderdg_lim_counters.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.aderdg_lim_free.argtypes = [vp]
+    for name in EXPORTS[:-1] + EXPORTS_2D + EXPORTS_3D + EXPORTS_LIM:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -245,7 +260,7 @@ def aderdg_operators(N):
     import numpy as np
     n = N + 1
     Ns = 2 * N + 1
-    cap = 2 * n + 3 * n * n + 2 * n + Ns * n
+    cap = 2 * n + 3 * n * n + 2 * n + 2 * Ns * n
     buf = (ctypes.c_double * cap)()
     got = load().aderdg_operators(N, buf, cap)
     if got < 0:
@@ -255,7 +270,8 @@ def aderdg_operators(N):
     out = {}
     for name, size, shape in [("xi", n, (n,)), ("w", n, (n,)), ("ktil", n * n, (n, n)),
                               ("kappa", n * n, (n, n)), ("Dtil", n * n, (n, n)),
-                              ("psi0", n, (n,)), ("psi1", n, (n,)), ("P", Ns * n, (Ns, n))]:
+                              ("psi0", n, (n,)), ("psi1", n, (n,)), ("P", Ns * n, (Ns, n)),
+                              ("R", n * Ns, (n, Ns))]:
         out[name] = a[o:o + size].reshape(shape)
         o += size
     return out
@@ -333,3 +349,37 @@ def aderdg3d_sweep_count(h):
 
 def aderdg3d_free(h):
     return _check(load().aderdg3d_free(h))
+
+
+# ------------------------------------------------------------- limited 1-D ----
+def lim_config(N, ncells, bc=LIM_TRANSMISSIVE, x0=0.0, x1=1.0, gamma=1.4, cfl=0.4, dims=1,
+               picard_tol=0.0, picard_max_iter=0):
+    return LimConfig(N, bc, ncells, x0, x1, gamma, cfl, dims, picard_max_iter, picard_tol)
+
+
+def aderdg_lim_init(cfg, stream=None):
+    lib = load()
+    h = ctypes.c_void_p()
+    st = _current_stream() if stream is None else stream
+    _check(lib.aderdg_lim_init(ctypes.byref(cfg), st, ctypes.byref(h)))
+    return h.value
+
+
+def aderdg_lim_project(h, u, v):
+    return _check(load().aderdg_lim_project(h, _ptr(u), _ptr(v)))
+
+
+def aderdg_lim_step(h, u, v, troubled, t, t_end, dt, status, nsteps):
+    return _check(load().aderdg_lim_step(h, _ptr(u), _ptr(v), _ptr(troubled), _ptr(t), _ptr(t_end),
+                                         _ptr(dt), _ptr(status), nsteps))
+
+
+def aderdg_lim_counters(h):
+    """(troubled cell-steps, first-order fallback steps, steps taken) since init."""
+    out = (ctypes.c_int64 * 3)()
+    _check(load().aderdg_lim_counters(h, out))
+    return tuple(out)
+
+
+def aderdg_lim_free(h):
+    return _check(load().aderdg_lim_free(h))

@@ -13,6 +13,7 @@
 #include "../../include/aderdg.h"
 #include "../../include/aderdg2d.h"
 #include "../../include/aderdg3d.h"
+#include "../../include/aderdg_lim.h"
 
 #include <hip/hip_runtime.h>
 
@@ -108,6 +109,18 @@ int ensure_tables(int device) {
   }
   hipError_t e = upload_tables(ops, opsf, weno);
   if (e != hipSuccess) return fail_hip(e, "upload of operator tables");
+  {
+    static DevLimR lim[kDevMaxn];
+    std::memset(lim, 0, sizeof(lim));
+    for (int N = 0; N < kDevMaxn; ++N) {
+      OpTables t;
+      if (!build_op_tables(N, t)) return fail(ADERDG_E_DEVICE, "operator construction failed");
+      for (int k = 0; k <= N; ++k)
+        for (int s = 0; s < t.Ns; ++s) lim[N].R[k][s] = t.R[k][s];
+    }
+    e = upload_lim_tables(lim);
+    if (e != hipSuccess) return fail_hip(e, "upload of limiter tables");
+  }
   e = upload_tables_2d(ops, opsf);
   if (e != hipSuccess) return fail_hip(e, "upload of 2-D operator tables");
   e = upload_tables_3d(ops, opsf);
@@ -654,7 +667,7 @@ int aderdg_operators(int32_t N, double* out, int64_t cap) {
   OpTables t;
   if (!out || !build_op_tables(N, t) || N < 0) return fail(ADERDG_E_INVAL, "bad degree or buffer");
   const int n = N + 1;
-  const int64_t need = 2 * n + 3 * n * n + 2 * n + (int64_t)t.Ns * n;
+  const int64_t need = 2 * n + 3 * n * n + 2 * n + 2 * (int64_t)t.Ns * n;
   if (cap < need) return fail(ADERDG_E_INVAL, "buffer too small");
   int64_t o = 0;
   for (int i = 0; i < n; ++i) out[o++] = t.xi[i];
@@ -665,6 +678,7 @@ int aderdg_operators(int32_t N, double* out, int64_t cap) {
   for (int i = 0; i < n; ++i) out[o++] = t.psi0[i];
   for (int i = 0; i < n; ++i) out[o++] = t.psi1[i];
   for (int s = 0; s < t.Ns; ++s) for (int k = 0; k < n; ++k) out[o++] = t.P[s][k];
+  for (int k = 0; k < n; ++k) for (int s = 0; s < t.Ns; ++s) out[o++] = t.R[k][s];
   return (int)o;
 }
 
@@ -963,6 +977,134 @@ int aderdg3d_free(aderdg3d_handle* h) {
   if (!h) return ADERDG_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
   release3d(h);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "stream synchronisation");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ limited 1-D ----
+// A limited handle owns the step's scratch: candidate volume terms, face
+// traces and fluxes, the troubled-cell list, subgrid results and a clock.
+
+struct aderdg_lim_handle {
+  hipStream_t stream = nullptr;
+  aderdg_lim_config cfg{};
+  void* scratch = nullptr;
+  LimArgs args{};
+};
+
+namespace {
+
+void release_lim(aderdg_lim_handle* h) {
+  if (h->scratch) hipFree(h->scratch);
+  if (h->args.clk) hipFree(h->args.clk);
+  delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aderdg_lim_init(const aderdg_lim_config* cfg, void* hip_stream, aderdg_lim_handle** out) {
+  g_last_error.clear();
+  if (!cfg || !out) return fail(ADERDG_E_INVAL, "null argument");
+  aderdg_lim_config c = *cfg;
+  if (c.N < 1 || c.N > 9) return fail(ADERDG_E_INVAL, "N must be in 1..9");
+  if (c.bc != ADERDG_LIM_PERIODIC && c.bc != ADERDG_LIM_TRANSMISSIVE)
+    return fail(ADERDG_E_INVAL, "bc must be ADERDG_LIM_PERIODIC or ADERDG_LIM_TRANSMISSIVE");
+  if (c.ncells < 3 || c.ncells > (int64_t)INT32_MAX / (2 * c.N + 1))
+    return fail(ADERDG_E_INVAL, "ncells must be >= 3 with ncells * (2N+1) below 2^31");
+  if (!(c.x1 > c.x0) || !std::isfinite(c.x1 - c.x0)) return fail(ADERDG_E_INVAL, "empty or non-finite domain");
+  if (!(c.gamma > 1.0) || !std::isfinite(c.gamma)) return fail(ADERDG_E_INVAL, "gamma must be > 1");
+  if (!(c.cfl > 0.0 && c.cfl <= 1.0)) return fail(ADERDG_E_INVAL, "cfl must be in (0, 1]");
+  if (c.dims < 1 || c.dims > 3) return fail(ADERDG_E_INVAL, "dims must be 1, 2 or 3");
+  if (!std::isfinite(c.picard_tol)) return fail(ADERDG_E_INVAL, "picard_tol must be finite");
+  if (c.picard_tol <= 0.0) c.picard_tol = 1e-14;
+  if (c.picard_max_iter <= 0) c.picard_max_iter = 64;
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  int rc = ensure_tables(device);
+  if (rc) return rc;
+  aderdg_lim_handle* h = new aderdg_lim_handle();
+  h->stream = (hipStream_t)hip_stream;
+  h->cfg = c;
+  const int64_t C = c.ncells, n = c.N + 1, Ns = 2 * c.N + 1, M = 3;
+  // doubles: vol, trL, trR, G, vfv, gs; then the int32 list
+  const int64_t nd = C * n * M + 2 * (C + 2) * n * M + (C + 1) * M + C * Ns * M + C * 2 * M;
+  e = hipMalloc(&h->scratch, sizeof(double) * nd + sizeof(int32_t) * C);
+  if (e != hipSuccess) { release_lim(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
+  e = hipMalloc((void**)&h->args.clk, sizeof(LimClock));
+  if (e != hipSuccess) { release_lim(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }
+  e = hipMemset(h->args.clk, 0, sizeof(LimClock));
+  if (e != hipSuccess) { release_lim(h); return fail_hip(e, "clock init"); }
+  LimArgs& A = h->args;
+  A.C = C;
+  A.N = c.N;
+  A.bc = c.bc;
+  A.x0 = c.x0;
+  A.dx = (c.x1 - c.x0) / (double)C;
+  A.cfl_d = c.cfl / (double)c.dims;
+  A.tol = c.picard_tol;
+  A.max_iter = c.picard_max_iter;
+  A.pp = PdeParams{c.gamma, 0.0, 0.0, 0.0};
+  double* d = (double*)h->scratch;
+  A.vol = d;  d += C * n * M;
+  A.trL = d;  d += (C + 2) * n * M;
+  A.trR = d;  d += (C + 2) * n * M;
+  A.G = d;    d += (C + 1) * M;
+  A.vfv = d;  d += C * Ns * M;
+  A.gs = d;   d += C * 2 * M;
+  A.list = (int32_t*)d;
+  *out = h;
+  return ADERDG_OK;
+}
+
+int aderdg_lim_project(aderdg_lim_handle* h, const double* u, double* v) {
+  g_last_error.clear();
+  if (!h || !u || !v) return fail(ADERDG_E_INVAL, "null argument");
+  hipError_t e = launch_lim_project(h->cfg.N, u, v, h->cfg.ncells, h->stream);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "projection launch");
+}
+
+int aderdg_lim_step(aderdg_lim_handle* h, double* u, double* v, int32_t* troubled, double* t,
+                    const double* t_end, double* dt, int32_t* status, int32_t nsteps) {
+  g_last_error.clear();
+  if (!h || !u || !v || !troubled || !t || !t_end || !dt || !status) return fail(ADERDG_E_INVAL, "null argument");
+  if (nsteps < 0) return fail(ADERDG_E_INVAL, "nsteps must be >= 0");
+  LimArgs A = h->args;
+  A.u = u;
+  A.v = v;
+  A.troubled = troubled;
+  A.t_end = t_end;
+  hipError_t e = launch_lim_begin(A.clk, t, h->stream);
+  if (e == hipSuccess) e = launch_lim_lambda(A, 0, h->stream);
+  for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+    A.step = s;
+    e = launch_lim_step(A, h->stream);
+  }
+  if (e == hipSuccess) e = launch_lim_end(A.clk, t, dt, status, h->stream);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "limited step launch");
+}
+
+int aderdg_lim_counters(aderdg_lim_handle* h, int64_t* out3) {
+  g_last_error.clear();
+  if (!h || !out3) return fail(ADERDG_E_INVAL, "null argument");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "stream synchronisation");
+  LimClock c;
+  e = hipMemcpy(&c, h->args.clk, sizeof(c), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "counter read");
+  out3[0] = (int64_t)c.total_troubled;
+  out3[1] = (int64_t)c.total_fallback;
+  out3[2] = (int64_t)c.total_steps;
+  return ADERDG_OK;
+}
+
+int aderdg_lim_free(aderdg_lim_handle* h) {
+  if (!h) return ADERDG_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  release_lim(h);
   return e == hipSuccess ? ADERDG_OK : fail_hip(e, "stream synchronisation");
 }
 

@@ -560,3 +560,6 @@ hipError_t upload_tables(const DevOps* ops, const DevOpsF* opsf, const DevWeno* 
 }
 
 }  // namespace aderdg
+
+// Kernels of the limited 1-D step (they share this file's operator and WENO tables).
+#include "limiter.hpp"

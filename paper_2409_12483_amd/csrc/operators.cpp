@@ -75,6 +75,31 @@ bool solve(int n, double A[kMaxn][kMaxn], double B[kMaxn][kMaxn], double X[kMaxn
   return true;
 }
 
+// Solve A X = B for X (n x m, m <= kMaxNs), A overwritten.  Partial pivoting.
+bool solve_wide(int n, int m, double A[kMaxn][kMaxn], double B[kMaxn][kMaxNs], double X[kMaxn][kMaxNs]) {
+  double a[kMaxn][kMaxn + kMaxNs];
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) a[i][j] = A[i][j];
+    for (int j = 0; j < m; ++j) a[i][n + j] = B[i][j];
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[r][c]) > std::fabs(a[piv][c])) piv = r;
+    if (a[piv][c] == 0.0) return false;
+    if (piv != c)
+      for (int j = 0; j < n + m; ++j) { double t = a[c][j]; a[c][j] = a[piv][j]; a[piv][j] = t; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = a[r][c] / a[c][c];
+      for (int j = c; j < n + m; ++j) a[r][j] -= f * a[c][j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < m; ++j) X[i][j] = a[i][n + j] / a[i][i];
+  return true;
+}
+
 }  // namespace
 
 bool build_op_tables(int N, OpTables& o) {
@@ -130,7 +155,18 @@ bool build_op_tables(int N, OpTables& o) {
       for (int q = 0; q < n; ++q) s += o.w[q] * lagrange(o.xi, n, k, (j + o.xi[q]) / o.Ns);
       o.P[j][k] = s;
     }
-  return true;
+  // R = (P^T P)^-1 P^T: the normal equations of the least-squares fit of a
+  // degree-N polynomial to N_s subcell averages (R P = 1, P R != 1 for N_s > n)
+  double A[kMaxn][kMaxn], Pt[kMaxn][kMaxNs];
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int q = 0; q < o.Ns; ++q) s += o.P[q][i] * o.P[q][j];
+      A[i][j] = s;
+    }
+    for (int q = 0; q < o.Ns; ++q) Pt[i][q] = o.P[q][i];
+  }
+  return solve_wide(n, o.Ns, A, Pt, o.R);
 }
 
 bool build_weno_tables(int Nw, WenoTables& t) {

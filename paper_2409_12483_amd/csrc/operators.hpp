@@ -4,7 +4,8 @@
 // k~ = Lambda^-1 Xi and kappa~ = Upsilon^-1 Lambda from the mass, stiffness
 // and Upsilon matrices (eq. m_and_kappa_matrices).  Sec. 1.2: D~_kl = w_l
 // D^phi_kl, psi_k = phi_k(0), psi~_k = phi_k(1).  Sec. 1.4: subcell
-// projection P_jk = N_s * integral of phi_k over subcell j, N_s = 2N+1.
+// projection P_jk = N_s * integral of phi_k over subcell j, N_s = 2N+1, and
+// the reconstruction R = (P^T P)^-1 P^T (so that R P = 1).
 // WENO tables (reading of eq. weno_reconstr, see weno_tables below).
 #pragma once
 
@@ -26,6 +27,7 @@ struct OpTables {
   double psi0[kMaxn] = {};           // phi_k(0)
   double psi1[kMaxn] = {};           // phi_k(1)
   double P[kMaxNs][kMaxn] = {};      // subcell averages
+  double R[kMaxn][kMaxNs] = {};      // subcell reconstruction: least-squares inverse of P
 };
 
 // WENO reconstruction of degree Nw (even) from Nw+1 cell averages per stencil,

@@ -14,13 +14,14 @@ import re
 import numpy as np
 import pytest
 
-from oracle import basis
+from oracle import basis, limiter
 from paper_2409_12483_amd import abi
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "aderdg.h")
 HEADER_2D = os.path.join(ROOT, "include", "aderdg2d.h")
 HEADER_3D = os.path.join(ROOT, "include", "aderdg3d.h")
+HEADER_LIM = os.path.join(ROOT, "include", "aderdg_lim.h")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(abi.LIBPATH),
                                 reason="libaderdg.so not built (run __graft_entry__.build())")
@@ -42,7 +43,8 @@ def test_header_declares_the_entry_points():
 
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(abi.LIBPATH)
-    for name in _declared_functions() + _declared_functions(HEADER_2D) + _declared_functions(HEADER_3D):
+    for name in (_declared_functions() + _declared_functions(HEADER_2D) + _declared_functions(HEADER_3D)
+                 + _declared_functions(HEADER_LIM)):
         assert hasattr(lib, name), name
 
 
@@ -63,6 +65,8 @@ def test_host_operator_tables_match_oracle(N):
     assert np.allclose(t["psi0"], ops.psi0, atol=1e-13, rtol=0)
     assert np.allclose(t["psi1"], ops.psi1, atol=1e-13, rtol=0)
     assert np.allclose(t["P"], ops.P, atol=1e-13, rtol=0)
+    if N >= 1:
+        assert np.allclose(t["R"], limiter.subcell_R(ops), atol=1e-11, rtol=0)
 
 
 def _init(pde, cfg):
@@ -118,8 +122,10 @@ def test_config_struct_layout_matches_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     fields = {"aderdg_pde_desc": (abi.PdeDesc, [f for f, _ in abi.PdeDesc._fields_]),
-              "aderdg_config": (abi.Config, [f for f, _ in abi.Config._fields_])}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "aderdg.h"', "int main(void) {"]
+              "aderdg_config": (abi.Config, [f for f, _ in abi.Config._fields_]),
+              "aderdg_lim_config": (abi.LimConfig, [f for f, _ in abi.LimConfig._fields_])}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "aderdg.h"', '#include "aderdg_lim.h"',
+             "int main(void) {"]
     for st, (_, names) in fields.items():
         lines.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
         for f in names:
@@ -243,3 +249,34 @@ def test_newton_inner_solver_only_for_dg_with_a_linear_source(pde, scheme):
     rc, _ = _init(abi.pde_desc(pde), abi.config(4, 20, scheme=scheme, inner=abi.INNER_NEWTON))
     assert rc == abi.ADERDG_E_INVAL
     assert "Newton" in abi.aderdg_last_error()
+
+
+def test_limiter_header_declares_the_entry_points():
+    assert set(_declared_functions(HEADER_LIM)) == set(abi.EXPORTS_LIM)
+
+
+def _init_lim(cfg):
+    lib = abi.load()
+    h = ctypes.c_void_p()
+    return lib.aderdg_lim_init(ctypes.byref(cfg), None, ctypes.byref(h)), h
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda c: setattr(c, "N", 0), "N must"),
+    (lambda c: setattr(c, "N", 10), "N must"),
+    (lambda c: setattr(c, "bc", 2), "bc must"),
+    (lambda c: setattr(c, "ncells", 2), "ncells"),
+    (lambda c: setattr(c, "ncells", 2 ** 31 // 19 + 1), "ncells"),
+    (lambda c: setattr(c, "x1", -1.0), "domain"),
+    (lambda c: setattr(c, "gamma", 0.9), "gamma"),
+    (lambda c: setattr(c, "cfl", 0.0), "cfl"),
+    (lambda c: setattr(c, "dims", 4), "dims"),
+    (lambda c: setattr(c, "picard_tol", float("inf")), "picard_tol"),
+])
+def test_invalid_limiter_configs_are_rejected(mutate, needle):
+    cfg = abi.lim_config(9, 50)
+    mutate(cfg)
+    rc, h = _init_lim(cfg)
+    assert rc == abi.ADERDG_E_INVAL and h.value is None
+    assert needle in abi.aderdg_last_error()
+    assert abi.load().aderdg_lim_free(None) == abi.ADERDG_OK
