@@ -775,6 +775,104 @@ def cpu_baseline(N, target_s=10.0, C=20_000):
                       f"{steps} steps in all over ~{target_s:.0f} s, NumPy FP64, one thread each"}
 
 
+def _lim_handle(N, C, u0, bc, dims):
+    import torch
+    from paper_2409_12483_amd import abi
+    dev = torch.device("cuda:0")
+    h = abi.aderdg_lim_init(abi.lim_config(N, C, bc=bc, cfl=0.4, dims=dims),
+                            stream=torch.cuda.current_stream().cuda_stream)
+    u = torch.tensor(u0, device=dev)
+    v = torch.empty((C, 2 * N + 1, 3), dtype=torch.float64, device=dev)
+    abi.aderdg_lim_project(h, u, v)
+    bufs = {"u": u, "v": v, "tr": torch.zeros(C, dtype=torch.int32, device=dev),
+            "t": torch.zeros(1, dtype=torch.float64, device=dev),
+            "dt": torch.zeros(1, dtype=torch.float64, device=dev),
+            "st": torch.zeros(1, dtype=torch.int32, device=dev)}
+    return h, bufs
+
+
+def _lim_steps(h, b, te, k):
+    from paper_2409_12483_amd import abi
+    abi.aderdg_lim_step(h, b["u"], b["v"], b["tr"], b["t"], te, b["dt"], b["st"], k)
+
+
+def lim_table9(N=9, C=50, chunk=400):
+    """The Riemann tests of Table 9 at the paper's configuration (N = 9, 50
+    cells, free outflow, CFL 0.4 with d = 2, t = 0.15): the whole run of each,
+    HIP-event timed (chunks of steps; the chunk after t_end is not timed)."""
+    import torch
+    from paper_2409_12483_amd import abi
+    from paper_2409_12483_amd import workloads as W
+    out = []
+    for test in (1, 2, 3, 4):
+        h, b = _lim_handle(N, C, W.riemann_nodal(C, N, test), abi.LIM_TRANSMISSIVE, 2)
+        te = torch.full((1,), 0.15, dtype=torch.float64, device="cuda:0")
+        secs = 0.0
+        while float(b["t"].item()) < 0.15:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _lim_steps(h, b, te, chunk)
+            e1.record()
+            e1.synchronize()
+            secs += e0.elapsed_time(e1) * 1e-3
+        tr, fb, steps, sw = abi.aderdg_lim_counters(h)
+        out.append({"test": test, "steps": steps, "troubled_cell_steps": tr, "fallback_steps": fb,
+                    "status": int(b["st"].item()), "run_ms": round(secs * 1e3, 2),
+                    "us_per_launched_step": round(secs / (steps + (-steps) % chunk) * 1e6, 2),
+                    "troubled_at_t_end": int(b["tr"].sum().item())})
+        abi.aderdg_lim_free(h)
+    return out
+
+
+def lim_array(N=5, C=131072, period=64, K=100, warmup=20):
+    """Throughput of the limited step on a large periodic mesh holding a row of
+    Sod problems (two jumps per 64 cells), against the fused unlimited step of
+    the same N and mesh size on smooth data."""
+    import torch
+    from paper_2409_12483_amd import abi
+    from paper_2409_12483_amd import workloads as W
+    M = 3
+    h, b = _lim_handle(N, C, W.riemann_array_nodal(C, N, 1, period), abi.LIM_PERIODIC, 1)
+    te = torch.full((1,), 1.0e300, dtype=torch.float64, device="cuda:0")
+    _lim_steps(h, b, te, warmup)
+    _sync()
+    c0 = abi.aderdg_lim_counters(h)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _lim_steps(h, b, te, K)
+    e1.record()
+    _sync()
+    secs = e0.elapsed_time(e1) * 1e-3
+    c1 = abi.aderdg_lim_counters(h)
+    status = int(b["st"].item())
+    abi.aderdg_lim_free(h)
+    sweeps = (c1[3] - c0[3]) / (C * K)
+    pred, rest = dg_flops_per_cell(N, M, sweeps)
+    flops = (pred + rest) * C * K
+    ref = DGRun(N, C, abi.FP64, noise=0.0)
+    ref.steps(warmup)
+    rs, rsw = ref.timed(K)
+    ref.close()
+    return {"workload": f"ADER-DG 1D Euler N={N}, {C} periodic cells, Sod states in blocks of {period} "
+                        "cells, CFL 0.4, a posteriori ADER-WENO2 subcell limiter",
+            "value": round(K * C * (N + 1) * M / secs, 1), "unit": "DoF-updates/s",
+            "ms_per_step": round(secs / K * 1e3, 5), "status": status,
+            "troubled_fraction": round((c1[0] - c0[0]) / (C * K), 5),
+            "fallback_steps": c1[1] - c0[1], "sweeps_per_cell": round(sweeps, 3),
+            "dg_flops_per_step": int(round(flops / K)),
+            "achieved_tflops_dg_part": round(flops / secs / 1e12, 3),
+            "frac_fp64_peak_dg_part": round(flops / secs / 1e12 / PEAK_FP64_VALU, 4),
+            "unlimited_fused_step_smooth_ms": round(rs / K * 1e3, 5),
+            "limited_over_unlimited_time": round(secs / rs, 3)}
+
+
+def limiter_section(quick=False):
+    out = {"array_n5": lim_array()}
+    if not quick:
+        out["table9_n9_50"] = lim_table9()
+    return out
+
+
 def emit(name, obj):
     """One JSON line per extra section (the last line of stdout is the headline)."""
     print(json.dumps({"extra": name, "result": obj}), flush=True)
@@ -811,6 +909,8 @@ def main():
                     help="first run a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--dg2d-only", action="store_true",
                     help="only the 2-D workload (512x512 cells, N=5; for profiling the 2-D kernels)")
+    ap.add_argument("--limiter-only", action="store_true",
+                    help="only the limited step on the 131072-cell Sod row (N=5; for profiling)")
     ap.add_argument("--dg3d-only", action="store_true",
                     help="only the 3-D workloads (N=3 on 64^3 and N=5 on 40^3 cells; for profiling)")
     a = ap.parse_args()
@@ -826,7 +926,7 @@ def main():
     # the oracle's host-core baseline runs first: its worker processes are
     # forked, which must happen before this process touches the GPU
     cpu = None
-    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only):
+    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only):
         cpu = cpu_baseline(N)
         emit("cpu_baseline", cpu)
 
@@ -846,6 +946,9 @@ def main():
         return
     if a.dg3d_only:
         print(json.dumps({"dg3d_euler_sine": dg3d_section(quick=True)}))
+        return
+    if a.limiter_only:
+        print(json.dumps({"limiter": limiter_section(quick=True)}))
         return
 
     run = DGRun(N, C, abi.FP64)
@@ -932,6 +1035,7 @@ def main():
                                            for rate in (50.0, 100.0)])
         emit("dg2d_euler_sine_512x512", dg2d_section())
         emit("dg3d_euler_sine", dg3d_section())
+        emit("limiter", limiter_section())
         # compact summaries for the headline line
         out["fp32_predictor"] = {"value": fp32["value"], "ms_per_step": fp32["ms_per_step"],
                                  "frac": fp32["roofline"]["frac"],

@@ -12,7 +12,7 @@
  * representation by u = R v, R the least-squares inverse of P (Sec. 1.4).
  * The PDE is Sec. 2, eq. system_of_equations in 1-D: U = (rho, rho u, E).
  *
- * Readings where the paper is silent (the same as the checker's):
+ * Readings where the paper is silent (the test oracle takes the same ones):
  *   - a limited cell keeps its subcell averages v between steps; the
  *     detectors and the next subgrid step start from them (never from P R v);
  *   - faces between a limited and an unlimited cell carry one flux, the
@@ -80,8 +80,9 @@ typedef struct aderdg_lim_handle aderdg_lim_handle;
 /*
  * aderdg_lim_init -- create a limited problem.  cfg is copied.  hip_stream: a
  * hipStream_t (NULL = default stream).  Allocates library-owned device
- * memory of about (14 N + 20) * 3 doubles per cell (candidate volume terms,
- * face traces and fluxes, subgrid results, the troubled-cell list) and a clock.
+ * memory of (5 N + 9) * 3 doubles and one int32 per cell (candidate volume terms,
+ * face traces and fluxes, subcell extrema, subgrid results, the troubled-cell
+ * list) and a clock.
  * Errors: E_INVAL (*out untouched), E_NOMEM, E_DEVICE.
  */
 int aderdg_lim_init(const aderdg_lim_config* cfg, void* hip_stream, aderdg_lim_handle** out);
@@ -112,15 +113,16 @@ int aderdg_lim_project(aderdg_lim_handle* h, const double* u, double* v);
  *             ADERDG_E_NOCONV (a Picard iteration did not converge) /
  *             ADERDG_E_NONPHYS (the new state is not admissible) met during
  *             the call.
- * Seven kernel launches per step plus one per call; no host synchronisation.
+ * Six kernel launches per step plus three per call; no host synchronisation.
  */
 int aderdg_lim_step(aderdg_lim_handle* h, double* u, double* v, int32_t* troubled, double* t,
                     const double* t_end, double* dt, int32_t* status, int32_t nsteps);
 
 /* aderdg_lim_counters -- host output, synchronous read: out[0] = troubled
  * cell-steps since init, out[1] = steps whose subgrid step fell back to first
- * order, out[2] = steps taken (dt > 0). */
-int aderdg_lim_counters(aderdg_lim_handle* h, int64_t* out3);
+ * order, out[2] = steps taken (dt > 0), out[3] = outer Picard sweeps of the
+ * candidate predictor summed over cells and steps (ghost cells excluded). */
+int aderdg_lim_counters(aderdg_lim_handle* h, int64_t* out4);
 
 /* aderdg_lim_free -- release the handle (synchronises its stream).  NULL accepted. */
 int aderdg_lim_free(aderdg_lim_handle* h);

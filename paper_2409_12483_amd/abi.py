@@ -375,8 +375,8 @@ def aderdg_lim_step(h, u, v, troubled, t, t_end, dt, status, nsteps):
 
 
 def aderdg_lim_counters(h):
-    """(troubled cell-steps, first-order fallback steps, steps taken) since init."""
-    out = (ctypes.c_int64 * 3)()
+    """(troubled cell-steps, first-order fallback steps, steps taken, predictor sweeps) since init."""
+    out = (ctypes.c_int64 * 4)()
     _check(load().aderdg_lim_counters(h, out))
     return tuple(out)
 

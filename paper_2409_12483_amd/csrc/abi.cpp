@@ -1030,8 +1030,8 @@ int aderdg_lim_init(const aderdg_lim_config* cfg, void* hip_stream, aderdg_lim_h
   h->stream = (hipStream_t)hip_stream;
   h->cfg = c;
   const int64_t C = c.ncells, n = c.N + 1, Ns = 2 * c.N + 1, M = 3;
-  // doubles: vol, trL, trR, G, vfv, gs; then the int32 list
-  const int64_t nd = C * n * M + 2 * (C + 2) * n * M + (C + 1) * M + C * Ns * M + C * 2 * M;
+  // doubles: vol, trL, trR, G, vext, vfv, gs; then the int32 list
+  const int64_t nd = C * n * M + 2 * (C + 2) * n * M + (C + 1) * M + C * 2 * M + C * Ns * M + C * 2 * M;
   e = hipMalloc(&h->scratch, sizeof(double) * nd + sizeof(int32_t) * C);
   if (e != hipSuccess) { release_lim(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
   e = hipMalloc((void**)&h->args.clk, sizeof(LimClock));
@@ -1053,6 +1053,7 @@ int aderdg_lim_init(const aderdg_lim_config* cfg, void* hip_stream, aderdg_lim_h
   A.trL = d;  d += (C + 2) * n * M;
   A.trR = d;  d += (C + 2) * n * M;
   A.G = d;    d += (C + 1) * M;
+  A.vext = d; d += C * 2 * M;
   A.vfv = d;  d += C * Ns * M;
   A.gs = d;   d += C * 2 * M;
   A.list = (int32_t*)d;
@@ -1087,17 +1088,20 @@ int aderdg_lim_step(aderdg_lim_handle* h, double* u, double* v, int32_t* trouble
   return e == hipSuccess ? ADERDG_OK : fail_hip(e, "limited step launch");
 }
 
-int aderdg_lim_counters(aderdg_lim_handle* h, int64_t* out3) {
+int aderdg_lim_counters(aderdg_lim_handle* h, int64_t* out4) {
   g_last_error.clear();
-  if (!h || !out3) return fail(ADERDG_E_INVAL, "null argument");
+  if (!h || !out4) return fail(ADERDG_E_INVAL, "null argument");
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail_hip(e, "stream synchronisation");
   LimClock c;
   e = hipMemcpy(&c, h->args.clk, sizeof(c), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail_hip(e, "counter read");
-  out3[0] = (int64_t)c.total_troubled;
-  out3[1] = (int64_t)c.total_fallback;
-  out3[2] = (int64_t)c.total_steps;
+  out4[0] = (int64_t)c.total_troubled;
+  out4[1] = (int64_t)c.total_fallback;
+  out4[2] = (int64_t)c.total_steps;
+  int64_t sw = 0;
+  for (int i = 0; i < kSlots; ++i) sw += (int64_t)c.sweeps[i].v;
+  out4[3] = sw;
   return ADERDG_OK;
 }
 

@@ -80,6 +80,7 @@ struct alignas(128) LimClock {
   unsigned long long total_troubled, total_fallback, total_steps;
   unsigned long long pad[9];
   Slot lam[2][kSlots];              // max signal speed of the state (bit patterns), by step parity
+  Slot sweeps[kSlots];              // outer Picard sweeps of the candidate's predictor, summed over cells
   StatusSlot stat[kSlots];          // most severe status (min)
 };
 
@@ -99,18 +100,19 @@ struct LimArgs {
   double* trL;                      // [C+2][n time][3] left face traces of the padded cells
   double* trR;                      // [C+2][n time][3] right face traces
   double* G;                        // [C+1][3] time-integrated DG face fluxes (dt/dx units)
+  double* vext;                     // [C][2][3] per-cell min / max of the subcell averages v
   int32_t* list;                    // [C] troubled cells of the step
   double* vfv;                      // [C][Ns][3] subgrid results (troubled cells)
   double* gs;                       // [C][2][3] subgrid fluxes at a troubled cell's faces (dt/dxs units)
 };
 
-constexpr int kLimSubgridBlocks = 2048;   // persistent workgroups of the subgrid kernels
+constexpr int kLimSubgridBlocks = 16384;  // workgroups (one wavefront each) of the subgrid kernels
 hipError_t launch_lim_begin(LimClock* clk, const double* t_user, hipStream_t st);
 hipError_t launch_lim_end(const LimClock* clk, double* t_user, double* dt_user, int32_t* status_user,
                           hipStream_t st);
 hipError_t launch_lim_project(int N, const double* u, double* v, int64_t C, hipStream_t st);
 hipError_t launch_lim_lambda(const LimArgs& A, int buf, hipStream_t st);
-// the seven kernels of one limited step
+// the six kernels of one limited step
 hipError_t launch_lim_step(const LimArgs& A, hipStream_t st);
 hipError_t launch_noalloc_setup(const ProbDev& step, const ProbDev& lam, void* base, hipStream_t st);
 

@@ -2,22 +2,22 @@
 // limiting (Sec. 1.4, Sec. 1.6) for the Euler gas.  Included once, by
 // kernels.hip, so that they share its operator and WENO tables.
 //
-// One step is seven launches on the problem's stream:
+// One step is six launches on the problem's stream:
 //   lim_clock     dt from the CFL rule (Sec. 1.5) over the subcell averages
 //   lim_pred      LST-DG predictor of every cell and of the two ghost cells;
 //                 per cell: the candidate's volume terms and the face traces
 //                 of every time node
-//   lim_faces     time-integrated Rusanov flux of every face
-//   lim_cand      candidate u* = u + volume - surface (in place), PAD and NAD
-//                 on its subcell averages, the list of troubled cells
+//   lim_cand      time-integrated Rusanov flux of every face, candidate
+//                 u* = u + volume - surface (in place), PAD and NAD on its
+//                 subcell averages, the list of troubled cells
 //   lim_subgrid   ADER-WENO2 step on the subgrid of every troubled cell, from
 //                 the stored subcell averages (one wavefront per cell)
 //   lim_subgrid0  first-order redo of those subgrid steps, only when one of
 //                 them left the admissible set
 //   lim_finish    u = R v in troubled cells (scaled toward the mean when
 //                 needed), the subgrid flux at their faces in the unlimited
-//                 neighbours, new subcell averages, the next step's signal
-//                 speed
+//                 neighbours, new subcell averages and their per-cell
+//                 extrema, the next step's signal speed
 #pragma once
 
 #include "device_common.hpp"
@@ -97,6 +97,23 @@ __device__ __forceinline__ double lim_cell_speed(const double (&uc)[N + 1][kLimM
   return lam;
 }
 
+// Per-cell extrema of the subcell averages v (per variable), for the NAD
+// window of the next step.
+template <int Ns>
+__device__ __forceinline__ void lim_store_extrema(const LimArgs& A, int64_t i, const double (&vs)[Ns][kLimM]) {
+#pragma unroll
+  for (int r = 0; r < kLimM; ++r) {
+    double mn = vs[0][r], mx = vs[0][r];
+#pragma unroll
+    for (int s = 1; s < Ns; ++s) {
+      mn = fmin(mn, vs[s][r]);
+      mx = fmax(mx, vs[s][r]);
+    }
+    A.vext[(i * 2) * kLimM + r] = mn;
+    A.vext[(i * 2 + 1) * kLimM + r] = mx;
+  }
+}
+
 // ------------------------------------------------------------ clock ----
 __global__ void lim_begin_kernel(LimClock* clk, const double* t_user) {
   const int i = threadIdx.x;
@@ -171,7 +188,8 @@ __global__ void __launch_bounds__(256) lim_project_kernel(const double* u, doubl
     }
 }
 
-// signal speed of the state at the start of a call (one thread per cell)
+// signal speed of the state and the subcell extrema at the start of a call
+// (one thread per cell)
 template <int N>
 __global__ void __launch_bounds__(256) lim_lambda_kernel(LimArgs A, int buf) {
   constexpr int n = N + 1;
@@ -184,6 +202,13 @@ __global__ void __launch_bounds__(256) lim_lambda_kernel(LimArgs A, int buf) {
 #pragma unroll
       for (int r = 0; r < kLimM; ++r) uc[k][r] = A.u[(i * n + k) * kLimM + r];
     lam = lim_cell_speed<N>(uc, A.pp);
+    constexpr int Ns = 2 * N + 1;
+    double vs[Ns][kLimM];
+#pragma unroll
+    for (int s = 0; s < Ns; ++s)
+#pragma unroll
+      for (int r = 0; r < kLimM; ++r) vs[s][r] = A.v[(i * Ns + s) * kLimM + r];
+    lim_store_extrema<Ns>(A, i, vs);
   }
   lim_publish_lambda(A.clk, buf, lam);
 }
@@ -280,49 +305,70 @@ lim_pred_kernel(LimArgs A) {
       }
     }
   }
+  const unsigned long long sw = wave_sum((out && a == 0 && p >= 1 && p <= C) ? (unsigned long long)(sweeps & 0xffff) : 0ull);
+  if (lane == 0 && sw) atomicAdd(&A.clk->sweeps[(blockIdx.x * WAVES + wave) % kSlots].v, sw);
   lim_status(A.clk, blockIdx.x, false, failed && out);
 }
 
-// ------------------------------------------------------------ faces ----
-// Face f (0..C) between padded cells f and f+1: sum_a w_a (dt/dx) Rusanov.
+// ------------------------------------------- faces, candidate, detectors ----
+// One thread per cell.  The thread of cell i computes the time-integrated
+// Rusanov flux of face i+1 (sum_a w_a (dt/dx) F^ of the traces), the first
+// thread of a workgroup also that of its cell's left face; the fluxes meet in
+// LDS.  Then u* = u + volume - surface (in place), PAD on u* and its subcell
+// averages, NAD against the per-cell subcell extrema of V_i, the troubled list.
+constexpr int kLimCandThreads = 256;
+
 template <int N>
-__global__ void __launch_bounds__(256) lim_faces_kernel(LimArgs A) {
+__device__ __forceinline__ void lim_face_flux(const LimArgs& A, int64_t f, double dtdx, double* g) {
   constexpr int n = N + 1, M = kLimM;
-  const double dt = A.clk->dt;
-  if (!(dt > 0.0)) return;
-  const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (f > A.C) return;
-  const double dtdx = dt / A.dx;
-  double acc[M] = {};
+#pragma unroll
+  for (int r = 0; r < M; ++r) g[r] = 0.0;
 #pragma unroll
   for (int a = 0; a < n; ++a) {
-    double qm[M], qp[M], g[M];
+    double qm[M], qp[M], h[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      qm[r] = A.trR[(f * n + a) * M + r];
-      qp[r] = A.trL[((f + 1) * n + a) * M + r];
+      qm[r] = A.trR[(f * n + a) * M + r];           // right trace of padded cell f (cell f-1)
+      qp[r] = A.trL[((f + 1) * n + a) * M + r];     // left trace of padded cell f+1 (cell f)
     }
-    lim_rusanov(qm, qp, g, A.pp);
+    lim_rusanov(qm, qp, h, A.pp);
     const double wa = c_ops[N].w[a] * dtdx;
 #pragma unroll
-    for (int r = 0; r < M; ++r) acc[r] += wa * g[r];
+    for (int r = 0; r < M; ++r) g[r] += wa * h[r];
   }
-#pragma unroll
-  for (int r = 0; r < M; ++r) A.G[f * M + r] = acc[r];
 }
 
-// -------------------------------------------------- candidate + detectors ----
 template <int N>
-__global__ void __launch_bounds__(256) lim_cand_kernel(LimArgs A) {
+__global__ void __launch_bounds__(kLimCandThreads) lim_cand_kernel(LimArgs A) {
   constexpr int n = N + 1, M = kLimM, Ns = 2 * N + 1;
+  __shared__ double sG[(kLimCandThreads + 1) * M];
   const int64_t C = A.C;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= C) return;
+  const int64_t i = (int64_t)blockIdx.x * kLimCandThreads + threadIdx.x;
   const double dt = A.clk->dt;
   if (!(dt > 0.0)) {
-    A.troubled[i] = 0;
+    if (i < C) A.troubled[i] = 0;
     return;
   }
+  const double dtdx = dt / A.dx;
+  if (i < C) {
+    double g[M];
+    lim_face_flux<N>(A, i + 1, dtdx, g);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      sG[(threadIdx.x + 1) * M + r] = g[r];
+      A.G[(i + 1) * M + r] = g[r];
+    }
+    if (threadIdx.x == 0) {
+      lim_face_flux<N>(A, i, dtdx, g);
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        sG[r] = g[r];
+        if (i == 0) A.G[r] = g[r];
+      }
+    }
+  }
+  __syncthreads();
+  if (i >= C) return;
   const PdeParams pp = A.pp;
   double uc[n][M];
   bool bad = false;
@@ -331,7 +377,7 @@ __global__ void __launch_bounds__(256) lim_cand_kernel(LimArgs A) {
     const double winv = c_ops[N].winv[k], p0 = c_ops[N].psi0[k], p1 = c_ops[N].psi1[k];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      const double GR = A.G[(i + 1) * M + r], GL = A.G[i * M + r];
+      const double GR = sG[(threadIdx.x + 1) * M + r], GL = sG[threadIdx.x * M + r];
       const double val = A.u[(i * n + k) * M + r] + A.vol[(i * n + k) * M + r] - winv * (p1 * GR - p0 * GL);
       uc[k][r] = val;
       A.u[(i * n + k) * M + r] = val;
@@ -339,36 +385,23 @@ __global__ void __launch_bounds__(256) lim_cand_kernel(LimArgs A) {
     bad |= !Euler::admissible(uc[k], pp);
   }
   // V_i: the cell and its face neighbours (one neighbour at a free-outflow end)
-  int64_t nb[3] = {i - 1, i, i + 1};
+  int64_t il = i - 1, ir = i + 1;
   if (A.bc == kLimPeriodic) {
-    if (nb[0] < 0) nb[0] += C;
-    if (nb[2] >= C) nb[2] -= C;
+    if (il < 0) il += C;
+    if (ir >= C) ir -= C;
   } else {
-    if (nb[0] < 0) nb[0] = 0;
-    if (nb[2] >= C) nb[2] = C - 1;
-  }
-  double mn[M], mx[M];
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
-    mn[r] = A.v[(nb[0] * Ns) * M + r];
-    mx[r] = mn[r];
-  }
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int s = 0; s < Ns; ++s)
-#pragma unroll
-      for (int r = 0; r < M; ++r) {
-        const double x = A.v[(nb[c] * Ns + s) * M + r];
-        mn[r] = fmin(mn[r], x);
-        mx[r] = fmax(mx[r], x);
-      }
+    if (il < 0) il = 0;
+    if (ir >= C) ir = C - 1;
   }
   double lo[M], hi[M];
 #pragma unroll
   for (int r = 0; r < M; ++r) {
-    const double delta = fmax(kLimDelta0, kLimEps0 * (mx[r] - mn[r]));
-    lo[r] = mn[r] - delta;
-    hi[r] = mx[r] + delta;
+    const double mn = fmin(fmin(A.vext[(il * 2) * M + r], A.vext[(i * 2) * M + r]), A.vext[(ir * 2) * M + r]);
+    const double mx = fmax(fmax(A.vext[(il * 2 + 1) * M + r], A.vext[(i * 2 + 1) * M + r]),
+                           A.vext[(ir * 2 + 1) * M + r]);
+    const double delta = fmax(kLimDelta0, kLimEps0 * (mx - mn));
+    lo[r] = mn - delta;
+    hi[r] = mx + delta;
   }
 #pragma unroll
   for (int s = 0; s < Ns; ++s) {
@@ -660,6 +693,7 @@ __global__ void __launch_bounds__(256) lim_finish_kernel(LimArgs A) {
       for (int s = 0; s < Ns; ++s)
 #pragma unroll
         for (int r = 0; r < M; ++r) A.v[(i * Ns + s) * M + r] = vs[s][r];
+      lim_store_extrema<Ns>(A, i, vs);
     } else {
 #pragma unroll
       for (int k = 0; k < n; ++k)
@@ -695,6 +729,7 @@ __global__ void __launch_bounds__(256) lim_finish_kernel(LimArgs A) {
 #pragma unroll
             for (int r = 0; r < M; ++r) A.u[(i * n + k) * M + r] = uc[k][r];
         }
+        double vs[Ns][M];
 #pragma unroll
         for (int s = 0; s < Ns; ++s)
 #pragma unroll
@@ -702,8 +737,10 @@ __global__ void __launch_bounds__(256) lim_finish_kernel(LimArgs A) {
             double acc = 0.0;
 #pragma unroll
             for (int k = 0; k < n; ++k) acc += c_ops[N].P[s][k] * uc[k][r];
+            vs[s][r] = acc;
             A.v[(i * Ns + s) * M + r] = acc;
           }
+        lim_store_extrema<Ns>(A, i, vs);
       }
     }
 #pragma unroll
@@ -720,13 +757,13 @@ static hipError_t launch_lim_step_n(const LimArgs& A, hipStream_t st) {
   constexpr int kWaves = 4;
   const int64_t C = A.C;
   const int64_t pc = (int64_t)kWaves * (64 / (N + 1));
-  const unsigned cb = (unsigned)((C + 255) / 256), fb = (unsigned)((C + 1 + 255) / 256);
+  const unsigned cb = (unsigned)((C + 255) / 256);
+  const unsigned kb = (unsigned)((C + kLimCandThreads - 1) / kLimCandThreads);
   const unsigned pb = (unsigned)((C + 2 + pc - 1) / pc);
   const unsigned sb = (unsigned)(C < kLimSubgridBlocks ? C : kLimSubgridBlocks);
   hipLaunchKernelGGL(lim_clock_kernel, dim3(1), dim3(64), 0, st, A);
   hipLaunchKernelGGL((lim_pred_kernel<N, kWaves>), dim3(pb), dim3(kWaves * 64), 0, st, A);
-  hipLaunchKernelGGL((lim_faces_kernel<N>), dim3(fb), dim3(256), 0, st, A);
-  hipLaunchKernelGGL((lim_cand_kernel<N>), dim3(cb), dim3(256), 0, st, A);
+  hipLaunchKernelGGL((lim_cand_kernel<N>), dim3(kb), dim3(kLimCandThreads), 0, st, A);
   hipLaunchKernelGGL((lim_subgrid_kernel<N>), dim3(sb), dim3(64), 0, st, A);
   hipLaunchKernelGGL((lim_subgrid0_kernel<N>), dim3(sb), dim3(64), 0, st, A);
   hipLaunchKernelGGL((lim_finish_kernel<N>), dim3(cb), dim3(256), 0, st, A);

@@ -235,3 +235,12 @@ def riemann_nodal(ncells, N, test, x0=0.0, x1=1.0, xc=0.5, gamma=1.4):
     xs = cell_points(ncells, N + 1, x0, x1)
     left = xs <= xc
     return _euler_conserved(np.where(left, rl, rr), np.where(left, ul, ur), np.where(left, pl, pr), gamma)
+
+
+def riemann_array_nodal(ncells, N, test=1, period=64, gamma=1.4):
+    """A periodic row of Table 9 Riemann problems: every block of `period`
+    cells holds the left state in its first half and the right state in its
+    second half (two discontinuities per block, at cell faces)."""
+    (rl, ul, pl), (rr, ur, pr) = RIEMANN_TESTS[test]
+    left = (np.arange(ncells) % period < period // 2)[:, None] & np.ones((1, N + 1), dtype=bool)
+    return _euler_conserved(np.where(left, rl, rr), np.where(left, ul, ur), np.where(left, pl, pr), gamma)

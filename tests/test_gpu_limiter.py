@@ -266,5 +266,5 @@ def test_call_past_t_end_changes_nothing():
     N, C = 2, 20
     u0 = W.riemann_nodal(C, N, 1)
     gu, gv, gtr, gt, gdt, st, cnt = _gpu(N, C, u0, 3, t0=0.5, t_end=0.5)
-    assert gdt == 0.0 and gt == 0.5 and st == 0 and cnt[2] == 0
+    assert gdt == 0.0 and gt == 0.5 and st == 0 and cnt[2] == 0 and cnt[3] == 0
     assert np.array_equal(gu, u0) and not gtr.any()
