@@ -58,7 +58,7 @@ def dg_flops_per_cell(N, M, sweeps_per_cell, flux=12):
     return sweeps_per_cell * sweep, corr + cfl
 
 
-KERNEL_SOURCES = ("kernels.hip", "predictor.hpp", "device_common.hpp", "launch.hpp", "operators.hpp")
+KERNEL_SOURCES = ("dg_step.hpp", "kernels.hip", "predictor.hpp", "device_common.hpp", "launch.hpp", "operators.hpp")
 PROFILE = os.path.join(ROOT, "profiles", "dg_step_euler_n5_c1e5_fp64.md")
 
 
@@ -976,8 +976,6 @@ def main():
                    "device_ramp_steps": ramp_steps},
         "roofline": roof, "status": status, "wall_s": round(wall, 4),
     }
-    u64 = run.u.cpu().numpy()
-    t64 = float(run.t.item())
     run.close()
 
     if not a.no_extras:
@@ -985,6 +983,12 @@ def main():
         r32.steps(Wm)
         s32, sw32 = r32.timed(K)
         u32 = r32.u.cpu().numpy()
+        # the FP64 state after the same Wm + K steps from the same initial state
+        r64 = DGRun(N, C, abi.FP64)
+        r64.steps(Wm + K)
+        u64 = r64.u.cpu().numpy()
+        t64 = float(r64.t.item())
+        r64.close()
         fp32 = {"value": round(K * dofs / s32, 1), "ms_per_step": round(s32 / K * 1e3, 5),
                 "roofline": roofline_entry(N, C, M, K, s32, sw32, "fp32"),
                 "status": int(r32.st.item()),

@@ -1032,7 +1032,8 @@ int aderdg_lim_init(const aderdg_lim_config* cfg, void* hip_stream, aderdg_lim_h
   const int64_t C = c.ncells, n = c.N + 1, Ns = 2 * c.N + 1, M = 3;
   // doubles: vol, trL, trR, G, vext, vfv, gs; then the int32 list
   const int64_t nd = C * n * M + 2 * (C + 2) * n * M + (C + 1) * M + C * 2 * M + C * Ns * M + C * 2 * M;
-  e = hipMalloc(&h->scratch, sizeof(double) * nd + sizeof(int32_t) * C);
+  // troubled list: kSlots sub-lists, each sized for the cells of its candidate workgroups
+  e = hipMalloc(&h->scratch, sizeof(double) * nd + sizeof(int32_t) * (C + (int64_t)(kSlots + 1) * 256));
   if (e != hipSuccess) { release_lim(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
   e = hipMalloc((void**)&h->args.clk, sizeof(LimClock));
   if (e != hipSuccess) { release_lim(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }

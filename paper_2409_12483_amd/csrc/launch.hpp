@@ -75,13 +75,14 @@ struct alignas(128) LimClock {
   double t_next;                    // its end
   double dt;                        // current step (0: the problem is at t_end)
   double dt_last;                   // last step > 0 of the call
-  int32_t ntroubled;                // troubled cells of the current step (list length)
   int32_t fallback;                 // the step's subgrid step fell back to first order
+  int32_t pad0;
   unsigned long long total_troubled, total_fallback, total_steps;
   unsigned long long pad[9];
   Slot lam[2][kSlots];              // max signal speed of the state (bit patterns), by step parity
   Slot sweeps[kSlots];              // outer Picard sweeps of the candidate's predictor, summed over cells
   StatusSlot stat[kSlots];          // most severe status (min)
+  StatusSlot ntr[kSlots];           // troubled cells of the current step, per sub-list
 };
 
 // Kernel arguments (passed by value).
@@ -101,7 +102,8 @@ struct LimArgs {
   double* trR;                      // [C+2][n time][3] right face traces
   double* G;                        // [C+1][3] time-integrated DG face fluxes (dt/dx units)
   double* vext;                     // [C][2][3] per-cell min / max of the subcell averages v
-  int32_t* list;                    // [C] troubled cells of the step
+  int32_t* list;                    // troubled cells of the step: kSlots sub-lists of list_cap entries
+  int64_t list_cap;
   double* vfv;                      // [C][Ns][3] subgrid results (troubled cells)
   double* gs;                       // [C][2][3] subgrid fluxes at a troubled cell's faces (dt/dxs units)
 };

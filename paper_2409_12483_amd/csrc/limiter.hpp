@@ -9,7 +9,8 @@
 //                 of every time node
 //   lim_cand      time-integrated Rusanov flux of every face, candidate
 //                 u* = u + volume - surface (in place), PAD and NAD on its
-//                 subcell averages, the list of troubled cells
+//                 subcell averages, the list of troubled cells (one lane per
+//                 (cell, node))
 //   lim_subgrid   ADER-WENO2 step on the subgrid of every troubled cell, from
 //                 the stored subcell averages (one wavefront per cell)
 //   lim_subgrid0  first-order redo of those subgrid steps, only when one of
@@ -147,7 +148,10 @@ __global__ void lim_clock_kernel(LimArgs A) {
   const int buf = A.step & 1;
   double lam = lane < kSlots ? from_bits(clk->lam[buf][lane].v) : 0.0;
   lam = wave_max(lam);
-  if (lane < kSlots) clk->lam[buf ^ 1][lane].v = 0ull;
+  if (lane < kSlots) {
+    clk->lam[buf ^ 1][lane].v = 0ull;
+    clk->ntr[lane].v = 0;
+  }
   if (lane == 0) {
     const double t = clk->t_next;
     double dt = A.cfl_d * A.dx / ((2.0 * A.N + 1.0) * lam);
@@ -157,7 +161,6 @@ __global__ void lim_clock_kernel(LimArgs A) {
     clk->t = t;
     clk->t_next = t + dt;
     clk->dt = dt;
-    clk->ntroubled = 0;
     clk->fallback = 0;
     if (dt > 0.0) {
       clk->dt_last = dt;
@@ -311,113 +314,176 @@ lim_pred_kernel(LimArgs A) {
 }
 
 // ------------------------------------------- faces, candidate, detectors ----
-// One thread per cell.  The thread of cell i computes the time-integrated
-// Rusanov flux of face i+1 (sum_a w_a (dt/dx) F^ of the traces), the first
-// thread of a workgroup also that of its cell's left face; the fluxes meet in
-// LDS.  Then u* = u + volume - surface (in place), PAD on u* and its subcell
-// averages, NAD against the per-cell subcell extrema of V_i, the troubled list.
-constexpr int kLimCandThreads = 256;
+// Lanes as in the predictor: lane a of a cell is time node a for the face
+// fluxes and space node a for the candidate.  Each cell computes the
+// time-integrated Rusanov flux of both its faces (a face's two cells do the
+// same arithmetic on the same traces, so they agree bit for bit), then
+// u* = u + volume - surface at node a (in place), PAD at the node; the
+// candidate's subcell averages s = a and s = a + n go through NAD against the
+// per-cell subcell extrema of V_i and PAD; a troubled cell joins the list.
+constexpr int kLimCandWaves = 4;
 
 template <int N>
-__device__ __forceinline__ void lim_face_flux(const LimArgs& A, int64_t f, double dtdx, double* g) {
-  constexpr int n = N + 1, M = kLimM;
-#pragma unroll
-  for (int r = 0; r < M; ++r) g[r] = 0.0;
-#pragma unroll
-  for (int a = 0; a < n; ++a) {
-    double qm[M], qp[M], h[M];
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-      qm[r] = A.trR[(f * n + a) * M + r];           // right trace of padded cell f (cell f-1)
-      qp[r] = A.trL[((f + 1) * n + a) * M + r];     // left trace of padded cell f+1 (cell f)
-    }
-    lim_rusanov(qm, qp, h, A.pp);
-    const double wa = c_ops[N].w[a] * dtdx;
-#pragma unroll
-    for (int r = 0; r < M; ++r) g[r] += wa * h[r];
-  }
-}
-
-template <int N>
-__global__ void __launch_bounds__(kLimCandThreads) lim_cand_kernel(LimArgs A) {
-  constexpr int n = N + 1, M = kLimM, Ns = 2 * N + 1;
-  __shared__ double sG[(kLimCandThreads + 1) * M];
+__global__ void __launch_bounds__(kLimCandWaves * 64) lim_cand_kernel(LimArgs A) {
+  constexpr int n = N + 1, M = kLimM, Ns = 2 * N + 1, CPW = 64 / n;
+  constexpr int CB = CPW * n * M;                       // doubles of one wave's cell blocks
+  __shared__ double sx[kLimCandWaves * CB];             // per cell: [n][M] face-flux parts, then u*
+  __shared__ int sbad[kLimCandWaves * CPW];
   const int64_t C = A.C;
-  const int64_t i = (int64_t)blockIdx.x * kLimCandThreads + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot0 = lane / n;
+  const bool active = slot0 < CPW;
+  const int slot = active ? slot0 : 0;
+  const int a = active ? lane % n : 0;
+  const int64_t i = ((int64_t)blockIdx.x * kLimCandWaves + wave) * CPW + slot;
+  const bool live = active && i < C;
   const double dt = A.clk->dt;
   if (!(dt > 0.0)) {
-    if (i < C) A.troubled[i] = 0;
+    if (live && a == 0) A.troubled[i] = 0;
     return;
   }
   const double dtdx = dt / A.dx;
-  if (i < C) {
-    double g[M];
-    lim_face_flux<N>(A, i + 1, dtdx, g);
+  const PdeParams pp = A.pp;
+  double* blk = sx + wave * CB + slot * (n * M);
+  // face fluxes: lane a takes time node a of both faces
+  double GL[M], GR[M];
+  {
+    const int64_t ic = live ? i : 0;
+    double qm[M], qp[M], hl[M], hr[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      sG[(threadIdx.x + 1) * M + r] = g[r];
-      A.G[(i + 1) * M + r] = g[r];
+      qm[r] = A.trR[(ic * n + a) * M + r];              // padded cell i: cell i-1
+      qp[r] = A.trL[((ic + 1) * n + a) * M + r];        // padded cell i+1: cell i
     }
-    if (threadIdx.x == 0) {
-      lim_face_flux<N>(A, i, dtdx, g);
+    lim_rusanov(qm, qp, hl, pp);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      qm[r] = A.trR[((ic + 1) * n + a) * M + r];
+      qp[r] = A.trL[((ic + 2) * n + a) * M + r];
+    }
+    lim_rusanov(qm, qp, hr, pp);
+    const double wa = c_ops[N].w[a] * dtdx;
+    // the two faces' weighted parts through the cell's block, summed over a in order
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      wave_sync();
+      if (active) {
+#pragma unroll
+        for (int r = 0; r < M; ++r) blk[a * M + r] = wa * (side ? hr[r] : hl[r]);
+      }
+      wave_sync();
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        sG[r] = g[r];
-        if (i == 0) A.G[r] = g[r];
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < n; ++b) acc += blk[b * M + r];
+        (side ? GR : GL)[r] = acc;
       }
     }
   }
-  __syncthreads();
-  if (i >= C) return;
-  const PdeParams pp = A.pp;
-  double uc[n][M];
+  if (live && a == 0) {
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      A.G[(i + 1) * M + r] = GR[r];
+      if (i == 0) A.G[r] = GL[r];
+    }
+  }
+  // candidate at node a
+  double uk[M];
   bool bad = false;
+  {
+    const int64_t ic = live ? i : 0;
+    const double winv = c_ops[N].winv[a], p0 = c_ops[N].psi0[a], p1 = c_ops[N].psi1[a];
 #pragma unroll
-  for (int k = 0; k < n; ++k) {
-    const double winv = c_ops[N].winv[k], p0 = c_ops[N].psi0[k], p1 = c_ops[N].psi1[k];
+    for (int r = 0; r < M; ++r)
+      uk[r] = A.u[(ic * n + a) * M + r] + A.vol[(ic * n + a) * M + r] - winv * (p1 * GR[r] - p0 * GL[r]);
+    if (live) {
+#pragma unroll
+      for (int r = 0; r < M; ++r) A.u[(i * n + a) * M + r] = uk[r];
+      bad = !Euler::admissible(uk, pp);
+    }
+  }
+  wave_sync();
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < M; ++r) blk[a * M + r] = uk[r];
+    if (a == 0) sbad[wave * CPW + slot] = 0;
+  }
+  wave_sync();
+  if (live) {
+    // V_i: the cell and its face neighbours (one neighbour at a free-outflow end)
+    int64_t il = i - 1, ir = i + 1;
+    if (A.bc == kLimPeriodic) {
+      if (il < 0) il += C;
+      if (ir >= C) ir -= C;
+    } else {
+      if (il < 0) il = 0;
+      if (ir >= C) ir = C - 1;
+    }
+    double lo[M], hi[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      const double GR = sG[(threadIdx.x + 1) * M + r], GL = sG[threadIdx.x * M + r];
-      const double val = A.u[(i * n + k) * M + r] + A.vol[(i * n + k) * M + r] - winv * (p1 * GR - p0 * GL);
-      uc[k][r] = val;
-      A.u[(i * n + k) * M + r] = val;
+      const double mn = fmin(fmin(A.vext[(il * 2) * M + r], A.vext[(i * 2) * M + r]), A.vext[(ir * 2) * M + r]);
+      const double mx = fmax(fmax(A.vext[(il * 2 + 1) * M + r], A.vext[(i * 2 + 1) * M + r]),
+                             A.vext[(ir * 2 + 1) * M + r]);
+      const double delta = fmax(kLimDelta0, kLimEps0 * (mx - mn));
+      lo[r] = mn - delta;
+      hi[r] = mx + delta;
     }
-    bad |= !Euler::admissible(uc[k], pp);
-  }
-  // V_i: the cell and its face neighbours (one neighbour at a free-outflow end)
-  int64_t il = i - 1, ir = i + 1;
-  if (A.bc == kLimPeriodic) {
-    if (il < 0) il += C;
-    if (ir >= C) ir -= C;
-  } else {
-    if (il < 0) il = 0;
-    if (ir >= C) ir = C - 1;
-  }
-  double lo[M], hi[M];
 #pragma unroll
-  for (int r = 0; r < M; ++r) {
-    const double mn = fmin(fmin(A.vext[(il * 2) * M + r], A.vext[(i * 2) * M + r]), A.vext[(ir * 2) * M + r]);
-    const double mx = fmax(fmax(A.vext[(il * 2 + 1) * M + r], A.vext[(i * 2 + 1) * M + r]),
-                           A.vext[(ir * 2 + 1) * M + r]);
-    const double delta = fmax(kLimDelta0, kLimEps0 * (mx - mn));
-    lo[r] = mn - delta;
-    hi[r] = mx + delta;
-  }
+    for (int h = 0; h < 2; ++h) {
+      const int s = a + h * n;
+      if (s < Ns) {
+        double vs[M];
 #pragma unroll
-  for (int s = 0; s < Ns; ++s) {
-    double vs[M];
+        for (int r = 0; r < M; ++r) {
+          double acc = 0.0;
 #pragma unroll
-    for (int r = 0; r < M; ++r) {
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < n; ++k) acc += c_ops[N].P[s][k] * uc[k][r];
-      vs[r] = acc;
-      bad |= !(acc >= lo[r] && acc <= hi[r]);
+          for (int k = 0; k < n; ++k) acc += c_ops[N].P[s][k] * blk[k * M + r];
+          vs[r] = acc;
+          bad |= !(acc >= lo[r] && acc <= hi[r]);
+        }
+        bad |= !Euler::admissible(vs, pp);
+      }
     }
-    bad |= !Euler::admissible(vs, pp);
+    if (bad) sbad[wave * CPW + slot] = 1;
   }
-  A.troubled[i] = bad ? 1 : 0;
-  if (bad) A.list[atomicAdd(&A.clk->ntroubled, 1)] = (int32_t)i;
+  wave_sync();
+  // append to sub-list blockIdx % kSlots: one atomic per wavefront, so that
+  // thousands of troubled cells do not serialise on one counter
+  const bool tb = live && a == 0 && sbad[wave * CPW + slot] != 0;
+  if (live && a == 0) A.troubled[i] = tb ? 1 : 0;
+  const unsigned long long mask = __ballot(tb);
+  if (mask) {
+    const int k = (int)(blockIdx.x % kSlots);
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&A.clk->ntr[k].v, __popcll(mask));
+    base = __shfl(base, 0, 64);
+    if (tb) A.list[k * A.list_cap + base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)i;
+  }
+}
+
+// Entry b of the step's troubled list (sub-lists in slot order); counts[k]
+// holds sub-list k's length in every lane of the calling wavefront's registers.
+__device__ __forceinline__ int64_t lim_list_entry(const LimArgs& A, int cnt_lane, int b) {
+  int k = 0;
+  for (; k < kSlots; ++k) {
+    const int c = __shfl(cnt_lane, k, 64);
+    if (b < c) break;
+    b -= c;
+  }
+  return A.list[k * A.list_cap + b];
+}
+
+// Sub-list lengths (lane k holds sub-list k's) and their total.
+__device__ __forceinline__ int lim_list_counts(const LimArgs& A, int* total) {
+  const int lane = threadIdx.x & 63;
+  const int c = lane < kSlots ? A.clk->ntr[lane].v : 0;
+  int t = c;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+  *total = t;
+  return c;
 }
 
 // ------------------------------------------------ subgrid ADER-WENO2 ----
@@ -441,7 +507,8 @@ __global__ void __launch_bounds__(64) lim_subgrid_kernel(LimArgs A) {
 
   const double dt = A.clk->dt;
   if (!(dt > 0.0)) return;
-  const int ntr = A.clk->ntroubled;
+  int ntr;
+  const int cnt = lim_list_counts(A, &ntr);
   const int64_t S = A.C * Ns;
   const double dxs = A.dx / Ns, dtdx = dt / dxs;
   const double t0 = A.clk->t;
@@ -457,7 +524,7 @@ __global__ void __launch_bounds__(64) lim_subgrid_kernel(LimArgs A) {
   double* red = red_all + (active ? pc : CPW) * 2;
 
   for (int b = blockIdx.x; b < ntr; b += gridDim.x) {
-    const int64_t i = A.list[b];
+    const int64_t i = lim_list_entry(A, cnt, b);
     const int64_t j0 = i * Ns;                     // first subcell of the cell
     __syncthreads();
     for (int e = lane; e < NV * M; e += 64) {
@@ -580,12 +647,13 @@ __global__ void __launch_bounds__(64) lim_subgrid0_kernel(LimArgs A) {
   __shared__ double F[(Ns + 1) * M];
   const double dt = A.clk->dt;
   if (!(dt > 0.0) || !A.clk->fallback) return;
-  const int ntr = A.clk->ntroubled;
+  int ntr;
+  const int cnt = lim_list_counts(A, &ntr);
   const int64_t S = A.C * Ns;
   const double dtdx = dt / (A.dx / Ns);
   const int s = threadIdx.x;
   for (int b = blockIdx.x; b < ntr; b += gridDim.x) {
-    const int64_t i = A.list[b];
+    const int64_t i = lim_list_entry(A, cnt, b);
     const int64_t j0 = i * Ns;
     __syncthreads();
     if (s <= Ns) {
@@ -624,7 +692,9 @@ __global__ void __launch_bounds__(256) lim_finish_kernel(LimArgs A) {
   const double dt = clk->dt;
   const PdeParams pp = A.pp;
   if (blockIdx.x == 0 && threadIdx.x == 0 && dt > 0.0) {
-    clk->total_troubled += (unsigned long long)clk->ntroubled;
+    int ntr = 0;
+    for (int k = 0; k < kSlots; ++k) ntr += clk->ntr[k].v;
+    clk->total_troubled += (unsigned long long)ntr;
     if (clk->fallback) clk->total_fallback += 1;
   }
   double uc[n][M];
@@ -758,15 +828,18 @@ static hipError_t launch_lim_step_n(const LimArgs& A, hipStream_t st) {
   const int64_t C = A.C;
   const int64_t pc = (int64_t)kWaves * (64 / (N + 1));
   const unsigned cb = (unsigned)((C + 255) / 256);
-  const unsigned kb = (unsigned)((C + kLimCandThreads - 1) / kLimCandThreads);
+  const int64_t kc = (int64_t)kLimCandWaves * (64 / (N + 1));
+  const unsigned kb = (unsigned)((C + kc - 1) / kc);
+  LimArgs B = A;
+  B.list_cap = ((int64_t)kb + kSlots - 1) / kSlots * kc;   // cells of the workgroups of one sub-list
   const unsigned pb = (unsigned)((C + 2 + pc - 1) / pc);
   const unsigned sb = (unsigned)(C < kLimSubgridBlocks ? C : kLimSubgridBlocks);
-  hipLaunchKernelGGL(lim_clock_kernel, dim3(1), dim3(64), 0, st, A);
-  hipLaunchKernelGGL((lim_pred_kernel<N, kWaves>), dim3(pb), dim3(kWaves * 64), 0, st, A);
-  hipLaunchKernelGGL((lim_cand_kernel<N>), dim3(kb), dim3(kLimCandThreads), 0, st, A);
-  hipLaunchKernelGGL((lim_subgrid_kernel<N>), dim3(sb), dim3(64), 0, st, A);
-  hipLaunchKernelGGL((lim_subgrid0_kernel<N>), dim3(sb), dim3(64), 0, st, A);
-  hipLaunchKernelGGL((lim_finish_kernel<N>), dim3(cb), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(lim_clock_kernel, dim3(1), dim3(64), 0, st, B);
+  hipLaunchKernelGGL((lim_pred_kernel<N, kWaves>), dim3(pb), dim3(kWaves * 64), 0, st, B);
+  hipLaunchKernelGGL((lim_cand_kernel<N>), dim3(kb), dim3(kLimCandWaves * 64), 0, st, B);
+  hipLaunchKernelGGL((lim_subgrid_kernel<N>), dim3(sb), dim3(64), 0, st, B);
+  hipLaunchKernelGGL((lim_subgrid0_kernel<N>), dim3(sb), dim3(64), 0, st, B);
+  hipLaunchKernelGGL((lim_finish_kernel<N>), dim3(cb), dim3(256), 0, st, B);
   return hipGetLastError();
 }
 
