@@ -8,7 +8,8 @@
  * candidate is checked in the subcell representation v = P u of N_s = 2N+1
  * subcells (Sec. 1.4) by the physical and numerical admissibility detectors
  * (Sec. 1.6); every troubled cell is recomputed by the ADER-WENO2
- * finite-volume scheme (Sec. 1.3) on its subgrid and returns to the DG
+ * finite-volume scheme (Sec. 1.3; WENO of degree 1 in the paper's
+ * ADER-WENO(N+1) naming) on its subgrid and returns to the DG
  * representation by u = R v, R the least-squares inverse of P (Sec. 1.4).
  * The PDE is Sec. 2, eq. system_of_equations in 1-D: U = (rho, rho u, E).
  *
@@ -18,7 +19,7 @@
  *   - faces between a limited and an unlimited cell carry one flux, the
  *     subgrid scheme's: the unlimited cell's update takes it in place of its
  *     DG flux;
- *   - if the ADER-WENO2 subgrid step leaves the admissible set in any troubled
+ *   - if the ADER-WENO subgrid step leaves the admissible set in any troubled
  *     cell, the subgrid step of that time step is redone at first order
  *     (Rusanov finite volumes), for every troubled cell;
  *   - a limited cell's u = m + theta (R v - m), m the mean of v, theta the
@@ -73,6 +74,10 @@ typedef struct {
                               Riemann tests of Sec. 2.2 run on a 2-D mesh) */
   int32_t picard_max_iter; /* <= 0: 64 */
   double picard_tol;       /* <= 0: 1e-14 */
+  int32_t weno_degree;     /* WENO degree of the subgrid scheme: 1 (0 = default) is the
+                              paper's ADER-WENO2 (its ADER-WENO(N+1) naming), 2 is
+                              ADER-WENO3 */
+  int32_t reserved;        /* must be 0 */
 } aderdg_lim_config;
 
 typedef struct aderdg_lim_handle aderdg_lim_handle;
@@ -100,8 +105,8 @@ int aderdg_lim_project(aderdg_lim_handle* h, const double* u, double* v);
  * (nested Picard predictor, Rusanov fluxes; ghost cells as the boundary
  * condition says); PAD (rho > 0, p > 0 of the candidate's subcell averages
  * and nodes) and NAD (eq. nad_ineq on the subcell averages) per cell; the
- * ADER-WENO2 subgrid step (with LST-DG predictor of degree 2, CFL-compatible
- * since N_s = 2N+1) for the troubled cells; u = R v in them and the flux
+ * ADER-WENO subgrid step (WENO and LST-DG predictor of degree weno_degree,
+ * CFL-compatible since N_s = 2N+1) for the troubled cells; u = R v in them and the flux
  * exchange at their faces.
  *   u         device state, updated in place.
  *   v         device subcell averages, in/out: aderdg_lim_project(u) before

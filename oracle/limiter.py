@@ -13,8 +13,8 @@ criteria), in one space dimension:
            delta = max(delta_0, eps_0 (max - min)), delta_0 = 1e-4,
            eps_0 = 1e-3 (Sec. 1.6);
   * a troubled cell is recomputed by the finite-volume ADER-WENO scheme
-    (Sec. 1.3) on its subgrid of N_s subcells, from v^n = P u^n, with the DG
-    step's dt (with N_s = 2N+1 it is the finite-volume CFL step of the
+    (Sec. 1.3, WENO of degree nw) on its subgrid of N_s subcells, from
+    v^n = P u^n, with the DG step's dt (with N_s = 2N+1 it is the finite-volume CFL step of the
     subgrid, Sec. 1.5), and returns to the DG representation by u = R v,
     R the pseudo-inverse of P (Sec. 1.4: R P = 1);
   * conservation at the faces between a troubled and an admissible cell: the
@@ -28,8 +28,10 @@ sign change), so the Riemann problem at the boundary face has equal states.
 The scheme is evaluated on a padded periodic mesh whose ghost cells are
 refreshed every step; ghost results are discarded.
 
-Limiter readings (the paper names ADER-WENO2 as the limiter of its Riemann
-tests): WENO degree 2 on the subgrid; when that step leaves the admissible
+Limiter readings: the paper names ADER-WENO2 as the limiter of its Riemann
+tests, and its ADER-WENO(N+1) naming (the WENO timing tables of Sec. 3) makes
+that the reconstruction of degree 1 (nw = 1, the default); nw = 2 gives
+ADER-WENO3.  When the subgrid step leaves the admissible
 set in a troubled cell, the subgrid step is redone at first order (degree 0);
 a limited cell's polynomial R v is scaled toward its mean when its subcell
 averages would leave the admissible set (admissible_reconstruction).  The
@@ -133,7 +135,7 @@ def subcell_averages(ops, u):
     return np.einsum("sk,ckr->csr", ops.P, u)
 
 
-def limited_step(ops, pde, u, t, dt, dx, x0, bc="periodic", nw=2, v=None, tol=1e-14, max_iter=64):
+def limited_step(ops, pde, u, t, dt, dx, x0, bc="periodic", nw=1, v=None, tol=1e-14, max_iter=64):
     """One ADER-DG step with a posteriori subcell ADER-WENO limiting.
 
     v [C, N_s, M] are the subcell averages at the step's start: P u for a cell
@@ -185,7 +187,7 @@ def limited_step(ops, pde, u, t, dt, dx, x0, bc="periodic", nw=2, v=None, tol=1e
     return u_new, bad, v_new
 
 
-def limited_run(ops, pde, u, x0, x1, cfl=0.4, t_end=np.inf, nsteps=None, bc="periodic", nw=2, dims=1):
+def limited_run(ops, pde, u, x0, x1, cfl=0.4, t_end=np.inf, nsteps=None, bc="periodic", nw=1, dims=1):
     """Limited ADER-DG steps to t_end (or nsteps).  The step is the CFL
     condition of Sec. 1.5, dt = CFL / d / (2N+1) * h / |lambda_max|; dims
     gives d: the Riemann tests of Sec. 2.2 run on a two-dimensional mesh,

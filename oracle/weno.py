@@ -7,8 +7,10 @@ eq. weno_reconstr) and is then used as the predictor's initial data
 constants are given, so this module is a reading (parity unpinned beyond
 its mathematical pins):
 
-  * degree N (even), three stencils of N+1 cells around cell i:
-        left  {i-N .. i},  central {i-N/2 .. i+N/2},  right {i .. i+N}
+  * degree N even: three stencils of N+1 cells around cell i,
+        left  {i-N .. i},  central {i-N/2 .. i+N/2},  right {i .. i+N};
+    degree 1 (the second-order ADER-WENO2 of the paper's ADER-WENO(N+1)
+    naming): the two stencils {i-1, i} and {i, i+1}, both sided;
   * on each stencil the unique degree-N polynomial p_s whose averages over
     the stencil cells equal the given averages (reference coordinate xi of
     cell i, cell i+o spans [o, o+1]);
@@ -30,10 +32,19 @@ POWER = 8
 
 
 def stencil_offsets(N):
+    if N == 1:
+        return [[-1, 0], [0, 1]]
     if N % 2:
-        raise ValueError("WENO reading needs an even degree N")
+        raise ValueError("WENO reading needs degree 1 or an even degree N")
     h = N // 2
     return [list(range(-N, 1)), list(range(-h, h + 1)), list(range(0, N + 1))]
+
+
+def linear_weights(N):
+    """lambda_s of the stencils of stencil_offsets(N), in the same order."""
+    if N == 1:
+        return np.array([LAMBDA_SIDED, LAMBDA_SIDED])
+    return np.array([LAMBDA_SIDED, LAMBDA_CENTRAL, LAMBDA_SIDED])
 
 
 def _monomial_cell_average(o, m):
@@ -44,7 +55,7 @@ def _monomial_cell_average(o, m):
 def stencil_polynomials(v, N):
     """Monomial coefficients (in xi - 1/2) of every stencil polynomial.
 
-    v: [C, M] cell averages (periodic).  Returns coeff [3, C, N+1, M].
+    v: [C, M] cell averages (periodic).  Returns coeff [S, C, N+1, M], S stencils.
     """
     out = []
     for offs in stencil_offsets(N):
@@ -56,7 +67,7 @@ def stencil_polynomials(v, N):
 
 
 def oscillation_indicators(coeff, N):
-    """sigma_s = sum_alpha int_0^1 (p^(alpha))^2 for every stencil: [3, C, M]."""
+    """sigma_s = sum_alpha int_0^1 (p^(alpha))^2 for every stencil: [S, C, M]."""
     xq, wq = gauss_legendre_01(N + 2)
     sig = np.zeros(coeff.shape[:2] + coeff.shape[3:])
     for alpha in range(1, N + 1):
@@ -70,8 +81,8 @@ def oscillation_indicators(coeff, N):
     return sig
 
 
-def weights(sig):
-    lam = np.array([LAMBDA_SIDED, LAMBDA_CENTRAL, LAMBDA_SIDED])[:, None, None]
+def weights(sig, N=None):
+    lam = (linear_weights(N) if N is not None else linear_weights(2 if sig.shape[0] == 3 else 1))[:, None, None]
     wt = lam / (sig + EPSILON) ** POWER
     return wt / wt.sum(axis=0, keepdims=True)
 
@@ -80,7 +91,7 @@ def reconstruct(v, ops):
     """Nodal values w^[c, k, r] of the WENO polynomial at the GL nodes of ops."""
     N = ops.N
     coeff = stencil_polynomials(v, N)
-    omega = weights(oscillation_indicators(coeff, N))
+    omega = weights(oscillation_indicators(coeff, N), N)
     Vn = np.stack([(ops.xi - 0.5) ** m for m in range(N + 1)], axis=1)   # [n, N+1]
     nodal = np.einsum("km,scmr->sckr", Vn, coeff)
     return np.einsum("scr,sckr->ckr", omega, nodal)

@@ -78,7 +78,7 @@ class LimConfig(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("bc", ctypes.c_int32), ("ncells", ctypes.c_int64),
                 ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("dims", ctypes.c_int32), ("picard_max_iter", ctypes.c_int32),
-                ("picard_tol", ctypes.c_double)]
+                ("picard_tol", ctypes.c_double), ("weno_degree", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class AderdgError(RuntimeError):
@@ -353,8 +353,8 @@ def aderdg3d_free(h):
 
 # ------------------------------------------------------------- limited 1-D ----
 def lim_config(N, ncells, bc=LIM_TRANSMISSIVE, x0=0.0, x1=1.0, gamma=1.4, cfl=0.4, dims=1,
-               picard_tol=0.0, picard_max_iter=0):
-    return LimConfig(N, bc, ncells, x0, x1, gamma, cfl, dims, picard_max_iter, picard_tol)
+               picard_tol=0.0, picard_max_iter=0, weno_degree=1):
+    return LimConfig(N, bc, ncells, x0, x1, gamma, cfl, dims, picard_max_iter, picard_tol, weno_degree, 0)
 
 
 def aderdg_lim_init(cfg, stream=None):

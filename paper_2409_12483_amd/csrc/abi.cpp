@@ -72,7 +72,7 @@ int ensure_tables(int device) {
   if (g_tables_devices.count(device)) return ADERDG_OK;
   DevOps* ops = g_host_ops;
   DevOpsF* opsf = g_host_opsf;
-  static DevWeno weno[2];
+  static DevWeno weno[3];   // WENO degree 2, 4 (finite-volume step) and 1 (limiter subgrid)
   std::memset(g_host_ops, 0, sizeof(g_host_ops));
   std::memset(g_host_opsf, 0, sizeof(g_host_opsf));
   std::memset(weno, 0, sizeof(weno));
@@ -97,10 +97,10 @@ int ensure_tables(int device) {
     for (int s = 0; s < t.Ns; ++s)
       for (int k = 0; k < n; ++k) ops[N].P[s][k] = t.P[s][k];
   }
-  for (int wi = 0; wi < 2; ++wi) {
+  for (int wi = 0; wi < 3; ++wi) {
     WenoTables w;
-    if (!build_weno_tables(2 * (wi + 1), w)) return fail(ADERDG_E_DEVICE, "WENO table construction failed");
-    for (int s = 0; s < 3; ++s)
+    if (!build_weno_tables(wi < 2 ? 2 * (wi + 1) : 1, w)) return fail(ADERDG_E_DEVICE, "WENO table construction failed");
+    for (int s = 0; s < w.nstencils; ++s)
       for (int i = 0; i < w.n; ++i)
         for (int j = 0; j < w.n; ++j) {
           weno[wi].R[s][i][j] = w.R[s][i][j];
@@ -118,7 +118,7 @@ int ensure_tables(int device) {
       for (int k = 0; k <= N; ++k)
         for (int s = 0; s < t.Ns; ++s) lim[N].R[k][s] = t.R[k][s];
     }
-    e = upload_lim_tables(lim);
+    e = upload_lim_tables(lim, &weno[2]);
     if (e != hipSuccess) return fail_hip(e, "upload of limiter tables");
   }
   e = upload_tables_2d(ops, opsf);
@@ -1018,6 +1018,9 @@ int aderdg_lim_init(const aderdg_lim_config* cfg, void* hip_stream, aderdg_lim_h
   if (!(c.gamma > 1.0) || !std::isfinite(c.gamma)) return fail(ADERDG_E_INVAL, "gamma must be > 1");
   if (!(c.cfl > 0.0 && c.cfl <= 1.0)) return fail(ADERDG_E_INVAL, "cfl must be in (0, 1]");
   if (c.dims < 1 || c.dims > 3) return fail(ADERDG_E_INVAL, "dims must be 1, 2 or 3");
+  if (c.weno_degree == 0) c.weno_degree = 1;
+  if (c.weno_degree != 1 && c.weno_degree != 2) return fail(ADERDG_E_INVAL, "weno_degree must be 1 or 2");
+  if (c.reserved != 0) return fail(ADERDG_E_INVAL, "reserved must be 0");
   if (!std::isfinite(c.picard_tol)) return fail(ADERDG_E_INVAL, "picard_tol must be finite");
   if (c.picard_tol <= 0.0) c.picard_tol = 1e-14;
   if (c.picard_max_iter <= 0) c.picard_max_iter = 64;
@@ -1048,6 +1051,7 @@ int aderdg_lim_init(const aderdg_lim_config* cfg, void* hip_stream, aderdg_lim_h
   A.cfl_d = c.cfl / (double)c.dims;
   A.tol = c.picard_tol;
   A.max_iter = c.picard_max_iter;
+  A.weno = c.weno_degree;
   A.pp = PdeParams{c.gamma, 0.0, 0.0, 0.0};
   double* d = (double*)h->scratch;
   A.vol = d;  d += C * n * M;

@@ -65,7 +65,8 @@ hipError_t noalloc_scratch(int device, void** out);
 struct DevLimR {
   double R[kDevMaxn][kDevMaxNs];
 };
-hipError_t upload_lim_tables(const DevLimR* r);
+// R per degree and the WENO tables of degree 1 (the ADER-WENO2 subgrid scheme)
+hipError_t upload_lim_tables(const DevLimR* r, const DevWeno* weno1);
 
 enum { kLimPeriodic = 0, kLimTransmissive = 1 };
 
@@ -91,6 +92,7 @@ struct LimArgs {
   int32_t N, bc;
   double x0, dx, cfl_d, tol;        // cfl_d = CFL / d
   int32_t max_iter, step;
+  int32_t weno, pad1;               // WENO degree of the subgrid scheme (1 or 2)
   PdeParams pp;
   double* u;                        // [C][n][3] caller's state
   double* v;                        // [C][Ns][3] caller's subcell averages

@@ -11,8 +11,9 @@
 //                 u* = u + volume - surface (in place), PAD and NAD on its
 //                 subcell averages, the list of troubled cells (one lane per
 //                 (cell, node))
-//   lim_subgrid   ADER-WENO2 step on the subgrid of every troubled cell, from
-//                 the stored subcell averages (one wavefront per cell)
+//   lim_subgrid   ADER-WENO step (WENO degree 1 or 2) on the subgrid of every
+//                 troubled cell, from the stored subcell averages (one
+//                 wavefront per cell)
 //   lim_subgrid0  first-order redo of those subgrid steps, only when one of
 //                 them left the admissible set
 //   lim_finish    u = R v in troubled cells (scaled toward the mean when
@@ -29,6 +30,7 @@
 namespace aderdg {
 
 __constant__ DevLimR c_limR[kDevMaxn];
+__constant__ DevWeno c_weno1;           // WENO of degree 1 (two one-sided stencils)
 
 constexpr int kLimM = 3;   // Euler: (rho, rho u, E)
 constexpr double kLimDelta0 = 1.0e-4, kLimEps0 = 1.0e-3;   // NAD tolerances (Sec. 1.6)
@@ -486,14 +488,17 @@ __device__ __forceinline__ int lim_list_counts(const LimArgs& A, int* total) {
   return c;
 }
 
-// ------------------------------------------------ subgrid ADER-WENO2 ----
+// ------------------------------------------------- subgrid ADER-WENO ----
 // One wavefront per troubled cell: its N_s subcells plus one on each side
-// are reconstructed (WENO degree 2 from the stored subcell averages, the
-// boundary condition applied on the subgrid), predicted (LST-DG, degree 2)
-// and updated; the fluxes through the cell's two faces are kept.
-template <int N>
+// are reconstructed (WENO of degree NW from the stored subcell averages, the
+// boundary condition applied on the subgrid; NW = 1 is the paper's
+// ADER-WENO2, NW = 2 ADER-WENO3), predicted (LST-DG of degree NW) and
+// updated; the fluxes through the cell's two faces are kept.
+template <int N, int NW>
 __global__ void __launch_bounds__(64) lim_subgrid_kernel(LimArgs A) {
-  constexpr int NW = 2, M = kLimM, Ns = 2 * N + 1;
+  constexpr int M = kLimM, Ns = 2 * N + 1;
+  constexpr int NS = NW == 1 ? 2 : 3;              // stencils
+  const DevWeno& WT = NW == 1 ? c_weno1 : c_weno[0];
   using G = Geo<NW, M, 1, true>;
   constexpr int n = G::n, CPW = G::CPW, PC = G::PC;
   constexpr int NV = PC + 2 * NW;
@@ -541,8 +546,9 @@ __global__ void __launch_bounds__(64) lim_subgrid_kernel(LimArgs A) {
       const int base = pc + NW;
       double wsum[M], acc[M];
 #pragma unroll
-      for (int s = 0; s < 3; ++s) {
-        const int off = s == 0 ? -NW : (s == 1 ? -NW / 2 : 0);
+      for (int s = 0; s < NS; ++s) {
+        const int off = NW == 1 ? s - 1 : (s == 0 ? -NW : (s == 1 ? -NW / 2 : 0));
+        const double lam = (NW != 1 && s == 1) ? 1.0e5 : 1.0;
 #pragma unroll
         for (int r = 0; r < M; ++r) {
           double v[n], d[n];
@@ -557,13 +563,13 @@ __global__ void __launch_bounds__(64) lim_subgrid_kernel(LimArgs A) {
           for (int q = 0; q < n; ++q) {
             double si = 0.0;
 #pragma unroll
-            for (int k = 0; k < n; ++k) si += c_weno[0].S[s][q][k] * d[k];
+            for (int k = 0; k < n; ++k) si += WT.S[s][q][k] * d[k];
             sig += d[q] * si;
-            val += c_weno[0].R[s][an][q] * v[q];
+            val += WT.R[s][an][q] * v[q];
           }
           const double e = sig + 1.0e-14;
           const double e2 = e * e, e4 = e2 * e2, e8 = e4 * e4;
-          const double om = (s == 1 ? 1.0e5 : 1.0) / e8;
+          const double om = lam / e8;
           wsum[r] = s == 0 ? om : wsum[r] + om;
           acc[r] = s == 0 ? om * val : acc[r] + om * val;
         }
@@ -837,7 +843,10 @@ static hipError_t launch_lim_step_n(const LimArgs& A, hipStream_t st) {
   hipLaunchKernelGGL(lim_clock_kernel, dim3(1), dim3(64), 0, st, B);
   hipLaunchKernelGGL((lim_pred_kernel<N, kWaves>), dim3(pb), dim3(kWaves * 64), 0, st, B);
   hipLaunchKernelGGL((lim_cand_kernel<N>), dim3(kb), dim3(kLimCandWaves * 64), 0, st, B);
-  hipLaunchKernelGGL((lim_subgrid_kernel<N>), dim3(sb), dim3(64), 0, st, B);
+  if (A.weno == 1)
+    hipLaunchKernelGGL((lim_subgrid_kernel<N, 1>), dim3(sb), dim3(64), 0, st, B);
+  else
+    hipLaunchKernelGGL((lim_subgrid_kernel<N, 2>), dim3(sb), dim3(64), 0, st, B);
   hipLaunchKernelGGL((lim_subgrid0_kernel<N>), dim3(sb), dim3(64), 0, st, B);
   hipLaunchKernelGGL((lim_finish_kernel<N>), dim3(cb), dim3(256), 0, st, B);
   return hipGetLastError();
@@ -888,8 +897,10 @@ hipError_t launch_lim_end(const LimClock* clk, double* t_user, double* dt_user, 
   return hipGetLastError();
 }
 
-hipError_t upload_lim_tables(const DevLimR* r) {
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_limR), r, sizeof(DevLimR) * kDevMaxn);
+hipError_t upload_lim_tables(const DevLimR* r, const DevWeno* weno1) {
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_limR), r, sizeof(DevLimR) * kDevMaxn);
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_weno1), weno1, sizeof(DevWeno));
 }
 
 }  // namespace aderdg

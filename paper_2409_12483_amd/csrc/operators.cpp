@@ -170,15 +170,22 @@ bool build_op_tables(int N, OpTables& o) {
 }
 
 bool build_weno_tables(int Nw, WenoTables& t) {
-  if (Nw < 2 || Nw > 8 || Nw % 2) return false;
+  if (Nw < 1 || Nw > 8 || (Nw > 1 && Nw % 2)) return false;
   t = WenoTables();
   const int n = Nw + 1;       // nodes of the reconstruction = stencil width
   t.Nw = Nw;
   t.n = n;
   t.width = n;
-  t.offset[0] = -Nw;
-  t.offset[1] = -Nw / 2;
-  t.offset[2] = 0;
+  if (Nw == 1) {              // the two one-sided stencils {i-1, i}, {i, i+1}
+    t.nstencils = 2;
+    t.offset[0] = -1;
+    t.offset[1] = 0;
+  } else {
+    t.nstencils = 3;
+    t.offset[0] = -Nw;
+    t.offset[1] = -Nw / 2;
+    t.offset[2] = 0;
+  }
   OpTables ops;
   if (!build_op_tables(Nw, ops)) return false;
   // monomials (xi - 1/2)^m; integral of (xi - 1/2)^p over [o, o+1]
@@ -194,7 +201,7 @@ bool build_weno_tables(int Nw, WenoTables& t) {
         for (int i = 0; i < a; ++i) { fm *= (m - i); fmm *= (mm - i); }
         G[m][mm] += fm * fmm * cell_int(0, (m - a) + (mm - a));
       }
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < t.nstencils; ++s) {
     double A[kMaxn][kMaxn], I[kMaxn][kMaxn] = {}, Ainv[kMaxn][kMaxn];
     for (int i = 0; i < n; ++i) {
       for (int m = 0; m < n; ++m) A[i][m] = cell_int(t.offset[s] + i, m);

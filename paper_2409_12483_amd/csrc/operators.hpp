@@ -30,10 +30,11 @@ struct OpTables {
   double R[kMaxn][kMaxNs] = {};      // subcell reconstruction: least-squares inverse of P
 };
 
-// WENO reconstruction of degree Nw (even) from Nw+1 cell averages per stencil,
-// three stencils: left {i-Nw..i}, central {i-Nw/2..i+Nw/2}, right {i..i+Nw}.
+// WENO reconstruction of degree Nw from Nw+1 cell averages per stencil: for
+// even Nw three stencils, left {i-Nw..i}, central {i-Nw/2..i+Nw/2}, right
+// {i..i+Nw}; for Nw = 1 the two one-sided stencils {i-1, i} and {i, i+1}.
 struct WenoTables {
-  int Nw = 0, n = 1, width = 1;
+  int Nw = 0, n = 1, width = 1, nstencils = 3;
   int offset[3] = {};                          // first stencil cell relative to i
   double R[3][kMaxn][kMaxn] = {};              // nodal value k = sum_i R[s][k][i] v_{offset+i}
   double S[3][kMaxn][kMaxn] = {};              // sigma_s = v^T S[s] v (oscillation indicator)

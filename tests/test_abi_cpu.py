@@ -272,6 +272,8 @@ def _init_lim(cfg):
     (lambda c: setattr(c, "cfl", 0.0), "cfl"),
     (lambda c: setattr(c, "dims", 4), "dims"),
     (lambda c: setattr(c, "picard_tol", float("inf")), "picard_tol"),
+    (lambda c: setattr(c, "weno_degree", 3), "weno_degree"),
+    (lambda c: setattr(c, "reserved", 1), "reserved"),
 ])
 def test_invalid_limiter_configs_are_rejected(mutate, needle):
     cfg = abi.lim_config(9, 50)

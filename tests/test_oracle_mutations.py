@@ -250,7 +250,7 @@ def _lim_pin_conservation():
     ops = basis.build_operators(N)
     u0 = W.riemann_nodal(10, N, 1)
     with np.errstate(all="ignore"):
-        u, _, info = limiter.limited_run(ops, P.Euler(), u0, 0.0, 1.0, cfl=0.4, nsteps=8, dims=2)
+        u, _, info = limiter.limited_run(ops, P.Euler(), u0, 0.0, 1.0, cfl=0.4, nsteps=16, dims=2)
     tot = lambda a: np.einsum("k,ckm->m", ops.w, a)
     return min(info["troubled"]) > 0 and np.abs(tot(u) - tot(u0)).max() <= 1e-13
 

@@ -20,7 +20,7 @@ def _poly_cell_averages(coeffs, C):
     return (np.polyval(P_int, e[1:]) - np.polyval(P_int, e[:-1])) * C
 
 
-@pytest.mark.parametrize("N", [2, 4])
+@pytest.mark.parametrize("N", [1, 2, 4])
 def test_weno_exact_for_polynomials(N):
     ops = basis.build_operators(N)
     C = 24
@@ -49,8 +49,9 @@ def test_weno_weights_are_convex_and_favour_smooth_stencil():
     assert w_hat.max() < 1.02 and w_hat.min() > 0.08
 
 
-def test_weno_mirror_symmetry():
-    ops = basis.build_operators(4)
+@pytest.mark.parametrize("N", [1, 4])
+def test_weno_mirror_symmetry(N):
+    ops = basis.build_operators(N)
     C = 30
     rng = np.random.default_rng(3)
     v = rng.uniform(0.5, 1.5, (C, 2))
@@ -69,6 +70,32 @@ def test_weno_order_on_smooth_data():
         errs.append(np.abs(w_hat[:, :, 0] - np.sin(2 * np.pi * W.cell_points(C, 5))).max())
     p = norms.order(errs[-2], errs[-1], 1 / Cs[-2], 1 / Cs[-1])
     assert p >= 4.5, (errs, p)
+
+
+def test_weno_degree_one_closed_forms():
+    """Degree 1 (ADER-WENO2): the stencil polynomials are the two one-sided
+    slopes, sigma_s = slope_s^2, the weights are (sigma + eps)^-8 normalised,
+    and the reconstruction keeps the cell average; at a kink it takes the
+    flatter side."""
+    ops = basis.build_operators(1)
+    rng = np.random.default_rng(7)
+    C = 12
+    v = rng.uniform(0.5, 1.5, (C, 1))
+    coeff = weno.stencil_polynomials(v, 1)
+    sl = v - np.roll(v, 1, axis=0)              # {i-1, i}
+    sr = np.roll(v, -1, axis=0) - v             # {i, i+1}
+    assert np.allclose(coeff[0, :, 1], sl, atol=1e-14) and np.allclose(coeff[1, :, 1], sr, atol=1e-14)
+    assert np.allclose(coeff[:, :, 0], v[None], atol=1e-14)        # value at the cell centre
+    sig = weno.oscillation_indicators(coeff, 1)
+    assert np.allclose(sig[0], sl ** 2, rtol=1e-13) and np.allclose(sig[1], sr ** 2, rtol=1e-13)
+    om = weno.weights(sig, 1)
+    a, b = (sl ** 2 + 1e-14) ** -8, (sr ** 2 + 1e-14) ** -8
+    assert np.allclose(om[0], a / (a + b), rtol=1e-12)
+    w_hat = weno.reconstruct(v, ops)
+    assert np.allclose(np.einsum("k,ckr->cr", ops.w, w_hat), v, atol=1e-14)
+    kink = np.array([0.0, 1.0, 2.0, 2.0, 2.0, 1.0, 0.0, 0.0])[:, None]
+    wk = weno.reconstruct(kink, ops)
+    assert np.allclose(wk[2], 2.0, atol=1e-10)                     # flat right side chosen at the kink
 
 
 def test_fv_constant_state_preserved():
