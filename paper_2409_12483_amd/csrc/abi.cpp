@@ -30,6 +30,7 @@
 #include "launch.hpp"
 #include "launch2d.hpp"
 #include "launch3d.hpp"
+#include "launch_lim.hpp"
 #include "operators.hpp"
 #include "rtc.hpp"
 

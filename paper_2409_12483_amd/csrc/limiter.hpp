@@ -25,6 +25,7 @@
 #include "device_common.hpp"
 #include "dg_step.hpp"
 #include "launch.hpp"
+#include "launch_lim.hpp"
 #include "predictor.hpp"
 
 namespace aderdg {
