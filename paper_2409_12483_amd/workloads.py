@@ -244,3 +244,20 @@ def riemann_array_nodal(ncells, N, test=1, period=64, gamma=1.4):
     (rl, ul, pl), (rr, ur, pr) = RIEMANN_TESTS[test]
     left = (np.arange(ncells) % period < period // 2)[:, None] & np.ones((1, N + 1), dtype=bool)
     return _euler_conserved(np.where(left, rl, rr), np.where(left, ul, ur), np.where(left, pl, pr), gamma)
+
+
+def euler2d_sine_averages(cx, cy, amp=0.5, kx=1, ky=1, velocity=(1.0, 1.0), pressure=1.0, gamma=1.4,
+                          npts=16, t=0.0):
+    """Cell averages v[Cx, Cy, 4] of the 2-D sine wave (conserved variables) at
+    time t of its translation, by an npts x npts Gauss-Legendre rule per cell
+    (the state is linear in rho, so the averages of rho u, rho v, E follow)."""
+    xs = cell_points(cx, npts)
+    ys = cell_points(cy, npts)
+    _, w = gl_points_01(npts)
+    X = xs[:, None, :, None]
+    Y = ys[None, :, None, :]
+    rho = euler2d_sine_wave_exact(X, Y, t, amp, kx, ky, velocity)
+    rbar = np.einsum("i,j,xyij->xy", w, w, np.broadcast_to(rho, (cx, cy, npts, npts)))
+    u, v = velocity
+    E = pressure / (gamma - 1.0) + 0.5 * rbar * (u * u + v * v)
+    return np.stack([rbar, rbar * u, rbar * v, E], axis=-1)

@@ -152,3 +152,59 @@ def test_planted_3d_mistake_breaks_a_pin(name, monkeypatch):
     MUTATIONS_3D[name](monkeypatch, ops)
     held = set(_pins_3d(ops))
     assert held != ALL_3D, f"{name}: every pin still holds"
+
+
+# 2-D ADER-WENO finite volumes: the tensor-polynomial exactness of the
+# reconstruction, the reduction to the 1-D scheme, and conservation
+
+
+def _pins_fv2d():
+    from oracle import fv, fv2d
+    from oracle import pde as P1
+    N = 2
+    ops = basis.build_operators(N)
+    ok = True
+    # reconstruction of x*y (degree 1 per direction, exact for degree 2)
+    Cx, Cy = 8, 8
+    e = np.linspace(0, 1, Cx + 1)
+    ax = (e[1:] ** 2 - e[:-1] ** 2) / 2 * Cx
+    v = (ax[:, None] * ax[None, :])[..., None]
+    w = fv2d.reconstruct2d(v, ops)
+    xs = W.cell_points(Cx, N + 1)
+    exact = xs[:, None, :, None] * xs[None, :, None, :]
+    ok &= np.abs(w[2:-2, 2:-2, :, :, 0] - exact[2:-2, 2:-2]).max() <= 1e-12
+    # x-only flow against the 1-D scheme
+    C, dt = 16, 0.004
+    x = (np.arange(C) + 0.5) / C
+    rho = 1 + 0.3 * np.sin(2 * np.pi * x)
+    v1 = np.stack([rho, 0.5 * rho, 1 / 0.4 + 0.125 * rho], -1)
+    v2 = np.zeros((C, 3, 4))
+    v2[..., 0], v2[..., 1], v2[..., 3] = rho[:, None], 0.5 * rho[:, None], v1[:, None, 2]
+    ref, _, _ = fv.fv_step(ops, P1.Euler(), v1, 0.0, dt, 1 / C, np.arange(C) / C)
+    got, _, _ = fv2d.fv2d_step(ops, dg2d.Euler2D(), v2, dt, 1 / C, 1 / 3)
+    ok &= np.abs(got[..., [0, 1, 3]] - ref[:, None, :]).max() <= 1e-13
+    # conservation on a 2-D wave
+    v0 = W.euler2d_sine_averages(6, 5)
+    vn, _, _ = fv2d.fv2d_step(ops, dg2d.Euler2D(), v0, 0.002, 1 / 6, 1 / 5)
+    ok &= np.abs(vn.sum(axis=(0, 1)) - v0.sum(axis=(0, 1))).max() <= 1e-12
+    return bool(ok)
+
+
+def test_unmutated_fv2d_oracle_passes_its_pins():
+    assert _pins_fv2d()
+
+
+def test_planted_fv2d_mistakes_break_a_pin(monkeypatch):
+    from oracle import fv2d
+    orig = fv2d.reconstruct2d
+
+    def x_only(v, ops):            # the y sweep forgotten: x reconstruction broadcast along y
+        from oracle import weno
+        wx = np.stack([weno.reconstruct(v[:, iy, :], ops) for iy in range(v.shape[1])], axis=1)
+        return np.repeat(wx[:, :, :, None, :], ops.n, axis=3)
+    monkeypatch.setattr(fv2d, "reconstruct2d", x_only)
+    assert not _pins_fv2d()
+    monkeypatch.setattr(fv2d, "reconstruct2d", orig)
+    orig_rx = fv2d.rusanov_x
+    monkeypatch.setattr(fv2d, "rusanov_x", lambda pde, qm, qp: orig_rx(pde, qp, qm))   # face states swapped
+    assert not _pins_fv2d()
