@@ -20,6 +20,8 @@
  *   u  [cells_x][cells_y][N+1 (x node)][N+1 (y node)][4]          fp64
  *   q  [cells_x][cells_y][N+1 (time)][N+1 (x)][N+1 (y)][4]        fp64, or
  *                                         fp32 in ADERDG_FP32_PREDICTOR mode
+ *   v  [cells_x][cells_y][4]                                       fp64 cell averages
+ *                                         (the state of the ADER-WENO scheme)
  * Cell (ix, iy) spans [x0 + ix dx, x0 + (ix+1) dx] x [y0 + iy dy, ...];
  * nodes are the Gauss-Legendre points of [0, 1] in each direction.
  */
@@ -45,7 +47,9 @@ typedef struct {
   double fixed_dt;         /* > 0: use this dt instead of the CFL rule; 0: CFL rule */
   double picard_tol;       /* <= 0: 1e-14 (FP64) or 1e-6 (FP32 predictor) */
   int32_t picard_max_iter; /* <= 0: 64 */
-  int32_t pad;
+  int32_t scheme;          /* ADERDG_SCHEME_DG (0), or ADERDG_SCHEME_FV: ADER-WENO finite
+                              volumes (Sec. 1.3 with d = 2), N = the WENO degree (1: the
+                              paper's ADER-WENO2, 2: ADER-WENO3), FP64 only */
 } aderdg2d_config;
 
 typedef struct aderdg2d_handle aderdg2d_handle;
@@ -60,7 +64,7 @@ typedef struct aderdg2d_handle aderdg2d_handle;
 int aderdg2d_init(const aderdg2d_config* cfg, void* hip_stream, aderdg2d_handle** out);
 
 /*
- * aderdg2d_predict -- LST-DG predictor of every cell (Sec. 1.1, the nested
+ * aderdg2d_predict -- (DG scheme) LST-DG predictor of every cell (Sec. 1.1, the nested
  * Picard iteration with the factors kappa~ (x) k~ (x) I and
  * kappa~ (x) I (x) k~; Algorithm 1 with the k_ksi and k_eta kernels of
  * Table 2).  u: device state (layout above); t, dt > 0: start and length of
@@ -84,6 +88,16 @@ int aderdg2d_predict(aderdg2d_handle* h, const double* u, double t, double dt, v
  *   status  device int32 [1], out: 0, or the most severe of ADERDG_E_NOCONV /
  *           ADERDG_E_NONPHYS met during the call.
  * Two kernel launches per step; no host synchronisation.
+ * With scheme ADERDG_SCHEME_FV the state is v (cell averages) and a step is
+ * the ADER-WENO scheme of Sec. 1.3 with d = 2: WENO reconstruction of degree N
+ * of the averages, dimension by dimension (along x for every row of cells,
+ * giving the averages over y at the x nodes, then along y at every x node;
+ * degree 1: stencils {i-1, i}, {i, i+1}; degree 2: {i-2..i}, {i-1..i+1},
+ * {i..i+2}; weights lambda_s / (sigma_s + 1e-14)^8, lambda = 1e5 for the
+ * central stencil, else 1), the predictor above from those nodal values, and
+ * v -= sum over the four faces of the time- and face-integrated Rusanov
+ * fluxes; dt = CFL / 2 min(dx / max(|u|+c), dy / max(|v|+c)) over the
+ * averages.  Three launches per step.
  */
 int aderdg2d_step(aderdg2d_handle* h, double* u, double* t, const double* t_end, double* dt,
                   int32_t* status, int32_t nsteps);

@@ -61,7 +61,7 @@ class Config2D(ctypes.Structure):
                 ("y0", ctypes.c_double), ("y1", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_double),
                 ("picard_tol", ctypes.c_double), ("picard_max_iter", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32)]
 
 
 class Config3D(ctypes.Structure):
@@ -284,10 +284,10 @@ def aderdg_last_error():
 
 # ------------------------------------------------------------------ 2-D ----
 def config2d(N, cells_x, cells_y, extent=(0.0, 1.0, 0.0, 1.0), gamma=1.4, cfl=0.4, fixed_dt=0.0,
-             precision=FP64, picard_tol=0.0, picard_max_iter=0):
+             precision=FP64, picard_tol=0.0, picard_max_iter=0, scheme=SCHEME_DG):
     x0, x1, y0, y1 = extent
     return Config2D(N, precision, cells_x, cells_y, x0, x1, y0, y1, gamma, cfl, fixed_dt,
-                    picard_tol, picard_max_iter, 0)
+                    picard_tol, picard_max_iter, scheme)
 
 
 def aderdg2d_init(cfg, stream=None):

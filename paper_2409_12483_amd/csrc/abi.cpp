@@ -122,7 +122,7 @@ int ensure_tables(int device) {
     e = upload_lim_tables(lim, &weno[2]);
     if (e != hipSuccess) return fail_hip(e, "upload of limiter tables");
   }
-  e = upload_tables_2d(ops, opsf);
+  e = upload_tables_2d(ops, opsf, &weno[2], &weno[0]);
   if (e != hipSuccess) return fail_hip(e, "upload of 2-D operator tables");
   e = upload_tables_3d(ops, opsf);
   if (e != hipSuccess) return fail_hip(e, "upload of 3-D operator tables");
@@ -698,6 +698,7 @@ struct aderdg2d_handle {
   int64_t cells = 0;
   double* part = nullptr;
   void* tr = nullptr;
+  double* w = nullptr;      // ADER-WENO: nodal WENO values of the averages
   Clock2D* clk = nullptr;
 };
 
@@ -706,6 +707,7 @@ namespace {
 void release2d(aderdg2d_handle* h) {
   if (h->part) hipFree(h->part);
   if (h->tr) hipFree(h->tr);
+  if (h->w) hipFree(h->w);
   if (h->clk) hipFree(h->clk);
   delete h;
 }
@@ -725,6 +727,7 @@ Args2D args2d(const aderdg2d_handle* h) {
   A.clk = h->clk;
   A.part = h->part;
   A.tr = h->tr;
+  A.scheme = c.scheme;
   return A;
 }
 
@@ -739,6 +742,9 @@ int aderdg2d_init(const aderdg2d_config* cfg, void* hip_stream, aderdg2d_handle*
   if (c.N < 1 || c.N > 9) return fail(ADERDG_E_INVAL, "N must be in 1..9");
   if (c.precision != ADERDG_FP64 && c.precision != ADERDG_FP32_PREDICTOR)
     return fail(ADERDG_E_INVAL, "unknown precision");
+  if (c.scheme != ADERDG_SCHEME_DG && c.scheme != ADERDG_SCHEME_FV) return fail(ADERDG_E_INVAL, "unknown scheme");
+  if (c.scheme == ADERDG_SCHEME_FV && (c.N > 2 || c.precision != ADERDG_FP64))
+    return fail(ADERDG_E_INVAL, "2-D ADER-WENO: N (the WENO degree) must be 1 or 2, precision FP64");
   if (c.cells_x < 1 || c.cells_y < 1 || c.cells_x > INT32_MAX / c.cells_y)
     return fail(ADERDG_E_INVAL, "cells_x, cells_y must be >= 1 with a product below 2^31");
   if (!(c.x1 > c.x0) || !(c.y1 > c.y0) || !std::isfinite(c.x1 - c.x0) || !std::isfinite(c.y1 - c.y0))
@@ -759,7 +765,9 @@ int aderdg2d_init(const aderdg2d_config* cfg, void* hip_stream, aderdg2d_handle*
   h->cfg = c;
   h->cells = c.cells_x * c.cells_y;
   const int64_t L = (int64_t)(c.N + 1) * (c.N + 1);
-  e = hipMalloc((void**)&h->part, sizeof(double) * h->cells * L * 4);
+  const bool fv = c.scheme == ADERDG_SCHEME_FV;
+  // DG: u + volume terms; ADER-WENO: the nodal WENO values (the predictor's initial data)
+  e = hipMalloc(fv ? (void**)&h->w : (void**)&h->part, sizeof(double) * h->cells * L * 4);
   const size_t tr_elem = c.precision == ADERDG_FP64 ? sizeof(double) : sizeof(float);
   if (e == hipSuccess) e = hipMalloc(&h->tr, tr_elem * h->cells * 4 * L * 4);
   if (e != hipSuccess) { release2d(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
@@ -775,6 +783,7 @@ int aderdg2d_predict(aderdg2d_handle* h, const double* u, double t, double dt, v
                      int32_t* iters_out) {
   g_last_error.clear();
   if (!h || !u || !q_out) return fail(ADERDG_E_INVAL, "null argument");
+  if (h->cfg.scheme != ADERDG_SCHEME_DG) return fail(ADERDG_E_INVAL, "predictor-only calls serve the DG scheme");
   if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return fail(ADERDG_E_INVAL, "dt must be > 0 and finite");
   Args2D A = args2d(h);
   A.mode = k2dPredict;
@@ -802,6 +811,21 @@ int aderdg2d_step(aderdg2d_handle* h, double* u, double* t, const double* t_end,
   const int cpb2 = cells_per_block_corr2d(N);
   const int64_t blocks = (h->cells + cpb - 1) / cpb, blocks2 = (h->cells + cpb2 - 1) / cpb2;
   hipError_t e = launch_clock2d_begin(h->clk, t, h->stream);
+  if (h->cfg.scheme == ADERDG_SCHEME_FV) {
+    // ADER-WENO: WENO reconstruction of the averages -> predictor from the
+    // nodal WENO values -> update of the averages from the face traces
+    if (e == hipSuccess && h->cfg.fixed_dt <= 0.0) e = launch_fv2d_lambda(A, h->stream);
+    Args2D P = A;
+    P.u = h->w;
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+      A.step = P.step = s;
+      e = launch_weno2d(N, A, h->w, h->stream);
+      if (e == hipSuccess) e = launch_pred2d(N, h->cfg.precision, P, blocks, h->stream);
+      if (e == hipSuccess) e = launch_fv2d_corr(N, A, h->stream);
+    }
+    if (e == hipSuccess) e = launch_clock2d_end(h->clk, t, dt, status, nsteps & 1, h->stream);
+    return e == hipSuccess ? ADERDG_OK : fail_hip(e, "2-D ADER-WENO step launch");
+  }
   if (e == hipSuccess && h->cfg.fixed_dt <= 0.0) e = launch_lambda2d(N, A, blocks2, h->stream);
   for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
     A.step = s;

@@ -35,6 +35,7 @@ namespace aderdg {
 
 __constant__ DevOps c2_ops[kDevMaxn];
 __constant__ DevOpsF c2_opsf[kDevMaxn];
+__constant__ DevWeno c2_weno[2];   // WENO of degree 1 (two one-sided stencils) and 2 (three stencils)
 
 // ------------------------------------------------------------- model ----
 // Sec. 2, eq. system_of_equations with two space dimensions:
@@ -140,7 +141,8 @@ __device__ __forceinline__ double step_dt2d(const Args2D& A, double& t, double* 
       if (l == 0) bcast[threadIdx.x >> 5] = v;
     }
     __syncthreads();
-    dt = A.cfl / (2.0 * (2 * N + 1)) * fmin(A.dx / bcast[0], A.dy / bcast[1]);
+    // Sec. 1.5 with d = 2; the finite-volume scheme has no 1/(2N+1) factor
+    dt = A.cfl / (2.0 * (A.scheme ? 1 : 2 * N + 1)) * fmin(A.dx / bcast[0], A.dy / bcast[1]);
   }
   const double rem = A.t_end[0] - t;
   if (dt > rem) dt = rem;
@@ -496,9 +498,11 @@ pred2d_kernel(Args2D A) {
 #pragma unroll
       for (int r = 0; r < M; ++r) vol[r] = fma(dy_, Vc[(L + ti * n + l) * M + r], vol[r]);
     }
-    double* pc = A.part + (cell * L + node) * M;
+    if (A.scheme == 0) {                     // the finite-volume update needs only the traces
+      double* pc = A.part + (cell * L + node) * M;
 #pragma unroll
-    for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
+      for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
+    }
   }
 
   // sweeps and status
@@ -716,6 +720,169 @@ __global__ void clock2d_end_kernel(const Clock2D* clk, double* t_user, double* d
 }
 
 // -------------------------------------------------------------- dispatch ----
+// ------------------------------------------------- ADER-WENO (scheme 1) ----
+// Dimension-by-dimension WENO reconstruction: the 1-D reconstruction along x
+// of every row of cell averages gives, at the x nodes, the averages over y of
+// the solution; the same reconstruction along y of those gives the nodal
+// values.  One thread per (cell, x node k): the x reconstruction at node k of
+// the 2 NW + 1 cells of its column, then the y reconstruction of those at the
+// n y nodes.  The oscillation indicators are evaluated on differences from
+// the centre value (the quadratic forms vanish on constants).
+template <int NW>
+__device__ __forceinline__ void weno1d(const double (&v)[2 * NW + 1], const DevWeno& T, double* out,
+                                       int k_only) {
+  constexpr int n = NW + 1, NS = NW == 1 ? 2 : 3;
+  double wsum = 0.0, acc[n];
+#pragma unroll
+  for (int k = 0; k < n; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int off = NW == 1 ? s : (s == 0 ? 0 : (s == 1 ? NW / 2 : NW));   // first cell, 0 = i - NW
+    double d[n];
+#pragma unroll
+    for (int q = 0; q < n; ++q) d[q] = v[off + q] - v[NW];
+    double sig = 0.0;
+#pragma unroll
+    for (int q = 0; q < n; ++q) {
+      double si = 0.0;
+#pragma unroll
+      for (int m = 0; m < n; ++m) si += T.S[s][q][m] * d[m];
+      sig += d[q] * si;
+    }
+    const double e = sig + 1.0e-14;
+    const double e2 = e * e, e4 = e2 * e2, e8 = e4 * e4;
+    const double om = ((NW != 1 && s == 1) ? 1.0e5 : 1.0) / e8;
+    wsum += om;
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+      if (k_only >= 0 && k != k_only) continue;
+      double val = 0.0;
+#pragma unroll
+      for (int q = 0; q < n; ++q) val += T.R[s][k][q] * v[off + q];
+      acc[k] += om * val;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < n; ++k) out[k] = acc[k] / wsum;
+}
+
+template <int NW>
+__global__ void __launch_bounds__(kFv2dThreads) weno2d_kernel(Args2D A, double* w) {
+  constexpr int n = NW + 1, M = 4, S = 2 * NW + 1;
+  const DevWeno& T = c2_weno[NW - 1];
+  const int64_t ncells = A.cx * A.cy;
+  const int64_t g = (int64_t)blockIdx.x * kFv2dThreads + threadIdx.x;
+  if (g >= ncells * n) return;
+  const int64_t cell = g / n;
+  const int k = (int)(g - cell * n);
+  const int64_t ix = cell / A.cy, iy = cell - ix * A.cy;
+  double colv[S][M];            // x reconstruction at node k of the column cells iy - NW .. iy + NW
+  for (int dy = 0; dy < S; ++dy) {
+    int64_t jy = iy - NW + dy;
+    jy = (jy % A.cy + A.cy) % A.cy;
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      double row[S];
+#pragma unroll
+      for (int dx = 0; dx < S; ++dx) {
+        int64_t jx = ix - NW + dx;
+        jx = (jx % A.cx + A.cx) % A.cx;
+        row[dx] = A.u[(jx * A.cy + jy) * M + r];
+      }
+      double o[n];
+      weno1d<NW>(row, T, o, k);
+      colv[dy][r] = o[k];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    double col[S], o[n];
+#pragma unroll
+    for (int dy = 0; dy < S; ++dy) col[dy] = colv[dy][r];
+    weno1d<NW>(col, T, o, -1);
+#pragma unroll
+    for (int l = 0; l < n; ++l) w[((cell * n + k) * n + l) * M + r] = o[l];
+  }
+}
+
+// Finite-volume update of the averages (in place), one thread per cell:
+// v -= sum_k w_k (Gx(east, k) - Gx(west, k) + Gy(north, k) - Gy(south, k)),
+// G the time-integrated Rusanov flux of the face traces (each face evaluated
+// by both adjacent cells, identically); then the signal speed of the new
+// averages for the next step's dt.
+template <int N>
+__global__ void __launch_bounds__(kFv2dThreads) fv2d_corr_kernel(Args2D A) {
+  constexpr int n = N + 1, L = n * n, M = 4;
+  __shared__ double bcast[2];
+  __shared__ double part[2 * (kFv2dThreads / 64)];
+  double t;
+  const double dt = step_dt2d<N>(A, t, bcast, false);
+  if (!(dt > 0.0)) return;
+  const double dtdx = dt / A.dx, dtdy = dt / A.dy;
+  const int64_t ncells = A.cx * A.cy;
+  const int64_t c = (int64_t)blockIdx.x * kFv2dThreads + threadIdx.x;
+  double lx = 0.0, ly = 0.0;
+  bool bad = false;
+  if (c < ncells) {
+    const int64_t ix = c / A.cy, iy = c - ix * A.cy;
+    double F[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) F[r] = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      int64_t cm, cp;
+      if (f == 0) { cm = (ix == 0 ? A.cx - 1 : ix - 1) * A.cy + iy; cp = c; }
+      else if (f == 1) { cm = c; cp = (ix + 1 == A.cx ? 0 : ix + 1) * A.cy + iy; }
+      else if (f == 2) { cm = ix * A.cy + (iy == 0 ? A.cy - 1 : iy - 1); cp = c; }
+      else { cm = c; cp = ix * A.cy + (iy + 1 == A.cy ? 0 : iy + 1); }
+      const int fm = f < 2 ? 1 : 3, fp = f < 2 ? 0 : 2;
+      const double sc = f < 2 ? dtdx : dtdy;
+      const double sign = (f & 1) ? 1.0 : -1.0;      // east / north add, west / south subtract
+      for (int k = 0; k < n; ++k) {
+        double acc[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc[r] = 0.0;
+        for (int a = 0; a < n; ++a) {
+          double qm[M], qp[M], Gr[M];
+#pragma unroll
+          for (int r = 0; r < M; ++r) {
+            qm[r] = reinterpret_cast<const double*>(A.tr)[((cm * 4 + fm) * L + a * n + k) * M + r];
+            qp[r] = reinterpret_cast<const double*>(A.tr)[((cp * 4 + fp) * L + a * n + k) * M + r];
+          }
+          if (f < 2) rusanov2<0>(qm, qp, Gr, A.gamma);
+          else rusanov2<1>(qm, qp, Gr, A.gamma);
+          const double wa = c2_ops[N].w[a];
+#pragma unroll
+          for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
+        }
+        const double wk = c2_ops[N].w[k];
+#pragma unroll
+        for (int r = 0; r < M; ++r) F[r] = fma(sign * wk, acc[r], F[r]);
+      }
+    }
+    double vn[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      vn[r] = A.u[c * M + r] - F[r];
+      A.u[c * M + r] = vn[r];
+    }
+    bad = !Euler2::admissible(vn, A.gamma);
+    Euler2::speeds(vn, A.gamma, lx, ly);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0)
+    atomicMin(&A.clk->stat[(blockIdx.x + (threadIdx.x >> 6)) % kSlots].v, -5);
+  publish_lambda(*A.clk, (A.step + 1) % 3, lx, ly, part);
+}
+
+// Signal speeds of the initial averages into lambda buffer 0.
+__global__ void __launch_bounds__(kFv2dThreads) fv2d_lambda_kernel(Args2D A) {
+  __shared__ double part[2 * (kFv2dThreads / 64)];
+  const int64_t c = (int64_t)blockIdx.x * kFv2dThreads + threadIdx.x;
+  double lx = 0.0, ly = 0.0;
+  if (c < A.cx * A.cy) Euler2::speeds(A.u + c * 4, A.gamma, lx, ly);
+  publish_lambda(*A.clk, 0, lx, ly, part);
+}
+
 template <class TP>
 static hipError_t launch_pred2d_p(int N, const Args2D& A, int64_t blocks, hipStream_t st) {
   dim3 grid((unsigned)blocks);
@@ -795,10 +962,38 @@ hipError_t launch_clock2d_end(const Clock2D* clk, double* t_user, double* dt_use
   return hipGetLastError();
 }
 
-hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf) {
+hipError_t launch_weno2d(int NW, const Args2D& A, double* w, hipStream_t st) {
+  const int64_t work = A.cx * A.cy * (NW + 1);
+  dim3 grid((unsigned)((work + kFv2dThreads - 1) / kFv2dThreads)), block(kFv2dThreads);
+  if (NW == 1) hipLaunchKernelGGL((weno2d_kernel<1>), grid, block, 0, st, A, w);
+  else if (NW == 2) hipLaunchKernelGGL((weno2d_kernel<2>), grid, block, 0, st, A, w);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_fv2d_corr(int NW, const Args2D& A, hipStream_t st) {
+  dim3 grid((unsigned)((A.cx * A.cy + kFv2dThreads - 1) / kFv2dThreads)), block(kFv2dThreads);
+  if (NW == 1) hipLaunchKernelGGL((fv2d_corr_kernel<1>), grid, block, 0, st, A);
+  else if (NW == 2) hipLaunchKernelGGL((fv2d_corr_kernel<2>), grid, block, 0, st, A);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_fv2d_lambda(const Args2D& A, hipStream_t st) {
+  dim3 grid((unsigned)((A.cx * A.cy + kFv2dThreads - 1) / kFv2dThreads)), block(kFv2dThreads);
+  hipLaunchKernelGGL(fv2d_lambda_kernel, grid, block, 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno1,
+                            const DevWeno* weno2) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c2_ops), ops, sizeof(DevOps) * kDevMaxn);
   if (e != hipSuccess) return e;
-  return hipMemcpyToSymbol(HIP_SYMBOL(c2_opsf), opsf, sizeof(DevOpsF) * kDevMaxn);
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c2_opsf), opsf, sizeof(DevOpsF) * kDevMaxn);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c2_weno), weno1, sizeof(DevWeno));
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c2_weno), weno2, sizeof(DevWeno), sizeof(DevWeno));
 }
 
 }  // namespace aderdg

@@ -34,7 +34,7 @@ struct Args2D {
   int32_t max_iter;
   int32_t mode;            // k2dStep or k2dPredict
   int32_t step;            // step index within the call (clock parity / lambda buffer)
-  int32_t pad;
+  int32_t scheme;          // 0: ADER-DG; 1: ADER-WENO finite volumes (state = cell averages)
   double t, dt;            // predictor mode: given time and step
   Clock2D* clk;
   const double* t_end;     // device, one value
@@ -55,6 +55,16 @@ int cells_per_block_corr2d(int N);
 hipError_t launch_clock2d_begin(Clock2D* clk, const double* t_user, hipStream_t st);
 hipError_t launch_clock2d_end(const Clock2D* clk, double* t_user, double* dt_user,
                               int32_t* status_user, int parity, hipStream_t st);
-hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf);
+hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno1,
+                            const DevWeno* weno2);
+// ADER-WENO finite volumes (scheme 1; NW = reconstruction degree = predictor degree, 1 or 2):
+// nodal WENO values w [cells][n][n][4] of the averages v (A.u), the update of
+// the averages in place from the predictor's traces, the signal speed of the
+// start state.  Thread counts: kFv2dThreads per workgroup, one thread per
+// (cell, x node) in the reconstruction, per cell in the update and lambda.
+constexpr int kFv2dThreads = 256;
+hipError_t launch_weno2d(int NW, const Args2D& A, double* w, hipStream_t st);
+hipError_t launch_fv2d_corr(int NW, const Args2D& A, hipStream_t st);
+hipError_t launch_fv2d_lambda(const Args2D& A, hipStream_t st);
 
 }  // namespace aderdg
