@@ -502,13 +502,58 @@ def dg2d_entry(N, C, precision, steps, warmup):
                          "kernels": "predictor + corrector launches of each step (HIP events around whole steps)"}}
 
 
-def dg2d_time_to_solution(N, C, precision=0, chunk=128):
+class FV2Run(DG2Run):
+    """The same sine wave as cell averages, advanced by the 2-D ADER-WENO
+    scheme (WENO of degree N, dimension by dimension; LST-DG predictor of
+    degree N)."""
+
+    def __init__(self, N, C, precision=0, cfl=0.4):
+        import torch
+        from paper_2409_12483_amd import abi
+        from paper_2409_12483_amd import workloads as W
+        self.abi, self.torch = abi, torch
+        dev = torch.device("cuda:0")
+        self.N, self.C, self.cfl = N, C, cfl
+        self.u = torch.tensor(W.euler2d_sine_averages(C, C), device=dev)
+        self.t = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.te = torch.full((1,), 1.0e300, dtype=torch.float64, device=dev)
+        self.dt = torch.zeros_like(self.t)
+        self.st = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.stream = torch.cuda.current_stream()
+        self.h = abi.aderdg2d_init(abi.config2d(N, C, C, cfl=cfl, scheme=abi.SCHEME_FV),
+                                   stream=self.stream.cuda_stream)
+
+
+def fv2d_entry(N, C, steps, warmup):
+    """Throughput of the 2-D ADER-WENO step on C x C cells; the roofline counts
+    the predictor's work only (its sweeps, the 2-D DG predictor model)."""
+    r = FV2Run(N, C)
+    r.steps(warmup)
+    secs, sweeps = r.timed(steps)
+    status = int(r.st.item())
+    r.close()
+    cells = C * C
+    spc = sweeps / (cells * steps)
+    pred, _ = dg2d_flops_per_cell(N, spc)
+    total = pred * cells * steps
+    return {"N": N, "scheme": f"ADER-WENO{N + 1}", "cells": f"{C}x{C}", "cfl": 0.4, "status": status,
+            "value": round(steps * cells * 4 / secs, 1), "unit": "DoF-updates/s",
+            "ms_per_step": round(secs / steps * 1e3, 5), "sweeps_per_cell": round(spc, 3),
+            "roofline": {"bound": "alu", "achieved": round(total / secs * 1e-12, 3), "peak": PEAK_FP64_VALU,
+                         "unit": "TFLOP/s", "frac": round(total / secs * 1e-12 / PEAK_FP64_VALU, 4),
+                         "flops_per_step": int(round(total / steps)),
+                         "kernels": "WENO + predictor + update launches of each step (HIP events); "
+                                    "flops of the predictor only"}}
+
+
+def dg2d_time_to_solution(N, C, precision=0, chunk=128, run_cls=None):
     """The paper's 2-D timing problem (Sec. 3, Table 10: the sine wave on C^2 cells,
     t_final = 1): wall time of the whole run on the GPU, host loop included.
     eager: aderdg2d_step calls sized to reach t_final; graph: replays of a HIP
     graph holding one call of `chunk` steps (steps past t_final do nothing)."""
     import torch
-    r = DG2Run(N, C, precision)
+    run_cls = run_cls or DG2Run
+    r = run_cls(N, C, precision)
     r.te.fill_(1.0)
     _sync()
     t0 = time.perf_counter()
@@ -525,7 +570,7 @@ def dg2d_time_to_solution(N, C, precision=0, chunk=128):
     r.close()
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
-        g = DG2Run(N, C, precision)
+        g = run_cls(N, C, precision)
         g.te.fill_(1.0)
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph, stream=side):
@@ -546,6 +591,27 @@ def dg2d_time_to_solution(N, C, precision=0, chunk=128):
     return {"N": N, "cells": f"{C}^2", "gpu_wall_s": round(eager, 5), "gpu_wall_s_graph": round(graphed, 5),
             "graph_replays": replays, "graph_equals_eager": same, "steps_approx": int(round(1.0 / dt)),
             "status": st}
+
+
+# The paper's CPU seconds for its 2-D ADER-WENO timing runs (Sec. 3, the
+# finite-volume table: T_JIT, sine wave to t = 1), for context only.
+PAPER_FV2D_TJIT = {(1, 5): 4.31e-2, (1, 10): 1.33e-1, (1, 15): 2.22e-1, (1, 20): 4.40e-1,
+                   (2, 5): 8.50e-2, (2, 10): 2.27e-1, (2, 15): 5.89e-1, (2, 20): 1.35}
+
+
+def fv2d_section():
+    out = {"workload": "2-D ADER-WENO, Euler gamma=1.4, sine wave rho=1+0.5 sin(2 pi (x+y)), velocity (1,1), "
+                       "p=1, cell averages, unit square, periodic, CFL 0.4 (d = 2)",
+           "throughput": [fv2d_entry(N, 1024, 20, 5) for N in (1, 2)]}
+    tts = []
+    for N in (1, 2):
+        for C in (5, 10, 15, 20):
+            e = dg2d_time_to_solution(N, C, run_cls=lambda n, c, p: FV2Run(n, c))
+            e["scheme"] = f"ADER-WENO{N + 1}"
+            e["paper_cpu_s_tjit"] = PAPER_FV2D_TJIT[(N, C)]
+            tts.append(e)
+    out["paper_fv_table_time_to_solution"] = tts
+    return out
 
 
 def oracle_rate(run, dofs_per_step, target_s=6.0, max_steps=40):
@@ -909,6 +975,8 @@ def main():
                     help="first run a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--dg2d-only", action="store_true",
                     help="only the 2-D workload (512x512 cells, N=5; for profiling the 2-D kernels)")
+    ap.add_argument("--fv2d-only", action="store_true",
+                    help="only the 2-D ADER-WENO workloads (1024^2 throughput, the paper's WENO timing meshes)")
     ap.add_argument("--limiter-only", action="store_true",
                     help="only the limited step on the 131072-cell Sod row (N=5; for profiling)")
     ap.add_argument("--dg3d-only", action="store_true",
@@ -926,7 +994,7 @@ def main():
     # the oracle's host-core baseline runs first: its worker processes are
     # forked, which must happen before this process touches the GPU
     cpu = None
-    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only):
+    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only or a.fv2d_only):
         cpu = cpu_baseline(N)
         emit("cpu_baseline", cpu)
 
@@ -949,6 +1017,9 @@ def main():
         return
     if a.limiter_only:
         print(json.dumps({"limiter": limiter_section(quick=True)}))
+        return
+    if a.fv2d_only:
+        print(json.dumps({"fv2d_euler_sine": fv2d_section()}))
         return
 
     run = DGRun(N, C, abi.FP64)
@@ -1040,6 +1111,7 @@ def main():
         emit("dg2d_euler_sine_512x512", dg2d_section())
         emit("dg3d_euler_sine", dg3d_section())
         emit("limiter", limiter_section())
+        emit("fv2d_euler_sine", fv2d_section())
         # compact summaries for the headline line
         out["fp32_predictor"] = {"value": fp32["value"], "ms_per_step": fp32["ms_per_step"],
                                  "frac": fp32["roofline"]["frac"],

@@ -724,10 +724,8 @@ __global__ void clock2d_end_kernel(const Clock2D* clk, double* t_user, double* d
 // Dimension-by-dimension WENO reconstruction: the 1-D reconstruction along x
 // of every row of cell averages gives, at the x nodes, the averages over y of
 // the solution; the same reconstruction along y of those gives the nodal
-// values.  One thread per (cell, x node k): the x reconstruction at node k of
-// the 2 NW + 1 cells of its column, then the y reconstruction of those at the
-// n y nodes.  The oscillation indicators are evaluated on differences from
-// the centre value (the quadratic forms vanish on constants).
+// values.  The oscillation indicators are evaluated on differences from the
+// centre value (the quadratic forms vanish on constants).
 template <int NW>
 __device__ __forceinline__ void weno1d(const double (&v)[2 * NW + 1], const DevWeno& T, double* out,
                                        int k_only) {
@@ -766,53 +764,70 @@ __device__ __forceinline__ void weno1d(const double (&v)[2 * NW + 1], const DevW
   for (int k = 0; k < n; ++k) out[k] = acc[k] / wsum;
 }
 
+// One workgroup per tile of kWenoTile x kWenoTile cells: the averages of the
+// tile and its halo of NW cells are staged in LDS; the x reconstruction is
+// formed once for every (tile column, halo row, variable) and kept in LDS at
+// the n x nodes; the y reconstruction of every (cell, x node, variable)
+// follows from it.
+constexpr int kWenoTile = 8;
+
 template <int NW>
 __global__ void __launch_bounds__(kFv2dThreads) weno2d_kernel(Args2D A, double* w) {
-  constexpr int n = NW + 1, M = 4, S = 2 * NW + 1;
-  const DevWeno& T = c2_weno[NW - 1];
-  const int64_t ncells = A.cx * A.cy;
-  const int64_t g = (int64_t)blockIdx.x * kFv2dThreads + threadIdx.x;
-  if (g >= ncells * n) return;
-  const int64_t cell = g / n;
-  const int k = (int)(g - cell * n);
-  const int64_t ix = cell / A.cy, iy = cell - ix * A.cy;
-  double colv[S][M];            // x reconstruction at node k of the column cells iy - NW .. iy + NW
-  for (int dy = 0; dy < S; ++dy) {
-    int64_t jy = iy - NW + dy;
+  constexpr int n = NW + 1, M = 4, S = 2 * NW + 1, T = kWenoTile, H = T + 2 * NW;
+  __shared__ double va[H * H * M];          // [x][y][r], tile + halo
+  __shared__ double wx[T * H * n * M];      // [tile column][halo row][x node][r]
+  const DevWeno& WT = c2_weno[NW - 1];
+  const int64_t tiles_y = (A.cy + T - 1) / T;
+  const int64_t tx = blockIdx.x / tiles_y, ty = blockIdx.x - tx * tiles_y;
+  const int64_t ix0 = tx * T, iy0 = ty * T;
+  for (int e = threadIdx.x; e < H * H * M; e += kFv2dThreads) {
+    const int hx = e / (H * M), rem = e - hx * (H * M), hy = rem / M, r = rem - hy * M;
+    int64_t jx = ix0 - NW + hx, jy = iy0 - NW + hy;
+    jx = (jx % A.cx + A.cx) % A.cx;
     jy = (jy % A.cy + A.cy) % A.cy;
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
-      double row[S];
-#pragma unroll
-      for (int dx = 0; dx < S; ++dx) {
-        int64_t jx = ix - NW + dx;
-        jx = (jx % A.cx + A.cx) % A.cx;
-        row[dx] = A.u[(jx * A.cy + jy) * M + r];
-      }
-      double o[n];
-      weno1d<NW>(row, T, o, k);
-      colv[dy][r] = o[k];
-    }
+    va[e] = A.u[(jx * A.cy + jy) * M + r];
   }
+  __syncthreads();
+  for (int e = threadIdx.x; e < T * H * M; e += kFv2dThreads) {
+    const int cx_ = e / (H * M), rem = e - cx_ * (H * M), hy = rem / M, r = rem - hy * M;
+    double row[S], o[n];
 #pragma unroll
-  for (int r = 0; r < M; ++r) {
+    for (int d = 0; d < S; ++d) row[d] = va[((cx_ + d) * H + hy) * M + r];
+    weno1d<NW>(row, WT, o, -1);
+#pragma unroll
+    for (int k = 0; k < n; ++k) wx[((cx_ * H + hy) * n + k) * M + r] = o[k];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < T * T * n * M; e += kFv2dThreads) {
+    const int cx_ = e / (T * n * M), rem = e - cx_ * (T * n * M);
+    const int cy_ = rem / (n * M), rem2 = rem - cy_ * (n * M), k = rem2 / M, r = rem2 - k * M;
+    const int64_t ix = ix0 + cx_, iy = iy0 + cy_;
+    if (ix >= A.cx || iy >= A.cy) continue;
     double col[S], o[n];
 #pragma unroll
-    for (int dy = 0; dy < S; ++dy) col[dy] = colv[dy][r];
-    weno1d<NW>(col, T, o, -1);
+    for (int d = 0; d < S; ++d) col[d] = wx[((cx_ * H + cy_ + d) * n + k) * M + r];
+    weno1d<NW>(col, WT, o, -1);
+    const int64_t cell = ix * A.cy + iy;
 #pragma unroll
     for (int l = 0; l < n; ++l) w[((cell * n + k) * n + l) * M + r] = o[l];
   }
 }
 
-// Finite-volume update of the averages (in place), one thread per cell:
+// Finite-volume update of the averages (in place):
 // v -= sum_k w_k (Gx(east, k) - Gx(west, k) + Gy(north, k) - Gy(south, k)),
 // G the time-integrated Rusanov flux of the face traces (each face evaluated
-// by both adjacent cells, identically); then the signal speed of the new
-// averages for the next step's dt.
+// by both adjacent cells, identically).  One thread per (cell, face, face
+// node) for the fluxes, gathered in LDS; then one thread per cell for the
+// update and the signal speed of the new averages (the next step's dt).
+template <int N>
+struct Fv2Geo {
+  static constexpr int n = N + 1, IT = 4 * n, CPB = kFv2dThreads / IT;
+};
+
 template <int N>
 __global__ void __launch_bounds__(kFv2dThreads) fv2d_corr_kernel(Args2D A) {
-  constexpr int n = N + 1, L = n * n, M = 4;
+  constexpr int n = N + 1, L = n * n, M = 4, IT = Fv2Geo<N>::IT, CPB = Fv2Geo<N>::CPB;
+  __shared__ double Gf[CPB * IT * M];
   __shared__ double bcast[2];
   __shared__ double part[2 * (kFv2dThreads / 64)];
   double t;
@@ -820,50 +835,53 @@ __global__ void __launch_bounds__(kFv2dThreads) fv2d_corr_kernel(Args2D A) {
   if (!(dt > 0.0)) return;
   const double dtdx = dt / A.dx, dtdy = dt / A.dy;
   const int64_t ncells = A.cx * A.cy;
-  const int64_t c = (int64_t)blockIdx.x * kFv2dThreads + threadIdx.x;
+  const int64_t cell0 = (int64_t)blockIdx.x * CPB;
+  const int ncl = (int)((ncells - cell0) < CPB ? (ncells - cell0) : CPB);
+  const int tid = threadIdx.x;
+  if (tid < ncl * IT) {
+    const int cl = tid / IT, rem = tid - cl * IT, f = rem / n, k = rem - f * n;
+    const int64_t c = cell0 + cl;
+    const int64_t ix = c / A.cy, iy = c - ix * A.cy;
+    int64_t cm, cp;
+    if (f == 0) { cm = (ix == 0 ? A.cx - 1 : ix - 1) * A.cy + iy; cp = c; }
+    else if (f == 1) { cm = c; cp = (ix + 1 == A.cx ? 0 : ix + 1) * A.cy + iy; }
+    else if (f == 2) { cm = ix * A.cy + (iy == 0 ? A.cy - 1 : iy - 1); cp = c; }
+    else { cm = c; cp = ix * A.cy + (iy + 1 == A.cy ? 0 : iy + 1); }
+    const int fm = f < 2 ? 1 : 3, fp = f < 2 ? 0 : 2;
+    const double sc = f < 2 ? dtdx : dtdy;
+    double acc[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      double qm[M], qp[M], Gr[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        qm[r] = reinterpret_cast<const double*>(A.tr)[((cm * 4 + fm) * L + a * n + k) * M + r];
+        qp[r] = reinterpret_cast<const double*>(A.tr)[((cp * 4 + fp) * L + a * n + k) * M + r];
+      }
+      if (f < 2) rusanov2<0>(qm, qp, Gr, A.gamma);
+      else rusanov2<1>(qm, qp, Gr, A.gamma);
+      const double wa = c2_ops[N].w[a];
+#pragma unroll
+      for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
+    }
+    const double wk = ((f & 1) ? 1.0 : -1.0) * c2_ops[N].w[k];   // east / north add, west / south subtract
+#pragma unroll
+    for (int r = 0; r < M; ++r) Gf[(cl * IT + rem) * M + r] = wk * acc[r];
+  }
+  __syncthreads();
   double lx = 0.0, ly = 0.0;
   bool bad = false;
-  if (c < ncells) {
-    const int64_t ix = c / A.cy, iy = c - ix * A.cy;
-    double F[M];
-#pragma unroll
-    for (int r = 0; r < M; ++r) F[r] = 0.0;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      int64_t cm, cp;
-      if (f == 0) { cm = (ix == 0 ? A.cx - 1 : ix - 1) * A.cy + iy; cp = c; }
-      else if (f == 1) { cm = c; cp = (ix + 1 == A.cx ? 0 : ix + 1) * A.cy + iy; }
-      else if (f == 2) { cm = ix * A.cy + (iy == 0 ? A.cy - 1 : iy - 1); cp = c; }
-      else { cm = c; cp = ix * A.cy + (iy + 1 == A.cy ? 0 : iy + 1); }
-      const int fm = f < 2 ? 1 : 3, fp = f < 2 ? 0 : 2;
-      const double sc = f < 2 ? dtdx : dtdy;
-      const double sign = (f & 1) ? 1.0 : -1.0;      // east / north add, west / south subtract
-      for (int k = 0; k < n; ++k) {
-        double acc[M];
-#pragma unroll
-        for (int r = 0; r < M; ++r) acc[r] = 0.0;
-        for (int a = 0; a < n; ++a) {
-          double qm[M], qp[M], Gr[M];
-#pragma unroll
-          for (int r = 0; r < M; ++r) {
-            qm[r] = reinterpret_cast<const double*>(A.tr)[((cm * 4 + fm) * L + a * n + k) * M + r];
-            qp[r] = reinterpret_cast<const double*>(A.tr)[((cp * 4 + fp) * L + a * n + k) * M + r];
-          }
-          if (f < 2) rusanov2<0>(qm, qp, Gr, A.gamma);
-          else rusanov2<1>(qm, qp, Gr, A.gamma);
-          const double wa = c2_ops[N].w[a];
-#pragma unroll
-          for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
-        }
-        const double wk = c2_ops[N].w[k];
-#pragma unroll
-        for (int r = 0; r < M; ++r) F[r] = fma(sign * wk, acc[r], F[r]);
-      }
-    }
+  if (tid < ncl) {
+    const int64_t c = cell0 + tid;
     double vn[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      vn[r] = A.u[c * M + r] - F[r];
+      double F = 0.0;
+#pragma unroll
+      for (int e = 0; e < IT; ++e) F += Gf[(tid * IT + e) * M + r];
+      vn[r] = A.u[c * M + r] - F;
       A.u[c * M + r] = vn[r];
     }
     bad = !Euler2::admissible(vn, A.gamma);
@@ -963,8 +981,8 @@ hipError_t launch_clock2d_end(const Clock2D* clk, double* t_user, double* dt_use
 }
 
 hipError_t launch_weno2d(int NW, const Args2D& A, double* w, hipStream_t st) {
-  const int64_t work = A.cx * A.cy * (NW + 1);
-  dim3 grid((unsigned)((work + kFv2dThreads - 1) / kFv2dThreads)), block(kFv2dThreads);
+  const int64_t tiles = ((A.cx + kWenoTile - 1) / kWenoTile) * ((A.cy + kWenoTile - 1) / kWenoTile);
+  dim3 grid((unsigned)tiles), block(kFv2dThreads);
   if (NW == 1) hipLaunchKernelGGL((weno2d_kernel<1>), grid, block, 0, st, A, w);
   else if (NW == 2) hipLaunchKernelGGL((weno2d_kernel<2>), grid, block, 0, st, A, w);
   else return hipErrorInvalidValue;
@@ -972,7 +990,9 @@ hipError_t launch_weno2d(int NW, const Args2D& A, double* w, hipStream_t st) {
 }
 
 hipError_t launch_fv2d_corr(int NW, const Args2D& A, hipStream_t st) {
-  dim3 grid((unsigned)((A.cx * A.cy + kFv2dThreads - 1) / kFv2dThreads)), block(kFv2dThreads);
+  const int64_t cells = A.cx * A.cy;
+  const int cpb = NW == 1 ? Fv2Geo<1>::CPB : Fv2Geo<2>::CPB;
+  dim3 grid((unsigned)((cells + cpb - 1) / cpb)), block(kFv2dThreads);
   if (NW == 1) hipLaunchKernelGGL((fv2d_corr_kernel<1>), grid, block, 0, st, A);
   else if (NW == 2) hipLaunchKernelGGL((fv2d_corr_kernel<2>), grid, block, 0, st, A);
   else return hipErrorInvalidValue;

@@ -60,8 +60,7 @@ hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf, const DevWen
 // ADER-WENO finite volumes (scheme 1; NW = reconstruction degree = predictor degree, 1 or 2):
 // nodal WENO values w [cells][n][n][4] of the averages v (A.u), the update of
 // the averages in place from the predictor's traces, the signal speed of the
-// start state.  Thread counts: kFv2dThreads per workgroup, one thread per
-// (cell, x node) in the reconstruction, per cell in the update and lambda.
+// start state (kFv2dThreads per workgroup).
 constexpr int kFv2dThreads = 256;
 hipError_t launch_weno2d(int NW, const Args2D& A, double* w, hipStream_t st);
 hipError_t launch_fv2d_corr(int NW, const Args2D& A, hipStream_t st);
