@@ -27,4 +27,4 @@ Functions whose result has no pin beyond oracle-vs-GPU parity say
 Riemann solver and the WENO constants (the paper defines neither).
 """
 
-from . import basis, pde, predictor, dg, dg2d, dg3d, weno, fv, fv2d, brute, pade, norms, limiter, riemann  # noqa: F401
+from . import basis, pde, predictor, dg, dg2d, dg3d, weno, fv, fv2d, fv3d, brute, pade, norms, limiter, riemann  # noqa: F401

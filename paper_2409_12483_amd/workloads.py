@@ -261,3 +261,17 @@ def euler2d_sine_averages(cx, cy, amp=0.5, kx=1, ky=1, velocity=(1.0, 1.0), pres
     u, v = velocity
     E = pressure / (gamma - 1.0) + 0.5 * rbar * (u * u + v * v)
     return np.stack([rbar, rbar * u, rbar * v, E], axis=-1)
+
+
+def euler3d_sine_averages(cx, cy, cz, amp=0.5, k=(1, 1, 1), velocity=(1.0, 1.0, 1.0), pressure=1.0,
+                          gamma=1.4, npts=8, t=0.0):
+    """Cell averages v[Cx, Cy, Cz, 5] of the 3-D sine wave at time t of its
+    translation, by an npts^3 Gauss-Legendre rule per cell (unit cube)."""
+    _, w = gl_points_01(npts)
+    X = cell_points(cx, npts)[:, None, None, :, None, None]
+    Y = cell_points(cy, npts)[None, :, None, None, :, None]
+    Z = cell_points(cz, npts)[None, None, :, None, None, :]
+    rho = euler3d_sine_wave_exact(X, Y, Z, t, amp, k, velocity)
+    rbar = np.einsum("i,j,k,xyzijk->xyz", w, w, w, np.broadcast_to(rho, (cx, cy, cz, npts, npts, npts)))
+    E = pressure / (gamma - 1.0) + 0.5 * rbar * sum(vv * vv for vv in velocity)
+    return np.stack([rbar, rbar * velocity[0], rbar * velocity[1], rbar * velocity[2], E], axis=-1)
