@@ -38,7 +38,10 @@ typedef struct {
   double fixed_dt;         /* > 0: this dt instead of the CFL rule */
   double picard_tol;       /* <= 0: 1e-14 (FP64) or 1e-6 (FP32 predictor) */
   int32_t picard_max_iter; /* <= 0: 64 */
-  int32_t pad;
+  int32_t scheme;          /* ADERDG_SCHEME_DG (0), or ADERDG_SCHEME_FV: ADER-WENO finite
+                              volumes (Sec. 1.3 with d = 3), N = the WENO degree (1: the
+                              paper's ADER-WENO2, 2: ADER-WENO3), FP64 only; the state is
+                              then the cell averages v [cells_x][cells_y][cells_z][5] */
 } aderdg3d_config;
 
 typedef struct aderdg3d_handle aderdg3d_handle;

@@ -71,7 +71,7 @@ class Config3D(ctypes.Structure):
                 ("y1", ctypes.c_double), ("z0", ctypes.c_double), ("z1", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_double),
                 ("picard_tol", ctypes.c_double), ("picard_max_iter", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32)]
 
 
 class LimConfig(ctypes.Structure):
@@ -318,11 +318,11 @@ def aderdg2d_free(h):
 
 # ------------------------------------------------------------------ 3-D ----
 def config3d(N, cells, extent=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.4, fixed_dt=0.0, precision=FP64,
-             picard_tol=0.0, picard_max_iter=0):
+             picard_tol=0.0, picard_max_iter=0, scheme=SCHEME_DG):
     """cells: (cx, cy, cz); extent: (Lx, Ly, Lz) of the domain [0, Lx] x [0, Ly] x [0, Lz]."""
     cx, cy, cz = cells
     return Config3D(N, precision, cx, cy, cz, 0.0, extent[0], 0.0, extent[1], 0.0, extent[2],
-                    gamma, cfl, fixed_dt, picard_tol, picard_max_iter, 0)
+                    gamma, cfl, fixed_dt, picard_tol, picard_max_iter, scheme)
 
 
 def aderdg3d_init(cfg, stream=None):

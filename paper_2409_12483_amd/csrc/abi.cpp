@@ -124,7 +124,7 @@ int ensure_tables(int device) {
   }
   e = upload_tables_2d(ops, opsf, &weno[2], &weno[0]);
   if (e != hipSuccess) return fail_hip(e, "upload of 2-D operator tables");
-  e = upload_tables_3d(ops, opsf);
+  e = upload_tables_3d(ops, opsf, &weno[2], &weno[0]);
   if (e != hipSuccess) return fail_hip(e, "upload of 3-D operator tables");
   g_tables_devices.insert(device);
   return ADERDG_OK;
@@ -865,6 +865,7 @@ struct aderdg3d_handle {
   aderdg3d_config cfg{};
   int64_t cells = 0;
   double* part = nullptr;
+  double* w = nullptr;      // ADER-WENO: nodal WENO values of the averages
   void* tr = nullptr;
   Clock3D* clk = nullptr;
 };
@@ -873,6 +874,7 @@ namespace {
 
 void release3d(aderdg3d_handle* h) {
   if (h->part) hipFree(h->part);
+  if (h->w) hipFree(h->w);
   if (h->tr) hipFree(h->tr);
   if (h->clk) hipFree(h->clk);
   delete h;
@@ -895,6 +897,7 @@ Args3D args3d(const aderdg3d_handle* h) {
   A.clk = h->clk;
   A.part = h->part;
   A.tr = h->tr;
+  A.scheme = c.scheme;
   return A;
 }
 
@@ -908,6 +911,9 @@ int aderdg3d_init(const aderdg3d_config* cfg, void* hip_stream, aderdg3d_handle*
   aderdg3d_config c = *cfg;
   if (c.precision != ADERDG_FP64 && c.precision != ADERDG_FP32_PREDICTOR)
     return fail(ADERDG_E_INVAL, "unknown precision");
+  if (c.scheme != ADERDG_SCHEME_DG && c.scheme != ADERDG_SCHEME_FV) return fail(ADERDG_E_INVAL, "unknown scheme");
+  if (c.scheme == ADERDG_SCHEME_FV && (c.N < 1 || c.N > 2 || c.precision != ADERDG_FP64))
+    return fail(ADERDG_E_INVAL, "3-D ADER-WENO: N (the WENO degree) must be 1 or 2, precision FP64");
   if (c.N < 1 || !supported_3d(c.N, c.precision))
     return fail(ADERDG_E_INVAL, "N must be in 1..5 (FP64) or 1..6 (FP32 predictor)");
   if (c.cells_x < 1 || c.cells_y < 1 || c.cells_z < 1 || c.cells_x > INT32_MAX / c.cells_y ||
@@ -932,7 +938,8 @@ int aderdg3d_init(const aderdg3d_config* cfg, void* hip_stream, aderdg3d_handle*
   h->cfg = c;
   h->cells = c.cells_x * c.cells_y * c.cells_z;
   const int64_t L = (int64_t)(c.N + 1) * (c.N + 1) * (c.N + 1);
-  e = hipMalloc((void**)&h->part, sizeof(double) * h->cells * L * 5);
+  // DG: u + volume terms; ADER-WENO: the nodal WENO values (the predictor's initial data)
+  e = hipMalloc(c.scheme == ADERDG_SCHEME_FV ? (void**)&h->w : (void**)&h->part, sizeof(double) * h->cells * L * 5);
   const size_t tr_elem = c.precision == ADERDG_FP64 ? sizeof(double) : sizeof(float);
   if (e == hipSuccess) e = hipMalloc(&h->tr, tr_elem * h->cells * 6 * L * 5);
   if (e != hipSuccess) { release3d(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
@@ -948,6 +955,7 @@ int aderdg3d_predict(aderdg3d_handle* h, const double* u, double t, double dt, v
                      int32_t* iters_out) {
   g_last_error.clear();
   if (!h || !u || !q_out) return fail(ADERDG_E_INVAL, "null argument");
+  if (h->cfg.scheme != ADERDG_SCHEME_DG) return fail(ADERDG_E_INVAL, "predictor-only calls serve the DG scheme");
   if (!(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(t)) return fail(ADERDG_E_INVAL, "dt must be > 0 and finite");
   Args3D A = args3d(h);
   A.mode = k3dPredict;
@@ -974,6 +982,21 @@ int aderdg3d_step(aderdg3d_handle* h, double* u, double* t, const double* t_end,
   const int cpb = cells_per_block_3d(N, h->cfg.precision), cpb2 = cells_per_block_corr3d(N);
   const int64_t blocks = (h->cells + cpb - 1) / cpb, blocks2 = (h->cells + cpb2 - 1) / cpb2;
   hipError_t e = launch_clock3d_begin(h->clk, t, h->stream);
+  if (h->cfg.scheme == ADERDG_SCHEME_FV) {
+    // ADER-WENO: WENO reconstruction of the averages -> predictor from the
+    // nodal WENO values -> update of the averages from the face traces
+    if (e == hipSuccess && h->cfg.fixed_dt <= 0.0) e = launch_fv3d_lambda(A, h->stream);
+    Args3D P = A;
+    P.u = h->w;
+    for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+      A.step = P.step = s;
+      e = launch_weno3d(N, A, h->w, h->stream);
+      if (e == hipSuccess) e = launch_pred3d(N, h->cfg.precision, P, blocks, h->stream);
+      if (e == hipSuccess) e = launch_fv3d_corr(N, A, h->stream);
+    }
+    if (e == hipSuccess) e = launch_clock3d_end(h->clk, t, dt, status, nsteps & 1, h->stream);
+    return e == hipSuccess ? ADERDG_OK : fail_hip(e, "3-D ADER-WENO step launch");
+  }
   if (e == hipSuccess && h->cfg.fixed_dt <= 0.0) e = launch_lambda3d(N, A, blocks2, h->stream);
   for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
     A.step = s;

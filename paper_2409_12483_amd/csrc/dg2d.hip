@@ -30,6 +30,7 @@
 // admissibility test, and the signal-speed maxima of the new state on the
 // subcell averages for the next step's dt.
 #include "launch2d.hpp"
+#include "weno_device.hpp"
 
 namespace aderdg {
 
@@ -726,44 +727,6 @@ __global__ void clock2d_end_kernel(const Clock2D* clk, double* t_user, double* d
 // the solution; the same reconstruction along y of those gives the nodal
 // values.  The oscillation indicators are evaluated on differences from the
 // centre value (the quadratic forms vanish on constants).
-template <int NW>
-__device__ __forceinline__ void weno1d(const double (&v)[2 * NW + 1], const DevWeno& T, double* out,
-                                       int k_only) {
-  constexpr int n = NW + 1, NS = NW == 1 ? 2 : 3;
-  double wsum = 0.0, acc[n];
-#pragma unroll
-  for (int k = 0; k < n; ++k) acc[k] = 0.0;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int off = NW == 1 ? s : (s == 0 ? 0 : (s == 1 ? NW / 2 : NW));   // first cell, 0 = i - NW
-    double d[n];
-#pragma unroll
-    for (int q = 0; q < n; ++q) d[q] = v[off + q] - v[NW];
-    double sig = 0.0;
-#pragma unroll
-    for (int q = 0; q < n; ++q) {
-      double si = 0.0;
-#pragma unroll
-      for (int m = 0; m < n; ++m) si += T.S[s][q][m] * d[m];
-      sig += d[q] * si;
-    }
-    const double e = sig + 1.0e-14;
-    const double e2 = e * e, e4 = e2 * e2, e8 = e4 * e4;
-    const double om = ((NW != 1 && s == 1) ? 1.0e5 : 1.0) / e8;
-    wsum += om;
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-      if (k_only >= 0 && k != k_only) continue;
-      double val = 0.0;
-#pragma unroll
-      for (int q = 0; q < n; ++q) val += T.R[s][k][q] * v[off + q];
-      acc[k] += om * val;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < n; ++k) out[k] = acc[k] / wsum;
-}
-
 // One workgroup per tile of kWenoTile x kWenoTile cells: the averages of the
 // tile and its halo of NW cells are staged in LDS; the x reconstruction is
 // formed once for every (tile column, halo row, variable) and kept in LDS at

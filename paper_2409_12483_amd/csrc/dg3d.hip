@@ -19,11 +19,13 @@
 // fluxes through the six faces, updates u in place and reduces the subcell
 // signal speeds for the next step.
 #include "launch3d.hpp"
+#include "weno_device.hpp"
 
 namespace aderdg {
 
 __constant__ DevOps c3_ops[kDevMaxn];
 __constant__ DevOpsF c3_opsf[kDevMaxn];
+__constant__ DevWeno c3_weno[2];   // WENO of degree 1 and 2
 
 // Sec. 2, eq. system_of_equations in three dimensions:
 // U = (rho, rho u, rho v, rho w, E), p = (gamma - 1) (E - rho |v|^2 / 2).
@@ -114,7 +116,8 @@ __device__ __forceinline__ double step_dt3d(const Args3D& A, double* bcast, bool
       }
     }
     __syncthreads();
-    dt = A.cfl / (3.0 * (2 * N + 1)) *
+    // Sec. 1.5 with d = 3; the finite-volume scheme has no 1/(2N+1) factor
+    dt = A.cfl / (3.0 * (A.scheme ? 1 : 2 * N + 1)) *
          fmin(fmin(A.h[0] / bcast[0], A.h[1] / bcast[1]), A.h[2] / bcast[2]);
   }
   const double rem = A.t_end[0] - t;
@@ -450,9 +453,11 @@ pred3d_kernel(Args3D A) {
         vol[r] = fma(dz_, Vc[(2 * L + (h2 * n + h1) * n + l) * M + r], vol[r]);
       }
     }
-    double* pc = A.part + (cell * L + line) * M;
+    if (A.scheme == 0) {                     // the finite-volume update needs only the traces
+      double* pc = A.part + (cell * L + line) * M;
 #pragma unroll
-    for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
+      for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
+    }
   }
 
   if (mine && line == 0) atomicAdd(&swsum, (unsigned int)sweeps);
@@ -648,6 +653,157 @@ lambda3d_kernel(Args3D A) {
   publish_lambda3(*A.clk, 0, lam, part);
 }
 
+// ------------------------------------------------- ADER-WENO (scheme 1) ----
+// Dimension-by-dimension WENO: along x for every line of cells, then along y
+// at every x node, then along z at every (x, y) node pair.  One workgroup per
+// tile of 4 x 4 x 2 cells: the averages of the tile and its halo of NW cells
+// are staged in LDS; the x sweep runs once per (tile x, halo y, halo z,
+// variable), the y sweep once per (tile x, tile y, halo z, x node, variable),
+// the z sweep per (cell, x node, y node, variable).  The y results reuse the
+// staging buffer (dead after the x sweep).
+constexpr int kW3x = 4, kW3y = 4, kW3z = 2;
+
+template <int NW>
+__global__ void __launch_bounds__(kFv3dThreads) weno3d_kernel(Args3D A, double* w) {
+  constexpr int n = NW + 1, M = 5, S = 2 * NW + 1;
+  constexpr int Hx = kW3x + 2 * NW, Hy = kW3y + 2 * NW, Hz = kW3z + 2 * NW;
+  constexpr int VA = Hx * Hy * Hz * M, WY = kW3x * kW3y * Hz * n * n * M;
+  __shared__ double buf[VA > WY ? VA : WY];            // staged averages, then the y sweep
+  __shared__ double wx[kW3x * Hy * Hz * n * M];
+  double* const va = buf;
+  double* const wy = buf;
+  const DevWeno& WT = c3_weno[NW - 1];
+  const int64_t tz = (A.c[2] + kW3z - 1) / kW3z, ty = (A.c[1] + kW3y - 1) / kW3y;
+  const int64_t bx = blockIdx.x / (ty * tz), by = (blockIdx.x / tz) % ty, bz = blockIdx.x % tz;
+  const int64_t x0 = bx * kW3x, y0 = by * kW3y, z0 = bz * kW3z;
+  for (int e = threadIdx.x; e < VA; e += kFv3dThreads) {
+    const int hx = e / (Hy * Hz * M), hy = (e / (Hz * M)) % Hy, hz = (e / M) % Hz, r = e % M;
+    int64_t jx = x0 - NW + hx, jy = y0 - NW + hy, jz = z0 - NW + hz;
+    jx = (jx % A.c[0] + A.c[0]) % A.c[0];
+    jy = (jy % A.c[1] + A.c[1]) % A.c[1];
+    jz = (jz % A.c[2] + A.c[2]) % A.c[2];
+    va[e] = A.u[((jx * A.c[1] + jy) * A.c[2] + jz) * M + r];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kW3x * Hy * Hz * M; e += kFv3dThreads) {
+    const int cx = e / (Hy * Hz * M), hy = (e / (Hz * M)) % Hy, hz = (e / M) % Hz, r = e % M;
+    double row[S], o[n];
+#pragma unroll
+    for (int d = 0; d < S; ++d) row[d] = va[(((cx + d) * Hy + hy) * Hz + hz) * M + r];
+    weno1d<NW>(row, WT, o, -1);
+#pragma unroll
+    for (int k = 0; k < n; ++k) wx[(((cx * Hy + hy) * Hz + hz) * n + k) * M + r] = o[k];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kW3x * kW3y * Hz * n * M; e += kFv3dThreads) {
+    const int cx = e / (kW3y * Hz * n * M), cy = (e / (Hz * n * M)) % kW3y, hz = (e / (n * M)) % Hz;
+    const int kx = (e / M) % n, r = e % M;
+    double col[S], o[n];
+#pragma unroll
+    for (int d = 0; d < S; ++d) col[d] = wx[(((cx * Hy + cy + d) * Hz + hz) * n + kx) * M + r];
+    weno1d<NW>(col, WT, o, -1);
+#pragma unroll
+    for (int k = 0; k < n; ++k) wy[((((cx * kW3y + cy) * Hz + hz) * n + kx) * n + k) * M + r] = o[k];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kW3x * kW3y * kW3z * n * n * M; e += kFv3dThreads) {
+    const int cx = e / (kW3y * kW3z * n * n * M), cy = (e / (kW3z * n * n * M)) % kW3y;
+    const int cz = (e / (n * n * M)) % kW3z, kx = (e / (n * M)) % n, ky = (e / M) % n, r = e % M;
+    const int64_t ix = x0 + cx, iy = y0 + cy, iz = z0 + cz;
+    if (ix >= A.c[0] || iy >= A.c[1] || iz >= A.c[2]) continue;
+    double col[S], o[n];
+#pragma unroll
+    for (int d = 0; d < S; ++d) col[d] = wy[((((cx * kW3y + cy) * Hz + cz + d) * n + kx) * n + ky) * M + r];
+    weno1d<NW>(col, WT, o, -1);
+    const int64_t cell = (ix * A.c[1] + iy) * A.c[2] + iz;
+#pragma unroll
+    for (int k = 0; k < n; ++k) w[(cell * n * n * n + (kx * n + ky) * n + k) * M + r] = o[k];
+  }
+}
+
+// Finite-volume update of the averages (in place): v -= sum over the six faces
+// of the time- and face-integrated Rusanov fluxes (signed, weighted by the
+// face node's weights), one thread per (cell, face, face node) gathered in LDS;
+// then the signal speeds of the new averages for the next step's dt.
+template <int N>
+struct Fv3Geo {
+  static constexpr int n = N + 1, F = n * n, IT = 6 * F, CPB = kFv3dThreads / IT;
+};
+
+template <int N>
+__global__ void __launch_bounds__(kFv3dThreads) fv3d_corr_kernel(Args3D A) {
+  constexpr int n = N + 1, L = n * n * n, M = 5, F = n * n, IT = Fv3Geo<N>::IT, CPB = Fv3Geo<N>::CPB;
+  __shared__ double Gf[CPB * IT * M];
+  __shared__ double bcast[3];
+  __shared__ double part[3 * (kFv3dThreads / 64)];
+  const double dt = step_dt3d<N>(A, bcast, false);
+  if (!(dt > 0.0)) return;
+  const int64_t ncells = A.c[0] * A.c[1] * A.c[2];
+  const int64_t cell0 = (int64_t)blockIdx.x * CPB;
+  const int ncl = (int)((ncells - cell0) < CPB ? (ncells - cell0) : CPB);
+  const int tid = threadIdx.x;
+  if (tid < ncl * IT) {
+    const int cl = tid / IT, rem = tid - cl * IT, f = rem / F, st = rem - f * F;
+    const int d = f >> 1;
+    const int64_t c = cell0 + cl;
+    int64_t nb[3] = {c / (A.c[1] * A.c[2]), (c / A.c[2]) % A.c[1], c % A.c[2]};
+    if (f & 1) nb[d] = (nb[d] + 1 == A.c[d]) ? 0 : nb[d] + 1;
+    else nb[d] = (nb[d] == 0) ? A.c[d] - 1 : nb[d] - 1;
+    const int64_t other = (nb[0] * A.c[1] + nb[1]) * A.c[2] + nb[2];
+    const int64_t cm = (f & 1) ? c : other, cp = (f & 1) ? other : c;
+    const double sc = dt / A.h[d];
+    double acc[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      double qm[M], qp[M], Gr[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        qm[r] = reinterpret_cast<const double*>(A.tr)[((cm * 6 + 2 * d + 1) * L + a * F + st) * M + r];
+        qp[r] = reinterpret_cast<const double*>(A.tr)[((cp * 6 + 2 * d) * L + a * F + st) * M + r];
+      }
+      if (d == 0) rusanov3<0>(qm, qp, Gr, A.gamma);
+      else if (d == 1) rusanov3<1>(qm, qp, Gr, A.gamma);
+      else rusanov3<2>(qm, qp, Gr, A.gamma);
+      const double wa = c3_ops[N].w[a];
+#pragma unroll
+      for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
+    }
+    const double wst = ((f & 1) ? 1.0 : -1.0) * c3_ops[N].w[st / n] * c3_ops[N].w[st % n];
+#pragma unroll
+    for (int r = 0; r < M; ++r) Gf[(cl * IT + rem) * M + r] = wst * acc[r];
+  }
+  __syncthreads();
+  double lam[3] = {0.0, 0.0, 0.0};
+  bool bad = false;
+  if (tid < ncl) {
+    const int64_t c = cell0 + tid;
+    double vn[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      double Fs = 0.0;
+      for (int e = 0; e < IT; ++e) Fs += Gf[(tid * IT + e) * M + r];
+      vn[r] = A.u[c * M + r] - Fs;
+      A.u[c * M + r] = vn[r];
+    }
+    bad = !Euler3::admissible(vn, A.gamma);
+    Euler3::speeds(vn, A.gamma, lam);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0)
+    atomicMin(&A.clk->stat[(blockIdx.x + (threadIdx.x >> 6)) % kSlots].v, -5);
+  publish_lambda3(*A.clk, (A.step + 1) % 3, lam, part);
+}
+
+// Signal speeds of the initial averages into lambda buffer 0.
+__global__ void __launch_bounds__(kFv3dThreads) fv3d_lambda_kernel(Args3D A) {
+  __shared__ double part[3 * (kFv3dThreads / 64)];
+  const int64_t c = (int64_t)blockIdx.x * kFv3dThreads + threadIdx.x;
+  double lam[3] = {0.0, 0.0, 0.0};
+  if (c < A.c[0] * A.c[1] * A.c[2]) Euler3::speeds(A.u + c * 5, A.gamma, lam);
+  publish_lambda3(*A.clk, 0, lam, part);
+}
+
 __global__ void clock3d_begin_kernel(Clock3D* clk, const double* t_user) {
   const int i = threadIdx.x;
   if (i == 0) {
@@ -770,10 +926,42 @@ hipError_t launch_clock3d_end(const Clock3D* clk, double* t_user, double* dt_use
   return hipGetLastError();
 }
 
-hipError_t upload_tables_3d(const DevOps* ops, const DevOpsF* opsf) {
+hipError_t launch_weno3d(int NW, const Args3D& A, double* w, hipStream_t st) {
+  const int64_t tiles = ((A.c[0] + kW3x - 1) / kW3x) * ((A.c[1] + kW3y - 1) / kW3y) *
+                        ((A.c[2] + kW3z - 1) / kW3z);
+  dim3 grid((unsigned)tiles), block(kFv3dThreads);
+  if (NW == 1) hipLaunchKernelGGL((weno3d_kernel<1>), grid, block, 0, st, A, w);
+  else if (NW == 2) hipLaunchKernelGGL((weno3d_kernel<2>), grid, block, 0, st, A, w);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_fv3d_corr(int NW, const Args3D& A, hipStream_t st) {
+  const int64_t cells = A.c[0] * A.c[1] * A.c[2];
+  const int cpb = NW == 1 ? Fv3Geo<1>::CPB : Fv3Geo<2>::CPB;
+  dim3 grid((unsigned)((cells + cpb - 1) / cpb)), block(kFv3dThreads);
+  if (NW == 1) hipLaunchKernelGGL((fv3d_corr_kernel<1>), grid, block, 0, st, A);
+  else if (NW == 2) hipLaunchKernelGGL((fv3d_corr_kernel<2>), grid, block, 0, st, A);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_fv3d_lambda(const Args3D& A, hipStream_t st) {
+  const int64_t cells = A.c[0] * A.c[1] * A.c[2];
+  dim3 grid((unsigned)((cells + kFv3dThreads - 1) / kFv3dThreads)), block(kFv3dThreads);
+  hipLaunchKernelGGL(fv3d_lambda_kernel, grid, block, 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t upload_tables_3d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno1,
+                            const DevWeno* weno2) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c3_ops), ops, sizeof(DevOps) * kDevMaxn);
   if (e != hipSuccess) return e;
-  return hipMemcpyToSymbol(HIP_SYMBOL(c3_opsf), opsf, sizeof(DevOpsF) * kDevMaxn);
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c3_opsf), opsf, sizeof(DevOpsF) * kDevMaxn);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c3_weno), weno1, sizeof(DevWeno));
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c3_weno), weno2, sizeof(DevWeno), sizeof(DevWeno));
 }
 
 }  // namespace aderdg

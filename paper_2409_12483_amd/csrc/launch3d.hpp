@@ -27,7 +27,8 @@ struct Args3D {
   int64_t c[3];            // cells per direction; cell index = (ix * cy + iy) * cz + iz
   double h[3];             // cell sizes
   double cfl, fixed_dt, tol, gamma;
-  int32_t max_iter, mode, step, pad;
+  int32_t max_iter, mode, step;
+  int32_t scheme;          // 0: ADER-DG; 1: ADER-WENO finite volumes (state = cell averages)
   double t, dt;            // predictor mode: given time and step
   Clock3D* clk;
   const double* t_end;     // device, one value
@@ -47,6 +48,15 @@ hipError_t launch_lambda3d(int N, const Args3D& A, int64_t blocks, hipStream_t s
 hipError_t launch_clock3d_begin(Clock3D* clk, const double* t_user, hipStream_t st);
 hipError_t launch_clock3d_end(const Clock3D* clk, double* t_user, double* dt_user,
                               int32_t* status_user, int parity, hipStream_t st);
-hipError_t upload_tables_3d(const DevOps* ops, const DevOpsF* opsf);
+hipError_t upload_tables_3d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno1,
+                            const DevWeno* weno2);
+// ADER-WENO finite volumes (scheme 1; NW = reconstruction degree = predictor
+// degree, 1 or 2): nodal WENO values w [cells][n][n][n][5] of the averages
+// (A.u), the update of the averages in place from the predictor's traces, the
+// signal speeds of the start state.
+constexpr int kFv3dThreads = 256;
+hipError_t launch_weno3d(int NW, const Args3D& A, double* w, hipStream_t st);
+hipError_t launch_fv3d_corr(int NW, const Args3D& A, hipStream_t st);
+hipError_t launch_fv3d_lambda(const Args3D& A, hipStream_t st);
 
 }  // namespace aderdg
