@@ -13,9 +13,12 @@
  *   q  [cells_x][cells_y][cells_z][N+1 (time)][N+1][N+1][N+1][5]           fp64,
  *                                    or fp32 in ADERDG_FP32_PREDICTOR mode
  * Cell (ix, iy, iz) has index (ix * cells_y + iy) * cells_z + iz.
- * Degrees: the predictor keeps two space-time tiles of (N+1)^4 * 5 values of
- * a cell in the 160 KB of LDS of a compute unit, so N = 1..5 in FP64 and
- * N = 1..6 with the FP32 predictor; other degrees are rejected (E_INVAL).
+ * Degrees N = 1..9.  The predictor keeps two space-time tiles of
+ * (N+1)^4 * 5 values of a cell in the 160 KB of LDS of a compute unit up to
+ * N = 5 in FP64 and N = 6 with the FP32 predictor; above, the two tiles live
+ * in a library-owned device buffer of 2 (N+1)^4 * 5 values (predictor
+ * precision, rounded up to 256 bytes) per cell, e.g. 0.8 MB per cell at
+ * N = 9 in FP64.
  */
 #ifndef ADERDG3D_H
 #define ADERDG3D_H
@@ -29,7 +32,7 @@ extern "C" {
 #endif
 
 typedef struct {
-  int32_t N;               /* 1..5 (FP64), 1..6 (FP32 predictor) */
+  int32_t N;               /* 1..9 (DG); 1..2 (ADER-WENO) */
   int32_t precision;       /* enum aderdg_prec */
   int64_t cells_x, cells_y, cells_z;   /* >= 1, product <= 2^31 - 1 */
   double x0, x1, y0, y1, z0, z1;       /* domain, upper > lower */
@@ -48,9 +51,10 @@ typedef struct aderdg3d_handle aderdg3d_handle;
 
 /*
  * aderdg3d_init -- create a 3-D problem (cfg copied; hip_stream NULL = default
- * stream).  Allocates per cell u + volume terms ((N+1)^3 5 doubles) and the
- * six face traces (6 (N+1)^3 5 values in the predictor precision), and a
- * device clock.  E_INVAL (*out untouched), E_NOMEM, E_DEVICE.
+ * stream).  Allocates per cell u + volume terms ((N+1)^3 5 doubles; ADER-WENO:
+ * the nodal WENO values, as many), the six face traces (6 (N+1)^3 5 values in
+ * the predictor precision) and, where the predictor's tiles exceed LDS, those
+ * tiles (above), and a device clock.  E_INVAL (*out untouched), E_NOMEM, E_DEVICE.
  */
 int aderdg3d_init(const aderdg3d_config* cfg, void* hip_stream, aderdg3d_handle** out);
 

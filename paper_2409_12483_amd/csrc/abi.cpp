@@ -867,12 +867,14 @@ struct aderdg3d_handle {
   double* part = nullptr;
   double* w = nullptr;      // ADER-WENO: nodal WENO values of the averages
   void* tr = nullptr;
+  void* qs = nullptr;       // predictor tiles of every cell where they exceed LDS
   Clock3D* clk = nullptr;
 };
 
 namespace {
 
 void release3d(aderdg3d_handle* h) {
+  if (h->qs) hipFree(h->qs);
   if (h->part) hipFree(h->part);
   if (h->w) hipFree(h->w);
   if (h->tr) hipFree(h->tr);
@@ -897,6 +899,7 @@ Args3D args3d(const aderdg3d_handle* h) {
   A.clk = h->clk;
   A.part = h->part;
   A.tr = h->tr;
+  A.qs = h->qs;
   A.scheme = c.scheme;
   return A;
 }
@@ -915,7 +918,7 @@ int aderdg3d_init(const aderdg3d_config* cfg, void* hip_stream, aderdg3d_handle*
   if (c.scheme == ADERDG_SCHEME_FV && (c.N < 1 || c.N > 2 || c.precision != ADERDG_FP64))
     return fail(ADERDG_E_INVAL, "3-D ADER-WENO: N (the WENO degree) must be 1 or 2, precision FP64");
   if (c.N < 1 || !supported_3d(c.N, c.precision))
-    return fail(ADERDG_E_INVAL, "N must be in 1..5 (FP64) or 1..6 (FP32 predictor)");
+    return fail(ADERDG_E_INVAL, "N must be in 1..9");
   if (c.cells_x < 1 || c.cells_y < 1 || c.cells_z < 1 || c.cells_x > INT32_MAX / c.cells_y ||
       c.cells_x * c.cells_y > INT32_MAX / c.cells_z)
     return fail(ADERDG_E_INVAL, "cells_x, cells_y, cells_z must be >= 1 with a product below 2^31");
@@ -942,6 +945,8 @@ int aderdg3d_init(const aderdg3d_config* cfg, void* hip_stream, aderdg3d_handle*
   e = hipMalloc(c.scheme == ADERDG_SCHEME_FV ? (void**)&h->w : (void**)&h->part, sizeof(double) * h->cells * L * 5);
   const size_t tr_elem = c.precision == ADERDG_FP64 ? sizeof(double) : sizeof(float);
   if (e == hipSuccess) e = hipMalloc(&h->tr, tr_elem * h->cells * 6 * L * 5);
+  const int64_t tile_bytes = pred3d_tile_bytes_per_cell(c.N, c.precision);
+  if (e == hipSuccess && tile_bytes > 0) e = hipMalloc(&h->qs, (size_t)tile_bytes * h->cells);
   if (e != hipSuccess) { release3d(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
   e = hipMalloc((void**)&h->clk, sizeof(Clock3D));
   if (e != hipSuccess) { release3d(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }

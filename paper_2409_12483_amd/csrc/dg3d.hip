@@ -143,8 +143,8 @@ __device__ __forceinline__ double step_dt3d(const Args3D& A, double* bcast, bool
 // time-slice strides carry small pads (per n, in elements) chosen by a
 // bank-model search so that the four access patterns of a sweep (lanes over
 // (a, j, k), (a, i, k), (a, i, j) and (i, j, k)) spread over the LDS banks.
-constexpr int kPad3[8][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0},
-                             {0, 3, 4}, {0, 0, 0}, {0, 0, 0}, {0, 0, 2}};
+constexpr int kPad3[11][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 3, 4}, {0, 0, 0},
+                              {0, 0, 0}, {0, 0, 2}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 
 template <int N, class TP>
 struct Pred3Geo {
@@ -163,13 +163,25 @@ struct Pred3Geo {
   // fluxes of the volume terms are in registers): overlay both, one barrier more
   static constexpr bool kVbOverQR = !kVbAlias && 2 * CPB * TILE * (int)sizeof(TP) >= VB * 8;
   static constexpr int kBytes = 2 * CPB * TILE * (int)sizeof(TP) + (kVbAlias || kVbOverQR ? 0 : VB * 8);
+  // tiles too large for LDS (FP64 from N = 6, FP32 from N = 7): Q and R live
+  // in a per-cell device buffer instead (L1/L2-resident while the cell's
+  // workgroup runs; the barriers order its global stores and loads as they
+  // do the LDS ones), one cell per workgroup
+  static constexpr bool kGlobal = kBytes > 159 * 1024;
+  // elements from the start of a cell's Q tile to its R tile (256-byte aligned)
+  static constexpr int kGStride = ((TILE * (int)sizeof(TP) + 255) / 256) * 256 / (int)sizeof(TP);
+  // outputs of a space contraction kept in registers at once (the line's
+  // fluxes are evaluated once per chunk)
+  static constexpr int CH = kGlobal && n > 7 ? (n + 1) / 2 : n;
   __device__ static constexpr int at(int a, int i, int j, int k) { return a * SA + i * SI + j * SJ + k * M; }
 };
 
+// Bytes of the device buffer a cell's predictor tiles need (0: they fit in LDS).
 template <int N, class TP>
-struct Fits3 {
-  static constexpr bool value = Pred3Geo<N, TP>::kBytes <= 159 * 1024;
-};
+constexpr int64_t pred3d_global_bytes() {
+  using G = Pred3Geo<N, TP>;
+  return G::kGlobal ? 2 * (int64_t)G::kGStride * (int64_t)sizeof(TP) : 0;
+}
 
 template <int N, class TP>
 __global__ void __launch_bounds__((Pred3Geo<N, TP>::NT))
@@ -178,13 +190,15 @@ pred3d_kernel(Args3D A) {
   constexpr int n = G::n, L = G::L, M = G::M, CPB = G::CPB;
   using Bits = decltype(ord_bits(TP(0)));
 
-  constexpr bool kQR = G::kVbOverQR;
+  constexpr bool kG = G::kGlobal;
+  constexpr bool kQR = G::kVbOverQR && !kG;
   __shared__ __align__(16) TP QR[kQR ? 2 * CPB * G::TILE : 1];
-  __shared__ TP Qsep[kQR ? 1 : CPB * G::TILE];
-  __shared__ TP Rsep[kQR ? 1 : CPB * G::TILE];
-  __shared__ double Vsep[G::kVbAlias || kQR ? 1 : G::VB];
-  TP* const Qs = kQR ? QR : Qsep;
-  TP* const Rs = kQR ? QR + CPB * G::TILE : Rsep;
+  __shared__ TP Qsep[kQR || kG ? 1 : CPB * G::TILE];
+  __shared__ TP Rsep[kQR || kG ? 1 : CPB * G::TILE];
+  __shared__ double Vsep[G::kVbAlias || kQR || kG ? 1 : G::VB];
+  TP* const Qg = kG ? reinterpret_cast<TP*>(A.qs) + (int64_t)blockIdx.x * (2 * G::kGStride) : nullptr;
+  TP* const Qs = kG ? Qg : kQR ? QR : Qsep;
+  TP* const Rs = kG ? Qg + G::kGStride : kQR ? QR + CPB * G::TILE : Rsep;
   __shared__ Bits red[2][CPB][2];
   __shared__ double bcast[3];
   __shared__ unsigned int swsum;
@@ -223,100 +237,141 @@ pred3d_kernel(Args3D A) {
     if (!__syncthreads_or(active)) break;
     if (active) {
       // X role, line (a, j, k): R = k~ (dt/dx) Fx along i
-      TP acc[n][M];
 #pragma unroll
-      for (int i = 0; i < n; ++i)
+      for (int i0 = 0; i0 < n; i0 += G::CH) {
+        constexpr int CH = G::CH;
+        TP acc[CH][M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) acc[i][r] = TP(0);
+        for (int i = 0; i < CH; ++i)
 #pragma unroll
-      for (int ip = 0; ip < n; ++ip) {
-        TP qq[M], f[M];
+          for (int r = 0; r < M; ++r) acc[i][r] = TP(0);
 #pragma unroll
-        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, ip, h1, h0) + r];
-        Euler3::flux<0>(qq, f, gm1);
-        const cptr3<TP> K = launder3(ktil3<N, TP>() + ip);
+        for (int ip = 0; ip < n; ++ip) {
+          TP qq[M], f[M];
 #pragma unroll
-        for (int i = 0; i < n; ++i)
+          for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, ip, h1, h0) + r];
+          Euler3::flux<0>(qq, f, gm1);
+          const cptr3<TP> K = launder3(ktil3<N, TP>() + ip);
 #pragma unroll
-          for (int r = 0; r < M; ++r) acc[i][r] = fma(K[i * kDevMaxn], c0 * f[r], acc[i][r]);
+          for (int i = 0; i < CH; ++i)
+            if (i0 + i < n)
+#pragma unroll
+              for (int r = 0; r < M; ++r) acc[i][r] = fma(K[(i0 + i) * kDevMaxn], c0 * f[r], acc[i][r]);
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+          if (i0 + i < n)
+#pragma unroll
+            for (int r = 0; r < M; ++r) Rc[G::at(h2, i0 + i, h1, h0) + r] = acc[i][r];
       }
-#pragma unroll
-      for (int i = 0; i < n; ++i)
-#pragma unroll
-        for (int r = 0; r < M; ++r) Rc[G::at(h2, i, h1, h0) + r] = acc[i][r];
     }
     __syncthreads();
     if (active) {
       // Y role, line (a, i, k): R += k~ (dt/dy) Fy along j
-      TP acc[n][M];
 #pragma unroll
-      for (int j = 0; j < n; ++j)
+      for (int j0 = 0; j0 < n; j0 += G::CH) {
+        constexpr int CH = G::CH;
+        TP acc[CH][M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) acc[j][r] = TP(0);
+        for (int j = 0; j < CH; ++j)
 #pragma unroll
-      for (int jp = 0; jp < n; ++jp) {
-        TP qq[M], f[M];
+          for (int r = 0; r < M; ++r) acc[j][r] = TP(0);
 #pragma unroll
-        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, jp, h0) + r];
-        Euler3::flux<1>(qq, f, gm1);
-        const cptr3<TP> K = launder3(ktil3<N, TP>() + jp);
+        for (int jp = 0; jp < n; ++jp) {
+          TP qq[M], f[M];
 #pragma unroll
-        for (int j = 0; j < n; ++j)
+          for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, jp, h0) + r];
+          Euler3::flux<1>(qq, f, gm1);
+          const cptr3<TP> K = launder3(ktil3<N, TP>() + jp);
 #pragma unroll
-          for (int r = 0; r < M; ++r) acc[j][r] = fma(K[j * kDevMaxn], c1 * f[r], acc[j][r]);
+          for (int j = 0; j < CH; ++j)
+            if (j0 + j < n)
+#pragma unroll
+              for (int r = 0; r < M; ++r) acc[j][r] = fma(K[(j0 + j) * kDevMaxn], c1 * f[r], acc[j][r]);
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+          if (j0 + j < n)
+#pragma unroll
+            for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, j0 + j, h0) + r] += acc[j][r];
       }
-#pragma unroll
-      for (int j = 0; j < n; ++j)
-#pragma unroll
-        for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, j, h0) + r] += acc[j][r];
     }
     __syncthreads();
     if (active) {
       // Z role, line (a, i, j): R += k~ (dt/dz) Fz along k
-      TP acc[n][M];
 #pragma unroll
-      for (int k = 0; k < n; ++k)
+      for (int k0 = 0; k0 < n; k0 += G::CH) {
+        constexpr int CH = G::CH;
+        TP acc[CH][M];
 #pragma unroll
-        for (int r = 0; r < M; ++r) acc[k][r] = TP(0);
+        for (int k = 0; k < CH; ++k)
 #pragma unroll
-      for (int kp = 0; kp < n; ++kp) {
-        TP qq[M], f[M];
+          for (int r = 0; r < M; ++r) acc[k][r] = TP(0);
 #pragma unroll
-        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, h0, kp) + r];
-        Euler3::flux<2>(qq, f, gm1);
-        const cptr3<TP> K = launder3(ktil3<N, TP>() + kp);
+        for (int kp = 0; kp < n; ++kp) {
+          TP qq[M], f[M];
 #pragma unroll
-        for (int k = 0; k < n; ++k)
+          for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, h0, kp) + r];
+          Euler3::flux<2>(qq, f, gm1);
+          const cptr3<TP> K = launder3(ktil3<N, TP>() + kp);
 #pragma unroll
-          for (int r = 0; r < M; ++r) acc[k][r] = fma(K[k * kDevMaxn], c2 * f[r], acc[k][r]);
+          for (int k = 0; k < CH; ++k)
+            if (k0 + k < n)
+#pragma unroll
+              for (int r = 0; r < M; ++r) acc[k][r] = fma(K[(k0 + k) * kDevMaxn], c2 * f[r], acc[k][r]);
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          if (k0 + k < n)
+#pragma unroll
+            for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, h0, k0 + k) + r] += acc[k][r];
       }
-#pragma unroll
-      for (int k = 0; k < n; ++k)
-#pragma unroll
-        for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, h0, k) + r] += acc[k][r];
     }
     __syncthreads();
     TP e_ = TP(0), qm_ = TP(0);
     if (active) {
       // T role: q_new[a] = u - sum_b kappa~[a][b] R[b][i][j][k] over the own time line
-      TP rr[n][M];
-#pragma unroll
-      for (int b = 0; b < n; ++b)
-#pragma unroll
-        for (int r = 0; r < M; ++r) rr[b][r] = Rc[G::at(b, h2, h1, h0) + r];
-#pragma unroll
-      for (int a = 0; a < n; ++a) {
-        const cptr3<TP> Kp = launder3(kappa3<N, TP>() + a * kDevMaxn);
+      if constexpr (kG) {
+        // one variable at a time: the time line of R for that variable only
+        // in registers (same sums, same order)
 #pragma unroll
         for (int r = 0; r < M; ++r) {
-          TP acc = TP(0);
+          TP rr[n];
 #pragma unroll
-          for (int b = 0; b < n; ++b) acc = fma(Kp[b], rr[b][r], acc);
-          const TP qn = TP(u0[r]) - acc;
-          TP* p = &Qc[G::at(a, h2, h1, h0) + r];
-          e_ = max_abs(e_, qn - *p);
-          qm_ = max_abs(qm_, qn);
-          *p = qn;
+          for (int b = 0; b < n; ++b) rr[b] = Rc[G::at(b, h2, h1, h0) + r];
+#pragma unroll
+          for (int a = 0; a < n; ++a) {
+            const cptr3<TP> Kp = launder3(kappa3<N, TP>() + a * kDevMaxn);
+            TP acc = TP(0);
+#pragma unroll
+            for (int b = 0; b < n; ++b) acc = fma(Kp[b], rr[b], acc);
+            const TP qn = TP(u0[r]) - acc;
+            TP* p = &Qc[G::at(a, h2, h1, h0) + r];
+            e_ = max_abs(e_, qn - *p);
+            qm_ = max_abs(qm_, qn);
+            *p = qn;
+          }
+        }
+      } else {
+        TP rr[n][M];
+#pragma unroll
+        for (int b = 0; b < n; ++b)
+#pragma unroll
+          for (int r = 0; r < M; ++r) rr[b][r] = Rc[G::at(b, h2, h1, h0) + r];
+#pragma unroll
+        for (int a = 0; a < n; ++a) {
+          const cptr3<TP> Kp = launder3(kappa3<N, TP>() + a * kDevMaxn);
+#pragma unroll
+          for (int r = 0; r < M; ++r) {
+            TP acc = TP(0);
+#pragma unroll
+            for (int b = 0; b < n; ++b) acc = fma(Kp[b], rr[b][r], acc);
+            const TP qn = TP(u0[r]) - acc;
+            TP* p = &Qc[G::at(a, h2, h1, h0) + r];
+            e_ = max_abs(e_, qn - *p);
+            qm_ = max_abs(qm_, qn);
+            *p = qn;
+          }
         }
       }
       ++sweeps;
@@ -831,53 +886,44 @@ __global__ void clock3d_end_kernel(const Clock3D* clk, double* t_user, double* d
 // -------------------------------------------------------------- dispatch ----
 template <int N, class TP>
 static hipError_t pred3d_one(const Args3D& A, int64_t blocks, hipStream_t st) {
-  if constexpr (Fits3<N, TP>::value) {
-    hipLaunchKernelGGL((pred3d_kernel<N, TP>), dim3((unsigned)blocks), dim3(Pred3Geo<N, TP>::NT), 0,
-                       st, A);
-    return hipGetLastError();
-  } else {
-    return hipErrorInvalidValue;
-  }
+  if (Pred3Geo<N, TP>::kGlobal && A.qs == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((pred3d_kernel<N, TP>), dim3((unsigned)blocks), dim3(Pred3Geo<N, TP>::NT), 0, st, A);
+  return hipGetLastError();
 }
+
+#define ADERDG3_DEGREES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9)
 
 template <class TP>
 static hipError_t launch_pred3d_p(int N, const Args3D& A, int64_t blocks, hipStream_t st) {
   switch (N) {
-    case 1: return pred3d_one<1, TP>(A, blocks, st);
-    case 2: return pred3d_one<2, TP>(A, blocks, st);
-    case 3: return pred3d_one<3, TP>(A, blocks, st);
-    case 4: return pred3d_one<4, TP>(A, blocks, st);
-    case 5: return pred3d_one<5, TP>(A, blocks, st);
-    case 6: return pred3d_one<6, TP>(A, blocks, st);
+#define ADERDG3_CASE(NN) case NN: return pred3d_one<NN, TP>(A, blocks, st);
+    ADERDG3_DEGREES(ADERDG3_CASE)
+#undef ADERDG3_CASE
     default: return hipErrorInvalidValue;
   }
 }
 
-template <class TP> static bool fits_p(int N) {
-  switch (N) {
-    case 1: return Fits3<1, TP>::value;
-    case 2: return Fits3<2, TP>::value;
-    case 3: return Fits3<3, TP>::value;
-    case 4: return Fits3<4, TP>::value;
-    case 5: return Fits3<5, TP>::value;
-    case 6: return Fits3<6, TP>::value;
-    default: return false;
-  }
-}
 template <class TP> static int cpb3_p(int N) {
   switch (N) {
-    case 1: return Pred3Geo<1, TP>::CPB;
-    case 2: return Pred3Geo<2, TP>::CPB;
-    case 3: return Pred3Geo<3, TP>::CPB;
-    case 4: return Pred3Geo<4, TP>::CPB;
-    case 5: return Pred3Geo<5, TP>::CPB;
-    case 6: return Pred3Geo<6, TP>::CPB;
+#define ADERDG3_CASE(NN) case NN: return Pred3Geo<NN, TP>::CPB;
+    ADERDG3_DEGREES(ADERDG3_CASE)
+#undef ADERDG3_CASE
     default: return 0;
   }
 }
 
-bool supported_3d(int N, int prec) { return prec ? fits_p<float>(N) : fits_p<double>(N); }
+template <class TP> static int64_t gbytes3_p(int N) {
+  switch (N) {
+#define ADERDG3_CASE(NN) case NN: return pred3d_global_bytes<NN, TP>();
+    ADERDG3_DEGREES(ADERDG3_CASE)
+#undef ADERDG3_CASE
+    default: return 0;
+  }
+}
+
+bool supported_3d(int N, int prec) { return N >= 1 && N <= 9 && (prec == 0 || prec == 1); }
 int cells_per_block_3d(int N, int prec) { return prec ? cpb3_p<float>(N) : cpb3_p<double>(N); }
+int64_t pred3d_tile_bytes_per_cell(int N, int prec) { return prec ? gbytes3_p<float>(N) : gbytes3_p<double>(N); }
 int cells_per_block_corr3d(int N) {
   const int L = (N + 1) * (N + 1) * (N + 1);
   return L >= 256 ? 1 : 256 / L;
@@ -892,7 +938,7 @@ static hipError_t launch_corr3d_p(int N, const Args3D& A, int64_t blocks, hipStr
   dim3 grid((unsigned)blocks), block(256);
   switch (N) {
 #define ADERDG3_CASE(NN) case NN: hipLaunchKernelGGL((corr3d_kernel<NN, TP>), grid, block, 0, st, A); break;
-    ADERDG3_CASE(1) ADERDG3_CASE(2) ADERDG3_CASE(3) ADERDG3_CASE(4) ADERDG3_CASE(5) ADERDG3_CASE(6)
+    ADERDG3_DEGREES(ADERDG3_CASE)
 #undef ADERDG3_CASE
     default: return hipErrorInvalidValue;
   }
@@ -907,7 +953,7 @@ hipError_t launch_lambda3d(int N, const Args3D& A, int64_t blocks, hipStream_t s
   dim3 grid((unsigned)blocks), block(256);
   switch (N) {
 #define ADERDG3_CASE(NN) case NN: hipLaunchKernelGGL((lambda3d_kernel<NN>), grid, block, 0, st, A); break;
-    ADERDG3_CASE(1) ADERDG3_CASE(2) ADERDG3_CASE(3) ADERDG3_CASE(4) ADERDG3_CASE(5) ADERDG3_CASE(6)
+    ADERDG3_DEGREES(ADERDG3_CASE)
 #undef ADERDG3_CASE
     default: return hipErrorInvalidValue;
   }

@@ -37,10 +37,15 @@ struct Args3D {
   void* tr;                // scratch [cells][6 faces][n time][n][n][5], predictor precision
   void* q_out;             // predictor mode: q [cells][n][n][n][n][5] in the predictor precision
   int32_t* iters;          // predictor mode: sweeps per cell (may be null)
+  void* qs;                // predictor tiles Q and R per cell where they exceed LDS
+                           // (pred3d_tile_bytes_per_cell > 0), else null
 };
 
 bool supported_3d(int N, int prec);
 int cells_per_block_3d(int N, int prec);
+// bytes of device memory per cell for the predictor's tiles when they do not
+// fit in LDS (FP64 N >= 6, FP32 N >= 7); 0 otherwise
+int64_t pred3d_tile_bytes_per_cell(int N, int prec);
 int cells_per_block_corr3d(int N);
 hipError_t launch_pred3d(int N, int prec, const Args3D& A, int64_t blocks, hipStream_t st);
 hipError_t launch_corr3d(int N, int prec, const Args3D& A, int64_t blocks, hipStream_t st);

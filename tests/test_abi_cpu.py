@@ -193,8 +193,8 @@ def test_3d_header_declares_the_entry_points():
 
 @pytest.mark.parametrize("mutate,needle", [
     (lambda c: setattr(c, "N", 0), "N must"),
-    (lambda c: setattr(c, "N", 6), "N must"),
-    (lambda c: (setattr(c, "N", 7), setattr(c, "precision", abi.FP32_PREDICTOR)), "N must"),
+    (lambda c: setattr(c, "N", 10), "N must"),
+    (lambda c: (setattr(c, "N", 10), setattr(c, "precision", abi.FP32_PREDICTOR)), "N must"),
     (lambda c: setattr(c, "precision", 2), "precision"),
     (lambda c: setattr(c, "cells_z", 0), "cells_x"),
     (lambda c: (setattr(c, "cells_x", 2048), setattr(c, "cells_y", 2048), setattr(c, "cells_z", 1024)), "2^31"),

@@ -1,14 +1,17 @@
 """3-D ADER-DG (Euler gas) on the GPU against the FP64 oracle, through the C ABI.
 
 * predictor alone: q of every cell and each cell's sweep count;
-* fused steps for every supported degree (1..5 FP64, up to 6 with the FP32
-  predictor), on meshes of unequal sides whose cell counts leave the last
-  workgroup partly empty;
+* fused steps for every degree 1..9 in FP64 and with the FP32 predictor, on
+  meshes of unequal sides whose cell counts leave the last workgroup partly
+  empty (from N = 6 in FP64 and N = 7 in FP32 the predictor's tiles live in a
+  device buffer instead of LDS);
+* the paper's 3-D timing mesh (Sec. 3, the 3-D DG table: 4^3 cells) at
+  N = 6 and 9 for a few steps;
 * edge cases: a single cell (its own neighbour on all six sides), one-cell
   slabs, zero steps, a fixed step, the last step clamped to t_end;
 * full size (48^3 and 64^3 cells at N = 3, 40^3 at N = 5 in FP64 and with the
-  FP32 predictor): a wave of period 4 cells equals, on every
-  cell, the oracle's 4^3 run repeated.
+  FP32 predictor, 24^3 at N = 7 and 16^3 at N = 9): a wave of period 4 cells
+  equals, on every cell, the oracle's 4^3 run repeated.
 """
 
 import numpy as np
@@ -46,7 +49,8 @@ def gpu_run(u0, N, nsteps, extent=(1.0, 1.0, 1.0), cfl=0.4, fixed_dt=0.0, prec=a
         abi.aderdg3d_free(h)
 
 
-@pytest.mark.parametrize("N,cells", [(1, (5, 4, 3)), (2, (3, 2, 3)), (3, (2, 3, 2)), (5, (2, 1, 2))])
+@pytest.mark.parametrize("N,cells", [(1, (5, 4, 3)), (2, (3, 2, 3)), (3, (2, 3, 2)), (5, (2, 1, 2)),
+                                     (6, (2, 2, 1)), (7, (1, 2, 2)), (9, (2, 1, 1))])
 def test_predictor_matches_oracle(N, cells):
     _say("3d predictor", N, cells)
     torch, dev = torch_dev()
@@ -69,9 +73,10 @@ def test_predictor_matches_oracle(N, cells):
         abi.aderdg3d_free(h)
 
 
-@pytest.mark.parametrize("N", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_fused_steps_match_oracle(N):
-    cells = {1: (5, 4, 3), 2: (3, 4, 3), 3: (3, 2, 3), 4: (3, 2, 2), 5: (2, 2, 2)}[N]
+    cells = {1: (5, 4, 3), 2: (3, 4, 3), 3: (3, 2, 3), 4: (3, 2, 2), 5: (2, 2, 2), 6: (2, 2, 2),
+             7: (2, 1, 2), 8: (1, 2, 2), 9: (2, 2, 1)}[N]
     _say("3d steps", N, cells)
     ops = basis.build_operators(N)
     ext = (1.0, 0.9, 0.7)
@@ -85,11 +90,11 @@ def test_fused_steps_match_oracle(N):
     assert sweeps == sum(k * v for k, v in info["sweep_hist"].items())
 
 
-@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_fp32_predictor_within_1e5(N):
     _say("3d fp32", N)
     ops = basis.build_operators(N)
-    cells = (2, 2, 2) if N >= 5 else (3, 3, 2)
+    cells = (2, 2, 1) if N >= 7 else (2, 2, 2) if N >= 5 else (3, 3, 2)
     u0 = W.euler3d_sine_wave(*cells, N, noise=1e-2, seed=3)
     ref, t_ref, _ = dg3d.dg3d_run(ops, E3, u0, nsteps=2)
     u, t, _, st, _ = gpu_run(u0, N, 2, prec=abi.FP32_PREDICTOR)
@@ -110,6 +115,22 @@ def test_tiny_meshes(N, cells):
     assert abs(t - t_ref) <= 1e-14 * t_ref
 
 
+@pytest.mark.parametrize("N", [6, 9])
+def test_paper_timing_mesh_high_degree(N):
+    """The sine wave of the paper's 3-D timing runs on its smallest mesh (4^3
+    cells, unit cube), three steps at the degrees whose tiles live in device
+    memory."""
+    _say("3d timing mesh", N)
+    ops = basis.build_operators(N)
+    u0 = W.euler3d_sine_wave(4, 4, 4, N)
+    ref, t_ref, info = dg3d.dg3d_run(ops, E3, u0, nsteps=3)
+    u, t, _, st, sweeps = gpu_run(u0, N, 3)
+    assert st == 0
+    assert rel_l2(u, ref) <= 1e-12
+    assert abs(t - t_ref) <= 1e-14 * t_ref
+    assert sweeps == sum(k * v for k, v in info["sweep_hist"].items())
+
+
 def test_zero_steps_fixed_dt_and_clamp():
     _say("3d zero steps / fixed dt / clamp")
     N = 2
@@ -126,7 +147,8 @@ def test_zero_steps_fixed_dt_and_clamp():
 
 
 @pytest.mark.parametrize("N,C,prec", [(3, 48, abi.FP64), (3, 64, abi.FP64), (5, 40, abi.FP64),
-                                       (5, 40, abi.FP32_PREDICTOR)])
+                                       (5, 40, abi.FP32_PREDICTOR), (7, 24, abi.FP64),
+                                       (9, 16, abi.FP64), (9, 16, abi.FP32_PREDICTOR)])
 def test_full_size_periodic_wave_equals_repeated_oracle(N, C, prec):
     """The mesh sizes, degrees, precisions and CFL number of the timed 3-D
     runs, with a wave of period 4 cells: every 4^3 block of the GPU result
