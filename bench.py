@@ -773,6 +773,17 @@ def dg3d_time_to_solution(N, C, precision=0):
             "status": st}
 
 
+# The paper's CPU seconds for its 3-D ADER-DG timing runs (Sec. 3, the 3-D DG
+# table: T_JIT, sine wave to t = 1 on C^3 cells), for context only.
+PAPER_DG3D_TJIT = {
+    (1, 4): 2.46, (1, 5): 3.28, (1, 6): 5.89, (1, 7): 5.20, (2, 4): 6.77, (2, 5): 8.93, (2, 6): 11.0,
+    (2, 7): 12.3, (3, 4): 19.9, (3, 5): 16.8, (3, 6): 35.7, (3, 7): 46.5, (4, 4): 29.4, (4, 5): 47.6,
+    (4, 6): 63.4, (4, 7): 87.4, (5, 4): 54.2, (5, 5): 84.1, (5, 6): 114.0, (5, 7): 170.0, (6, 4): 81.8,
+    (6, 5): 131.0, (6, 6): 216.0, (6, 7): 333.0, (7, 4): 139.0, (7, 5): 229.0, (7, 6): 390.0,
+    (7, 7): 638.0, (8, 4): 300.0, (8, 5): 502.0, (8, 6): 819.0, (8, 7): 1220.0, (9, 4): 549.0,
+    (9, 5): 1050.0, (9, 6): 2230.0, (9, 7): 3690.0}
+
+
 def dg3d_section(quick=False):
     from paper_2409_12483_amd import abi
     out = {"workload": "ADER-DG 3D Euler gamma=1.4, sine wave rho=1+0.5 sin(2 pi (x+y+z)), velocity (1,1,1), "
@@ -782,12 +793,84 @@ def dg3d_section(quick=False):
     out["n5_40c_fp32_predictor"] = dg3d_entry(5, 40, abi.FP32_PREDICTOR, 10, 3)
     if quick:
         return out
-    sizes = {1: 96, 2: 72, 3: 64, 4: 48, 5: 40}
+    sizes = {1: 96, 2: 72, 3: 64, 4: 48, 5: 40, 6: 32, 7: 24, 8: 20, 9: 16}
     out["per_degree_fp64"] = [dg3d_entry(N, C, abi.FP64, 10, 3) for N, C in sizes.items()]
     out["n6_32c_fp32_predictor"] = dg3d_entry(6, 32, abi.FP32_PREDICTOR, 10, 3)
-    out["paper_table11_time_to_solution"] = [dg3d_time_to_solution(N, C) for N in range(1, 6)
-                                             for C in (4, 5, 6, 7)]
+    out["n9_16c_fp32_predictor"] = dg3d_entry(9, 16, abi.FP32_PREDICTOR, 10, 3)
+    # the paper's 3-D DG timing runs: every mesh up to N = 5, the smallest and
+    # the largest mesh above (whole runs of 1000-2500 steps)
+    tts = []
+    for N in range(1, 10):
+        for C in ((4, 5, 6, 7) if N <= 5 else (4, 7)):
+            e = dg3d_time_to_solution(N, C)
+            e["paper_cpu_s_tjit"] = PAPER_DG3D_TJIT[(N, C)]
+            tts.append(e)
+    out["paper_table11_time_to_solution"] = tts
     out["cpu_baseline_n3"] = dg3d_cpu_baseline()
+    return out
+
+
+class FV3Run(DG3Run):
+    """The 3-D sine wave as cell averages, advanced by the 3-D ADER-WENO scheme
+    (WENO of degree N, dimension by dimension; LST-DG predictor of degree N)."""
+
+    def __init__(self, N, C, precision=0, cfl=0.4):
+        import torch
+        from paper_2409_12483_amd import abi
+        from paper_2409_12483_amd import workloads as W
+        self.abi, self.torch = abi, torch
+        dev = torch.device("cuda:0")
+        self.u = torch.tensor(W.euler3d_sine_averages(C, C, C, npts=4), device=dev)
+        self.t = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.te = torch.full((1,), 1.0e300, dtype=torch.float64, device=dev)
+        self.dt = torch.zeros_like(self.t)
+        self.st = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.stream = torch.cuda.current_stream()
+        self.h = abi.aderdg3d_init(abi.config3d(N, (C, C, C), cfl=cfl, scheme=abi.SCHEME_FV),
+                                   stream=self.stream.cuda_stream)
+
+
+def fv3d_entry(N, C, steps, warmup):
+    """Throughput of the 3-D ADER-WENO step on C^3 cells; the roofline counts
+    the predictor's work only (its sweeps, the 3-D DG predictor model)."""
+    r = FV3Run(N, C)
+    r.steps(warmup)
+    secs, sweeps = r.timed(steps)
+    status = int(r.st.item())
+    r.close()
+    cells = C ** 3
+    spc = sweeps / (cells * steps)
+    pred, _ = dg3d_flops_per_cell(N, spc)
+    total = pred * cells * steps
+    return {"N": N, "scheme": f"ADER-WENO{N + 1}", "cells": f"{C}^3", "cfl": 0.4, "status": status,
+            "value": round(steps * cells * 5 / secs, 1), "unit": "DoF-updates/s",
+            "ms_per_step": round(secs / steps * 1e3, 5), "sweeps_per_cell": round(spc, 3),
+            "roofline": {"bound": "alu", "achieved": round(total / secs * 1e-12, 3), "peak": PEAK_FP64_VALU,
+                         "unit": "TFLOP/s", "frac": round(total / secs * 1e-12 / PEAK_FP64_VALU, 4),
+                         "flops_per_step": int(round(total / steps)),
+                         "kernels": "WENO + predictor + update launches of each step (HIP events); "
+                                    "flops of the predictor only"}}
+
+
+# The paper's CPU seconds for its 3-D ADER-WENO timing runs (Sec. 3, the 3-D
+# finite-volume table: T_JIT, sine wave to t = 1), for context only.
+PAPER_FV3D_TJIT = {(1, 5): 1.45, (1, 10): 4.71, (1, 15): 2.00e1, (1, 20): 5.87e1,
+                   (2, 5): 4.78, (2, 10): 1.34e1, (2, 15): 6.18e1, (2, 20): 2.23e2}
+
+
+def fv3d_section():
+    out = {"workload": "3-D ADER-WENO, Euler gamma=1.4, sine wave rho=1+0.5 sin(2 pi (x+y+z)), velocity (1,1,1), "
+                       "p=1, cell averages, unit cube, periodic, CFL 0.4 (d = 3)",
+           "throughput": [fv3d_entry(N, 128, 10, 3) for N in (1, 2)]}
+    tts = []
+    for N in (1, 2):
+        for C in (5, 10, 15, 20):
+            e = dg2d_time_to_solution(N, C, run_cls=lambda n, c, p: FV3Run(n, c))
+            e["cells"] = f"{C}^3"
+            e["scheme"] = f"ADER-WENO{N + 1}"
+            e["paper_cpu_s_tjit"] = PAPER_FV3D_TJIT[(N, C)]
+            tts.append(e)
+    out["paper_fv_table_time_to_solution"] = tts
     return out
 
 
@@ -977,6 +1060,8 @@ def main():
                     help="only the 2-D workload (512x512 cells, N=5; for profiling the 2-D kernels)")
     ap.add_argument("--fv2d-only", action="store_true",
                     help="only the 2-D ADER-WENO workloads (1024^2 throughput, the paper's WENO timing meshes)")
+    ap.add_argument("--fv3d-only", action="store_true",
+                    help="only the 3-D ADER-WENO workloads (128^3 throughput, the paper's WENO timing meshes)")
     ap.add_argument("--limiter-only", action="store_true",
                     help="only the limited step on the 131072-cell Sod row (N=5; for profiling)")
     ap.add_argument("--dg3d-only", action="store_true",
@@ -994,7 +1079,7 @@ def main():
     # the oracle's host-core baseline runs first: its worker processes are
     # forked, which must happen before this process touches the GPU
     cpu = None
-    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only or a.fv2d_only):
+    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only or a.fv2d_only or a.fv3d_only):
         cpu = cpu_baseline(N)
         emit("cpu_baseline", cpu)
 
@@ -1020,6 +1105,9 @@ def main():
         return
     if a.fv2d_only:
         print(json.dumps({"fv2d_euler_sine": fv2d_section()}))
+        return
+    if a.fv3d_only:
+        print(json.dumps({"fv3d_euler_sine": fv3d_section()}))
         return
 
     run = DGRun(N, C, abi.FP64)
@@ -1112,6 +1200,7 @@ def main():
         emit("dg3d_euler_sine", dg3d_section())
         emit("limiter", limiter_section())
         emit("fv2d_euler_sine", fv2d_section())
+        emit("fv3d_euler_sine", fv3d_section())
         # compact summaries for the headline line
         out["fp32_predictor"] = {"value": fp32["value"], "ms_per_step": fp32["ms_per_step"],
                                  "frac": fp32["roofline"]["frac"],

@@ -776,70 +776,100 @@ __global__ void __launch_bounds__(kFv3dThreads) weno3d_kernel(Args3D A, double* 
   }
 }
 
-// Finite-volume update of the averages (in place): v -= sum over the six faces
-// of the time- and face-integrated Rusanov fluxes (signed, weighted by the
-// face node's weights), one thread per (cell, face, face node) gathered in LDS;
-// then the signal speeds of the new averages for the next step's dt.
-template <int N>
-struct Fv3Geo {
-  static constexpr int n = N + 1, F = n * n, IT = 6 * F, CPB = kFv3dThreads / IT;
-};
+// Finite-volume update of the averages (in place): v -= sum over the three
+// directions of the differences of the time- and face-integrated Rusanov
+// fluxes through a cell's two faces (weighted by the face nodes' weights);
+// then the signal speeds of the new averages for the next step's dt.  One
+// workgroup per tile of 4^3 cells: for each direction, one thread per
+// (face, face node) of the tile evaluates each face once (the tile's boundary
+// faces are evaluated by both neighbouring tiles, identically) into LDS, and
+// one thread per cell takes the difference of its two faces.
+constexpr int kF3 = 4;
 
 template <int N>
 __global__ void __launch_bounds__(kFv3dThreads) fv3d_corr_kernel(Args3D A) {
-  constexpr int n = N + 1, L = n * n * n, M = 5, F = n * n, IT = Fv3Geo<N>::IT, CPB = Fv3Geo<N>::CPB;
-  __shared__ double Gf[CPB * IT * M];
+  constexpr int n = N + 1, L = n * n * n, M = 5, F = n * n;
+  constexpr int kFaces = (kF3 + 1) * kF3 * kF3;
+  __shared__ double Gf[kFaces * F * M];
   __shared__ double bcast[3];
   __shared__ double part[3 * (kFv3dThreads / 64)];
   const double dt = step_dt3d<N>(A, bcast, false);
   if (!(dt > 0.0)) return;
-  const int64_t ncells = A.c[0] * A.c[1] * A.c[2];
-  const int64_t cell0 = (int64_t)blockIdx.x * CPB;
-  const int ncl = (int)((ncells - cell0) < CPB ? (ncells - cell0) : CPB);
+  const int64_t ty = (A.c[1] + kF3 - 1) / kF3, tz = (A.c[2] + kF3 - 1) / kF3;
+  const int64_t b = blockIdx.x;
+  const int64_t o[3] = {(b / (ty * tz)) * kF3, ((b / tz) % ty) * kF3, (b % tz) * kF3};
+  int ext[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ext[d] = (int)((A.c[d] - o[d]) < kF3 ? (A.c[d] - o[d]) : kF3);
   const int tid = threadIdx.x;
-  if (tid < ncl * IT) {
-    const int cl = tid / IT, rem = tid - cl * IT, f = rem / F, st = rem - f * F;
-    const int d = f >> 1;
-    const int64_t c = cell0 + cl;
-    int64_t nb[3] = {c / (A.c[1] * A.c[2]), (c / A.c[2]) % A.c[1], c % A.c[2]};
-    if (f & 1) nb[d] = (nb[d] + 1 == A.c[d]) ? 0 : nb[d] + 1;
-    else nb[d] = (nb[d] == 0) ? A.c[d] - 1 : nb[d] - 1;
-    const int64_t other = (nb[0] * A.c[1] + nb[1]) * A.c[2] + nb[2];
-    const int64_t cm = (f & 1) ? c : other, cp = (f & 1) ? other : c;
+  const int lc[3] = {tid / (kF3 * kF3), (tid / kF3) % kF3, tid % kF3};
+  const bool own = tid < kF3 * kF3 * kF3 && lc[0] < ext[0] && lc[1] < ext[1] && lc[2] < ext[2];
+  double dv[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) dv[r] = 0.0;
+
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+    const int nf = (ext[d] + 1) * ext[e1] * ext[e2];
     const double sc = dt / A.h[d];
-    double acc[M];
+    for (int w = tid; w < nf * F; w += kFv3dThreads) {
+      const int face = w / F, st = w - face * F;
+      const int fd = face / (ext[e1] * ext[e2]), r1 = (face / ext[e2]) % ext[e1], r2 = face % ext[e2];
+      // face fd lies between local cells fd - 1 (minus side) and fd (plus side)
+      int64_t pc[3], mc[3];
+      pc[d] = o[d] + fd;
+      if (pc[d] == A.c[d]) pc[d] = 0;
+      mc[d] = o[d] + fd - 1;
+      if (mc[d] < 0) mc[d] = A.c[d] - 1;
+      pc[e1] = mc[e1] = o[e1] + r1;
+      pc[e2] = mc[e2] = o[e2] + r2;
+      const int64_t cm = (mc[0] * A.c[1] + mc[1]) * A.c[2] + mc[2];
+      const int64_t cp = (pc[0] * A.c[1] + pc[1]) * A.c[2] + pc[2];
+      double acc[M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) acc[r] = 0.0;
+      for (int r = 0; r < M; ++r) acc[r] = 0.0;
 #pragma unroll
-    for (int a = 0; a < n; ++a) {
-      double qm[M], qp[M], Gr[M];
+      for (int a = 0; a < n; ++a) {
+        double qm[M], qp[M], Gr[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          qm[r] = reinterpret_cast<const double*>(A.tr)[((cm * 6 + 2 * d + 1) * L + a * F + st) * M + r];
+          qp[r] = reinterpret_cast<const double*>(A.tr)[((cp * 6 + 2 * d) * L + a * F + st) * M + r];
+        }
+        if (d == 0) rusanov3<0>(qm, qp, Gr, A.gamma);
+        else if (d == 1) rusanov3<1>(qm, qp, Gr, A.gamma);
+        else rusanov3<2>(qm, qp, Gr, A.gamma);
+        const double wa = c3_ops[N].w[a];
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
+      }
+      const double wst = c3_ops[N].w[st / n] * c3_ops[N].w[st % n];
+#pragma unroll
+      for (int r = 0; r < M; ++r) Gf[(face * F + st) * M + r] = wst * acc[r];
+    }
+    __syncthreads();
+    if (own) {
+      const int lo = (lc[d] * ext[e1] + lc[e1]) * ext[e2] + lc[e2];
+      const int hi = ((lc[d] + 1) * ext[e1] + lc[e1]) * ext[e2] + lc[e2];
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        qm[r] = reinterpret_cast<const double*>(A.tr)[((cm * 6 + 2 * d + 1) * L + a * F + st) * M + r];
-        qp[r] = reinterpret_cast<const double*>(A.tr)[((cp * 6 + 2 * d) * L + a * F + st) * M + r];
+        double s = 0.0;
+        for (int st = 0; st < F; ++st) s += Gf[(hi * F + st) * M + r] - Gf[(lo * F + st) * M + r];
+        dv[r] += s;
       }
-      if (d == 0) rusanov3<0>(qm, qp, Gr, A.gamma);
-      else if (d == 1) rusanov3<1>(qm, qp, Gr, A.gamma);
-      else rusanov3<2>(qm, qp, Gr, A.gamma);
-      const double wa = c3_ops[N].w[a];
-#pragma unroll
-      for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
     }
-    const double wst = ((f & 1) ? 1.0 : -1.0) * c3_ops[N].w[st / n] * c3_ops[N].w[st % n];
-#pragma unroll
-    for (int r = 0; r < M; ++r) Gf[(cl * IT + rem) * M + r] = wst * acc[r];
+    __syncthreads();
   }
-  __syncthreads();
+
   double lam[3] = {0.0, 0.0, 0.0};
   bool bad = false;
-  if (tid < ncl) {
-    const int64_t c = cell0 + tid;
+  if (own) {
+    const int64_t c = ((o[0] + lc[0]) * A.c[1] + (o[1] + lc[1])) * A.c[2] + (o[2] + lc[2]);
     double vn[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      double Fs = 0.0;
-      for (int e = 0; e < IT; ++e) Fs += Gf[(tid * IT + e) * M + r];
-      vn[r] = A.u[c * M + r] - Fs;
+      vn[r] = A.u[c * M + r] - dv[r];
       A.u[c * M + r] = vn[r];
     }
     bad = !Euler3::admissible(vn, A.gamma);
@@ -983,9 +1013,8 @@ hipError_t launch_weno3d(int NW, const Args3D& A, double* w, hipStream_t st) {
 }
 
 hipError_t launch_fv3d_corr(int NW, const Args3D& A, hipStream_t st) {
-  const int64_t cells = A.c[0] * A.c[1] * A.c[2];
-  const int cpb = NW == 1 ? Fv3Geo<1>::CPB : Fv3Geo<2>::CPB;
-  dim3 grid((unsigned)((cells + cpb - 1) / cpb)), block(kFv3dThreads);
+  const int64_t tiles = ((A.c[0] + kF3 - 1) / kF3) * ((A.c[1] + kF3 - 1) / kF3) * ((A.c[2] + kF3 - 1) / kF3);
+  dim3 grid((unsigned)tiles), block(kFv3dThreads);
   if (NW == 1) hipLaunchKernelGGL((fv3d_corr_kernel<1>), grid, block, 0, st, A);
   else if (NW == 2) hipLaunchKernelGGL((fv3d_corr_kernel<2>), grid, block, 0, st, A);
   else return hipErrorInvalidValue;
