@@ -1,4 +1,5 @@
-"""Planted mistakes in the 2-D and 3-D oracles: each must break at least one pin.
+"""Planted mistakes in the 2-D and 3-D oracles (DG and ADER-WENO): each must
+break at least one pin.
 
 Each mistake is planted for the duration of one test, by a copy of the
 operator tables or by replacing one oracle function or model method (CPU
@@ -208,3 +209,68 @@ def test_planted_fv2d_mistakes_break_a_pin(monkeypatch):
     orig_rx = fv2d.rusanov_x
     monkeypatch.setattr(fv2d, "rusanov_x", lambda pde, qm, qp: orig_rx(pde, qp, qm))   # face states swapped
     assert not _pins_fv2d()
+
+
+# 3-D ADER-WENO finite volumes: the reconstruction's exactness for a
+# trilinear product, the reduction to the pinned 2-D scheme along z, the
+# closed-form time step on a uniform state, and conservation
+
+
+def _pins_fv3d():
+    from oracle import fv2d, fv3d
+    N = 2
+    ops = basis.build_operators(N)
+    e3 = dg3d.Euler3D()
+    ok = True
+    # reconstruction of x*y*z (degree 1 per direction, exact for degree 2)
+    C = 7
+    e = np.linspace(0, 1, C + 1)
+    ax = (e[1:] ** 2 - e[:-1] ** 2) / 2 * C
+    v = (ax[:, None, None] * ax[None, :, None] * ax[None, None, :])[..., None]
+    w = fv3d.reconstruct3d(v, ops)
+    xs = W.cell_points(C, N + 1)
+    exact = xs[:, None, None, :, None, None] * xs[None, :, None, None, :, None] * xs[None, None, :, None, None, :]
+    s = slice(2, C - 2)
+    ok &= np.abs(w[s, s, s, :, :, :, 0] - exact[s, s, s]).max() <= 1e-12
+    # flow in the x-y plane, constant along z, against the 2-D scheme
+    v2 = W.euler2d_sine_averages(6, 5, velocity=(0.7, -0.4))
+    dt = 0.003
+    ref, _, _ = fv2d.fv2d_step(ops, dg2d.Euler2D(), v2, dt, 1 / 6, 1 / 5)
+    v3 = np.zeros((6, 5, 3, 5))
+    v3[..., 0], v3[..., 1], v3[..., 2], v3[..., 4] = (v2[..., k][:, :, None] for k in range(4))
+    got, _, _ = fv3d.fv3d_step(ops, e3, v3, dt, (1 / 6, 1 / 5, 1 / 3))
+    ok &= np.abs(got[..., [0, 1, 2, 4]] - ref[:, :, None, :]).max() <= 1e-13
+    # Sec. 1.5 with d = 3 on a uniform state: CFL / 3 * min_d h_d / (|u_d| + c)
+    q = np.array([1.2, 0.6, -0.3, 0.24, 2.9])
+    u = np.tile(q, (3, 3, 3, 1))
+    c = np.sqrt(1.4 * 0.4 * (q[4] - 0.5 * (q[1] ** 2 + q[2] ** 2 + q[3] ** 2) / q[0]) / q[0])
+    hh = (0.1, 0.2, 0.05)
+    want = 0.4 / 3 * min(hh[d] / (abs(q[1 + d] / q[0]) + c) for d in range(3))
+    ok &= abs(fv3d.fv3d_dt(e3, u, hh, 0.4) - want) <= 1e-15 * want
+    # conservation of the five totals
+    v0 = W.euler3d_sine_averages(5, 4, 3)
+    vn, _, _ = fv3d.fv3d_step(ops, e3, v0, 0.002, (1 / 5, 1 / 4, 1 / 3))
+    ok &= np.abs(vn.sum(axis=(0, 1, 2)) - v0.sum(axis=(0, 1, 2))).max() <= 1e-12
+    return bool(ok)
+
+
+def test_unmutated_fv3d_oracle_passes_its_pins():
+    assert _pins_fv3d()
+
+
+def test_planted_fv3d_mistakes_break_a_pin(monkeypatch):
+    from oracle import fv3d
+
+    def no_z_sweep(v, ops):        # the z sweep forgotten: the x-y reconstruction broadcast along z
+        wy = fv3d._along(fv3d._along(v, ops, 0), ops, 1)
+        return np.repeat(wy[..., None, :], ops.n, axis=-2)
+    monkeypatch.setattr(fv3d, "reconstruct3d", no_z_sweep)
+    assert not _pins_fv3d()
+    monkeypatch.undo()
+    orig_rs = fv3d.rusanov
+    monkeypatch.setattr(fv3d, "rusanov", lambda pde, qm, qp, d: orig_rs(pde, qp, qm, d))   # face states swapped
+    assert not _pins_fv3d()
+    monkeypatch.undo()
+    monkeypatch.setattr(fv3d, "fv3d_dt", lambda pde, v, h, cfl: cfl / 2.0 * min(
+        h[d] / float(pde.speed(v, d).max()) for d in range(3)))                               # d = 2 factor
+    assert not _pins_fv3d()
