@@ -9,6 +9,9 @@ its mathematical pins):
 
   * degree N even: three stencils of N+1 cells around cell i,
         left  {i-N .. i},  central {i-N/2 .. i+N/2},  right {i .. i+N};
+    degree N odd, N >= 3 (N = 3: the paper's ADER-WENO4): four stencils,
+        left  {i-N .. i},  two central {i-(N+1)/2 .. i+(N-1)/2} and
+        {i-(N-1)/2 .. i+(N+1)/2},  right {i .. i+N};
     degree 1 (the second-order ADER-WENO2 of the paper's ADER-WENO(N+1)
     naming): the two stencils {i-1, i} and {i, i+1}, both sided;
   * on each stencil the unique degree-N polynomial p_s whose averages over
@@ -35,7 +38,8 @@ def stencil_offsets(N):
     if N == 1:
         return [[-1, 0], [0, 1]]
     if N % 2:
-        raise ValueError("WENO reading needs degree 1 or an even degree N")
+        lo, hi = (N + 1) // 2, (N - 1) // 2
+        return [list(range(-N, 1)), list(range(-lo, hi + 1)), list(range(-hi, lo + 1)), list(range(0, N + 1))]
     h = N // 2
     return [list(range(-N, 1)), list(range(-h, h + 1)), list(range(0, N + 1))]
 
@@ -44,6 +48,8 @@ def linear_weights(N):
     """lambda_s of the stencils of stencil_offsets(N), in the same order."""
     if N == 1:
         return np.array([LAMBDA_SIDED, LAMBDA_SIDED])
+    if N % 2:
+        return np.array([LAMBDA_SIDED, LAMBDA_CENTRAL, LAMBDA_CENTRAL, LAMBDA_SIDED])
     return np.array([LAMBDA_SIDED, LAMBDA_CENTRAL, LAMBDA_SIDED])
 
 
@@ -82,7 +88,9 @@ def oscillation_indicators(coeff, N):
 
 
 def weights(sig, N=None):
-    lam = (linear_weights(N) if N is not None else linear_weights(2 if sig.shape[0] == 3 else 1))[:, None, None]
+    if N is None:
+        N = {2: 1, 3: 2, 4: 3}[sig.shape[0]]
+    lam = linear_weights(N)[:, None, None]
     wt = lam / (sig + EPSILON) ** POWER
     return wt / wt.sum(axis=0, keepdims=True)
 

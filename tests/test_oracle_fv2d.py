@@ -8,7 +8,7 @@
 * A uniform state is kept; the totals of all four variables are conserved.
 * The 2-D sine wave of Sec. 2.1: the error falls at the order of the
   reconstruction degree + 1 (degree 1: the paper's ADER-WENO2; degree 2:
-  ADER-WENO3).
+  ADER-WENO3; degree 3: ADER-WENO4, measured 5.3 on 8 -> 16 cells).
 """
 
 import numpy as np
@@ -25,7 +25,7 @@ def _poly_avgs(c, C):
     return (np.polyval(Pi, e[1:]) - np.polyval(Pi, e[:-1])) * C
 
 
-@pytest.mark.parametrize("N", [1, 2])
+@pytest.mark.parametrize("N", [1, 2, 3])
 def test_reconstruction_exact_for_tensor_polynomials(N):
     ops = basis.build_operators(N)
     rng = np.random.default_rng(N)
@@ -51,7 +51,7 @@ def _x_only(C, Cy, seed):
     return v1, v2
 
 
-@pytest.mark.parametrize("N", [1, 2])
+@pytest.mark.parametrize("N", [1, 2, 3])
 def test_reduces_to_the_1d_scheme_along_each_axis(N):
     ops = basis.build_operators(N)
     C, Cy, dt = 24, 5, 0.004
@@ -67,7 +67,7 @@ def test_reduces_to_the_1d_scheme_along_each_axis(N):
     assert np.abs(np.swapaxes(goty, 0, 1)[..., [0, 2, 1, 3]] - got).max() <= 1e-13
 
 
-@pytest.mark.parametrize("N", [1, 2])
+@pytest.mark.parametrize("N", [1, 2, 3])
 def test_uniform_state_and_conservation(N):
     ops = basis.build_operators(N)
     e = dg2d.Euler2D()
@@ -80,7 +80,7 @@ def test_uniform_state_and_conservation(N):
     assert np.abs(vn.sum(axis=(0, 1)) - v0.sum(axis=(0, 1))).max() <= 1e-12
 
 
-@pytest.mark.parametrize("N,meshes,p_min", [(1, (32, 64), 1.7), (2, (16, 32), 2.6)])
+@pytest.mark.parametrize("N,meshes,p_min", [(1, (32, 64), 1.7), (2, (16, 32), 2.6), (3, (8, 16), 3.5)])
 def test_sine_wave_order(N, meshes, p_min):
     """Degree 1 is pre-asymptotic on 16 cells (its nonlinear weights pick the
     flatter one-sided slope near the extrema): 16 -> 32 gives order 1.06,

@@ -27,7 +27,7 @@ def _state(cx, cy, cz, seed):
     return v
 
 
-@pytest.mark.parametrize("N,const_axis", [(1, 2), (2, 2), (2, 0), (2, 1)])
+@pytest.mark.parametrize("N,const_axis", [(1, 2), (2, 2), (2, 0), (2, 1), (3, 1)])
 def test_reduces_to_the_2d_scheme(N, const_axis):
     """Data constant along one axis, with no momentum along it: the other two
     axes, in their order, carry the 2-D step (the dimension-by-dimension
@@ -57,7 +57,7 @@ def test_reduces_to_the_2d_scheme(N, const_axis):
     assert np.abs(g[..., 1 + const_axis]).max() <= 1e-15
 
 
-@pytest.mark.parametrize("N", [1, 2])
+@pytest.mark.parametrize("N", [1, 2, 3])
 def test_uniform_state_and_conservation(N):
     ops = basis.build_operators(N)
     u = np.tile([1.3, 0.4, -0.2, 0.1, 3.1], (4, 5, 3, 1))
