@@ -596,15 +596,16 @@ def dg2d_time_to_solution(N, C, precision=0, chunk=128, run_cls=None):
 # The paper's CPU seconds for its 2-D ADER-WENO timing runs (Sec. 3, the
 # finite-volume table: T_JIT, sine wave to t = 1), for context only.
 PAPER_FV2D_TJIT = {(1, 5): 4.31e-2, (1, 10): 1.33e-1, (1, 15): 2.22e-1, (1, 20): 4.40e-1,
-                   (2, 5): 8.50e-2, (2, 10): 2.27e-1, (2, 15): 5.89e-1, (2, 20): 1.35}
+                   (2, 5): 8.50e-2, (2, 10): 2.27e-1, (2, 15): 5.89e-1, (2, 20): 1.35,
+                   (3, 5): 1.65e-1, (3, 10): 4.64e-1, (3, 15): 8.52e-1, (3, 20): 1.84}
 
 
 def fv2d_section():
     out = {"workload": "2-D ADER-WENO, Euler gamma=1.4, sine wave rho=1+0.5 sin(2 pi (x+y)), velocity (1,1), "
                        "p=1, cell averages, unit square, periodic, CFL 0.4 (d = 2)",
-           "throughput": [fv2d_entry(N, 1024, 20, 5) for N in (1, 2)]}
+           "throughput": [fv2d_entry(N, 1024, 20, 5) for N in (1, 2, 3)]}
     tts = []
-    for N in (1, 2):
+    for N in (1, 2, 3):
         for C in (5, 10, 15, 20):
             e = dg2d_time_to_solution(N, C, run_cls=lambda n, c, p: FV2Run(n, c))
             e["scheme"] = f"ADER-WENO{N + 1}"
@@ -693,12 +694,15 @@ class DG3Run:
     """The 3-D sine wave of Sec. 2.1 (rho = 1 + 0.5 sin(2 pi (x + y + z)),
     velocity (1, 1, 1), p = 1, gamma = 1.4, unit cube, periodic) on C^3 cells."""
 
-    def __init__(self, N, C, precision, cfl=0.4):
+    def __init__(self, N, C, precision, cfl=None):
         import torch
         from paper_2409_12483_amd import abi
         from paper_2409_12483_amd import workloads as W
         self.abi, self.torch = abi, torch
         dev = torch.device("cuda:0")
+        # CFL 0.4 lies beyond the linear stability bound for N >= 8 (as in 1-D)
+        cfl = cfl if cfl is not None else (0.4 if N <= 7 else 0.3)
+        self.cfl = cfl
         self.u = torch.tensor(W.euler3d_sine_wave(C, C, C, N), device=dev)
         self.t = torch.zeros(1, dtype=torch.float64, device=dev)
         self.te = torch.full((1,), 1.0e300, dtype=torch.float64, device=dev)
@@ -745,7 +749,7 @@ def dg3d_entry(N, C, precision, steps, warmup):
         peak = total / t_roof * 1e-12
     n = N + 1
     return {"N": N, "cells": f"{C}^3", "precision": "fp64" if precision == abi.FP64 else "fp32_predictor",
-            "status": status, "value": round(steps * cells * n ** 3 * 5 / secs, 1), "unit": "DoF-updates/s",
+            "cfl": r.cfl, "status": status, "value": round(steps * cells * n ** 3 * 5 / secs, 1), "unit": "DoF-updates/s",
             "ms_per_step": round(secs / steps * 1e3, 5), "sweeps_per_cell": round(spc, 3),
             "roofline": {"bound": "alu", "achieved": round(total / secs * 1e-12, 3), "peak": round(peak, 2),
                          "unit": "TFLOP/s", "frac": round(t_roof / secs, 4),
@@ -769,8 +773,8 @@ def dg3d_time_to_solution(N, C, precision=0):
     el = time.perf_counter() - t0
     st = int(r.st.item())
     r.close()
-    return {"N": N, "cells": f"{C}^3", "gpu_wall_s": round(el, 5), "steps_approx": int(round(1.0 / dt)),
-            "status": st}
+    return {"N": N, "cells": f"{C}^3", "cfl": r.cfl, "gpu_wall_s": round(el, 5),
+            "steps_approx": int(round(1.0 / dt)), "status": st}
 
 
 # The paper's CPU seconds for its 3-D ADER-DG timing runs (Sec. 3, the 3-D DG
@@ -784,7 +788,7 @@ PAPER_DG3D_TJIT = {
     (9, 5): 1050.0, (9, 6): 2230.0, (9, 7): 3690.0}
 
 
-def dg3d_section(quick=False):
+def dg3d_section(quick=False, table11_full=False):
     from paper_2409_12483_amd import abi
     out = {"workload": "ADER-DG 3D Euler gamma=1.4, sine wave rho=1+0.5 sin(2 pi (x+y+z)), velocity (1,1,1), "
                        "p=1, unit cube, periodic, CFL 0.4, Rusanov"}
@@ -797,11 +801,11 @@ def dg3d_section(quick=False):
     out["per_degree_fp64"] = [dg3d_entry(N, C, abi.FP64, 10, 3) for N, C in sizes.items()]
     out["n6_32c_fp32_predictor"] = dg3d_entry(6, 32, abi.FP32_PREDICTOR, 10, 3)
     out["n9_16c_fp32_predictor"] = dg3d_entry(9, 16, abi.FP32_PREDICTOR, 10, 3)
-    # the paper's 3-D DG timing runs: every mesh up to N = 5, the smallest and
-    # the largest mesh above (whole runs of 1000-2500 steps)
+    # the paper's 3-D DG timing runs: every mesh up to N = 5, the smallest
+    # above (whole runs of 1000-3600 steps; every mesh with --table11-full)
     tts = []
     for N in range(1, 10):
-        for C in ((4, 5, 6, 7) if N <= 5 else (4, 7)):
+        for C in ((4, 5, 6, 7) if N <= 5 or table11_full else (4,)):
             e = dg3d_time_to_solution(N, C)
             e["paper_cpu_s_tjit"] = PAPER_DG3D_TJIT[(N, C)]
             tts.append(e)
@@ -855,15 +859,16 @@ def fv3d_entry(N, C, steps, warmup):
 # The paper's CPU seconds for its 3-D ADER-WENO timing runs (Sec. 3, the 3-D
 # finite-volume table: T_JIT, sine wave to t = 1), for context only.
 PAPER_FV3D_TJIT = {(1, 5): 1.45, (1, 10): 4.71, (1, 15): 2.00e1, (1, 20): 5.87e1,
-                   (2, 5): 4.78, (2, 10): 1.34e1, (2, 15): 6.18e1, (2, 20): 2.23e2}
+                   (2, 5): 4.78, (2, 10): 1.34e1, (2, 15): 6.18e1, (2, 20): 2.23e2,
+                   (3, 5): 1.33e1, (3, 10): 4.39e1, (3, 15): 1.96e2, (3, 20): 6.65e2}
 
 
 def fv3d_section():
     out = {"workload": "3-D ADER-WENO, Euler gamma=1.4, sine wave rho=1+0.5 sin(2 pi (x+y+z)), velocity (1,1,1), "
                        "p=1, cell averages, unit cube, periodic, CFL 0.4 (d = 3)",
-           "throughput": [fv3d_entry(N, 128, 10, 3) for N in (1, 2)]}
+           "throughput": [fv3d_entry(N, 128, 10, 3) for N in (1, 2, 3)]}
     tts = []
-    for N in (1, 2):
+    for N in (1, 2, 3):
         for C in (5, 10, 15, 20):
             e = dg2d_time_to_solution(N, C, run_cls=lambda n, c, p: FV3Run(n, c))
             e["cells"] = f"{C}^3"
@@ -1060,6 +1065,8 @@ def main():
                     help="only the 2-D workload (512x512 cells, N=5; for profiling the 2-D kernels)")
     ap.add_argument("--fv2d-only", action="store_true",
                     help="only the 2-D ADER-WENO workloads (1024^2 throughput, the paper's WENO timing meshes)")
+    ap.add_argument("--table11-full", action="store_true",
+                    help="the paper's 3-D DG timing runs on every mesh for N = 6..9 too (about a minute more)")
     ap.add_argument("--fv3d-only", action="store_true",
                     help="only the 3-D ADER-WENO workloads (128^3 throughput, the paper's WENO timing meshes)")
     ap.add_argument("--limiter-only", action="store_true",
@@ -1197,7 +1204,7 @@ def main():
         emit("c5_serving_fp32_predictor", [c5_serving(rate, 150, precision=abi.FP32_PREDICTOR)
                                            for rate in (50.0, 100.0)])
         emit("dg2d_euler_sine_512x512", dg2d_section())
-        emit("dg3d_euler_sine", dg3d_section())
+        emit("dg3d_euler_sine", dg3d_section(table11_full=a.table11_full))
         emit("limiter", limiter_section())
         emit("fv2d_euler_sine", fv2d_section())
         emit("fv3d_euler_sine", fv3d_section())

@@ -49,7 +49,7 @@ typedef struct {
   int32_t picard_max_iter; /* <= 0: 64 */
   int32_t scheme;          /* ADERDG_SCHEME_DG (0), or ADERDG_SCHEME_FV: ADER-WENO finite
                               volumes (Sec. 1.3 with d = 2), N = the WENO degree (1: the
-                              paper's ADER-WENO2, 2: ADER-WENO3), FP64 only */
+                              paper's ADER-WENO2, 2: ADER-WENO3, 3: ADER-WENO4), FP64 only */
 } aderdg2d_config;
 
 typedef struct aderdg2d_handle aderdg2d_handle;
@@ -93,8 +93,9 @@ int aderdg2d_predict(aderdg2d_handle* h, const double* u, double t, double dt, v
  * of the averages, dimension by dimension (along x for every row of cells,
  * giving the averages over y at the x nodes, then along y at every x node;
  * degree 1: stencils {i-1, i}, {i, i+1}; degree 2: {i-2..i}, {i-1..i+1},
- * {i..i+2}; weights lambda_s / (sigma_s + 1e-14)^8, lambda = 1e5 for the
- * central stencil, else 1), the predictor above from those nodal values, and
+ * {i..i+2}; degree 3: {i-3..i}, {i-2..i+1}, {i-1..i+2}, {i..i+3}; weights
+ * lambda_s / (sigma_s + 1e-14)^8, lambda = 1e5 for the central stencils,
+ * else 1), the predictor above from those nodal values, and
  * v -= sum over the four faces of the time- and face-integrated Rusanov
  * fluxes; dt = CFL / 2 min(dx / max(|u|+c), dy / max(|v|+c)) over the
  * averages.  Three launches per step.

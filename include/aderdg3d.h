@@ -32,7 +32,7 @@ extern "C" {
 #endif
 
 typedef struct {
-  int32_t N;               /* 1..9 (DG); 1..2 (ADER-WENO) */
+  int32_t N;               /* 1..9 (DG); 1..3 (ADER-WENO) */
   int32_t precision;       /* enum aderdg_prec */
   int64_t cells_x, cells_y, cells_z;   /* >= 1, product <= 2^31 - 1 */
   double x0, x1, y0, y1, z0, z1;       /* domain, upper > lower */
@@ -43,7 +43,8 @@ typedef struct {
   int32_t picard_max_iter; /* <= 0: 64 */
   int32_t scheme;          /* ADERDG_SCHEME_DG (0), or ADERDG_SCHEME_FV: ADER-WENO finite
                               volumes (Sec. 1.3 with d = 3), N = the WENO degree (1: the
-                              paper's ADER-WENO2, 2: ADER-WENO3), FP64 only; the state is
+                              paper's ADER-WENO2, 2: ADER-WENO3, 3: ADER-WENO4), FP64 only;
+                              the state is
                               then the cell averages v [cells_x][cells_y][cells_z][5] */
 } aderdg3d_config;
 

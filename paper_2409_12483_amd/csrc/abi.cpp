@@ -73,7 +73,8 @@ int ensure_tables(int device) {
   if (g_tables_devices.count(device)) return ADERDG_OK;
   DevOps* ops = g_host_ops;
   DevOpsF* opsf = g_host_opsf;
-  static DevWeno weno[3];   // WENO degree 2, 4 (finite-volume step) and 1 (limiter subgrid)
+  static DevWeno weno[4];   // WENO degree 2, 4 (finite-volume step), 1 (limiter subgrid), 3
+  static DevWeno fvw[3];    // degrees 1, 2, 3 (2-D and 3-D finite volumes)
   std::memset(g_host_ops, 0, sizeof(g_host_ops));
   std::memset(g_host_opsf, 0, sizeof(g_host_opsf));
   std::memset(weno, 0, sizeof(weno));
@@ -98,9 +99,10 @@ int ensure_tables(int device) {
     for (int s = 0; s < t.Ns; ++s)
       for (int k = 0; k < n; ++k) ops[N].P[s][k] = t.P[s][k];
   }
-  for (int wi = 0; wi < 3; ++wi) {
+  for (int wi = 0; wi < 4; ++wi) {
     WenoTables w;
-    if (!build_weno_tables(wi < 2 ? 2 * (wi + 1) : 1, w)) return fail(ADERDG_E_DEVICE, "WENO table construction failed");
+    const int deg = wi < 2 ? 2 * (wi + 1) : wi == 2 ? 1 : 3;
+    if (!build_weno_tables(deg, w)) return fail(ADERDG_E_DEVICE, "WENO table construction failed");
     for (int s = 0; s < w.nstencils; ++s)
       for (int i = 0; i < w.n; ++i)
         for (int j = 0; j < w.n; ++j) {
@@ -122,9 +124,12 @@ int ensure_tables(int device) {
     e = upload_lim_tables(lim, &weno[2]);
     if (e != hipSuccess) return fail_hip(e, "upload of limiter tables");
   }
-  e = upload_tables_2d(ops, opsf, &weno[2], &weno[0]);
+  fvw[0] = weno[2];
+  fvw[1] = weno[0];
+  fvw[2] = weno[3];
+  e = upload_tables_2d(ops, opsf, fvw);
   if (e != hipSuccess) return fail_hip(e, "upload of 2-D operator tables");
-  e = upload_tables_3d(ops, opsf, &weno[2], &weno[0]);
+  e = upload_tables_3d(ops, opsf, fvw);
   if (e != hipSuccess) return fail_hip(e, "upload of 3-D operator tables");
   g_tables_devices.insert(device);
   return ADERDG_OK;
@@ -743,8 +748,8 @@ int aderdg2d_init(const aderdg2d_config* cfg, void* hip_stream, aderdg2d_handle*
   if (c.precision != ADERDG_FP64 && c.precision != ADERDG_FP32_PREDICTOR)
     return fail(ADERDG_E_INVAL, "unknown precision");
   if (c.scheme != ADERDG_SCHEME_DG && c.scheme != ADERDG_SCHEME_FV) return fail(ADERDG_E_INVAL, "unknown scheme");
-  if (c.scheme == ADERDG_SCHEME_FV && (c.N > 2 || c.precision != ADERDG_FP64))
-    return fail(ADERDG_E_INVAL, "2-D ADER-WENO: N (the WENO degree) must be 1 or 2, precision FP64");
+  if (c.scheme == ADERDG_SCHEME_FV && (c.N > 3 || c.precision != ADERDG_FP64))
+    return fail(ADERDG_E_INVAL, "2-D ADER-WENO: N (the WENO degree) must be 1..3, precision FP64");
   if (c.cells_x < 1 || c.cells_y < 1 || c.cells_x > INT32_MAX / c.cells_y)
     return fail(ADERDG_E_INVAL, "cells_x, cells_y must be >= 1 with a product below 2^31");
   if (!(c.x1 > c.x0) || !(c.y1 > c.y0) || !std::isfinite(c.x1 - c.x0) || !std::isfinite(c.y1 - c.y0))
@@ -915,8 +920,8 @@ int aderdg3d_init(const aderdg3d_config* cfg, void* hip_stream, aderdg3d_handle*
   if (c.precision != ADERDG_FP64 && c.precision != ADERDG_FP32_PREDICTOR)
     return fail(ADERDG_E_INVAL, "unknown precision");
   if (c.scheme != ADERDG_SCHEME_DG && c.scheme != ADERDG_SCHEME_FV) return fail(ADERDG_E_INVAL, "unknown scheme");
-  if (c.scheme == ADERDG_SCHEME_FV && (c.N < 1 || c.N > 2 || c.precision != ADERDG_FP64))
-    return fail(ADERDG_E_INVAL, "3-D ADER-WENO: N (the WENO degree) must be 1 or 2, precision FP64");
+  if (c.scheme == ADERDG_SCHEME_FV && (c.N < 1 || c.N > 3 || c.precision != ADERDG_FP64))
+    return fail(ADERDG_E_INVAL, "3-D ADER-WENO: N (the WENO degree) must be 1..3, precision FP64");
   if (c.N < 1 || !supported_3d(c.N, c.precision))
     return fail(ADERDG_E_INVAL, "N must be in 1..9");
   if (c.cells_x < 1 || c.cells_y < 1 || c.cells_z < 1 || c.cells_x > INT32_MAX / c.cells_y ||

@@ -37,8 +37,8 @@ struct DevOpsF {
 };
 
 struct DevWeno {
-  double R[3][kWenoMaxn][kWenoMaxn];
-  double S[3][kWenoMaxn][kWenoMaxn];
+  double R[4][kWenoMaxn][kWenoMaxn];   // up to four stencils (odd degrees >= 3)
+  double S[4][kWenoMaxn][kWenoMaxn];
 };
 
 struct PdeParams {

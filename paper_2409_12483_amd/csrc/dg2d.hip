@@ -36,7 +36,7 @@ namespace aderdg {
 
 __constant__ DevOps c2_ops[kDevMaxn];
 __constant__ DevOpsF c2_opsf[kDevMaxn];
-__constant__ DevWeno c2_weno[2];   // WENO of degree 1 (two one-sided stencils) and 2 (three stencils)
+__constant__ DevWeno c2_weno[3];   // WENO of degree 1 (two one-sided stencils), 2 (three) and 3 (four)
 
 // ------------------------------------------------------------- model ----
 // Sec. 2, eq. system_of_equations with two space dimensions:
@@ -948,16 +948,18 @@ hipError_t launch_weno2d(int NW, const Args2D& A, double* w, hipStream_t st) {
   dim3 grid((unsigned)tiles), block(kFv2dThreads);
   if (NW == 1) hipLaunchKernelGGL((weno2d_kernel<1>), grid, block, 0, st, A, w);
   else if (NW == 2) hipLaunchKernelGGL((weno2d_kernel<2>), grid, block, 0, st, A, w);
+  else if (NW == 3) hipLaunchKernelGGL((weno2d_kernel<3>), grid, block, 0, st, A, w);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_fv2d_corr(int NW, const Args2D& A, hipStream_t st) {
   const int64_t cells = A.cx * A.cy;
-  const int cpb = NW == 1 ? Fv2Geo<1>::CPB : Fv2Geo<2>::CPB;
+  const int cpb = NW == 1 ? Fv2Geo<1>::CPB : NW == 2 ? Fv2Geo<2>::CPB : Fv2Geo<3>::CPB;
   dim3 grid((unsigned)((cells + cpb - 1) / cpb)), block(kFv2dThreads);
   if (NW == 1) hipLaunchKernelGGL((fv2d_corr_kernel<1>), grid, block, 0, st, A);
   else if (NW == 2) hipLaunchKernelGGL((fv2d_corr_kernel<2>), grid, block, 0, st, A);
+  else if (NW == 3) hipLaunchKernelGGL((fv2d_corr_kernel<3>), grid, block, 0, st, A);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -968,15 +970,12 @@ hipError_t launch_fv2d_lambda(const Args2D& A, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno1,
-                            const DevWeno* weno2) {
+hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c2_ops), ops, sizeof(DevOps) * kDevMaxn);
   if (e != hipSuccess) return e;
   e = hipMemcpyToSymbol(HIP_SYMBOL(c2_opsf), opsf, sizeof(DevOpsF) * kDevMaxn);
   if (e != hipSuccess) return e;
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c2_weno), weno1, sizeof(DevWeno));
-  if (e != hipSuccess) return e;
-  return hipMemcpyToSymbol(HIP_SYMBOL(c2_weno), weno2, sizeof(DevWeno), sizeof(DevWeno));
+  return hipMemcpyToSymbol(HIP_SYMBOL(c2_weno), weno, sizeof(DevWeno) * 3);
 }
 
 }  // namespace aderdg

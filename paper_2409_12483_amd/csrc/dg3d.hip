@@ -25,7 +25,7 @@ namespace aderdg {
 
 __constant__ DevOps c3_ops[kDevMaxn];
 __constant__ DevOpsF c3_opsf[kDevMaxn];
-__constant__ DevWeno c3_weno[2];   // WENO of degree 1 and 2
+__constant__ DevWeno c3_weno[3];   // WENO of degree 1 (two one-sided stencils), 2 (three) and 3 (four)
 
 // Sec. 2, eq. system_of_equations in three dimensions:
 // U = (rho, rho u, rho v, rho w, E), p = (gamma - 1) (E - rho |v|^2 / 2).
@@ -1008,6 +1008,7 @@ hipError_t launch_weno3d(int NW, const Args3D& A, double* w, hipStream_t st) {
   dim3 grid((unsigned)tiles), block(kFv3dThreads);
   if (NW == 1) hipLaunchKernelGGL((weno3d_kernel<1>), grid, block, 0, st, A, w);
   else if (NW == 2) hipLaunchKernelGGL((weno3d_kernel<2>), grid, block, 0, st, A, w);
+  else if (NW == 3) hipLaunchKernelGGL((weno3d_kernel<3>), grid, block, 0, st, A, w);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -1017,6 +1018,7 @@ hipError_t launch_fv3d_corr(int NW, const Args3D& A, hipStream_t st) {
   dim3 grid((unsigned)tiles), block(kFv3dThreads);
   if (NW == 1) hipLaunchKernelGGL((fv3d_corr_kernel<1>), grid, block, 0, st, A);
   else if (NW == 2) hipLaunchKernelGGL((fv3d_corr_kernel<2>), grid, block, 0, st, A);
+  else if (NW == 3) hipLaunchKernelGGL((fv3d_corr_kernel<3>), grid, block, 0, st, A);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -1028,15 +1030,12 @@ hipError_t launch_fv3d_lambda(const Args3D& A, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t upload_tables_3d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno1,
-                            const DevWeno* weno2) {
+hipError_t upload_tables_3d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c3_ops), ops, sizeof(DevOps) * kDevMaxn);
   if (e != hipSuccess) return e;
   e = hipMemcpyToSymbol(HIP_SYMBOL(c3_opsf), opsf, sizeof(DevOpsF) * kDevMaxn);
   if (e != hipSuccess) return e;
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c3_weno), weno1, sizeof(DevWeno));
-  if (e != hipSuccess) return e;
-  return hipMemcpyToSymbol(HIP_SYMBOL(c3_weno), weno2, sizeof(DevWeno), sizeof(DevWeno));
+  return hipMemcpyToSymbol(HIP_SYMBOL(c3_weno), weno, sizeof(DevWeno) * 3);
 }
 
 }  // namespace aderdg

@@ -55,9 +55,9 @@ int cells_per_block_corr2d(int N);
 hipError_t launch_clock2d_begin(Clock2D* clk, const double* t_user, hipStream_t st);
 hipError_t launch_clock2d_end(const Clock2D* clk, double* t_user, double* dt_user,
                               int32_t* status_user, int parity, hipStream_t st);
-hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno1,
-                            const DevWeno* weno2);
-// ADER-WENO finite volumes (scheme 1; NW = reconstruction degree = predictor degree, 1 or 2):
+hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf,
+                            const DevWeno* weno);   // WENO of degree 1, 2, 3
+// ADER-WENO finite volumes (scheme 1; NW = reconstruction degree = predictor degree, 1..3):
 // nodal WENO values w [cells][n][n][4] of the averages v (A.u), the update of
 // the averages in place from the predictor's traces, the signal speed of the
 // start state (kFv2dThreads per workgroup).

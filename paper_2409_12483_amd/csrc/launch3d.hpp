@@ -53,10 +53,10 @@ hipError_t launch_lambda3d(int N, const Args3D& A, int64_t blocks, hipStream_t s
 hipError_t launch_clock3d_begin(Clock3D* clk, const double* t_user, hipStream_t st);
 hipError_t launch_clock3d_end(const Clock3D* clk, double* t_user, double* dt_user,
                               int32_t* status_user, int parity, hipStream_t st);
-hipError_t upload_tables_3d(const DevOps* ops, const DevOpsF* opsf, const DevWeno* weno1,
-                            const DevWeno* weno2);
+hipError_t upload_tables_3d(const DevOps* ops, const DevOpsF* opsf,
+                            const DevWeno* weno);   // WENO of degree 1, 2, 3
 // ADER-WENO finite volumes (scheme 1; NW = reconstruction degree = predictor
-// degree, 1 or 2): nodal WENO values w [cells][n][n][n][5] of the averages
+// degree, 1..3): nodal WENO values w [cells][n][n][n][5] of the averages
 // (A.u), the update of the averages in place from the predictor's traces, the
 // signal speeds of the start state.
 constexpr int kFv3dThreads = 256;

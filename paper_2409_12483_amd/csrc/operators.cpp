@@ -170,7 +170,7 @@ bool build_op_tables(int N, OpTables& o) {
 }
 
 bool build_weno_tables(int Nw, WenoTables& t) {
-  if (Nw < 1 || Nw > 8 || (Nw > 1 && Nw % 2)) return false;
+  if (Nw < 1 || Nw > 8) return false;
   t = WenoTables();
   const int n = Nw + 1;       // nodes of the reconstruction = stencil width
   t.Nw = Nw;
@@ -180,6 +180,12 @@ bool build_weno_tables(int Nw, WenoTables& t) {
     t.nstencils = 2;
     t.offset[0] = -1;
     t.offset[1] = 0;
+  } else if (Nw % 2) {        // odd degree: one-sided, the two nearest-centred, one-sided
+    t.nstencils = 4;
+    t.offset[0] = -Nw;
+    t.offset[1] = -(Nw + 1) / 2;
+    t.offset[2] = -(Nw - 1) / 2;
+    t.offset[3] = 0;
   } else {
     t.nstencils = 3;
     t.offset[0] = -Nw;

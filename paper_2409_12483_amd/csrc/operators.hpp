@@ -35,9 +35,9 @@ struct OpTables {
 // {i..i+Nw}; for Nw = 1 the two one-sided stencils {i-1, i} and {i, i+1}.
 struct WenoTables {
   int Nw = 0, n = 1, width = 1, nstencils = 3;
-  int offset[3] = {};                          // first stencil cell relative to i
-  double R[3][kMaxn][kMaxn] = {};              // nodal value k = sum_i R[s][k][i] v_{offset+i}
-  double S[3][kMaxn][kMaxn] = {};              // sigma_s = v^T S[s] v (oscillation indicator)
+  int offset[4] = {};                          // first stencil cell relative to i
+  double R[4][kMaxn][kMaxn] = {};              // nodal value k = sum_i R[s][k][i] v_{offset+i}
+  double S[4][kMaxn][kMaxn] = {};              // sigma_s = v^T S[s] v (oscillation indicator)
 };
 
 bool build_op_tables(int N, OpTables& out);

@@ -2,14 +2,14 @@
 GPU against the oracle (`oracle/fv2d.py`), through the C ABI.
 
 * Steps on non-square meshes and domains, WENO degree 1 (the paper's
-  ADER-WENO2) and 2 (ADER-WENO3): the averages after 1 and 15 CFL steps and
-  the time, to 1e-12 relative (max norm over the averages).
+  ADER-WENO2), 2 (ADER-WENO3) and 3 (ADER-WENO4): the averages after 1 and
+  15 CFL steps and the time, to 1e-12 relative (max norm over the averages).
 * A uniform state stays uniform; the totals stay constant to rounding.
 * The sine wave of Sec. 2.1: order >= degree + 1 - 0.3 on the GPU.
 * The paper's WENO timing workload (Sec. 3, the 2-D table of ADER-WENO costs:
   the sine wave to t = 1 on 5^2 .. 20^2 cells): the whole run on 5^2 and
-  10^2 cells against the oracle's to 1e-10.
-* Validation: predictor-only calls, degrees above 2 and the FP32 predictor
+  10^2 cells against the oracle's to 1e-10 (degree 3: 5^2).
+* Validation: predictor-only calls, degrees above 3 and the FP32 predictor
   are refused for this scheme.
 """
 
@@ -59,7 +59,7 @@ def _wave(cx, cy, seed):
 
 
 @pytest.mark.parametrize("N,cx,cy,nsteps", [(1, 12, 9, 1), (2, 12, 9, 1), (1, 33, 17, 15), (2, 33, 17, 15),
-                                            (2, 7, 40, 15), (1, 64, 64, 5)])
+                                            (2, 7, 40, 15), (1, 64, 64, 5), (3, 12, 9, 1), (3, 19, 26, 10)])
 def test_steps_match_oracle(N, cx, cy, nsteps):
     _say("fv2d steps", N, cx, cy, nsteps)
     ops = basis.build_operators(N)
@@ -72,7 +72,7 @@ def test_steps_match_oracle(N, cx, cy, nsteps):
     assert _rel(v, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("N", [1, 2])
+@pytest.mark.parametrize("N", [1, 2, 3])
 def test_uniform_state_and_conservation(N):
     _say("fv2d uniform / totals", N)
     u = np.tile([1.3, 0.4, -0.2, 3.1], (10, 7, 1))
@@ -84,7 +84,7 @@ def test_uniform_state_and_conservation(N):
     assert np.abs(v.sum(axis=(0, 1)) - v0.sum(axis=(0, 1))).max() <= 1e-12 * np.abs(v0.sum(axis=(0, 1))).max()
 
 
-@pytest.mark.parametrize("N,meshes", [(1, (64, 128)), (2, (32, 64))])
+@pytest.mark.parametrize("N,meshes", [(1, (64, 128)), (2, (32, 64)), (3, (16, 32))])
 def test_sine_wave_order_on_the_gpu(N, meshes):
     _say("fv2d order", N)
     errs = []
@@ -96,7 +96,7 @@ def test_sine_wave_order_on_the_gpu(N, meshes):
     assert p >= N + 1 - 0.3, (errs, p)
 
 
-@pytest.mark.parametrize("N,C", [(1, 5), (2, 5), (1, 10), (2, 10)])
+@pytest.mark.parametrize("N,C", [(1, 5), (2, 5), (1, 10), (2, 10), (3, 5)])
 def test_paper_wenotiming_workload_matches_oracle(N, C):
     """The sine wave to t = 1 on the paper's WENO timing meshes."""
     _say("fv2d timing workload", N, C)
@@ -111,7 +111,7 @@ def test_paper_wenotiming_workload_matches_oracle(N, C):
 def test_scheme_validation():
     import ctypes
     lib = abi.load()
-    for cfg in (abi.config2d(3, 8, 8, scheme=abi.SCHEME_FV),
+    for cfg in (abi.config2d(4, 8, 8, scheme=abi.SCHEME_FV),
                 abi.config2d(1, 8, 8, scheme=abi.SCHEME_FV, precision=abi.FP32_PREDICTOR),
                 abi.config2d(1, 8, 8, scheme=7)):
         h = ctypes.c_void_p()

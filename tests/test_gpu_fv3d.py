@@ -2,7 +2,8 @@
 GPU against the oracle (`oracle/fv3d.py`), through the C ABI.
 
 * Steps on non-cubic meshes and domains, WENO degree 1 (the paper's
-  ADER-WENO2) and 2 (ADER-WENO3): the averages after 1 and several CFL steps
+  ADER-WENO2), 2 (ADER-WENO3) and 3 (ADER-WENO4): the averages after 1 and
+  several CFL steps
   and the time, to 1e-12 relative (max norm over the averages).  The meshes
   span several reconstruction tiles along every axis with ragged tails.
 * A uniform state stays uniform; the totals stay constant to rounding.
@@ -10,8 +11,8 @@ GPU against the oracle (`oracle/fv3d.py`), through the C ABI.
   pre-asymptotic on the meshes used: >= 1.5).
 * The paper's 3-D WENO timing workload (Sec. 3, the 3-D table of ADER-WENO
   costs: the sine wave to t = 1 on 5^3 .. 20^3 cells): the whole run on 5^3
-  (both degrees) and 10^3 (degree 1) cells against the oracle's to 1e-10.
-* Validation: predictor-only calls, degrees above 2 and the FP32 predictor
+  (every degree) and 10^3 (degree 1) cells against the oracle's to 1e-10.
+* Validation: predictor-only calls, degrees above 3 and the FP32 predictor
   are refused for this scheme.
 """
 
@@ -61,7 +62,8 @@ def _state(cx, cy, cz, seed):
 
 
 @pytest.mark.parametrize("N,cells,nsteps", [(1, (9, 6, 5), 1), (2, (9, 6, 5), 1), (1, (11, 9, 7), 6),
-                                            (2, (11, 9, 7), 6), (2, (5, 13, 3), 4), (1, (4, 4, 17), 4)])
+                                            (2, (11, 9, 7), 6), (2, (5, 13, 3), 4), (1, (4, 4, 17), 4),
+                                            (3, (9, 6, 5), 1), (3, (6, 5, 9), 3)])
 def test_steps_match_oracle(N, cells, nsteps):
     _say("fv3d steps", N, cells, nsteps)
     ops = basis.build_operators(N)
@@ -74,7 +76,7 @@ def test_steps_match_oracle(N, cells, nsteps):
     assert _rel(v, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("N", [1, 2])
+@pytest.mark.parametrize("N", [1, 2, 3])
 def test_uniform_state_and_conservation(N):
     _say("fv3d uniform / totals", N)
     u = np.tile([1.3, 0.4, -0.2, 0.3, 3.1], (6, 5, 7, 1))
@@ -87,7 +89,7 @@ def test_uniform_state_and_conservation(N):
     assert np.abs(v.sum(axis=(0, 1, 2)) - tot0).max() <= 1e-12 * np.abs(tot0).max()
 
 
-@pytest.mark.parametrize("N,meshes,p_min", [(1, (32, 64), 1.5), (2, (16, 32), 2.6)])
+@pytest.mark.parametrize("N,meshes,p_min", [(1, (32, 64), 1.5), (2, (16, 32), 2.6), (3, (12, 24), 3.5)])
 def test_sine_wave_order_on_the_gpu(N, meshes, p_min):
     """Degree 1 is pre-asymptotic on the coarse meshes (its nonlinear weights
     pick the flatter one-sided slope near the extrema): measured orders 1.07
@@ -102,7 +104,7 @@ def test_sine_wave_order_on_the_gpu(N, meshes, p_min):
     assert p >= p_min, (errs, p)
 
 
-@pytest.mark.parametrize("N,C", [(1, 5), (2, 5), (1, 10)])
+@pytest.mark.parametrize("N,C", [(1, 5), (2, 5), (1, 10), (3, 5)])
 def test_paper_wenotiming_workload_matches_oracle(N, C):
     """The 3-D sine wave to t = 1 on the paper's WENO timing meshes."""
     _say("fv3d timing workload", N, C)
@@ -117,7 +119,7 @@ def test_paper_wenotiming_workload_matches_oracle(N, C):
 def test_scheme_validation():
     import ctypes
     lib = abi.load()
-    for cfg in (abi.config3d(3, (6, 6, 6), scheme=abi.SCHEME_FV),
+    for cfg in (abi.config3d(4, (6, 6, 6), scheme=abi.SCHEME_FV),
                 abi.config3d(1, (6, 6, 6), scheme=abi.SCHEME_FV, precision=abi.FP32_PREDICTOR),
                 abi.config3d(1, (6, 6, 6), scheme=7)):
         h = ctypes.c_void_p()
