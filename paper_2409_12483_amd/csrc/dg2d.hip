@@ -778,74 +778,96 @@ __global__ void __launch_bounds__(kFv2dThreads) weno2d_kernel(Args2D A, double* 
 
 // Finite-volume update of the averages (in place):
 // v -= sum_k w_k (Gx(east, k) - Gx(west, k) + Gy(north, k) - Gy(south, k)),
-// G the time-integrated Rusanov flux of the face traces (each face evaluated
-// by both adjacent cells, identically).  One thread per (cell, face, face
-// node) for the fluxes, gathered in LDS; then one thread per cell for the
-// update and the signal speed of the new averages (the next step's dt).
-template <int N>
-struct Fv2Geo {
-  static constexpr int n = N + 1, IT = 4 * n, CPB = kFv2dThreads / IT;
-};
+// G the time-integrated Rusanov flux of the face traces.  One workgroup per
+// tile of kFvTile x kFvTile cells: for each direction, one thread per (face,
+// face node) of the tile evaluates each face once into LDS (the tile's
+// boundary faces are evaluated by both neighbouring tiles, identically); one
+// thread per cell takes the difference of its two faces, updates v and forms
+// the signal speed of the new averages (the next step's dt).
+constexpr int kFvTile = 8;
 
 template <int N>
 __global__ void __launch_bounds__(kFv2dThreads) fv2d_corr_kernel(Args2D A) {
-  constexpr int n = N + 1, L = n * n, M = 4, IT = Fv2Geo<N>::IT, CPB = Fv2Geo<N>::CPB;
-  __shared__ double Gf[CPB * IT * M];
+  constexpr int n = N + 1, L = n * n, M = 4, T = kFvTile, kFaces = (T + 1) * T;
+  static_assert(T * T <= kFv2dThreads, "one thread per cell of the tile");
+  __shared__ double Gf[kFaces * n * M];
   __shared__ double bcast[2];
   __shared__ double part[2 * (kFv2dThreads / 64)];
   double t;
   const double dt = step_dt2d<N>(A, t, bcast, false);
   if (!(dt > 0.0)) return;
-  const double dtdx = dt / A.dx, dtdy = dt / A.dy;
-  const int64_t ncells = A.cx * A.cy;
-  const int64_t cell0 = (int64_t)blockIdx.x * CPB;
-  const int ncl = (int)((ncells - cell0) < CPB ? (ncells - cell0) : CPB);
+  const int64_t c[2] = {A.cx, A.cy};
+  const int64_t ty = (A.cy + T - 1) / T;
+  const int64_t o[2] = {((int64_t)blockIdx.x / ty) * T, ((int64_t)blockIdx.x % ty) * T};
+  const int ext[2] = {(int)((c[0] - o[0]) < T ? (c[0] - o[0]) : T), (int)((c[1] - o[1]) < T ? (c[1] - o[1]) : T)};
   const int tid = threadIdx.x;
-  if (tid < ncl * IT) {
-    const int cl = tid / IT, rem = tid - cl * IT, f = rem / n, k = rem - f * n;
-    const int64_t c = cell0 + cl;
-    const int64_t ix = c / A.cy, iy = c - ix * A.cy;
-    int64_t cm, cp;
-    if (f == 0) { cm = (ix == 0 ? A.cx - 1 : ix - 1) * A.cy + iy; cp = c; }
-    else if (f == 1) { cm = c; cp = (ix + 1 == A.cx ? 0 : ix + 1) * A.cy + iy; }
-    else if (f == 2) { cm = ix * A.cy + (iy == 0 ? A.cy - 1 : iy - 1); cp = c; }
-    else { cm = c; cp = ix * A.cy + (iy + 1 == A.cy ? 0 : iy + 1); }
-    const int fm = f < 2 ? 1 : 3, fp = f < 2 ? 0 : 2;
-    const double sc = f < 2 ? dtdx : dtdy;
-    double acc[M];
+  const int lc[2] = {tid / T, tid % T};
+  const bool own = tid < T * T && lc[0] < ext[0] && lc[1] < ext[1];
+  double dv[M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) acc[r] = 0.0;
+  for (int r = 0; r < M; ++r) dv[r] = 0.0;
+
 #pragma unroll
-    for (int a = 0; a < n; ++a) {
-      double qm[M], qp[M], Gr[M];
+  for (int d = 0; d < 2; ++d) {
+    const int e = 1 - d;
+    const int nf = (ext[d] + 1) * ext[e];
+    const double sc = dt / (d == 0 ? A.dx : A.dy);
+    for (int w = tid; w < nf * n; w += kFv2dThreads) {
+      const int face = w / n, k = w - face * n;
+      const int fd = face / ext[e], r1 = face - fd * ext[e];
+      // face fd lies between local cells fd - 1 (minus side) and fd (plus side)
+      int64_t pc[2], mc[2];
+      pc[d] = o[d] + fd;
+      if (pc[d] == c[d]) pc[d] = 0;
+      mc[d] = o[d] + fd - 1;
+      if (mc[d] < 0) mc[d] = c[d] - 1;
+      pc[e] = mc[e] = o[e] + r1;
+      const int64_t cm = mc[0] * A.cy + mc[1], cp = pc[0] * A.cy + pc[1];
+      const int fm = 2 * d + 1, fp = 2 * d;        // minus cell's plus face, plus cell's minus face
+      double acc[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) acc[r] = 0.0;
+#pragma unroll
+      for (int a = 0; a < n; ++a) {
+        double qm[M], qp[M], Gr[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          qm[r] = reinterpret_cast<const double*>(A.tr)[((cm * 4 + fm) * L + a * n + k) * M + r];
+          qp[r] = reinterpret_cast<const double*>(A.tr)[((cp * 4 + fp) * L + a * n + k) * M + r];
+        }
+        if (d == 0) rusanov2<0>(qm, qp, Gr, A.gamma);
+        else rusanov2<1>(qm, qp, Gr, A.gamma);
+        const double wa = c2_ops[N].w[a];
+#pragma unroll
+        for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
+      }
+      const double wk = c2_ops[N].w[k];
+#pragma unroll
+      for (int r = 0; r < M; ++r) Gf[(face * n + k) * M + r] = wk * acc[r];
+    }
+    __syncthreads();
+    if (own) {
+      const int lo = lc[d] * ext[e] + lc[e], hi = (lc[d] + 1) * ext[e] + lc[e];
 #pragma unroll
       for (int r = 0; r < M; ++r) {
-        qm[r] = reinterpret_cast<const double*>(A.tr)[((cm * 4 + fm) * L + a * n + k) * M + r];
-        qp[r] = reinterpret_cast<const double*>(A.tr)[((cp * 4 + fp) * L + a * n + k) * M + r];
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) sum += Gf[(hi * n + k) * M + r] - Gf[(lo * n + k) * M + r];
+        dv[r] += sum;
       }
-      if (f < 2) rusanov2<0>(qm, qp, Gr, A.gamma);
-      else rusanov2<1>(qm, qp, Gr, A.gamma);
-      const double wa = c2_ops[N].w[a];
-#pragma unroll
-      for (int r = 0; r < M; ++r) acc[r] = fma(wa, sc * Gr[r], acc[r]);
     }
-    const double wk = ((f & 1) ? 1.0 : -1.0) * c2_ops[N].w[k];   // east / north add, west / south subtract
-#pragma unroll
-    for (int r = 0; r < M; ++r) Gf[(cl * IT + rem) * M + r] = wk * acc[r];
+    __syncthreads();
   }
-  __syncthreads();
+
   double lx = 0.0, ly = 0.0;
   bool bad = false;
-  if (tid < ncl) {
-    const int64_t c = cell0 + tid;
+  if (own) {
+    const int64_t cell = (o[0] + lc[0]) * A.cy + (o[1] + lc[1]);
     double vn[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-      double F = 0.0;
-#pragma unroll
-      for (int e = 0; e < IT; ++e) F += Gf[(tid * IT + e) * M + r];
-      vn[r] = A.u[c * M + r] - F;
-      A.u[c * M + r] = vn[r];
+      vn[r] = A.u[cell * M + r] - dv[r];
+      A.u[cell * M + r] = vn[r];
     }
     bad = !Euler2::admissible(vn, A.gamma);
     Euler2::speeds(vn, A.gamma, lx, ly);
@@ -954,9 +976,8 @@ hipError_t launch_weno2d(int NW, const Args2D& A, double* w, hipStream_t st) {
 }
 
 hipError_t launch_fv2d_corr(int NW, const Args2D& A, hipStream_t st) {
-  const int64_t cells = A.cx * A.cy;
-  const int cpb = NW == 1 ? Fv2Geo<1>::CPB : NW == 2 ? Fv2Geo<2>::CPB : Fv2Geo<3>::CPB;
-  dim3 grid((unsigned)((cells + cpb - 1) / cpb)), block(kFv2dThreads);
+  const int64_t tiles = ((A.cx + kFvTile - 1) / kFvTile) * ((A.cy + kFvTile - 1) / kFvTile);
+  dim3 grid((unsigned)tiles), block(kFv2dThreads);
   if (NW == 1) hipLaunchKernelGGL((fv2d_corr_kernel<1>), grid, block, 0, st, A);
   else if (NW == 2) hipLaunchKernelGGL((fv2d_corr_kernel<2>), grid, block, 0, st, A);
   else if (NW == 3) hipLaunchKernelGGL((fv2d_corr_kernel<3>), grid, block, 0, st, A);
