@@ -226,6 +226,32 @@ int aderdg_user_compile_check(const char* model_source, int32_t nvars, int32_t N
 int aderdg_free(aderdg_handle* h);
 
 /*
+ * aderdg_set_waves -- wavefronts per workgroup of the fused DG step (Sec. 1.1-1.2 in one
+ * launch, as aderdg_step) for every launch group of the handle that has two compiled
+ * sizes: DG scheme, Picard inner iterations, a compiled-in model.  waves = 4 (the
+ * default) or 2; a workgroup then writes waves * floor(64/(N+1)) - 2 cells.  Every cell's arithmetic, the dt reduction and the counters are the same, so
+ * the results are bitwise those of the other size; only the speed differs.  The problem
+ * table is rewritten in stream order on the handle's stream.  E_INVAL for other values.
+ */
+int aderdg_set_waves(aderdg_handle* h, int32_t waves);
+
+/*
+ * aderdg_autotune -- for every launch group aderdg_set_waves applies to, time `steps`
+ * fused steps (1..10000, after 2 untimed ones) with each compiled workgroup size on
+ * device copies of the states u (host array of nprob device pointers, read only) and
+ * keep the faster.  The problems' clocks, counters and states are left as they were:
+ * the next aderdg_step continues exactly as without this call.  The choice is cached
+ * for the process under (device architecture, model, N, precision, total cells of the
+ * group rounded up to a power of 2) and, if the environment variable ADERDG_TUNE_FILE
+ * names a file, read from and appended to it ("key waves" per line); a cached key is
+ * not timed again.  waves_out: optional host int32 [nprob], the size now used by each
+ * problem's group (4 for groups that are not tuned).  Allocates device memory for the
+ * copies (stream-ordered) and synchronises the handle's stream.
+ * Errors: E_INVAL, E_NOMEM, E_DEVICE.
+ */
+int aderdg_autotune(aderdg_handle* h, double* const* u, int32_t steps, int32_t* waves_out);
+
+/*
  * aderdg_set_stream -- enqueue later work of the handle on another HIP stream.
  */
 int aderdg_set_stream(aderdg_handle* h, void* hip_stream);

@@ -30,7 +30,7 @@ NVARS = {PDE_ADVECTION: 1, PDE_EULER: 3, PDE_EULER_REACT: 5, PDE_SWE: 3}
 EXPORTS = ["aderdg_init", "aderdg_predict", "aderdg_correct", "aderdg_step", "aderweno_step",
            "aderdg_free", "aderdg_set_stream", "aderdg_sweep_count", "aderdg_contraction_count",
            "aderdg_operators", "aderdg_conserved_totals", "aderdg_step_noalloc", "aderdg_user_init",
-           "aderdg_user_compile_check", "aderdg_last_error"]
+           "aderdg_user_compile_check", "aderdg_set_waves", "aderdg_autotune", "aderdg_last_error"]
 EXPORTS_2D = ["aderdg2d_init", "aderdg2d_predict", "aderdg2d_step", "aderdg2d_sweep_count",
               "aderdg2d_free"]
 EXPORTS_3D = ["aderdg3d_init", "aderdg3d_predict", "aderdg3d_step", "aderdg3d_sweep_count",
@@ -120,6 +120,8 @@ def load(path=None):
     lib.aderdg_user_compile_check.argtypes = [ctypes.c_char_p, i32, i32, i32, ctypes.c_char_p, i64]
     lib.aderdg_step_noalloc.argtypes = [ctypes.POINTER(PdeDesc), ctypes.POINTER(Config), vp, vp, vp,
                                         vp, vp, i32, vp]
+    lib.aderdg_set_waves.argtypes = [vp, i32]
+    lib.aderdg_autotune.argtypes = [vp, vp, i32, vp]
     lib.aderdg_last_error.argtypes = []
     lib.aderdg_last_error.restype = ctypes.c_char_p
     lib.aderdg2d_init.argtypes = [ctypes.POINTER(Config2D), vp, ctypes.POINTER(vp)]
@@ -203,6 +205,18 @@ def aderdg_step(h, u, t, t_end, dt, status, nsteps):
 
 def aderweno_step(h, v, t, t_end, dt, status, nsteps):
     return _check(load().aderweno_step(h, _ptr_array(v), _ptr(t), _ptr(t_end), _ptr(dt), _ptr(status), nsteps))
+
+
+def aderdg_set_waves(h, waves):
+    return _check(load().aderdg_set_waves(h, waves))
+
+
+def aderdg_autotune(h, u, steps, nprob=None):
+    """Returns the workgroup size now used by each problem's group (list of ints)."""
+    n = nprob if nprob is not None else len(u)
+    out = (ctypes.c_int32 * n)()
+    _check(load().aderdg_autotune(h, _ptr_array(u), steps, out))
+    return list(out)
 
 
 def aderdg_step_noalloc(pde, cfg, u, t, t_end, dt, status, nsteps, stream=None):

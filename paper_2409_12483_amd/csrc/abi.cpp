@@ -19,7 +19,9 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
 #include <set>
@@ -146,6 +148,7 @@ struct Group {
   std::vector<ProbDev> lam_host;
   ProbDev* lam_dev = nullptr;
   bool any_cfl = false;
+  int waves = kDgWaves;     // wavefronts per workgroup of the fused DG step
 };
 
 }  // namespace
@@ -315,7 +318,7 @@ int run_steps(aderdg_handle* h, int scheme, double* const* u, double* t, const d
         e = rtc_launch(g->rtc->dg[2], A, g->blocks, kRtcWaves * 64, h->stream);
       else
         e = scheme == ADERDG_SCHEME_DG ? launch_dg(g->pde, g->N, g->prec, 2, A, g->blocks, h->stream,
-                                                   g->inner == ADERDG_INNER_NEWTON)
+                                                   g->inner == ADERDG_INNER_NEWTON, g->waves)
                                         : launch_fv(g->pde, g->N, g->prec, A, g->blocks, h->stream);
       if (e != hipSuccess) return fail_hip(e, "step kernel");
     }
@@ -331,6 +334,104 @@ int run_steps(aderdg_handle* h, int scheme, double* const* u, double* t, const d
       }
   }
   return ADERDG_OK;
+}
+
+// A group whose fused step can run with either compiled workgroup size.
+bool tunable(const Group& g) {
+  return g.scheme == ADERDG_SCHEME_DG && !g.rtc && g.inner == ADERDG_INNER_PICARD;
+}
+
+// Tile the group's problems for `waves` wavefronts per workgroup and upload
+// the table (stream-ordered).
+int set_group_waves(aderdg_handle* h, Group& g, int waves) {
+  const int64_t tile = dg_tile_cells(g.N, true, waves);
+  int64_t b = 0;
+  for (ProbDev& d : g.host) {
+    d.tile_begin = b;
+    d.tiles = (d.ncells + tile - 1) / tile;
+    b += d.tiles;
+  }
+  if (b >= ((int64_t)1 << 31)) return fail(ADERDG_E_INVAL, "grid too large");
+  g.blocks = b;
+  g.waves = waves;
+  return upload_group(h, g);
+}
+
+// Process-wide cache of tuned workgroup sizes: key (device arch, model, N,
+// precision, total cells of the group rounded up to a power of 2); also
+// kept in the file named by ADERDG_TUNE_FILE (one "key waves" line each).
+std::mutex g_tune_mutex;
+std::map<std::string, int> g_tune_cache;
+bool g_tune_file_read = false;
+
+std::string tune_key(int device, const Group& g) {
+  hipDeviceProp_t prop;
+  std::string arch = hipGetDeviceProperties(&prop, device) == hipSuccess ? prop.gcnArchName : "unknown";
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  int64_t cells = 0;
+  for (const ProbDev& d : g.host) cells += d.ncells;
+  int lg = 0;
+  while (((int64_t)1 << lg) < cells) ++lg;
+  return arch + "/pde" + std::to_string(g.pde) + "/N" + std::to_string(g.N) + "/p" + std::to_string(g.prec) +
+         "/c2^" + std::to_string(lg);
+}
+
+void tune_file_load() {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = std::getenv("ADERDG_TUNE_FILE");
+  if (!path) return;
+  std::ifstream in(path);
+  std::string key;
+  int w;
+  while (in >> key >> w)
+    if (w == kDgWaves || w == kDgWavesAlt) g_tune_cache[key] = w;
+}
+
+void tune_file_append(const std::string& key, int w) {
+  const char* path = std::getenv("ADERDG_TUNE_FILE");
+  if (!path) return;
+  std::ofstream out(path, std::ios::app);
+  out << key << " " << w << "\n";
+}
+
+// Seconds of `steps` fused steps of group g from the states src (copied to
+// work first), with `waves` wavefronts per workgroup; -1 on error.
+double time_group(aderdg_handle* h, Group& g, int waves, double* const* src, double* const* work,
+                  double* t_dev, const double* tend_dev, int32_t steps) {
+  if (set_group_waves(h, g, waves)) return -1.0;
+  for (size_t i = 0; i < g.pids.size(); ++i) {
+    const int k = g.pids[i];
+    if (launch_copy(src[k], work[k], h->elems[k], h->stream) != hipSuccess) return -1.0;
+  }
+  if (bind_states(h, g, work)) return -1.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+  hipError_t e = launch_clock_begin(h->clocks, t_dev, h->nprob, h->stream);
+  StepArgs A{};
+  A.clocks = h->clocks;
+  A.t_end = tend_dev;
+  if (e == hipSuccess && g.any_cfl) {
+    A.probs = g.lam_dev;
+    A.nprob = (int)g.pids.size();
+    e = launch_lambda(g.pde, g.N, true, A, g.lam_blocks, h->stream);
+  }
+  A.probs = g.dev;
+  A.nprob = (int)g.pids.size();
+  const int warm = 2;
+  for (int s = 0; s < warm + steps && e == hipSuccess; ++s) {
+    if (s == warm) e = hipEventRecord(e0, h->stream);
+    A.step = s;
+    if (e == hipSuccess) e = launch_dg(g.pde, g.N, g.prec, 2, A, g.blocks, h->stream, false, waves);
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = -1.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return e == hipSuccess ? ms * 1e-3 : -1.0;
 }
 
 int init_handle(const aderdg_pde_desc* pdes, const aderdg_config* cfgs, int32_t nprob, void* hip_stream,
@@ -554,6 +655,82 @@ int aderdg_step(aderdg_handle* h, double* const* u, double* t, const double* t_e
 int aderweno_step(aderdg_handle* h, double* const* v, double* t, const double* t_end, double* dt,
                   int32_t* status, int32_t nsteps) {
   return run_steps(h, ADERDG_SCHEME_FV, v, t, t_end, dt, status, nsteps);
+}
+
+int aderdg_set_waves(aderdg_handle* h, int32_t waves) {
+  g_last_error.clear();
+  if (!h) return fail(ADERDG_E_INVAL, "null handle");
+  if (waves != kDgWaves && waves != kDgWavesAlt) return fail(ADERDG_E_INVAL, "waves must be 4 or 2");
+  for (Group& g : h->groups) {
+    if (!tunable(g)) continue;
+    int rc = set_group_waves(h, g, waves);
+    if (rc) return rc;
+  }
+  return ADERDG_OK;
+}
+
+int aderdg_autotune(aderdg_handle* h, double* const* u, int32_t steps, int32_t* waves_out) {
+  g_last_error.clear();
+  if (!h || !u) return fail(ADERDG_E_INVAL, "null argument");
+  if (steps < 1 || steps > 10000) return fail(ADERDG_E_INVAL, "steps must be in 1..10000");
+  for (int k = 0; k < h->nprob; ++k)
+    if (!u[k]) return fail(ADERDG_E_INVAL, "null state pointer for problem " + std::to_string(k));
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  tune_file_load();
+  hipStream_t st = h->stream;
+  // work copies of the states, the clocks saved, a start time and an open end
+  std::vector<double*> work(h->nprob, nullptr);
+  ProbClock* saved = nullptr;
+  double* tt = nullptr;
+  auto cleanup = [&]() {
+    for (double* p : work) if (p) (void)hipFreeAsync(p, st);
+    if (saved) (void)hipFreeAsync(saved, st);
+    if (tt) (void)hipFreeAsync(tt, st);
+    (void)hipStreamSynchronize(st);
+  };
+  hipError_t e = hipMallocAsync((void**)&saved, sizeof(ProbClock) * h->nprob, st);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&tt, sizeof(double) * 2 * h->nprob, st);
+  for (int k = 0; k < h->nprob && e == hipSuccess; ++k) e = hipMallocAsync((void**)&work[k], sizeof(double) * h->elems[k], st);
+  if (e != hipSuccess) { cleanup(); return fail(ADERDG_E_NOMEM, "autotune buffers"); }
+  std::vector<double> host_t(2 * h->nprob, 0.0);     // start times, then end times
+  for (int k = 0; k < h->nprob; ++k) host_t[h->nprob + k] = 1.0e300;
+  e = hipMemcpyAsync(saved, h->clocks, sizeof(ProbClock) * h->nprob, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(tt, host_t.data(), sizeof(double) * 2 * h->nprob, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { cleanup(); return fail_hip(e, "autotune set-up"); }
+  int rc = ADERDG_OK;
+  for (Group& g : h->groups) {
+    if (!tunable(g)) continue;
+    const std::string key = tune_key(h->device, g);
+    auto it = g_tune_cache.find(key);
+    int best = kDgWaves;
+    if (it != g_tune_cache.end()) {
+      best = it->second;
+    } else {
+      std::vector<double> times;
+      for (int w : {kDgWaves, kDgWavesAlt}) {
+        double s = time_group(h, g, w, u, work.data(), tt, tt + h->nprob, steps);
+        if (s < 0.0) { rc = fail(ADERDG_E_DEVICE, "autotune timing run"); break; }
+        times.push_back(s);
+      }
+      if (rc) break;
+      best = times[1] < times[0] ? kDgWavesAlt : kDgWaves;
+      g_tune_cache[key] = best;
+      tune_file_append(key, best);
+    }
+    rc = set_group_waves(h, g, best);
+    if (rc) break;
+  }
+  // leave the problems as they were: clocks restored; the state pointers are
+  // bound again by the next step call
+  e = hipMemcpyAsync(h->clocks, saved, sizeof(ProbClock) * h->nprob, hipMemcpyDeviceToDevice, st);
+  cleanup();
+  if (rc) return rc;
+  if (e != hipSuccess) return fail_hip(e, "autotune restore");
+  if (waves_out)
+    for (const Group& g : h->groups)
+      for (int k : g.pids) waves_out[k] = tunable(g) ? g.waves : kDgWaves;
+  return ADERDG_OK;
 }
 
 int aderdg_free(aderdg_handle* h) {

@@ -454,25 +454,48 @@ static hipError_t launch_dg_n(int N, int mode, const StepArgs& A, int64_t blocks
   }
 }
 
+// The fused step with kDgWavesAlt wavefronts per workgroup (the tile of a
+// workgroup shrinks with it; every cell's arithmetic is the same).
+template <class PDE, class TP>
+static hipError_t launch_dg_alt(int N, const StepArgs& A, int64_t blocks, hipStream_t st) {
+  dim3 grid((unsigned)blocks), block(kDgWavesAlt * 64);
+  switch (N) {
+#define ADERDG_CASE(NN)                                                                                  \
+  case NN:                                                                                               \
+    hipLaunchKernelGGL((dg_kernel<NN, PDE, TP, kDgWavesAlt, kStep, false>), grid, block, 0, st, A); \
+    break;
+    ADERDG_CASE(1) ADERDG_CASE(2) ADERDG_CASE(3) ADERDG_CASE(4) ADERDG_CASE(5)
+    ADERDG_CASE(6) ADERDG_CASE(7) ADERDG_CASE(8) ADERDG_CASE(9)
+#undef ADERDG_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <class PDE, bool NEWTON = false>
 static hipError_t launch_dg_p(int N, int prec, int mode, const StepArgs& A, int64_t blocks,
-                              hipStream_t st) {
+                              hipStream_t st, int waves) {
+  if (waves == kDgWavesAlt) {
+    if (NEWTON || mode != kStep) return hipErrorInvalidValue;
+    return prec == 1 ? launch_dg_alt<PDE, float>(N, A, blocks, st) : launch_dg_alt<PDE, double>(N, A, blocks, st);
+  }
+  if (waves != kDgWaves) return hipErrorInvalidValue;
   return prec == 1 ? launch_dg_n<PDE, float, NEWTON>(N, mode, A, blocks, st)
                    : launch_dg_n<PDE, double, NEWTON>(N, mode, A, blocks, st);
 }
 
 hipError_t launch_dg(int pde, int N, int prec, int mode, const StepArgs& A, int64_t blocks,
-                     hipStream_t st, bool newton) {
+                     hipStream_t st, bool newton, int waves) {
   if (newton) {
     // Newton inner iterations are compiled for the model with a linear source
     if (pde != 2) return hipErrorInvalidValue;
-    return launch_dg_p<EulerReact, true>(N, prec, mode, A, blocks, st);
+    return launch_dg_p<EulerReact, true>(N, prec, mode, A, blocks, st, waves);
   }
   switch (pde) {
-    case 0: return launch_dg_p<Advection>(N, prec, mode, A, blocks, st);
-    case 1: return launch_dg_p<Euler>(N, prec, mode, A, blocks, st);
-    case 2: return launch_dg_p<EulerReact>(N, prec, mode, A, blocks, st);
-    case 3: return launch_dg_p<ShallowWater>(N, prec, mode, A, blocks, st);
+    case 0: return launch_dg_p<Advection>(N, prec, mode, A, blocks, st, waves);
+    case 1: return launch_dg_p<Euler>(N, prec, mode, A, blocks, st, waves);
+    case 2: return launch_dg_p<EulerReact>(N, prec, mode, A, blocks, st, waves);
+    case 3: return launch_dg_p<ShallowWater>(N, prec, mode, A, blocks, st, waves);
     default: return hipErrorInvalidValue;
   }
 }
@@ -544,9 +567,9 @@ hipError_t launch_copy(const double* src, double* dst, int64_t count, hipStream_
   return hipGetLastError();
 }
 
-int64_t dg_tile_cells(int N, bool halo) {
+int64_t dg_tile_cells(int N, bool halo, int waves) {
   const int cpw = 64 / (N + 1);
-  return (int64_t)kDgWaves * cpw - (halo ? 2 : 0);
+  return (int64_t)waves * cpw - (halo ? 2 : 0);
 }
 
 int64_t fv_tile_cells(int NW) { return (int64_t)kFvWaves * (64 / (NW + 1)) - 2; }

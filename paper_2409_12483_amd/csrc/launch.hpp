@@ -8,11 +8,15 @@
 
 namespace aderdg {
 
-constexpr int kDgWaves = 4;   // wavefronts per DG workgroup
+constexpr int kDgWaves = 4;   // wavefronts per DG workgroup (default)
+constexpr int kDgWavesAlt = 2;   // the other compiled size of the fused step (Picard, built-in models)
 constexpr int kFvWaves = 4;   // wavefronts per FV workgroup
 
+// waves: wavefronts per workgroup of the fused step; kDgWavesAlt is compiled
+// for mode 2 (step) with Picard inner iterations, every other launch uses
+// kDgWaves (hipErrorInvalidValue otherwise)
 hipError_t launch_dg(int pde, int N, int prec, int mode, const StepArgs& A, int64_t blocks,
-                     hipStream_t st, bool newton = false);
+                     hipStream_t st, bool newton = false, int waves = kDgWaves);
 hipError_t launch_fv(int pde, int NW, int prec, const StepArgs& A, int64_t blocks, hipStream_t st);
 hipError_t launch_lambda(int pde, int N, bool dg, const StepArgs& A, int64_t blocks, hipStream_t st);
 hipError_t launch_clock_begin(ProbClock* clocks, const double* t_user, int nprob, hipStream_t st);
@@ -45,7 +49,7 @@ inline int64_t totals_partials(int64_t ncells) {
 }
 hipError_t launch_totals(const double* u, int64_t ncells, int N, int nodes, int M, double dx,
                          double* partials, double* out, hipStream_t st);
-int64_t dg_tile_cells(int N, bool halo);
+int64_t dg_tile_cells(int N, bool halo, int waves = kDgWaves);
 int64_t fv_tile_cells(int NW);
 
 // Static scratch of the allocation-free step entry point (noalloc.hip):
