@@ -295,6 +295,55 @@ def c1_latency(reps=100, k=10):
             "eager": {"p50": pct(le, 50), "p99": pct(le, 99)}, "status": status}
 
 
+def autotune_section():
+    """The fused 1-D step with its default workgroup size (4 wavefronts) and
+    with the size aderdg_autotune picks (2 or 4, timed on copies of the
+    states), on meshes from the C1 size to 1e6 cells, and the 256-problem
+    batch with every degree group tuned."""
+    import torch
+    from paper_2409_12483_amd import abi
+    from paper_2409_12483_amd import batch as B
+    from paper_2409_12483_amd import workloads as W
+    rows = []
+    for N, C, prec, K in [(2, 100, abi.FP64, 400), (5, 1000, abi.FP64, 400), (5, 10000, abi.FP64, 200),
+                          (5, 100000, abi.FP64, 100), (5, 100000, abi.FP32_PREDICTOR, 100),
+                          (1, 1000000, abi.FP64, 40), (3, 1000000, abi.FP64, 20), (9, 1000000, abi.FP64, 10)]:
+        r = DGRun(N, C, prec, cfl=0.4 if N <= 7 else 0.3)
+        ramp(r, seconds=0.3)
+        r.steps(10)
+        s4, _ = r.timed(K)
+        waves = abi.aderdg_autotune(r.h, [r.u], 20)[0]
+        st, _ = r.timed(K)
+        rows.append({"N": N, "cells": C, "precision": "fp64" if prec == abi.FP64 else "fp32_predictor",
+                     "us_per_step_4_waves": round(s4 / K * 1e6, 2), "chosen_waves": waves,
+                     "us_per_step_tuned": round(st / K * 1e6, 2), "status": int(r.st.item())})
+        r.close()
+    specs = W.batched_euler_problems(nprob=256, seed=0)
+    out = {"single_problems": rows}
+    for tune in (False, True):
+        s = torch.cuda.Stream()
+        b = B.Batch(specs, precision=abi.FP32_PREDICTOR, stream=s)
+        if tune:
+            with torch.cuda.stream(s):
+                b.step(1)
+            s.synchronize()
+            out["batch_chosen_waves"] = sorted(set(zip([sp["N"] for sp in specs],
+                                                       abi.aderdg_autotune(b.h, b.u, 10))))
+        b.capture(10)
+        for _ in range(2):
+            b.replay()
+        s.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(5):
+            b.replay()
+        e1.record(s)
+        e1.synchronize()
+        out["batch_fp32_ms_per_step_" + ("tuned" if tune else "4_waves")] = round(e0.elapsed_time(e1) / 50, 4)
+        b.close()
+    return out
+
+
 def c4_batched(nprob=256, k=10, reps=6):
     """256 independent Euler problems (log-uniform 1e3..1e5 cells, N uniform in
     1..7, seeded wave numbers and phases) advanced as one batch -- one launch
@@ -1063,6 +1112,8 @@ def main():
                     help="first run a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--dg2d-only", action="store_true",
                     help="only the 2-D workload (512x512 cells, N=5; for profiling the 2-D kernels)")
+    ap.add_argument("--autotune-only", action="store_true",
+                    help="only the workgroup-size autotuner comparison (1-D DG step, single problems and the batch)")
     ap.add_argument("--fv2d-only", action="store_true",
                     help="only the 2-D ADER-WENO workloads (1024^2 throughput, the paper's WENO timing meshes)")
     ap.add_argument("--table11-full", action="store_true",
@@ -1086,7 +1137,7 @@ def main():
     # the oracle's host-core baseline runs first: its worker processes are
     # forked, which must happen before this process touches the GPU
     cpu = None
-    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only or a.fv2d_only or a.fv3d_only):
+    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only or a.fv2d_only or a.fv3d_only or a.autotune_only):
         cpu = cpu_baseline(N)
         emit("cpu_baseline", cpu)
 
@@ -1109,6 +1160,9 @@ def main():
         return
     if a.limiter_only:
         print(json.dumps({"limiter": limiter_section(quick=True)}))
+        return
+    if a.autotune_only:
+        print(json.dumps({"autotune": autotune_section()}))
         return
     if a.fv2d_only:
         print(json.dumps({"fv2d_euler_sine": fv2d_section()}))
@@ -1200,6 +1254,7 @@ def main():
         emit("c1_step_latency", c1_latency())
         c4 = c4_batched()
         emit("c4_batched_256", c4)
+        emit("autotune", autotune_section())
         emit("c5_serving", [c5_serving(rate, 150) for rate in (25.0, 50.0, 100.0)])
         emit("c5_serving_fp32_predictor", [c5_serving(rate, 150, precision=abi.FP32_PREDICTOR)
                                            for rate in (50.0, 100.0)])
