@@ -176,11 +176,126 @@ struct Pred3Geo {
   __device__ static constexpr int at(int a, int i, int j, int k) { return a * SA + i * SI + j * SJ + k * M; }
 };
 
-// Bytes of the device buffer a cell's predictor tiles need (0: they fit in LDS).
-template <int N, class TP>
-constexpr int64_t pred3d_global_bytes() {
-  using G = Pred3Geo<N, TP>;
-  return G::kGlobal ? 2 * (int64_t)G::kGStride * (int64_t)sizeof(TP) : 0;
+
+
+// Epilogue of the predictor kernels, for the cell's node (h2, h1, h0) =
+// line: the six face traces from the lines through the node (in the
+// predictor precision), q and the sweep count in predictor-only mode, the
+// volume terms of the corrector from the time-integrated fluxes (through the
+// buffer Vc of 3 L M doubles per cell, which may overlay tiles that are dead
+// once the loop is over: sync_before_vb adds a barrier before it is
+// written), u + volume terms into A.part (DG), and the counters.
+template <int N, class TP, class G>
+__device__ __forceinline__ void pred3d_epilogue(const Args3D& A, const TP* Qc, double* Vc, const double (&u0)[5],
+                                                double dt, bool mine, int64_t cell, int line, int h2, int h1,
+                                                int h0, int sweeps, bool failed, unsigned int* swsum_p,
+                                                bool sync_before_vb) {
+  constexpr int n = G::n, L = G::L, M = G::M;
+  unsigned int& swsum = *swsum_p;
+  const int tid = threadIdx.x;
+  // ---- epilogue: traces from the X, Y, Z roles' lines (line index = (a, s, t))
+  if (mine) {
+    double tm[3][M], tp[3][M];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int r = 0; r < M; ++r) tm[d][r] = tp[d][r] = 0.0;
+#pragma unroll
+    for (int p = 0; p < n; ++p) {
+      const double p0 = c3_ops[N].psi0[p], p1 = c3_ops[N].psi1[p];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        const double vx = (double)Qc[G::at(h2, p, h1, h0) + r];
+        const double vy = (double)Qc[G::at(h2, h1, p, h0) + r];
+        const double vz = (double)Qc[G::at(h2, h1, h0, p) + r];
+        tm[0][r] = fma(p0, vx, tm[0][r]);
+        tp[0][r] = fma(p1, vx, tp[0][r]);
+        tm[1][r] = fma(p0, vy, tm[1][r]);
+        tp[1][r] = fma(p1, vy, tp[1][r]);
+        tm[2][r] = fma(p0, vz, tm[2][r]);
+        tp[2][r] = fma(p1, vz, tp[2][r]);
+      }
+    }
+    TP* trc = reinterpret_cast<TP*>(A.tr) + cell * (6 * L * M);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        trc[((2 * d) * L + line) * M + r] = TP(tm[d][r]);
+        trc[((2 * d + 1) * L + line) * M + r] = TP(tp[d][r]);
+      }
+    if (A.mode == k3dPredict) {
+      TP* qo = reinterpret_cast<TP*>(A.q_out) + cell * (n * L * M);
+#pragma unroll
+      for (int a = 0; a < n; ++a)
+#pragma unroll
+        for (int r = 0; r < M; ++r) qo[(a * L + line) * M + r] = Qc[G::at(a, h2, h1, h0) + r];
+      if (A.iters && line == 0) A.iters[cell] = sweeps;
+    }
+  }
+  // volume terms from the time-integrated fluxes of the (promoted) predictor
+  double fb[3][M];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int r = 0; r < M; ++r) fb[d][r] = 0.0;
+  if (mine) {
+#pragma unroll
+    for (int a = 0; a < n; ++a) {
+      double qd[M], f[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) qd[r] = (double)Qc[G::at(a, h2, h1, h0) + r];
+      const double wa = c3_ops[N].w[a];
+      Euler3::flux<0>(qd, f, A.gamma - 1.0);
+#pragma unroll
+      for (int r = 0; r < M; ++r) fb[0][r] = fma(wa, (dt / A.h[0]) * f[r], fb[0][r]);
+      Euler3::flux<1>(qd, f, A.gamma - 1.0);
+#pragma unroll
+      for (int r = 0; r < M; ++r) fb[1][r] = fma(wa, (dt / A.h[1]) * f[r], fb[1][r]);
+      Euler3::flux<2>(qd, f, A.gamma - 1.0);
+#pragma unroll
+      for (int r = 0; r < M; ++r) fb[2][r] = fma(wa, (dt / A.h[2]) * f[r], fb[2][r]);
+    }
+  }
+  // Vb overlays R (last read before the loop's final barriers), or Q and R:
+  // then every read of Q above must be done before the first store
+  if (sync_before_vb) __syncthreads();
+  if (mine) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int r = 0; r < M; ++r) Vc[(d * L + line) * M + r] = fb[d][r];
+  }
+  __syncthreads();
+  if (mine) {
+    double vol[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) vol[r] = 0.0;
+#pragma unroll
+    for (int l = 0; l < n; ++l) {
+      const double dx_ = c3_ops[N].Dw[h2][l], dy_ = c3_ops[N].Dw[h1][l], dz_ = c3_ops[N].Dw[h0][l];
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        vol[r] = fma(dx_, Vc[(0 * L + (l * n + h1) * n + h0) * M + r], vol[r]);
+        vol[r] = fma(dy_, Vc[(1 * L + (h2 * n + l) * n + h0) * M + r], vol[r]);
+        vol[r] = fma(dz_, Vc[(2 * L + (h2 * n + h1) * n + l) * M + r], vol[r]);
+      }
+    }
+    if (A.scheme == 0) {                     // the finite-volume update needs only the traces
+      double* pc = A.part + (cell * L + line) * M;
+#pragma unroll
+      for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
+    }
+  }
+
+  if (mine && line == 0) atomicAdd(&swsum, (unsigned int)sweeps);
+  const bool any_fail = __any(failed);
+  __syncthreads();
+  if (A.mode == k3dStep) {
+    const int slot = (int)(blockIdx.x % kSlots);
+    if (tid == 0 && swsum) atomicAdd(&A.clk->sweeps[slot].v, (unsigned long long)swsum);
+    if ((tid & 63) == 0 && any_fail) atomicMin(&A.clk->stat[(slot + (tid >> 6)) % kSlots].v, -4);
+  }
 }
 
 template <int N, class TP>
@@ -418,111 +533,178 @@ pred3d_kernel(Args3D A) {
     }
   }
 
-  // ---- epilogue: traces from the X, Y, Z roles' lines (line index = (a, s, t))
+  // volume-term buffer: overlays R (dead after the loop), or Q and R
+  double* const Vb = G::kVbAlias ? reinterpret_cast<double*>(Rs) : kQR ? reinterpret_cast<double*>(QR) : Vsep;
+  pred3d_epilogue<N, TP, G>(A, Qc, Vb + (mine ? cl : 0) * (3 * L * M), u0, dt, mine, cell, line, h2, h1, h0,
+                            sweeps, failed, &swsum, kQR);
+}
+
+// ------------------------------------------ predictor, large tiles ----
+// Degrees whose two tiles do not fit in LDS (FP64 N >= 6, FP32 N >= 7): the
+// sweep streams the time slices of Q.  A cell is served by n^3 threads, one
+// per node (i, j, k), each owning the node's time line of Q.  For each time
+// slice b: every thread evaluates the three fluxes of its node into LDS; after
+// a barrier every thread forms R[b] at its node from the k~ contractions
+// along x, y and z of those fluxes (the sums of the line-owner kernel, in its
+// order), and adds kappa~[a][b] R[b] to its registers for every time node a.
+// After the last slice each thread writes its own time line of Q: Q is only
+// ever touched by its owner inside the loop, so it stays in LDS where it fits
+// (FP64 N = 6, FP32 N = 7) and otherwise lives in a per-cell device buffer,
+// read and written once per sweep.  LDS holds one slice of fluxes (3 n^3 5
+// values), which is the volume-term buffer of the epilogue afterwards.
+template <int N, class TP>
+struct Slab3Geo {
+  using G = Pred3Geo<N, TP>;
+  static constexpr int L = G::L, M = G::M;
+  static constexpr int NT = ((L + 63) / 64) * 64;
+  static constexpr bool kQlds = G::TILE * (int)sizeof(TP) + 3 * L * M * 8 <= 159 * 1024;
+  static constexpr int kGStride = ((G::TILE * (int)sizeof(TP) + 255) / 256) * 256 / (int)sizeof(TP);
+};
+
+template <int N, class TP>
+__global__ void __launch_bounds__((Slab3Geo<N, TP>::NT))
+pred3d_slab_kernel(Args3D A) {
+  using G = Pred3Geo<N, TP>;
+  using S = Slab3Geo<N, TP>;
+  constexpr int n = G::n, L = G::L, M = G::M;
+  using Bits = decltype(ord_bits(TP(0)));
+  __shared__ __align__(16) TP Qlds[S::kQlds ? G::TILE : 1];
+  __shared__ __align__(16) double FV[3 * L * M];
+  __shared__ Bits red[2][2];
+  __shared__ double bcast[3];
+  __shared__ unsigned int swsum;
+
+  const int tid = threadIdx.x;
+  const int line = tid;
+  const int h2 = line / (n * n), h1 = (line / n) % n, h0 = line % n;
+  const int64_t ncells = A.c[0] * A.c[1] * A.c[2];
+  const int64_t cell = blockIdx.x;
+  const bool mine = line < L && cell < ncells;
+
+  const double dt = step_dt3d<N>(A, bcast, blockIdx.x == 0);
+  if (!(dt > 0.0)) return;
+  const TP c0 = TP(dt / A.h[0]), c1 = TP(dt / A.h[1]), c2 = TP(dt / A.h[2]), gm1 = TP(A.gamma - 1.0);
+  if (tid < 4) (&red[0][0])[tid] = 0;
+  if (tid == 0) swsum = 0u;
+
+  TP* const Qc = S::kQlds ? Qlds : reinterpret_cast<TP*>(A.qs) + (int64_t)blockIdx.x * S::kGStride;
+  TP* const Fx = reinterpret_cast<TP*>(FV);
+  TP* const Fy = Fx + L * M;
+  TP* const Fz = Fy + L * M;
+  double u0[M];
+#pragma unroll
+  for (int r = 0; r < M; ++r) u0[r] = mine ? A.u[(cell * L + line) * M + r] : 1.0;
   if (mine) {
-    double tm[3][M], tp[3][M];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int a = 0; a < n; ++a)
 #pragma unroll
-      for (int r = 0; r < M; ++r) tm[d][r] = tp[d][r] = 0.0;
+      for (int r = 0; r < M; ++r) Qc[G::at(a, h2, h1, h0) + r] = TP(u0[r]);
+  }
+  const TP tol = TP(A.tol);
+  bool active = mine, failed = false;
+  int sweeps = 0;
+
+  for (int it = 0;; ++it) {
+    if (!__syncthreads_or(active)) break;
+    TP acc[n][M];
 #pragma unroll
-    for (int p = 0; p < n; ++p) {
-      const double p0 = c3_ops[N].psi0[p], p1 = c3_ops[N].psi1[p];
+    for (int a = 0; a < n; ++a)
 #pragma unroll
-      for (int r = 0; r < M; ++r) {
-        const double vx = (double)Qc[G::at(h2, p, h1, h0) + r];
-        const double vy = (double)Qc[G::at(h2, h1, p, h0) + r];
-        const double vz = (double)Qc[G::at(h2, h1, h0, p) + r];
-        tm[0][r] = fma(p0, vx, tm[0][r]);
-        tp[0][r] = fma(p1, vx, tp[0][r]);
-        tm[1][r] = fma(p0, vy, tm[1][r]);
-        tp[1][r] = fma(p1, vy, tp[1][r]);
-        tm[2][r] = fma(p0, vz, tm[2][r]);
-        tp[2][r] = fma(p1, vz, tp[2][r]);
+      for (int r = 0; r < M; ++r) acc[a][r] = TP(0);
+    for (int b = 0; b < n; ++b) {
+      if (active) {
+        TP qq[M], f[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(b, h2, h1, h0) + r];
+        Euler3::flux<0>(qq, f, gm1);
+#pragma unroll
+        for (int r = 0; r < M; ++r) Fx[line * M + r] = f[r];
+        Euler3::flux<1>(qq, f, gm1);
+#pragma unroll
+        for (int r = 0; r < M; ++r) Fy[line * M + r] = f[r];
+        Euler3::flux<2>(qq, f, gm1);
+#pragma unroll
+        for (int r = 0; r < M; ++r) Fz[line * M + r] = f[r];
       }
+      __syncthreads();
+      if (active) {
+        TP R[M], t[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) R[r] = TP(0);
+#pragma unroll
+        for (int p = 0; p < n; ++p) {        // along x: node (p, j, k)
+          const TP k = launder3(ktil3<N, TP>() + p)[h2 * kDevMaxn];
+#pragma unroll
+          for (int r = 0; r < M; ++r) R[r] = fma(k, c0 * Fx[((p * n + h1) * n + h0) * M + r], R[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < M; ++r) t[r] = TP(0);
+#pragma unroll
+        for (int p = 0; p < n; ++p) {        // along y: node (i, p, k)
+          const TP k = launder3(ktil3<N, TP>() + p)[h1 * kDevMaxn];
+#pragma unroll
+          for (int r = 0; r < M; ++r) t[r] = fma(k, c1 * Fy[((h2 * n + p) * n + h0) * M + r], t[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < M; ++r) R[r] += t[r];
+#pragma unroll
+        for (int r = 0; r < M; ++r) t[r] = TP(0);
+#pragma unroll
+        for (int p = 0; p < n; ++p) {        // along z: node (i, j, p)
+          const TP k = launder3(ktil3<N, TP>() + p)[h0 * kDevMaxn];
+#pragma unroll
+          for (int r = 0; r < M; ++r) t[r] = fma(k, c2 * Fz[((h2 * n + h1) * n + p) * M + r], t[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < M; ++r) R[r] += t[r];
+        // kappa~ along time: acc[a] += kappa~[a][b] R[b]
+#pragma unroll
+        for (int a = 0; a < n; ++a) {
+          const TP kb = launder3(kappa3<N, TP>() + a * kDevMaxn)[b];
+#pragma unroll
+          for (int r = 0; r < M; ++r) acc[a][r] = fma(kb, R[r], acc[a][r]);
+        }
+      }
+      __syncthreads();                       // the next slice overwrites the fluxes
     }
-    TP* trc = reinterpret_cast<TP*>(A.tr) + cell * (6 * L * M);
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int r = 0; r < M; ++r) {
-        trc[((2 * d) * L + line) * M + r] = TP(tm[d][r]);
-        trc[((2 * d + 1) * L + line) * M + r] = TP(tp[d][r]);
-      }
-    if (A.mode == k3dPredict) {
-      TP* qo = reinterpret_cast<TP*>(A.q_out) + cell * (n * L * M);
+    TP e_ = TP(0), qm_ = TP(0);
+    if (active) {
 #pragma unroll
       for (int a = 0; a < n; ++a)
 #pragma unroll
-        for (int r = 0; r < M; ++r) qo[(a * L + line) * M + r] = Qc[G::at(a, h2, h1, h0) + r];
-      if (A.iters && line == 0) A.iters[cell] = sweeps;
+        for (int r = 0; r < M; ++r) {
+          const TP qn = TP(u0[r]) - acc[a][r];
+          TP* p = &Qc[G::at(a, h2, h1, h0) + r];
+          e_ = max_abs(e_, qn - *p);
+          qm_ = max_abs(qm_, qn);
+          *p = qn;
+        }
+      ++sweeps;
     }
-  }
-  // volume terms from the time-integrated fluxes of the (promoted) predictor
-  double* const Vb = G::kVbAlias ? reinterpret_cast<double*>(Rs) : kQR ? reinterpret_cast<double*>(QR) : Vsep;
-  double* const Vc = Vb + (mine ? cl : 0) * (3 * L * M);
-  double fb[3][M];
+    // cell maxima: one cell per workgroup -> whole-wavefront reductions;
+    // every lane takes part, inactive lanes contribute zeros
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int r = 0; r < M; ++r) fb[d][r] = 0.0;
-  if (mine) {
-#pragma unroll
-    for (int a = 0; a < n; ++a) {
-      double qd[M], f[M];
-#pragma unroll
-      for (int r = 0; r < M; ++r) qd[r] = (double)Qc[G::at(a, h2, h1, h0) + r];
-      const double wa = c3_ops[N].w[a];
-      Euler3::flux<0>(qd, f, A.gamma - 1.0);
-#pragma unroll
-      for (int r = 0; r < M; ++r) fb[0][r] = fma(wa, (dt / A.h[0]) * f[r], fb[0][r]);
-      Euler3::flux<1>(qd, f, A.gamma - 1.0);
-#pragma unroll
-      for (int r = 0; r < M; ++r) fb[1][r] = fma(wa, (dt / A.h[1]) * f[r], fb[1][r]);
-      Euler3::flux<2>(qd, f, A.gamma - 1.0);
-#pragma unroll
-      for (int r = 0; r < M; ++r) fb[2][r] = fma(wa, (dt / A.h[2]) * f[r], fb[2][r]);
+    for (int off = 32; off > 0; off >>= 1) {
+      e_ = dmax(e_, __shfl_xor(e_, off, 64));
+      qm_ = dmax(qm_, __shfl_xor(qm_, off, 64));
     }
-  }
-  // Vb overlays R (last read before the loop's final barriers), or Q and R:
-  // then every read of Q above must be done before the first store
-  if constexpr (kQR) __syncthreads();
-  if (mine) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int r = 0; r < M; ++r) Vc[(d * L + line) * M + r] = fb[d][r];
-  }
-  __syncthreads();
-  if (mine) {
-    double vol[M];
-#pragma unroll
-    for (int r = 0; r < M; ++r) vol[r] = 0.0;
-#pragma unroll
-    for (int l = 0; l < n; ++l) {
-      const double dx_ = c3_ops[N].Dw[h2][l], dy_ = c3_ops[N].Dw[h1][l], dz_ = c3_ops[N].Dw[h0][l];
-#pragma unroll
-      for (int r = 0; r < M; ++r) {
-        vol[r] = fma(dx_, Vc[(0 * L + (l * n + h1) * n + h0) * M + r], vol[r]);
-        vol[r] = fma(dy_, Vc[(1 * L + (h2 * n + l) * n + h0) * M + r], vol[r]);
-        vol[r] = fma(dz_, Vc[(2 * L + (h2 * n + h1) * n + l) * M + r], vol[r]);
+    if (active && (tid & 63) == 0) {
+      atomicMax(&red[it & 1][0], ord_bits(e_));
+      atomicMax(&red[it & 1][1], ord_bits(qm_));
+    }
+    if (tid < 2) red[(it + 1) & 1][tid] = 0;
+    __syncthreads();
+    if (active) {
+      const TP E = from_bits(red[it & 1][0]), Qm = from_bits(red[it & 1][1]);
+      if (E <= tol * dmax(TP(1), Qm)) {
+        active = false;
+      } else if (sweeps >= A.max_iter) {
+        active = false;
+        failed = true;
       }
     }
-    if (A.scheme == 0) {                     // the finite-volume update needs only the traces
-      double* pc = A.part + (cell * L + line) * M;
-#pragma unroll
-      for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
-    }
   }
-
-  if (mine && line == 0) atomicAdd(&swsum, (unsigned int)sweeps);
-  const bool any_fail = __any(failed);
-  __syncthreads();
-  if (A.mode == k3dStep) {
-    const int slot = (int)(blockIdx.x % kSlots);
-    if (tid == 0 && swsum) atomicAdd(&A.clk->sweeps[slot].v, (unsigned long long)swsum);
-    if ((tid & 63) == 0 && any_fail) atomicMin(&A.clk->stat[(slot + (tid >> 6)) % kSlots].v, -4);
-  }
+  pred3d_epilogue<N, TP, G>(A, Qc, FV, u0, dt, mine, cell, line, h2, h1, h0, sweeps, failed, &swsum, false);
 }
 
 // ----------------------------------------------------------- corrector ----
@@ -916,8 +1098,12 @@ __global__ void clock3d_end_kernel(const Clock3D* clk, double* t_user, double* d
 // -------------------------------------------------------------- dispatch ----
 template <int N, class TP>
 static hipError_t pred3d_one(const Args3D& A, int64_t blocks, hipStream_t st) {
-  if (Pred3Geo<N, TP>::kGlobal && A.qs == nullptr) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((pred3d_kernel<N, TP>), dim3((unsigned)blocks), dim3(Pred3Geo<N, TP>::NT), 0, st, A);
+  if constexpr (Pred3Geo<N, TP>::kGlobal) {
+    if (!Slab3Geo<N, TP>::kQlds && A.qs == nullptr) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((pred3d_slab_kernel<N, TP>), dim3((unsigned)blocks), dim3(Slab3Geo<N, TP>::NT), 0, st, A);
+  } else {
+    hipLaunchKernelGGL((pred3d_kernel<N, TP>), dim3((unsigned)blocks), dim3(Pred3Geo<N, TP>::NT), 0, st, A);
+  }
   return hipGetLastError();
 }
 
@@ -940,6 +1126,15 @@ template <class TP> static int cpb3_p(int N) {
 #undef ADERDG3_CASE
     default: return 0;
   }
+}
+
+// Bytes of the device buffer a cell's predictor tile needs (0: it is in LDS).
+template <int N, class TP>
+constexpr int64_t pred3d_global_bytes() {
+  if constexpr (Pred3Geo<N, TP>::kGlobal && !Slab3Geo<N, TP>::kQlds)
+    return (int64_t)Slab3Geo<N, TP>::kGStride * (int64_t)sizeof(TP);
+  else
+    return 0;
 }
 
 template <class TP> static int64_t gbytes3_p(int N) {
