@@ -14,7 +14,8 @@
 // applies kappa~ from registers, writes q_new over its own time line of Q and
 // tests convergence.  Every contraction runs from registers over a line the
 // thread owns.  Two tiles of n^4 M values must fit in LDS: N <= 5 in FP64,
-// N <= 6 in the FP32-predictor mode.  The epilogue writes the six face traces
+// N <= 6 in the FP32-predictor mode; above, pred3d_slab_kernel streams the
+// time slices instead (see there).  The epilogue writes the six face traces
 // (in the predictor precision) and u + volume terms (FP64); the corrector kernel evaluates the Rusanov
 // fluxes through the six faces, updates u in place and reduces the subcell
 // signal speeds for the next step.
@@ -163,16 +164,9 @@ struct Pred3Geo {
   // fluxes of the volume terms are in registers): overlay both, one barrier more
   static constexpr bool kVbOverQR = !kVbAlias && 2 * CPB * TILE * (int)sizeof(TP) >= VB * 8;
   static constexpr int kBytes = 2 * CPB * TILE * (int)sizeof(TP) + (kVbAlias || kVbOverQR ? 0 : VB * 8);
-  // tiles too large for LDS (FP64 from N = 6, FP32 from N = 7): Q and R live
-  // in a per-cell device buffer instead (L1/L2-resident while the cell's
-  // workgroup runs; the barriers order its global stores and loads as they
-  // do the LDS ones), one cell per workgroup
+  // tiles too large for LDS (FP64 from N = 6, FP32 from N = 7): served by
+  // the slice-streaming kernel below instead
   static constexpr bool kGlobal = kBytes > 159 * 1024;
-  // elements from the start of a cell's Q tile to its R tile (256-byte aligned)
-  static constexpr int kGStride = ((TILE * (int)sizeof(TP) + 255) / 256) * 256 / (int)sizeof(TP);
-  // outputs of a space contraction kept in registers at once (the line's
-  // fluxes are evaluated once per chunk)
-  static constexpr int CH = kGlobal && n > 7 ? (n + 1) / 2 : n;
   __device__ static constexpr int at(int a, int i, int j, int k) { return a * SA + i * SI + j * SJ + k * M; }
 };
 
@@ -305,15 +299,14 @@ pred3d_kernel(Args3D A) {
   constexpr int n = G::n, L = G::L, M = G::M, CPB = G::CPB;
   using Bits = decltype(ord_bits(TP(0)));
 
-  constexpr bool kG = G::kGlobal;
-  constexpr bool kQR = G::kVbOverQR && !kG;
+  static_assert(!G::kGlobal, "tiles beyond LDS are served by pred3d_slab_kernel");
+  constexpr bool kQR = G::kVbOverQR;
   __shared__ __align__(16) TP QR[kQR ? 2 * CPB * G::TILE : 1];
-  __shared__ TP Qsep[kQR || kG ? 1 : CPB * G::TILE];
-  __shared__ TP Rsep[kQR || kG ? 1 : CPB * G::TILE];
-  __shared__ double Vsep[G::kVbAlias || kQR || kG ? 1 : G::VB];
-  TP* const Qg = kG ? reinterpret_cast<TP*>(A.qs) + (int64_t)blockIdx.x * (2 * G::kGStride) : nullptr;
-  TP* const Qs = kG ? Qg : kQR ? QR : Qsep;
-  TP* const Rs = kG ? Qg + G::kGStride : kQR ? QR + CPB * G::TILE : Rsep;
+  __shared__ TP Qsep[kQR ? 1 : CPB * G::TILE];
+  __shared__ TP Rsep[kQR ? 1 : CPB * G::TILE];
+  __shared__ double Vsep[G::kVbAlias || kQR ? 1 : G::VB];
+  TP* const Qs = kQR ? QR : Qsep;
+  TP* const Rs = kQR ? QR + CPB * G::TILE : Rsep;
   __shared__ Bits red[2][CPB][2];
   __shared__ double bcast[3];
   __shared__ unsigned int swsum;
@@ -352,122 +345,83 @@ pred3d_kernel(Args3D A) {
     if (!__syncthreads_or(active)) break;
     if (active) {
       // X role, line (a, j, k): R = k~ (dt/dx) Fx along i
+      TP acc[n][M];
 #pragma unroll
-      for (int i0 = 0; i0 < n; i0 += G::CH) {
-        constexpr int CH = G::CH;
-        TP acc[CH][M];
+      for (int i = 0; i < n; ++i)
 #pragma unroll
-        for (int i = 0; i < CH; ++i)
+        for (int r = 0; r < M; ++r) acc[i][r] = TP(0);
 #pragma unroll
-          for (int r = 0; r < M; ++r) acc[i][r] = TP(0);
+      for (int ip = 0; ip < n; ++ip) {
+        TP qq[M], f[M];
 #pragma unroll
-        for (int ip = 0; ip < n; ++ip) {
-          TP qq[M], f[M];
+        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, ip, h1, h0) + r];
+        Euler3::flux<0>(qq, f, gm1);
+        const cptr3<TP> K = launder3(ktil3<N, TP>() + ip);
 #pragma unroll
-          for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, ip, h1, h0) + r];
-          Euler3::flux<0>(qq, f, gm1);
-          const cptr3<TP> K = launder3(ktil3<N, TP>() + ip);
+        for (int i = 0; i < n; ++i)
 #pragma unroll
-          for (int i = 0; i < CH; ++i)
-            if (i0 + i < n)
-#pragma unroll
-              for (int r = 0; r < M; ++r) acc[i][r] = fma(K[(i0 + i) * kDevMaxn], c0 * f[r], acc[i][r]);
-        }
-#pragma unroll
-        for (int i = 0; i < CH; ++i)
-          if (i0 + i < n)
-#pragma unroll
-            for (int r = 0; r < M; ++r) Rc[G::at(h2, i0 + i, h1, h0) + r] = acc[i][r];
+          for (int r = 0; r < M; ++r) acc[i][r] = fma(K[i * kDevMaxn], c0 * f[r], acc[i][r]);
       }
+#pragma unroll
+      for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int r = 0; r < M; ++r) Rc[G::at(h2, i, h1, h0) + r] = acc[i][r];
     }
     __syncthreads();
     if (active) {
       // Y role, line (a, i, k): R += k~ (dt/dy) Fy along j
+      TP acc[n][M];
 #pragma unroll
-      for (int j0 = 0; j0 < n; j0 += G::CH) {
-        constexpr int CH = G::CH;
-        TP acc[CH][M];
+      for (int j = 0; j < n; ++j)
 #pragma unroll
-        for (int j = 0; j < CH; ++j)
+        for (int r = 0; r < M; ++r) acc[j][r] = TP(0);
 #pragma unroll
-          for (int r = 0; r < M; ++r) acc[j][r] = TP(0);
+      for (int jp = 0; jp < n; ++jp) {
+        TP qq[M], f[M];
 #pragma unroll
-        for (int jp = 0; jp < n; ++jp) {
-          TP qq[M], f[M];
+        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, jp, h0) + r];
+        Euler3::flux<1>(qq, f, gm1);
+        const cptr3<TP> K = launder3(ktil3<N, TP>() + jp);
 #pragma unroll
-          for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, jp, h0) + r];
-          Euler3::flux<1>(qq, f, gm1);
-          const cptr3<TP> K = launder3(ktil3<N, TP>() + jp);
+        for (int j = 0; j < n; ++j)
 #pragma unroll
-          for (int j = 0; j < CH; ++j)
-            if (j0 + j < n)
-#pragma unroll
-              for (int r = 0; r < M; ++r) acc[j][r] = fma(K[(j0 + j) * kDevMaxn], c1 * f[r], acc[j][r]);
-        }
-#pragma unroll
-        for (int j = 0; j < CH; ++j)
-          if (j0 + j < n)
-#pragma unroll
-            for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, j0 + j, h0) + r] += acc[j][r];
+          for (int r = 0; r < M; ++r) acc[j][r] = fma(K[j * kDevMaxn], c1 * f[r], acc[j][r]);
       }
+#pragma unroll
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, j, h0) + r] += acc[j][r];
     }
     __syncthreads();
     if (active) {
       // Z role, line (a, i, j): R += k~ (dt/dz) Fz along k
+      TP acc[n][M];
 #pragma unroll
-      for (int k0 = 0; k0 < n; k0 += G::CH) {
-        constexpr int CH = G::CH;
-        TP acc[CH][M];
+      for (int k = 0; k < n; ++k)
 #pragma unroll
-        for (int k = 0; k < CH; ++k)
+        for (int r = 0; r < M; ++r) acc[k][r] = TP(0);
 #pragma unroll
-          for (int r = 0; r < M; ++r) acc[k][r] = TP(0);
+      for (int kp = 0; kp < n; ++kp) {
+        TP qq[M], f[M];
 #pragma unroll
-        for (int kp = 0; kp < n; ++kp) {
-          TP qq[M], f[M];
+        for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, h0, kp) + r];
+        Euler3::flux<2>(qq, f, gm1);
+        const cptr3<TP> K = launder3(ktil3<N, TP>() + kp);
 #pragma unroll
-          for (int r = 0; r < M; ++r) qq[r] = Qc[G::at(h2, h1, h0, kp) + r];
-          Euler3::flux<2>(qq, f, gm1);
-          const cptr3<TP> K = launder3(ktil3<N, TP>() + kp);
+        for (int k = 0; k < n; ++k)
 #pragma unroll
-          for (int k = 0; k < CH; ++k)
-            if (k0 + k < n)
-#pragma unroll
-              for (int r = 0; r < M; ++r) acc[k][r] = fma(K[(k0 + k) * kDevMaxn], c2 * f[r], acc[k][r]);
-        }
-#pragma unroll
-        for (int k = 0; k < CH; ++k)
-          if (k0 + k < n)
-#pragma unroll
-            for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, h0, k0 + k) + r] += acc[k][r];
+          for (int r = 0; r < M; ++r) acc[k][r] = fma(K[k * kDevMaxn], c2 * f[r], acc[k][r]);
       }
+#pragma unroll
+      for (int k = 0; k < n; ++k)
+#pragma unroll
+        for (int r = 0; r < M; ++r) Rc[G::at(h2, h1, h0, k) + r] += acc[k][r];
     }
     __syncthreads();
     TP e_ = TP(0), qm_ = TP(0);
     if (active) {
       // T role: q_new[a] = u - sum_b kappa~[a][b] R[b][i][j][k] over the own time line
-      if constexpr (kG) {
-        // one variable at a time: the time line of R for that variable only
-        // in registers (same sums, same order)
-#pragma unroll
-        for (int r = 0; r < M; ++r) {
-          TP rr[n];
-#pragma unroll
-          for (int b = 0; b < n; ++b) rr[b] = Rc[G::at(b, h2, h1, h0) + r];
-#pragma unroll
-          for (int a = 0; a < n; ++a) {
-            const cptr3<TP> Kp = launder3(kappa3<N, TP>() + a * kDevMaxn);
-            TP acc = TP(0);
-#pragma unroll
-            for (int b = 0; b < n; ++b) acc = fma(Kp[b], rr[b], acc);
-            const TP qn = TP(u0[r]) - acc;
-            TP* p = &Qc[G::at(a, h2, h1, h0) + r];
-            e_ = max_abs(e_, qn - *p);
-            qm_ = max_abs(qm_, qn);
-            *p = qn;
-          }
-        }
-      } else {
+      {
         TP rr[n][M];
 #pragma unroll
         for (int b = 0; b < n; ++b)
@@ -559,6 +513,16 @@ struct Slab3Geo {
   static constexpr int NT = ((L + 63) / 64) * 64;
   static constexpr bool kQlds = G::TILE * (int)sizeof(TP) + 3 * L * M * 8 <= 159 * 1024;
   static constexpr int kGStride = ((G::TILE * (int)sizeof(TP) + 255) / 256) * 256 / (int)sizeof(TP);
+};
+
+// Degrees served by the slice-streaming kernel: those whose tiles exceed LDS,
+// and (one cell per workgroup) those from ADERDG_SLAB_FROM on.
+#ifndef ADERDG_SLAB_FROM
+#define ADERDG_SLAB_FROM 10
+#endif
+template <int N, class TP>
+struct UseSlab3 {
+  static constexpr bool value = Pred3Geo<N, TP>::kGlobal || (N >= ADERDG_SLAB_FROM && Pred3Geo<N, TP>::CPB == 1);
 };
 
 template <int N, class TP>
@@ -1098,7 +1062,7 @@ __global__ void clock3d_end_kernel(const Clock3D* clk, double* t_user, double* d
 // -------------------------------------------------------------- dispatch ----
 template <int N, class TP>
 static hipError_t pred3d_one(const Args3D& A, int64_t blocks, hipStream_t st) {
-  if constexpr (Pred3Geo<N, TP>::kGlobal) {
+  if constexpr (UseSlab3<N, TP>::value) {
     if (!Slab3Geo<N, TP>::kQlds && A.qs == nullptr) return hipErrorInvalidValue;
     hipLaunchKernelGGL((pred3d_slab_kernel<N, TP>), dim3((unsigned)blocks), dim3(Slab3Geo<N, TP>::NT), 0, st, A);
   } else {
@@ -1131,7 +1095,7 @@ template <class TP> static int cpb3_p(int N) {
 // Bytes of the device buffer a cell's predictor tile needs (0: it is in LDS).
 template <int N, class TP>
 constexpr int64_t pred3d_global_bytes() {
-  if constexpr (Pred3Geo<N, TP>::kGlobal && !Slab3Geo<N, TP>::kQlds)
+  if constexpr (UseSlab3<N, TP>::value && !Slab3Geo<N, TP>::kQlds)
     return (int64_t)Slab3Geo<N, TP>::kGStride * (int64_t)sizeof(TP);
   else
     return 0;
