@@ -1125,6 +1125,8 @@ def main():
                     help="first run a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--dg2d-only", action="store_true",
                     help="only the 2-D workload (512x512 cells, N=5; for profiling the 2-D kernels)")
+    ap.add_argument("--fp32-predictor-only", action="store_true",
+                    help="only the headline workload with the FP32 predictor (for profiling that mode)")
     ap.add_argument("--autotune-only", action="store_true",
                     help="only the workgroup-size autotuner comparison (1-D DG step, single problems and the batch)")
     ap.add_argument("--fv2d-only", action="store_true",
@@ -1150,7 +1152,8 @@ def main():
     # the oracle's host-core baseline runs first: its worker processes are
     # forked, which must happen before this process touches the GPU
     cpu = None
-    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only or a.fv2d_only or a.fv3d_only or a.autotune_only):
+    if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only or a.fv2d_only or a.fv3d_only or a.autotune_only
+                                          or a.fp32_predictor_only):
         cpu = cpu_baseline(N)
         emit("cpu_baseline", cpu)
 
@@ -1182,6 +1185,17 @@ def main():
         return
     if a.fv3d_only:
         print(json.dumps({"fv3d_euler_sine": fv3d_section()}))
+        return
+
+    if a.fp32_predictor_only:
+        r32 = DGRun(N, C, abi.FP32_PREDICTOR)
+        ramp(r32)
+        r32.steps(Wm)
+        s32, sw32 = r32.timed(K)
+        print(json.dumps({"fp32_predictor_c2": {
+            "value": round(K * C * (N + 1) * M / s32, 1), "ms_per_step": round(s32 / K * 1e3, 5),
+            "roofline": roofline_entry(N, C, M, K, s32, sw32, "fp32"), "status": int(r32.st.item())}}))
+        r32.close()
         return
 
     run = DGRun(N, C, abi.FP64)
