@@ -457,49 +457,51 @@ pred2d_kernel(Args2D A) {
       if (A.iters && line == 0) A.iters[cell] = sweeps;
     }
   }
-  // volume terms: time-integrated fluxes of the (promoted) predictor at every node
-  double* const Vb = G::kVbAlias ? reinterpret_cast<double*>(Rs) : Vsep;
-  double* const Vc = Vb + (mine ? cl : 0) * (2 * L * M);
-  if (mine) {
-    double fxb[M], fyb[M];
+  // volume terms (DG only: the finite-volume update needs only the traces;
+  // the scheme is the same for every thread, so the barrier inside is too)
+  if (A.scheme == 0) {
+    // volume terms: time-integrated fluxes of the (promoted) predictor at every node
+    double* const Vb = G::kVbAlias ? reinterpret_cast<double*>(Rs) : Vsep;
+    double* const Vc = Vb + (mine ? cl : 0) * (2 * L * M);
+    if (mine) {
+      double fxb[M], fyb[M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) fxb[r] = fyb[r] = 0.0;
+      for (int r = 0; r < M; ++r) fxb[r] = fyb[r] = 0.0;
 #pragma unroll
-    for (int a = 0; a < n; ++a) {
-      double qd[M], f[M];
-      TP v[M];
-      ld4<PL>(Qc + G::at(a, ti, tj), v);
+      for (int a = 0; a < n; ++a) {
+        double qd[M], f[M];
+        TP v[M];
+        ld4<PL>(Qc + G::at(a, ti, tj), v);
 #pragma unroll
-      for (int r = 0; r < M; ++r) qd[r] = (double)v[r];
-      const double wa = c2_ops[N].w[a];
-      Euler2::flux_x(qd, f, A.gamma - 1.0);
+        for (int r = 0; r < M; ++r) qd[r] = (double)v[r];
+        const double wa = c2_ops[N].w[a];
+        Euler2::flux_x(qd, f, A.gamma - 1.0);
 #pragma unroll
-      for (int r = 0; r < M; ++r) fxb[r] = fma(wa, dtdx * f[r], fxb[r]);
-      Euler2::flux_y(qd, f, A.gamma - 1.0);
+        for (int r = 0; r < M; ++r) fxb[r] = fma(wa, dtdx * f[r], fxb[r]);
+        Euler2::flux_y(qd, f, A.gamma - 1.0);
 #pragma unroll
-      for (int r = 0; r < M; ++r) fyb[r] = fma(wa, dtdy * f[r], fyb[r]);
+        for (int r = 0; r < M; ++r) fyb[r] = fma(wa, dtdy * f[r], fyb[r]);
+      }
+      // in FP64, Vb aliases R, last read before the loop's final barriers
+#pragma unroll
+      for (int r = 0; r < M; ++r) {
+        Vc[node * M + r] = fxb[r];
+        Vc[(L + node) * M + r] = fyb[r];
+      }
     }
-    // in FP64, Vb aliases R, last read before the loop's final barriers
+    __syncthreads();
+    if (mine) {
+      double vol[M];
 #pragma unroll
-    for (int r = 0; r < M; ++r) {
-      Vc[node * M + r] = fxb[r];
-      Vc[(L + node) * M + r] = fyb[r];
-    }
-  }
-  __syncthreads();
-  if (mine) {
-    double vol[M];
+      for (int r = 0; r < M; ++r) vol[r] = 0.0;
 #pragma unroll
-    for (int r = 0; r < M; ++r) vol[r] = 0.0;
+      for (int l = 0; l < n; ++l) {
+        const double dx_ = c2_ops[N].Dw[ti][l], dy_ = c2_ops[N].Dw[tj][l];
 #pragma unroll
-    for (int l = 0; l < n; ++l) {
-      const double dx_ = c2_ops[N].Dw[ti][l], dy_ = c2_ops[N].Dw[tj][l];
+        for (int r = 0; r < M; ++r) vol[r] = fma(dx_, Vc[(l * n + tj) * M + r], vol[r]);
 #pragma unroll
-      for (int r = 0; r < M; ++r) vol[r] = fma(dx_, Vc[(l * n + tj) * M + r], vol[r]);
-#pragma unroll
-      for (int r = 0; r < M; ++r) vol[r] = fma(dy_, Vc[(L + ti * n + l) * M + r], vol[r]);
-    }
-    if (A.scheme == 0) {                     // the finite-volume update needs only the traces
+        for (int r = 0; r < M; ++r) vol[r] = fma(dy_, Vc[(L + ti * n + l) * M + r], vol[r]);
+      }
       double* pc = A.part + (cell * L + node) * M;
 #pragma unroll
       for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];

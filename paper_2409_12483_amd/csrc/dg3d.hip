@@ -227,55 +227,57 @@ __device__ __forceinline__ void pred3d_epilogue(const Args3D& A, const TP* Qc, d
       if (A.iters && line == 0) A.iters[cell] = sweeps;
     }
   }
-  // volume terms from the time-integrated fluxes of the (promoted) predictor
-  double fb[3][M];
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int r = 0; r < M; ++r) fb[d][r] = 0.0;
-  if (mine) {
-#pragma unroll
-    for (int a = 0; a < n; ++a) {
-      double qd[M], f[M];
-#pragma unroll
-      for (int r = 0; r < M; ++r) qd[r] = (double)Qc[G::at(a, h2, h1, h0) + r];
-      const double wa = c3_ops[N].w[a];
-      Euler3::flux<0>(qd, f, A.gamma - 1.0);
-#pragma unroll
-      for (int r = 0; r < M; ++r) fb[0][r] = fma(wa, (dt / A.h[0]) * f[r], fb[0][r]);
-      Euler3::flux<1>(qd, f, A.gamma - 1.0);
-#pragma unroll
-      for (int r = 0; r < M; ++r) fb[1][r] = fma(wa, (dt / A.h[1]) * f[r], fb[1][r]);
-      Euler3::flux<2>(qd, f, A.gamma - 1.0);
-#pragma unroll
-      for (int r = 0; r < M; ++r) fb[2][r] = fma(wa, (dt / A.h[2]) * f[r], fb[2][r]);
-    }
-  }
-  // Vb overlays R (last read before the loop's final barriers), or Q and R:
-  // then every read of Q above must be done before the first store
-  if (sync_before_vb) __syncthreads();
-  if (mine) {
+  // volume terms (DG only: the finite-volume update needs only the traces;
+  // the scheme is the same for every thread, so the barriers inside are too)
+  if (A.scheme == 0) {
+    // volume terms from the time-integrated fluxes of the (promoted) predictor
+    double fb[3][M];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-      for (int r = 0; r < M; ++r) Vc[(d * L + line) * M + r] = fb[d][r];
-  }
-  __syncthreads();
-  if (mine) {
-    double vol[M];
+      for (int r = 0; r < M; ++r) fb[d][r] = 0.0;
+    if (mine) {
 #pragma unroll
-    for (int r = 0; r < M; ++r) vol[r] = 0.0;
+      for (int a = 0; a < n; ++a) {
+        double qd[M], f[M];
 #pragma unroll
-    for (int l = 0; l < n; ++l) {
-      const double dx_ = c3_ops[N].Dw[h2][l], dy_ = c3_ops[N].Dw[h1][l], dz_ = c3_ops[N].Dw[h0][l];
+        for (int r = 0; r < M; ++r) qd[r] = (double)Qc[G::at(a, h2, h1, h0) + r];
+        const double wa = c3_ops[N].w[a];
+        Euler3::flux<0>(qd, f, A.gamma - 1.0);
 #pragma unroll
-      for (int r = 0; r < M; ++r) {
-        vol[r] = fma(dx_, Vc[(0 * L + (l * n + h1) * n + h0) * M + r], vol[r]);
-        vol[r] = fma(dy_, Vc[(1 * L + (h2 * n + l) * n + h0) * M + r], vol[r]);
-        vol[r] = fma(dz_, Vc[(2 * L + (h2 * n + h1) * n + l) * M + r], vol[r]);
+        for (int r = 0; r < M; ++r) fb[0][r] = fma(wa, (dt / A.h[0]) * f[r], fb[0][r]);
+        Euler3::flux<1>(qd, f, A.gamma - 1.0);
+#pragma unroll
+        for (int r = 0; r < M; ++r) fb[1][r] = fma(wa, (dt / A.h[1]) * f[r], fb[1][r]);
+        Euler3::flux<2>(qd, f, A.gamma - 1.0);
+#pragma unroll
+        for (int r = 0; r < M; ++r) fb[2][r] = fma(wa, (dt / A.h[2]) * f[r], fb[2][r]);
       }
     }
-    if (A.scheme == 0) {                     // the finite-volume update needs only the traces
+    // Vb overlays R (last read before the loop's final barriers), or Q and R:
+    // then every read of Q above must be done before the first store
+    if (sync_before_vb) __syncthreads();
+    if (mine) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int r = 0; r < M; ++r) Vc[(d * L + line) * M + r] = fb[d][r];
+    }
+    __syncthreads();
+    if (mine) {
+      double vol[M];
+#pragma unroll
+      for (int r = 0; r < M; ++r) vol[r] = 0.0;
+#pragma unroll
+      for (int l = 0; l < n; ++l) {
+        const double dx_ = c3_ops[N].Dw[h2][l], dy_ = c3_ops[N].Dw[h1][l], dz_ = c3_ops[N].Dw[h0][l];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          vol[r] = fma(dx_, Vc[(0 * L + (l * n + h1) * n + h0) * M + r], vol[r]);
+          vol[r] = fma(dy_, Vc[(1 * L + (h2 * n + l) * n + h0) * M + r], vol[r]);
+          vol[r] = fma(dz_, Vc[(2 * L + (h2 * n + h1) * n + l) * M + r], vol[r]);
+        }
+      }
       double* pc = A.part + (cell * L + line) * M;
 #pragma unroll
       for (int r = 0; r < M; ++r) pc[r] = u0[r] + vol[r];
