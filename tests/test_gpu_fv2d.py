@@ -125,3 +125,17 @@ def test_scheme_validation():
             abi.aderdg2d_predict(h, u, 0.0, 0.01, q)
     finally:
         abi.aderdg2d_free(h)
+
+
+@pytest.mark.parametrize("N,cx,cy", [(1, 1, 6), (2, 5, 1), (3, 2, 3)])
+def test_meshes_thinner_than_the_stencil(N, cx, cy):
+    """A dimension of one or two cells (the WENO stencils of 2N+1 cells wrap
+    around it several times) and meshes smaller than one tile."""
+    _say("fv2d thin mesh", N, cx, cy)
+    ops = basis.build_operators(N)
+    v0 = _wave(cx, cy, 21 + N)
+    ref, t_ref, info = fv2d.fv2d_run(ops, E2, v0, cfl=0.4, nsteps=3)
+    v, t, st = gpu_fv(v0, N, 3)
+    assert st == 0 and not info["failed"]
+    assert t == pytest.approx(t_ref, rel=1e-13)
+    assert _rel(v, ref) <= 1e-12

@@ -133,3 +133,17 @@ def test_scheme_validation():
             abi.aderdg3d_predict(h, u, 0.0, 0.01, q)
     finally:
         abi.aderdg3d_free(h)
+
+
+@pytest.mark.parametrize("N,cells", [(1, (1, 5, 4)), (2, (3, 1, 2)), (3, (2, 3, 1))])
+def test_meshes_thinner_than_the_stencil(N, cells):
+    """A dimension of one or two cells (the WENO stencils of 2N+1 cells wrap
+    around it several times) and meshes smaller than one tile."""
+    _say("fv3d thin mesh", N, cells)
+    ops = basis.build_operators(N)
+    v0 = _state(*cells, seed=11 + N)
+    ref, t_ref, info = fv3d.fv3d_run(ops, E3, v0, cfl=0.4, nsteps=3)
+    v, t, st = gpu_fv(v0, N, 3)
+    assert st == 0 and not info["failed"]
+    assert t == pytest.approx(t_ref, rel=1e-13)
+    assert _rel(v, ref) <= 1e-12
