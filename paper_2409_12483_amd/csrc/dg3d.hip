@@ -859,16 +859,22 @@ lambda3d_kernel(Args3D A) {
 // ------------------------------------------------- ADER-WENO (scheme 1) ----
 // Dimension-by-dimension WENO: along x for every line of cells, then along y
 // at every x node, then along z at every (x, y) node pair.  One workgroup per
-// tile of 4 x 4 x 2 cells: the averages of the tile and its halo of NW cells
-// are staged in LDS; the x sweep runs once per (tile x, halo y, halo z,
-// variable), the y sweep once per (tile x, tile y, halo z, x node, variable),
-// the z sweep per (cell, x node, y node, variable).  The y results reuse the
-// staging buffer (dead after the x sweep).
-constexpr int kW3x = 4, kW3y = 4, kW3z = 2;
+// tile of 4 x 4 x 2 cells (2 x 4 x 2 at degree 3, whose y results of n^2
+// values per cell and halo layer would otherwise leave room for one workgroup
+// per CU; the x extent does not change the sweeps per cell): the averages of
+// the tile and its halo of NW cells are staged in LDS; the x sweep runs once
+// per (tile x, halo y, halo z, variable), the y sweep once per (tile x,
+// tile y, halo z, x node, variable), the z sweep per (cell, x node, y node,
+// variable).  The y results reuse the staging buffer (dead after the x sweep).
+template <int NW>
+struct W3Tile {
+  static constexpr int x = NW >= 3 ? 2 : 4, y = 4, z = 2;
+};
 
 template <int NW>
 __global__ void __launch_bounds__(kFv3dThreads) weno3d_kernel(Args3D A, double* w) {
   constexpr int n = NW + 1, M = 5, S = 2 * NW + 1;
+  constexpr int kW3x = W3Tile<NW>::x, kW3y = W3Tile<NW>::y, kW3z = W3Tile<NW>::z;
   constexpr int Hx = kW3x + 2 * NW, Hy = kW3y + 2 * NW, Hz = kW3z + 2 * NW;
   constexpr int VA = Hx * Hy * Hz * M, WY = kW3x * kW3y * Hz * n * n * M;
   __shared__ double buf[VA > WY ? VA : WY];            // staged averages, then the y sweep
@@ -1163,9 +1169,14 @@ hipError_t launch_clock3d_end(const Clock3D* clk, double* t_user, double* dt_use
   return hipGetLastError();
 }
 
+template <int NW>
+static int64_t weno3d_tiles(const Args3D& A) {
+  using T = W3Tile<NW>;
+  return ((A.c[0] + T::x - 1) / T::x) * ((A.c[1] + T::y - 1) / T::y) * ((A.c[2] + T::z - 1) / T::z);
+}
+
 hipError_t launch_weno3d(int NW, const Args3D& A, double* w, hipStream_t st) {
-  const int64_t tiles = ((A.c[0] + kW3x - 1) / kW3x) * ((A.c[1] + kW3y - 1) / kW3y) *
-                        ((A.c[2] + kW3z - 1) / kW3z);
+  const int64_t tiles = NW == 1 ? weno3d_tiles<1>(A) : NW == 2 ? weno3d_tiles<2>(A) : weno3d_tiles<3>(A);
   dim3 grid((unsigned)tiles), block(kFv3dThreads);
   if (NW == 1) hipLaunchKernelGGL((weno3d_kernel<1>), grid, block, 0, st, A, w);
   else if (NW == 2) hipLaunchKernelGGL((weno3d_kernel<2>), grid, block, 0, st, A, w);
