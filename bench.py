@@ -661,6 +661,7 @@ def fv2d_section():
             e["paper_cpu_s_tjit"] = PAPER_FV2D_TJIT[(N, C)]
             tts.append(e)
     out["paper_fv_table_time_to_solution"] = tts
+    out["cpu_baseline_degree2"] = fv2d_cpu_baseline()
     return out
 
 
@@ -702,6 +703,49 @@ def dg3d_cpu_baseline(N=3, C=8):
     v, steps = oracle_rate(one, C ** 3 * (N + 1) ** 3 * 5)
     return {"value": v, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"the same sine wave on {C}^3 cells, N={N}, {steps} steps, NumPy FP64, single thread"}
+
+
+def fv2d_cpu_baseline(N=2, C=32):
+    from oracle import basis, dg2d, fv2d
+    from paper_2409_12483_amd import workloads as W
+    ops, pde = basis.build_operators(N), dg2d.Euler2D()
+    state = {"v": W.euler2d_sine_averages(C, C)}
+
+    def one():
+        state["v"], _, _ = fv2d.fv2d_run(ops, pde, state["v"], nsteps=1)
+    v, steps = oracle_rate(one, C * C * 4)
+    return {"value": v, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"the same sine wave on {C}x{C} cells, WENO degree {N} (ADER-WENO{N + 1}), {steps} steps, "
+                      "NumPy FP64, single thread"}
+
+
+def fv3d_cpu_baseline(N=2, C=10):
+    from oracle import basis, dg3d, fv3d
+    from paper_2409_12483_amd import workloads as W
+    ops, pde = basis.build_operators(N), dg3d.Euler3D()
+    state = {"v": W.euler3d_sine_averages(C, C, C)}
+
+    def one():
+        state["v"], _, _ = fv3d.fv3d_run(ops, pde, state["v"], nsteps=1)
+    v, steps = oracle_rate(one, C ** 3 * 5)
+    return {"value": v, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"the same sine wave on {C}^3 cells, WENO degree {N} (ADER-WENO{N + 1}), {steps} steps, "
+                      "NumPy FP64, single thread"}
+
+
+def lim_cpu_baseline(N=5, C=1024, period=64):
+    from oracle import basis, limiter
+    from oracle import pde as OP
+    from paper_2409_12483_amd import workloads as W
+    ops, pde = basis.build_operators(N), OP.Euler()
+    state = {"u": W.riemann_array_nodal(C, N, 1, period), "v": None}
+
+    def one():
+        state["u"], _, info = limiter.limited_run(ops, pde, state["u"], 0.0, 1.0, nsteps=1)
+    v, steps = oracle_rate(one, C * (N + 1) * 3)
+    return {"value": v, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"the same row of Sod problems (blocks of {period} cells) on {C} cells, N={N}, {steps} "
+                      "limited steps, NumPy FP64, single thread"}
 
 
 def dg2d_section(quick=False):
@@ -925,6 +969,7 @@ def fv3d_section():
             e["paper_cpu_s_tjit"] = PAPER_FV3D_TJIT[(N, C)]
             tts.append(e)
     out["paper_fv_table_time_to_solution"] = tts
+    out["cpu_baseline_degree2"] = fv3d_cpu_baseline()
     return out
 
 
@@ -1084,6 +1129,7 @@ def lim_array(N=5, C=131072, period=64, K=100, warmup=20):
 
 def limiter_section(quick=False):
     out = {"array_n5": lim_array()}
+    out["cpu_baseline_array_n5"] = lim_cpu_baseline()
     if not quick:
         out["table9_n9_50"] = lim_table9()
     return out
