@@ -134,6 +134,22 @@ def predict2d(ops, pde, u, dt, dx, dy, tol=1e-14, max_iter=64):
     return (q_prev.reshape(Cx, Cy, n, n, n, M), sweeps.reshape(Cx, Cy), failed.reshape(Cx, Cy))
 
 
+def face_fluxes2d(ops, pde, q, dt, dx, dy):
+    """Time-integrated Rusanov fluxes through the east face [Cx, Cy, n (y node), M]
+    and the north face [Cx, Cy, n (x node), M] of every cell (periodic
+    neighbours), scaled by dt/dx and dt/dy: sum_a w_a G(trace; a, node)."""
+    w = ops.w
+    # face traces (Algorithm 7 per direction): [Cx, Cy, a, j or i, M]
+    west = np.einsum("p,xyapjr->xyajr", ops.psi0, q)
+    east = np.einsum("p,xyapjr->xyajr", ops.psi1, q)
+    south = np.einsum("p,xyaipr->xyair", ops.psi0, q)
+    north = np.einsum("p,xyaipr->xyair", ops.psi1, q)
+    # flux through the east face of every cell: this cell's east trace, the next cell's west trace
+    Gx = (dt / dx) * rusanov_x(pde, east, np.roll(west, -1, axis=0))
+    Gy = (dt / dy) * rusanov_y(pde, north, np.roll(south, -1, axis=1))
+    return np.einsum("a,xyajr->xyjr", w, Gx), np.einsum("a,xyair->xyir", w, Gy)
+
+
 def correct2d(ops, pde, u, q, dt, dx, dy):
     """u^{n+1} from u^n and the predictor (eq. ader_dg_method_full, d = 2)."""
     w = ops.w
@@ -143,16 +159,7 @@ def correct2d(ops, pde, u, q, dt, dx, dy):
     fybar = np.einsum("a,xyaijr->xyijr", w, fy)
     vol = (np.einsum("il,xyljr->xyijr", ops.Dtil, fxbar) / w[None, None, :, None, None]
            + np.einsum("jl,xyilr->xyijr", ops.Dtil, fybar) / w[None, None, None, :, None])
-    # face traces (Algorithm 7 per direction): [Cx, Cy, a, j or i, M]
-    west = np.einsum("p,xyapjr->xyajr", ops.psi0, q)
-    east = np.einsum("p,xyapjr->xyajr", ops.psi1, q)
-    south = np.einsum("p,xyaipr->xyair", ops.psi0, q)
-    north = np.einsum("p,xyaipr->xyair", ops.psi1, q)
-    # flux through the east face of every cell: this cell's east trace, the next cell's west trace
-    Gx = (dt / dx) * rusanov_x(pde, east, np.roll(west, -1, axis=0))
-    Gy = (dt / dy) * rusanov_y(pde, north, np.roll(south, -1, axis=1))
-    Gxbar = np.einsum("a,xyajr->xyjr", w, Gx)
-    Gybar = np.einsum("a,xyair->xyir", w, Gy)
+    Gxbar, Gybar = face_fluxes2d(ops, pde, q, dt, dx, dy)
     Gx_e, Gx_w = Gxbar, np.roll(Gxbar, 1, axis=0)
     Gy_n, Gy_s = Gybar, np.roll(Gybar, 1, axis=1)
     surf_x = (ops.psi1[None, None, :, None, None] * Gx_e[:, :, None, :, :]

@@ -47,8 +47,10 @@ def fv2d_dt(pde, v, dx, dy, cfl):
     return cfl / 2.0 * min(dx / float(pde.speed_x(v).max()), dy / float(pde.speed_y(v).max()))
 
 
-def fv2d_step(ops, pde, v, dt, dx, dy, tol=1e-14, max_iter=64):
-    """One ADER-WENO step of the averages; returns (v_new, sweeps, failed)."""
+def fv2d_step(ops, pde, v, dt, dx, dy, tol=1e-14, max_iter=64, fluxes=False):
+    """One ADER-WENO step of the averages; returns (v_new, sweeps, failed), and
+    with fluxes=True also the integrated fluxes through the east and the north
+    face of every cell [Cx, Cy, M] (v_new = v - the differences of these)."""
     w_hat = reconstruct2d(v, ops)
     q, sweeps, failed = predict2d(ops, pde, w_hat, dt, dx, dy, tol, max_iter)
     w = ops.w
@@ -61,6 +63,8 @@ def fv2d_step(ops, pde, v, dt, dx, dy, tol=1e-14, max_iter=64):
     Fx = np.einsum("a,k,xyakr->xyr", w, w, Gx)
     Fy = np.einsum("a,k,xyakr->xyr", w, w, Gy)
     v_new = v - (Fx - np.roll(Fx, 1, axis=0)) - (Fy - np.roll(Fy, 1, axis=1))
+    if fluxes:
+        return v_new, sweeps, failed, Fx, Fy
     return v_new, sweeps, failed
 
 

@@ -246,6 +246,33 @@ def riemann_array_nodal(ncells, N, test=1, period=64, gamma=1.4):
     return _euler_conserved(np.where(left, rl, rr), np.where(left, ul, ur), np.where(left, pl, pr), gamma)
 
 
+def euler2d_explosion_nodal(cx, cy, N, r0=0.5, inside=(1.0, 1.0), outside=(0.125, 0.1), gamma=1.4,
+                            extent=(-1.0, 1.0, -1.0, 1.0)):
+    """Conserved nodal data [cx, cy, N+1, N+1, 4] of the cylindrical explosion of
+    Sec. 2.2 (a two-dimensional Sod problem): (rho, p) = inside where the node's
+    distance to the centre of the square is at most r0, outside elsewhere; the
+    gas at rest; the square [-1, 1]^2 by default.  A cell that the circle
+    r = r0 cuts (nodes on both sides) takes the constant state of the
+    Gauss-Legendre mean of its nodal values (positive weights, so admissible),
+    instead of the overshooting interpolant of a jump."""
+    x0, x1, y0, y1 = extent
+    xs = cell_points(cx, N + 1, x0, x1)
+    ys = cell_points(cy, N + 1, y0, y1)
+    X = xs[:, None, :, None]
+    Y = ys[None, :, None, :]
+    r = np.sqrt((X - 0.5 * (x0 + x1)) ** 2 + (Y - 0.5 * (y0 + y1)) ** 2)
+    rho = np.where(r <= r0, inside[0], outside[0])
+    p = np.where(r <= r0, inside[1], outside[1])
+    z = np.zeros_like(rho)
+    u = np.stack([rho, z, z, p / (gamma - 1.0)], axis=-1)
+    inner = r <= r0
+    cut = inner.any(axis=(2, 3)) & ~inner.all(axis=(2, 3))
+    _, w = gl_points_01(N + 1)
+    mean = np.einsum("i,j,xyijr->xyr", w, w, u)
+    u[cut] = mean[cut][:, None, None, :]
+    return u
+
+
 def euler2d_sine_averages(cx, cy, amp=0.5, kx=1, ky=1, velocity=(1.0, 1.0), pressure=1.0, gamma=1.4,
                           npts=16, t=0.0):
     """Cell averages v[Cx, Cy, 4] of the 2-D sine wave (conserved variables) at
