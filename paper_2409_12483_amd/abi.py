@@ -1,5 +1,6 @@
 """Thin ctypes binding of include/aderdg.h, include/aderdg2d.h,
-include/aderdg3d.h and include/aderdg_lim.h (argument marshalling only).
+include/aderdg3d.h, include/aderdg_lim.h and include/aderdg_lim2d.h (argument
+marshalling only).
 
 Every entry point keeps its C name.  Buffers may be torch tensors on the HIP
 device (their data_ptr() is passed) or raw integer device addresses.  All
@@ -38,6 +39,8 @@ EXPORTS_3D = ["aderdg3d_init", "aderdg3d_predict", "aderdg3d_step", "aderdg3d_sw
 EXPORTS_LIM = ["aderdg_lim_init", "aderdg_lim_project", "aderdg_lim_step", "aderdg_lim_counters",
                "aderdg_lim_free"]
 LIM_PERIODIC, LIM_TRANSMISSIVE = 0, 1
+EXPORTS_LIM2D = ["aderdg2d_lim_init", "aderdg2d_lim_project", "aderdg2d_lim_step", "aderdg2d_lim_counters",
+                 "aderdg2d_lim_free"]
 
 
 class PdeDesc(ctypes.Structure):
@@ -79,6 +82,14 @@ class LimConfig(ctypes.Structure):
                 ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("dims", ctypes.c_int32), ("picard_max_iter", ctypes.c_int32),
                 ("picard_tol", ctypes.c_double), ("weno_degree", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Lim2DConfig(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("bc", ctypes.c_int32), ("cells_x", ctypes.c_int64),
+                ("cells_y", ctypes.c_int64), ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+                ("y0", ctypes.c_double), ("y1", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("picard_tol", ctypes.c_double),
+                ("picard_max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class AderdgError(RuntimeError):
@@ -139,7 +150,12 @@ def load(path=None):
     lib.aderdg_lim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32]
     lib.aderdg_lim_counters.argtypes = [vp, ctypes.POINTER(i64)]
     lib.aderdg_lim_free.argtypes = [vp]
-    for name in EXPORTS[:-1] + EXPORTS_2D + EXPORTS_3D + EXPORTS_LIM:
+    lib.aderdg2d_lim_init.argtypes = [ctypes.POINTER(Lim2DConfig), vp, ctypes.POINTER(vp)]
+    lib.aderdg2d_lim_project.argtypes = [vp, vp, vp]
+    lib.aderdg2d_lim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32]
+    lib.aderdg2d_lim_counters.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.aderdg2d_lim_free.argtypes = [vp]
+    for name in EXPORTS[:-1] + EXPORTS_2D + EXPORTS_3D + EXPORTS_LIM + EXPORTS_LIM2D:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -397,3 +413,38 @@ def aderdg_lim_counters(h):
 
 def aderdg_lim_free(h):
     return _check(load().aderdg_lim_free(h))
+
+
+# ------------------------------------------------------------- limited 2-D ----
+def lim2d_config(N, cells_x, cells_y, bc=LIM_TRANSMISSIVE, extent=(-1.0, 1.0, -1.0, 1.0), gamma=1.4, cfl=0.4,
+                 picard_tol=0.0, picard_max_iter=0):
+    x0, x1, y0, y1 = extent
+    return Lim2DConfig(N, bc, cells_x, cells_y, x0, x1, y0, y1, cfl, gamma, picard_tol, picard_max_iter, 0)
+
+
+def aderdg2d_lim_init(cfg, stream=None):
+    lib = load()
+    h = ctypes.c_void_p()
+    st = _current_stream() if stream is None else stream
+    _check(lib.aderdg2d_lim_init(ctypes.byref(cfg), st, ctypes.byref(h)))
+    return h.value
+
+
+def aderdg2d_lim_project(h, u, v):
+    return _check(load().aderdg2d_lim_project(h, _ptr(u), _ptr(v)))
+
+
+def aderdg2d_lim_step(h, u, v, troubled, t, t_end, dt, status, nsteps):
+    return _check(load().aderdg2d_lim_step(h, _ptr(u), _ptr(v), _ptr(troubled), _ptr(t), _ptr(t_end),
+                                           _ptr(dt), _ptr(status), nsteps))
+
+
+def aderdg2d_lim_counters(h):
+    """(troubled cell-steps, first-order redo steps, 0, candidate predictor sweeps) since init."""
+    out = (ctypes.c_int64 * 4)()
+    _check(load().aderdg2d_lim_counters(h, out))
+    return tuple(out)
+
+
+def aderdg2d_lim_free(h):
+    return _check(load().aderdg2d_lim_free(h))

@@ -14,6 +14,7 @@
 #include "../../include/aderdg2d.h"
 #include "../../include/aderdg3d.h"
 #include "../../include/aderdg_lim.h"
+#include "../../include/aderdg_lim2d.h"
 
 #include <hip/hip_runtime.h>
 
@@ -125,6 +126,8 @@ int ensure_tables(int device) {
     }
     e = upload_lim_tables(lim, &weno[2]);
     if (e != hipSuccess) return fail_hip(e, "upload of limiter tables");
+    e = upload_lim2d_tables(lim);
+    if (e != hipSuccess) return fail_hip(e, "upload of 2-D limiter tables");
   }
   fvw[0] = weno[2];
   fvw[1] = weno[0];
@@ -1349,6 +1352,166 @@ int aderdg_lim_free(aderdg_lim_handle* h) {
   if (!h) return ADERDG_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
   release_lim(h);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "stream synchronisation");
+}
+
+}  // extern "C"
+
+// --------------------------------------------------- limited 2-D step ----
+struct aderdg2d_lim_handle {
+  hipStream_t stream = nullptr;
+  aderdg2d_lim_config cfg{};
+  void* scratch = nullptr;
+  Clock2D* clk = nullptr;
+  Lim2Args args{};
+};
+
+namespace {
+
+void release_lim2d(aderdg2d_lim_handle* h) {
+  if (h->scratch) hipFree(h->scratch);
+  if (h->clk) hipFree(h->clk);
+  delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aderdg2d_lim_init(const aderdg2d_lim_config* cfg, void* hip_stream, aderdg2d_lim_handle** out) {
+  g_last_error.clear();
+  if (!cfg || !out) return fail(ADERDG_E_INVAL, "null argument");
+  aderdg2d_lim_config c = *cfg;
+  if (c.N < 1 || c.N > 9) return fail(ADERDG_E_INVAL, "N must be in 1..9");
+  if (c.bc != ADERDG_LIM_PERIODIC && c.bc != ADERDG_LIM_TRANSMISSIVE)
+    return fail(ADERDG_E_INVAL, "bc must be ADERDG_LIM_PERIODIC or ADERDG_LIM_TRANSMISSIVE");
+  if (c.cells_x < 3 || c.cells_y < 3 || c.cells_x > (1 << 16) || c.cells_y > (1 << 16))
+    return fail(ADERDG_E_INVAL, "cells_x and cells_y must be in 3..65536");
+  if ((c.cells_x + 2) * (c.cells_y + 2) > ((int64_t)1 << 24))
+    return fail(ADERDG_E_INVAL, "at most 2^24 cells with the ghost ring");
+  if (!(c.x1 > c.x0) || !(c.y1 > c.y0) || !std::isfinite(c.x1 - c.x0) || !std::isfinite(c.y1 - c.y0))
+    return fail(ADERDG_E_INVAL, "empty or non-finite domain");
+  if (!(c.gamma > 1.0) || !std::isfinite(c.gamma)) return fail(ADERDG_E_INVAL, "gamma must be > 1");
+  if (!(c.cfl > 0.0 && c.cfl <= 1.0)) return fail(ADERDG_E_INVAL, "cfl must be in (0, 1]");
+  if (c.reserved != 0) return fail(ADERDG_E_INVAL, "reserved must be 0");
+  if (!std::isfinite(c.picard_tol)) return fail(ADERDG_E_INVAL, "picard_tol must be finite");
+  if (c.picard_tol <= 0.0) c.picard_tol = 1e-14;
+  if (c.picard_max_iter <= 0) c.picard_max_iter = 64;
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  int rc = ensure_tables(device);
+  if (rc) return rc;
+  aderdg2d_lim_handle* h = new aderdg2d_lim_handle();
+  h->stream = (hipStream_t)hip_stream;
+  h->cfg = c;
+  const int64_t cx = c.cells_x, cy = c.cells_y, P = (cx + 2) * (cy + 2);
+  const int64_t n = c.N + 1, L = n * n, Ns = 2 * c.N + 1, M = 4;
+  // doubles: up, part, tr (4 faces x L per padded cell), gface, vfv, sflux; then 3 counters
+  const int64_t nd = P * L * M * 2 + P * 4 * L * M + P * 2 * n * M + cx * cy * Ns * Ns * M + cx * cy * 4 * Ns * M;
+  e = hipMalloc(&h->scratch, sizeof(double) * nd + 4 * sizeof(unsigned long long));
+  if (e != hipSuccess) { release_lim2d(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
+  e = hipMalloc((void**)&h->clk, sizeof(Clock2D));
+  if (e != hipSuccess) { release_lim2d(h); return fail(ADERDG_E_NOMEM, "clock allocation"); }
+  e = hipMemset(h->clk, 0, sizeof(Clock2D));
+  if (e == hipSuccess) e = hipMemset(h->scratch, 0, sizeof(double) * nd + 4 * sizeof(unsigned long long));
+  if (e != hipSuccess) { release_lim2d(h); return fail_hip(e, "scratch init"); }
+  Lim2Args& A = h->args;
+  A.cx = cx;
+  A.cy = cy;
+  A.N = c.N;
+  A.bc = c.bc == ADERDG_LIM_PERIODIC ? kLim2Periodic : kLim2Transmissive;
+  double* d = (double*)h->scratch;
+  A.up = d;       d += P * L * M;
+  double* part = d; d += P * L * M;
+  double* tr = d;   d += P * 4 * L * M;
+  double* gface = d; d += P * 2 * n * M;
+  A.vfv = d;      d += cx * cy * Ns * Ns * M;
+  A.sflux = d;    d += cx * cy * 4 * Ns * M;
+  A.cnt = (unsigned long long*)d;
+  Args2D& G = A.dg;
+  G.cx = cx + 2;
+  G.cy = cy + 2;
+  G.dx = (c.x1 - c.x0) / (double)cx;
+  G.dy = (c.y1 - c.y0) / (double)cy;
+  G.cfl = c.cfl;
+  G.tol = c.picard_tol;
+  G.gamma = c.gamma;
+  G.max_iter = c.picard_max_iter;
+  G.mode = k2dStep;
+  G.scheme = 0;
+  G.clk = h->clk;
+  G.u = A.up;
+  G.part = part;
+  G.tr = tr;
+  G.gface = gface;
+  G.candidate = 1;
+  *out = h;
+  return ADERDG_OK;
+}
+
+int aderdg2d_lim_project(aderdg2d_lim_handle* h, const double* u, double* v) {
+  g_last_error.clear();
+  if (!h || !u || !v) return fail(ADERDG_E_INVAL, "null argument");
+  Lim2Args A = h->args;
+  A.u = const_cast<double*>(u);
+  A.v = v;
+  hipError_t e = launch_lim2d_project(A, h->stream);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "projection launch");
+}
+
+int aderdg2d_lim_step(aderdg2d_lim_handle* h, double* u, double* v, int32_t* troubled, double* t,
+                      const double* t_end, double* dt, int32_t* status, int32_t nsteps) {
+  g_last_error.clear();
+  if (!h || !u || !v || !troubled || !t || !t_end || !dt || !status) return fail(ADERDG_E_INVAL, "null argument");
+  if (nsteps < 0) return fail(ADERDG_E_INVAL, "nsteps must be >= 0");
+  Lim2Args A = h->args;
+  A.u = u;
+  A.v = v;
+  A.troubled = troubled;
+  A.dg.t_end = t_end;
+  const int N = h->cfg.N;
+  const int64_t P = A.dg.cx * A.dg.cy;
+  const int64_t cpb = cells_per_block_2d(N, ADERDG_FP64), cpc = cells_per_block_corr2d(N);
+  hipError_t e = launch_clock2d_begin(A.dg.clk, t, h->stream);
+  if (e == hipSuccess) e = launch_lim2d_copy(A, 1, h->stream);
+  if (e == hipSuccess) e = launch_lim2d_ghosts(A, h->stream);
+  if (e == hipSuccess) e = launch_lambda2d(N, A.dg, (P + cpc - 1) / cpc, h->stream);
+  for (int s = 0; s < nsteps && e == hipSuccess; ++s) {
+    A.dg.step = s;
+    if (s > 0) e = launch_lim2d_ghosts(A, h->stream);
+    if (e == hipSuccess) e = launch_pred2d(N, ADERDG_FP64, A.dg, (P + cpb - 1) / cpb, h->stream);
+    if (e == hipSuccess) e = launch_corr2d(N, ADERDG_FP64, A.dg, (P + cpc - 1) / cpc, h->stream);
+    if (e == hipSuccess) e = launch_lim2d_after_candidate(A, h->stream);
+  }
+  if (e == hipSuccess) e = launch_lim2d_copy(A, 0, h->stream);
+  if (e == hipSuccess) e = launch_clock2d_end(A.dg.clk, t, dt, status, nsteps & 1, h->stream);
+  return e == hipSuccess ? ADERDG_OK : fail_hip(e, "limited 2-D step launch");
+}
+
+int aderdg2d_lim_counters(aderdg2d_lim_handle* h, int64_t* out4) {
+  g_last_error.clear();
+  if (!h || !out4) return fail(ADERDG_E_INVAL, "null argument");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail_hip(e, "stream synchronisation");
+  unsigned long long cnt[3];
+  e = hipMemcpy(cnt, h->args.cnt, sizeof(cnt), hipMemcpyDeviceToHost);
+  Clock2D clk;
+  if (e == hipSuccess) e = hipMemcpy(&clk, h->clk, sizeof(clk), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail_hip(e, "counter read");
+  out4[0] = (int64_t)cnt[0];
+  out4[1] = (int64_t)cnt[1];
+  out4[2] = 0;
+  int64_t sw = 0;
+  for (int i = 0; i < kSlots; ++i) sw += (int64_t)clk.sweeps[i].v;
+  out4[3] = sw;
+  return ADERDG_OK;
+}
+
+int aderdg2d_lim_free(aderdg2d_lim_handle* h) {
+  if (!h) return ADERDG_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  release_lim2d(h);
   return e == hipSuccess ? ADERDG_OK : fail_hip(e, "stream synchronisation");
 }
 

@@ -644,6 +644,10 @@ corr2d_kernel(Args2D A) {
     }
 #pragma unroll
     for (int r = 0; r < M; ++r) Gf[((cl * 4 + f) * n + k) * M + r] = acc[r];
+    if (A.gface && (f == 1 || f == 3)) {
+#pragma unroll
+      for (int r = 0; r < M; ++r) A.gface[((c * 2 + (f >> 1)) * n + k) * M + r] = acc[r];
+    }
   }
   __syncthreads();
 
@@ -668,6 +672,7 @@ corr2d_kernel(Args2D A) {
     }
     bad |= !Euler2::admissible(un, A.gamma);
   }
+  if (A.candidate) return;                  // the limited step takes over (uniform branch)
   if (__any(bad) && (threadIdx.x & 63) == 0)
     atomicMin(&A.clk->stat[(blockIdx.x + (threadIdx.x >> 6)) % kSlots].v, -5);
   __syncthreads();
@@ -1002,3 +1007,6 @@ hipError_t upload_tables_2d(const DevOps* ops, const DevOpsF* opsf, const DevWen
 }
 
 }  // namespace aderdg
+
+// Kernels of the limited 2-D step (they share this file's operator and WENO tables).
+#include "limiter2d.hpp"

@@ -44,6 +44,11 @@ struct Args2D {
                            // predictor precision (FP64, or FP32 in the FP32-predictor mode)
   void* q_out;             // predictor mode: q [cells][n][n][n][4] in the predictor precision
   int32_t* iters;          // predictor mode: sweeps per cell (may be null)
+  double* gface;           // candidate mode: the corrector's time-integrated fluxes through the east
+                           // and north face of every cell [cells][2][n][4] (null: not stored)
+  int32_t candidate;       // 1: the corrector neither publishes signal speeds nor reports a
+                           // non-physical state (the limited step decides on both)
+  int32_t pad_c;
 };
 
 int cells_per_block_2d(int N, int prec);
@@ -65,5 +70,27 @@ constexpr int kFv2dThreads = 256;
 hipError_t launch_weno2d(int NW, const Args2D& A, double* w, hipStream_t st);
 hipError_t launch_fv2d_corr(int NW, const Args2D& A, hipStream_t st);
 hipError_t launch_fv2d_lambda(const Args2D& A, hipStream_t st);
+
+// ---- limited 2-D step (a posteriori subcell ADER-WENO2 limiting; the kernels
+// live in limiter2d.hpp, compiled as part of dg2d.hip) ----
+enum { kLim2Periodic = 0, kLim2Transmissive = 1 };
+struct Lim2Args {
+  Args2D dg;               // the DG step on the padded mesh (cx + 2) x (cy + 2): clock, step, dt
+  int64_t cx, cy;          // interior cells
+  int32_t N, bc;
+  double* up;              // padded state [(cx+2)(cy+2)][n][n][4] (ghost ring around the interior)
+  double* u;               // caller's state [cx][cy][n][n][4] (copied in and out once per call)
+  double* v;               // caller's subcell averages [cx][cy][Ns][Ns][4] (v^n in, v^{n+1} out)
+  int32_t* troubled;       // caller's mask [cx][cy]
+  double* vfv;             // [cx][cy][Ns][Ns][4] subgrid results of troubled cells
+  double* sflux;           // [cx][cy][4 faces W,E,S,N][Ns][4] subgrid fluxes through a troubled cell's faces
+  unsigned long long* cnt; // [0] troubled cells summed over steps, [1] first-order redo steps, [2] redo flag
+};
+hipError_t upload_lim2d_tables(const void* limR);     // DevLimR[kDevMaxn]
+hipError_t launch_lim2d_copy(const Lim2Args& L, int to_padded, hipStream_t st);
+hipError_t launch_lim2d_ghosts(const Lim2Args& L, hipStream_t st);
+hipError_t launch_lim2d_project(const Lim2Args& L, hipStream_t st);
+// the limiter kernels of one step after the candidate (detect, subgrid, first-order redo, finish)
+hipError_t launch_lim2d_after_candidate(const Lim2Args& L, hipStream_t st);
 
 }  // namespace aderdg

@@ -22,6 +22,7 @@ HEADER = os.path.join(ROOT, "include", "aderdg.h")
 HEADER_2D = os.path.join(ROOT, "include", "aderdg2d.h")
 HEADER_3D = os.path.join(ROOT, "include", "aderdg3d.h")
 HEADER_LIM = os.path.join(ROOT, "include", "aderdg_lim.h")
+HEADER_LIM2D = os.path.join(ROOT, "include", "aderdg_lim2d.h")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(abi.LIBPATH),
                                 reason="libaderdg.so not built (run __graft_entry__.build())")
@@ -44,7 +45,7 @@ def test_header_declares_the_entry_points():
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(abi.LIBPATH)
     for name in (_declared_functions() + _declared_functions(HEADER_2D) + _declared_functions(HEADER_3D)
-                 + _declared_functions(HEADER_LIM)):
+                 + _declared_functions(HEADER_LIM) + _declared_functions(HEADER_LIM2D)):
         assert hasattr(lib, name), name
 
 
@@ -253,6 +254,7 @@ def test_newton_inner_solver_only_for_dg_with_a_linear_source(pde, scheme):
 
 def test_limiter_header_declares_the_entry_points():
     assert set(_declared_functions(HEADER_LIM)) == set(abi.EXPORTS_LIM)
+    assert set(_declared_functions(HEADER_LIM2D)) == set(abi.EXPORTS_LIM2D)
 
 
 def _init_lim(cfg):

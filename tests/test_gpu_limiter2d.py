@@ -1,0 +1,133 @@
+"""The limited 2-D step (include/aderdg_lim2d.h) on the GPU against the
+oracle (oracle/limiter2d.py), through the C ABI.
+
+* The cylindrical explosion of Sec. 2.2 (troubled cells along the circle),
+  periodic and free-outflow boundaries, N = 1, 2, 3, 5 and 9: the state, the
+  subcell averages and the time after several steps to 1e-12 relative (max
+  norm), the troubled cells of the last step equal.
+* A Table 9 Riemann problem constant along y (and along x): the same.
+* A uniform state: kept, nothing troubled.
+* Invalid configurations are refused.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import basis, dg2d, limiter2d
+from paper_2409_12483_amd import abi
+from paper_2409_12483_amd import workloads as W
+
+from gpu_util import BIG, torch_dev
+
+pytestmark = pytest.mark.gpu
+E2 = dg2d.Euler2D()
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def gpu_lim(u0, N, bc, nsteps, extent=(-1.0, 1.0, -1.0, 1.0), t_end=BIG):
+    torch, dev = torch_dev()
+    cx, cy = u0.shape[:2]
+    Ns = 2 * N + 1
+    h = abi.aderdg2d_lim_init(abi.lim2d_config(N, cx, cy, bc=bc, extent=extent))
+    try:
+        u = torch.tensor(np.ascontiguousarray(u0), dtype=torch.float64, device=dev)
+        v = torch.zeros((cx, cy, Ns, Ns, 4), dtype=torch.float64, device=dev)
+        tr = torch.zeros((cx, cy), dtype=torch.int32, device=dev)
+        t = torch.zeros(1, dtype=torch.float64, device=dev)
+        te = torch.tensor([t_end], dtype=torch.float64, device=dev)
+        dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        abi.aderdg2d_lim_project(h, u, v)
+        abi.aderdg2d_lim_step(h, u, v, tr, t, te, dt, st, nsteps)
+        torch.cuda.synchronize()
+        cnt = abi.aderdg2d_lim_counters(h)
+        return (u.cpu().numpy(), v.cpu().numpy(), tr.cpu().numpy().astype(bool), float(t[0]), int(st[0]), cnt)
+    finally:
+        abi.aderdg2d_lim_free(h)
+
+
+def oracle_lim(u0, N, bc, nsteps, extent=(-1.0, 1.0, -1.0, 1.0)):
+    ops = basis.build_operators(N)
+    u = np.array(u0, dtype=np.float64)
+    x0, x1, y0, y1 = extent
+    dx, dy = (x1 - x0) / u.shape[0], (y1 - y0) / u.shape[1]
+    t, v, bad, total = 0.0, None, None, 0
+    for _ in range(nsteps):
+        dt = dg2d.cfl_dt2d(ops, E2, u, dx, dy, 0.4)
+        with np.errstate(all="ignore"):
+            u, bad, v = limiter2d.limited_step2d(ops, E2, u, dt, dx, dy, "periodic" if bc == abi.LIM_PERIODIC
+                                                 else "transmissive", 1, v)
+        total += int(bad.sum())
+        t += dt
+    return u, v, bad, t, total
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _check(u0, N, bc, nsteps, extent=(-1.0, 1.0, -1.0, 1.0)):
+    u, v, tr, t, st, cnt = gpu_lim(u0, N, bc, nsteps, extent)
+    ru, rv, rbad, rt, total = oracle_lim(u0, N, bc, nsteps, extent)
+    assert st == 0
+    assert t == pytest.approx(rt, rel=1e-13)
+    assert (tr == rbad).all()
+    assert cnt[0] == total
+    assert _rel(u, ru) <= 1e-12
+    assert _rel(v, rv) <= 1e-12
+    return total
+
+
+@pytest.mark.parametrize("N,C,bc,nsteps", [(2, 10, abi.LIM_PERIODIC, 4), (2, 10, abi.LIM_TRANSMISSIVE, 4),
+                                           (1, 12, abi.LIM_TRANSMISSIVE, 5), (3, 8, abi.LIM_TRANSMISSIVE, 3),
+                                           (5, 6, abi.LIM_TRANSMISSIVE, 2), (9, 4, abi.LIM_TRANSMISSIVE, 1)])
+def test_explosion_matches_oracle(N, C, bc, nsteps):
+    _say("lim2d explosion", N, C, bc, nsteps)
+    total = _check(W.euler2d_explosion_nodal(C, C, N), N, bc, nsteps)
+    assert total > 0
+
+
+def _rows(u1, Cy):
+    C, n, _ = u1.shape
+    u2 = np.zeros((C, Cy, n, n, 4))
+    u2[..., 0], u2[..., 1], u2[..., 3] = (u1[:, None, :, None, k] for k in range(3))
+    return u2
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_riemann_problem_along_each_axis(axis):
+    _say("lim2d riemann", axis)
+    N, C, Cy = 3, 24, 3
+    u2 = _rows(W.riemann_nodal(C, N, 1), Cy)
+    extent = (0.0, 1.0, 0.0, 0.7)
+    if axis == 1:
+        u2 = np.ascontiguousarray(np.swapaxes(np.swapaxes(u2, 0, 1), 2, 3)[..., [0, 2, 1, 3]])
+        extent = (0.0, 0.7, 0.0, 1.0)
+    assert _check(u2, N, abi.LIM_TRANSMISSIVE, 3, extent) > 0
+
+
+def test_uniform_state_is_kept():
+    _say("lim2d uniform")
+    N = 3
+    u0 = np.tile([1.2, 0.3, -0.2, 2.9], (5, 6, N + 1, N + 1, 1))
+    for bc in (abi.LIM_PERIODIC, abi.LIM_TRANSMISSIVE):
+        u, v, tr, t, st, cnt = gpu_lim(u0, N, bc, 4, extent=(0.0, 1.0, 0.0, 1.0))
+        assert st == 0 and not tr.any() and cnt[0] == 0
+        assert np.abs(u - u0).max() <= 1e-13
+
+
+def test_invalid_configs_are_refused():
+    lib = abi.load()
+    for mut in (lambda c: setattr(c, "N", 0), lambda c: setattr(c, "N", 10), lambda c: setattr(c, "bc", 5),
+                lambda c: setattr(c, "cells_x", 2), lambda c: setattr(c, "cfl", 0.0),
+                lambda c: setattr(c, "gamma", 1.0), lambda c: setattr(c, "reserved", 1),
+                lambda c: setattr(c, "x1", -2.0)):
+        cfg = abi.lim2d_config(2, 8, 8)
+        mut(cfg)
+        h = ctypes.c_void_p()
+        assert lib.aderdg2d_lim_init(ctypes.byref(cfg), None, ctypes.byref(h)) == abi.ADERDG_E_INVAL
