@@ -1127,6 +1127,123 @@ def lim_array(N=5, C=131072, period=64, K=100, warmup=20):
             "limited_over_unlimited_same_data_time": round(secs / ss, 3)}
 
 
+# Table 14 (cylindrical explosion, ADER-DG-P_N with the ADER-WENO2 subcell
+# limiter, t_final = 0.25), T_JIT column: the paper's CPU seconds (other
+# hardware), for context.
+PAPER_LIM2D_TJIT = {
+    (1, 11): 2.66e-1, (1, 21): 1.03, (1, 31): 2.48, (1, 41): 5.16,
+    (2, 11): 6.54e-1, (2, 21): 2.93, (2, 31): 6.94, (2, 41): 1.37e1,
+    (3, 11): 1.71, (3, 21): 6.50, (3, 31): 1.76e1, (3, 41): 3.52e1,
+    (4, 11): 2.95, (4, 21): 1.18e1, (4, 31): 2.93e1, (4, 41): 5.97e1,
+    (5, 11): 5.71, (5, 21): 2.13e1, (5, 31): 5.46e1, (5, 41): 1.06e2,
+    (6, 11): 9.17, (6, 21): 3.53e1, (6, 31): 8.67e1, (6, 41): 1.73e2,
+    (7, 11): 1.42e1, (7, 21): 5.57e1, (7, 31): 1.37e2, (7, 41): 2.78e2,
+    (8, 11): 2.09e1, (8, 21): 8.15e1, (8, 31): 2.18e2, (8, 41): 4.29e2,
+    (9, 11): 3.04e1, (9, 21): 1.21e2, (9, 31): 3.30e2, (9, 41): 6.57e2}
+
+
+class Lim2Run:
+    """The cylindrical explosion of Sec. 2.2 on C^2 cells of [-1, 1]^2, free
+    outflow, CFL 0.4, through the limited 2-D ABI."""
+
+    def __init__(self, N, C):
+        import torch
+        from paper_2409_12483_amd import abi
+        from paper_2409_12483_amd import workloads as W
+        self.abi, self.torch = abi, torch
+        dev = torch.device("cuda:0")
+        self.N, self.C = N, C
+        Ns = 2 * N + 1
+        self.stream = torch.cuda.current_stream()
+        self.h = abi.aderdg2d_lim_init(abi.lim2d_config(N, C, C), stream=self.stream.cuda_stream)
+        self.u = torch.tensor(W.euler2d_explosion_nodal(C, C, N), device=dev)
+        self.v = torch.zeros((C, C, Ns, Ns, 4), dtype=torch.float64, device=dev)
+        self.tr = torch.zeros((C, C), dtype=torch.int32, device=dev)
+        self.t = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.te = torch.full((1,), 0.25, dtype=torch.float64, device=dev)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.st = torch.zeros(1, dtype=torch.int32, device=dev)
+        abi.aderdg2d_lim_project(self.h, self.u, self.v)
+
+    def steps(self, k):
+        self.abi.aderdg2d_lim_step(self.h, self.u, self.v, self.tr, self.t, self.te, self.dt, self.st, k)
+
+    def close(self):
+        self.abi.aderdg2d_lim_free(self.h)
+
+
+def lim2d_time_to_solution(N, C):
+    """The whole run to t_final = 0.25 (Table 14's workload): GPU wall time with
+    the host loop (calls of 64 steps; steps past t_final do nothing)."""
+    r = Lim2Run(N, C)
+    _sync()
+    t0 = time.perf_counter()
+    calls = 0
+    while True:
+        r.steps(64)
+        calls += 1
+        _sync()
+        if float(r.t.item()) >= 0.25 or int(r.st.item()) != 0:
+            break
+    secs = time.perf_counter() - t0
+    cnt = r.abi.aderdg2d_lim_counters(r.h)
+    out = {"N": N, "cells": f"{C}^2", "gpu_wall_s": round(secs, 5), "calls_of_64_steps": calls,
+           "t": float(r.t.item()), "status": int(r.st.item()), "troubled_cell_steps": int(cnt[0]),
+           "first_order_redo_steps": int(cnt[1]), "paper_cpu_s_tjit": PAPER_LIM2D_TJIT[(N, C)]}
+    r.close()
+    return out
+
+
+def lim2d_throughput(N=9, C=41, K=100, warmup=20):
+    """ms per limited step and DoF-updates/s on the explosion (N = 9, 41^2 cells,
+    the paper's main configuration of Sec. 2.2), timed with HIP events over K
+    steps after `warmup` steps (the troubled cells then line the expanding shock)."""
+    import torch
+    r = Lim2Run(N, C)
+    r.te.fill_(1.0e300)
+    r.steps(warmup)
+    _sync()
+    c0 = r.abi.aderdg2d_lim_counters(r.h)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(r.stream)
+    r.steps(K)
+    e1.record(r.stream)
+    _sync()
+    secs = e0.elapsed_time(e1) * 1e-3
+    c1 = r.abi.aderdg2d_lim_counters(r.h)
+    out = {"workload": f"ADER-DG-P{N} 2D Euler, cylindrical explosion of Sec. 2.2 on {C}^2 cells of [-1,1]^2, "
+                       "free outflow, CFL 0.4, ADER-WENO2 subcell limiter",
+           "ms_per_step": round(secs / K * 1e3, 5),
+           "value": round(K * C * C * (N + 1) ** 2 * 4 / secs, 1), "unit": "DoF-updates/s",
+           "troubled_fraction": round((c1[0] - c0[0]) / (C * C * K), 4),
+           "first_order_redo_steps": int(c1[1] - c0[1]), "status": int(r.st.item())}
+    r.close()
+    return out
+
+
+def lim2d_cpu_baseline(N=2, C=11, nsteps=6):
+    from oracle import basis, dg2d, limiter2d
+    from paper_2409_12483_amd import workloads as W
+    from threadpoolctl import threadpool_limits
+    ops = basis.build_operators(N)
+    u = W.euler2d_explosion_nodal(C, C, N)
+    with threadpool_limits(limits=1), np.errstate(all="ignore"):
+        t0 = time.perf_counter()
+        limiter2d.limited_run2d(ops, dg2d.Euler2D(), u, extent=(-1, 1, -1, 1), nsteps=nsteps, bc="transmissive")
+        el = time.perf_counter() - t0
+    return {"value": round(nsteps * C * C * (N + 1) ** 2 * 4 / el, 1), "unit": "DoF-updates/s", "cores": 1,
+            "kind": "oracle", "sample": f"the same explosion on {C}^2 cells, N={N}, {nsteps} limited steps, "
+                                        "NumPy FP64, single thread"}
+
+
+def lim2d_section(quick=False):
+    out = {"throughput_n9_41": lim2d_throughput()}
+    Ns = (1, 2, 3, 5, 9) if quick else range(1, 10)
+    out["paper_table14_time_to_solution"] = [lim2d_time_to_solution(N, C) for N in Ns for C in (11, 21, 31, 41)]
+    out["cpu_baseline_n2"] = lim2d_cpu_baseline()
+    return out
+
+
 def limiter_section(quick=False):
     out = {"array_n5": lim_array()}
     out["cpu_baseline_array_n5"] = lim_cpu_baseline()
@@ -1181,6 +1298,8 @@ def main():
                     help="the paper's 3-D DG timing runs on every mesh for N = 6..9 too (about a minute more)")
     ap.add_argument("--fv3d-only", action="store_true",
                     help="only the 3-D ADER-WENO workloads (128^3 throughput, the paper's WENO timing meshes)")
+    ap.add_argument("--lim2d-only", action="store_true",
+                    help="only the limited 2-D step (explosion: throughput at N = 9 on 41^2, Table 14 runs)")
     ap.add_argument("--limiter-only", action="store_true",
                     help="only the limited step on the 131072-cell Sod row (N=5; for profiling)")
     ap.add_argument("--dg3d-only", action="store_true",
@@ -1199,7 +1318,7 @@ def main():
     # forked, which must happen before this process touches the GPU
     cpu = None
     if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only or a.fv2d_only or a.fv3d_only or a.autotune_only
-                                          or a.fp32_predictor_only):
+                                          or a.fp32_predictor_only or a.lim2d_only):
         cpu = cpu_baseline(N)
         emit("cpu_baseline", cpu)
 
@@ -1222,6 +1341,9 @@ def main():
         return
     if a.limiter_only:
         print(json.dumps({"limiter": limiter_section(quick=True)}))
+        return
+    if a.lim2d_only:
+        print(json.dumps({"lim2d_explosion": lim2d_section()}))
         return
     if a.autotune_only:
         print(json.dumps({"autotune": autotune_section()}))
@@ -1334,6 +1456,7 @@ def main():
         emit("dg2d_euler_sine_512x512", dg2d_section())
         emit("dg3d_euler_sine", dg3d_section(table11_full=a.table11_full))
         emit("limiter", limiter_section())
+        emit("lim2d_explosion", lim2d_section())
         emit("fv2d_euler_sine", fv2d_section())
         emit("fv3d_euler_sine", fv3d_section())
         # compact summaries for the headline line

@@ -79,8 +79,11 @@ int aderdg2d_lim_project(aderdg2d_lim_handle* h, const double* u, double* v);
  * step's start, then of its end: P u for unlimited cells, the subgrid result
  * for limited ones) and troubled (out).  t (in/out), t_end (in), dt (out),
  * status (out): device arrays of one value, as in aderdg2d_step; status is
- * ADERDG_E_NONPHYS if a final state leaves the admissible set and
- * ADERDG_E_NOCONV if a candidate's predictor did not converge. */
+ * ADERDG_E_NONPHYS if a subcell average of a final state leaves the admissible
+ * set (the limiter keeps those admissible; a polynomial may dip below zero at
+ * a node between them, and its next candidate then fails the detectors and
+ * is recomputed from them) and ADERDG_E_NOCONV if a candidate's predictor did
+ * not converge. */
 int aderdg2d_lim_step(aderdg2d_lim_handle* h, double* u, double* v, int32_t* troubled, double* t,
                       const double* t_end, double* dt, int32_t* status, int32_t nsteps);
 

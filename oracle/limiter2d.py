@@ -35,7 +35,11 @@ oracle (module `limiter`), taken per direction:
 The subgrid scheme runs on the whole mesh's subgrid (cells left unlimited
 take no part in the result); when it leaves the admissible set in a troubled
 cell, it is redone at first order (reconstruction and predictor of degree 0),
-as in one dimension.
+as in one dimension.  The exchange changes unlimited cells after their
+detection, so the detection and correction cascade (the a posteriori loop
+repeated while a corrected state fails the checks, reading): an unlimited
+cell whose corrected state fails PAD joins the troubled cells and the
+correction is redone, three passes at most.
 
 Boundaries: periodic, or transmissive (free outflow, Sec. 2.2): one ghost cell
 on every side, the mirror image of the boundary cell (nodes, or subcells, in
@@ -118,16 +122,24 @@ def admissible_reconstruction2d(ops, pde, R, v):
     return np.array(m)
 
 
+PASSES = 3
+
+
 def limited_step2d(ops, pde, u, dt, dx, dy, bc="periodic", nw=1, v=None, tol=1e-14, max_iter=64):
     """One 2-D ADER-DG step with a posteriori subcell ADER-WENO limiting.
 
     u [Cx, Cy, n, n, M]; v [Cx, Cy, Ns, Ns, M] the subcell averages at the
     step's start (P u for a cell the previous step left unlimited, its
     finite-volume averages for a cell it limited; None: (P (x) P) u).
-    Returns (u_new, troubled mask [Cx, Cy], v_new)."""
+    Returns (u_new, troubled mask [Cx, Cy], v_new).
+
+    Detection and correction cascade (reading: the a posteriori limiting
+    loop is repeated while a corrected state fails the checks): an unlimited
+    cell whose state after the flux exchange fails PAD (nodes or subcell
+    averages) joins the troubled cells and the correction is redone, at most
+    PASSES times in all."""
     Cx, Cy, n, _, M = u.shape
     Ns = ops.Ns
-    periodic = bc == "periodic"
     if v is None:
         v = subcell_averages(ops, u)
     up = pad2d(u, bc)
@@ -139,14 +151,31 @@ def limited_step2d(ops, pde, u, dt, dx, dy, bc="periodic", nw=1, v=None, tol=1e-
         return u_cand, bad, subcell_averages(ops, u_cand)
     sub = to_subgrid(pad2d(v, bc))
     with np.errstate(all="ignore"):
-        s_new, _, _, Fx, Fy = fv2d_step(basis.build_operators(nw), pde, sub, dt, dx / Ns, dy / Ns,
-                                        tol, max_iter, fluxes=True)
-    v_fv = from_subgrid(s_new, Ns)[1:-1, 1:-1]
-    if not pde.admissible(v_fv[bad]).all():
-        # first order on the whole subgrid (degree-0 reconstruction and predictor)
-        s_new, _, _, Fx, Fy = fv2d_step(basis.build_operators(0), pde, sub, dt, dx / Ns, dy / Ns,
-                                        tol, max_iter, fluxes=True)
-        v_fv = from_subgrid(s_new, Ns)[1:-1, 1:-1]
+        s_ho, _, _, Fx_ho, Fy_ho = fv2d_step(basis.build_operators(nw), pde, sub, dt, dx / Ns, dy / Ns,
+                                             tol, max_iter, fluxes=True)
+    first_order = None
+    for p in range(PASSES):
+        v_fv, Fx, Fy = from_subgrid(s_ho, Ns)[1:-1, 1:-1], Fx_ho, Fy_ho
+        if first_order is None and not pde.admissible(v_fv[bad]).all():
+            # first order on the whole subgrid (degree-0 reconstruction and predictor)
+            first_order = fv2d_step(basis.build_operators(0), pde, sub, dt, dx / Ns, dy / Ns,
+                                    tol, max_iter, fluxes=True)
+        if first_order is not None:
+            v_fv, Fx, Fy = from_subgrid(first_order[0], Ns)[1:-1, 1:-1], first_order[3], first_order[4]
+        u_new, v_new = _correct(ops, pde, u_cand, bad, v_fv, Fx, Fy, Gx, Gy, bc)
+        fails = ~bad & ~(pde.admissible(u_new).all(axis=(2, 3)) & pde.admissible(v_new).all(axis=(2, 3)))
+        if p == PASSES - 1 or not fails.any():
+            return u_new, bad, v_new
+        bad = bad | fails
+
+
+def _correct(ops, pde, u_cand, bad, v_fv, Fx, Fy, Gx, Gy, bc):
+    """The corrected state of one pass: (R (x) R) v_fv in the troubled cells,
+    the candidate with the exchanged face fluxes elsewhere; and its subcell
+    averages (the finite-volume ones in the troubled cells)."""
+    Cx, Cy = u_cand.shape[:2]
+    Ns = ops.Ns
+    periodic = bc == "periodic"
     R = subcell_R(ops)
     u_new = u_cand.copy()
     for ix, iy in zip(*np.nonzero(bad)):
@@ -184,7 +213,7 @@ def limited_step2d(ops, pde, u, dt, dx, dy, bc="periodic", nw=1, v=None, tol=1e-
                 u_new[ix, jy] += s0[None, :, None] * dG[:, None, :]
     v_new = subcell_averages(ops, u_new)
     v_new[bad] = v_fv[bad]
-    return u_new, bad, v_new
+    return u_new, v_new
 
 
 def limited_run2d(ops, pde, u, extent=(0.0, 1.0, 0.0, 1.0), cfl=0.4, t_end=np.inf, nsteps=None,

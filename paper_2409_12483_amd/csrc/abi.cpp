@@ -1407,8 +1407,9 @@ int aderdg2d_lim_init(const aderdg2d_lim_config* cfg, void* hip_stream, aderdg2d
   h->cfg = c;
   const int64_t cx = c.cells_x, cy = c.cells_y, P = (cx + 2) * (cy + 2);
   const int64_t n = c.N + 1, L = n * n, Ns = 2 * c.N + 1, M = 4;
-  // doubles: up, part, tr (4 faces x L per padded cell), gface, vfv, sflux; then 3 counters
-  const int64_t nd = P * L * M * 2 + P * 4 * L * M + P * 2 * n * M + cx * cy * Ns * Ns * M + cx * cy * 4 * Ns * M;
+  // doubles: up, part, tr (4 faces x L per padded cell), gface, vfv, sflux, uout, vout; then 3 counters
+  const int64_t nd = P * L * M * 2 + P * 4 * L * M + P * 2 * n * M + cx * cy * Ns * Ns * M + cx * cy * 4 * Ns * M +
+                     cx * cy * L * M + cx * cy * Ns * Ns * M;
   e = hipMalloc(&h->scratch, sizeof(double) * nd + 4 * sizeof(unsigned long long));
   if (e != hipSuccess) { release_lim2d(h); return fail(ADERDG_E_NOMEM, "scratch allocation"); }
   e = hipMalloc((void**)&h->clk, sizeof(Clock2D));
@@ -1428,7 +1429,10 @@ int aderdg2d_lim_init(const aderdg2d_lim_config* cfg, void* hip_stream, aderdg2d
   double* gface = d; d += P * 2 * n * M;
   A.vfv = d;      d += cx * cy * Ns * Ns * M;
   A.sflux = d;    d += cx * cy * 4 * Ns * M;
+  A.uout = d;     d += cx * cy * L * M;
+  A.vout = d;     d += cx * cy * Ns * Ns * M;
   A.cnt = (unsigned long long*)d;
+  A.npass = 3;
   Args2D& G = A.dg;
   G.cx = cx + 2;
   G.cy = cy + 2;

@@ -91,7 +91,10 @@ __device__ __forceinline__ void rusanov2(const double* qm, const double* qp, dou
   }
   Euler2::speeds(qm, gamma, sxm, sym);
   Euler2::speeds(qp, gamma, sxp, syp);
-  const double s = DIR == 0 ? fmax(sxm, sxp) : fmax(sym, syp);
+  // a state without a sound speed (p < 0) makes the flux NaN, as in the oracle
+  // (fmax alone would drop the NaN and hide the non-physical trace)
+  const double a = DIR == 0 ? sxm : sym, b = DIR == 0 ? sxp : syp;
+  const double s = (isnan(a) || isnan(b)) ? a + b : fmax(a, b);
 #pragma unroll
   for (int r = 0; r < 4; ++r) G[r] = 0.5 * (fm[r] + fp[r]) - 0.5 * s * (qp[r] - qm[r]);
 }

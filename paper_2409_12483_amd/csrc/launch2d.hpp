@@ -85,6 +85,9 @@ struct Lim2Args {
   double* vfv;             // [cx][cy][Ns][Ns][4] subgrid results of troubled cells
   double* sflux;           // [cx][cy][4 faces W,E,S,N][Ns][4] subgrid fluxes through a troubled cell's faces
   unsigned long long* cnt; // [0] troubled cells summed over steps, [1] first-order redo steps, [2] redo flag
+  double* uout;            // [cx][cy][n][n][4] corrected state of the current pass
+  double* vout;            // [cx][cy][Ns][Ns][4] its subcell averages
+  int32_t pass, npass;     // detection / correction pass of the step (troubled = pass of detection)
 };
 hipError_t upload_lim2d_tables(const void* limR);     // DevLimR[kDevMaxn]
 hipError_t launch_lim2d_copy(const Lim2Args& L, int to_padded, hipStream_t st);

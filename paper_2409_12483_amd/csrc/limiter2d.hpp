@@ -18,7 +18,15 @@
 //             until admissible; for an unlimited cell the candidate, with the
 //             flux of every face it shares with a troubled cell replaced, per
 //             face node k, by sum_s F_s (integral of phi_k over sub-face s) /
-//             (N_s w_k); v^{n+1}; the signal speed of the final state.
+//             (N_s w_k); v^{n+1}; the signal speed of the final state; the
+//             status E_NONPHYS when a subcell average of v^{n+1} is not
+//             admissible.
+// The exchange changes unlimited cells after their detection, so subgrid,
+// subgrid0 and finish run in up to three passes (the detection / correction
+// cascade): an unlimited cell whose corrected state fails PAD is marked with
+// the next pass's number and recomputed like the others; troubled[c] holds
+// the pass in which a cell was found troubled (1 = by the detectors).  The
+// passes write uout / vout; a commit kernel copies the last one back.
 #pragma once
 
 #include "launch_lim.hpp"
@@ -243,7 +251,7 @@ __global__ void __launch_bounds__(Sub2Geo<N>::NT) lim2d_subgrid_kernel(Lim2Args 
   const double dt = step_dt2d<N>(L.dg, t, bc2, false);
   if (!(dt > 0.0)) return;
   const int64_t c = blockIdx.x;
-  if (!L.troubled[c]) return;                 // uniform per workgroup
+  if (L.troubled[c] != L.pass + 1) return;    // found troubled in this pass (uniform per workgroup)
   const int64_t ix = c / L.cy, iy = c - ix * L.cy;
   const double gamma = L.dg.gamma, gm1 = gamma - 1.0;
   const double dxs = L.dg.dx / Ns, dys = L.dg.dy / Ns;
@@ -432,7 +440,8 @@ __global__ void __launch_bounds__(256) lim2d_subgrid0_kernel(Lim2Args L) {
   if (!(dt > 0.0)) return;
   if (!L.cnt[2]) return;
   const int64_t c = blockIdx.x;
-  if (!L.troubled[c]) return;
+  const int tv = L.troubled[c];
+  if (tv < 1 || tv > L.pass + 1) return;
   const int64_t ix = c / L.cy, iy = c - ix * L.cy;
   const double gamma = L.dg.gamma;
   const double cx_ = dt / (L.dg.dx / Ns), cy_ = dt / (L.dg.dy / Ns);
@@ -490,10 +499,13 @@ __global__ void __launch_bounds__(256) lim2d_finish_kernel(Lim2Args L) {
   if (!(dt > 0.0)) return;
   const int64_t c = blockIdx.x, ix = c / L.cy, iy = c - ix * L.cy;
   const int64_t py = L.cy + 2;
-  double* const up = L.up + ((ix + 1) * py + iy + 1) * LL * M;
-  double* const vc = L.v + c * S2 * M;
-  const bool bad = L.troubled[c] != 0;                // uniform per workgroup
-  if (c == 0 && threadIdx.x == 0) {
+  const double* const up = L.up + ((ix + 1) * py + iy + 1) * LL * M;    // the candidate
+  double* const uo = L.uout + c * LL * M;
+  double* const vc = L.vout + c * S2 * M;
+  const bool last = L.pass == L.npass - 1;
+  const int tv = L.troubled[c];
+  const bool bad = tv >= 1 && tv <= L.pass + 1;       // uniform per workgroup
+  if (last && c == 0 && threadIdx.x == 0) {
     if (L.cnt[2]) atomicAdd(&L.cnt[1], 1ull);
   }
   if (bad) {
@@ -537,7 +549,7 @@ __global__ void __launch_bounds__(256) lim2d_finish_kernel(Lim2Args L) {
       for (int w = threadIdx.x; w < LL * M; w += 256) Ub[w] = mean[w % M];
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < LL * M; w += 256) up[w] = Ub[w];
+    for (int w = threadIdx.x; w < LL * M; w += 256) uo[w] = Ub[w];
     for (int k = threadIdx.x; k < S2 * M; k += 256) vc[k] = vf[k];
     for (int w = threadIdx.x; w < LL * M; w += 256) U[w] = Ub[w];
   } else {
@@ -552,7 +564,8 @@ __global__ void __launch_bounds__(256) lim2d_finish_kernel(Lim2Args L) {
       const bool inside = (jx >= 0 && jx < L.cx && jy >= 0 && jy < L.cy);
       bool m1, m2;
       nb[f] = lim2_src(jx, L.cx, L.bc, m1) * L.cy + lim2_src(jy, L.cy, L.bc, m2);
-      nbad[f] = (inside || L.bc == kLim2Periodic) && L.troubled[nb[f]] != 0;
+      const int tn = (inside || L.bc == kLim2Periodic) ? L.troubled[nb[f]] : 0;
+      nbad[f] = tn >= 1 && tn <= L.pass + 1;        // a mark of this pass (racing write) counts next pass
     }
     for (int w = threadIdx.x; w < 4 * n * M; w += 256) {
       const int f = w / (n * M), k = (w / M) % n, r = w % M;
@@ -582,18 +595,48 @@ __global__ void __launch_bounds__(256) lim2d_finish_kernel(Lim2Args L) {
       U[w] = val;
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < LL * M; w += 256) up[w] = U[w];
+    for (int w = threadIdx.x; w < LL * M; w += 256) uo[w] = U[w];
     lim2_project<N>(U, T, S);
     for (int k = threadIdx.x; k < S2 * M; k += 256) vc[k] = S[k];
+    if (!last) {
+      // the cascade: a corrected state that fails PAD joins the troubled cells
+      bool fail = false;
+      for (int w = threadIdx.x; w < S2; w += 256) fail |= !Euler2::admissible(S + w * M, L.dg.gamma);
+      for (int w = threadIdx.x; w < LL; w += 256) fail |= !Euler2::admissible(U + w * M, L.dg.gamma);
+      if (__syncthreads_or(fail) && threadIdx.x == 0) {
+        L.troubled[c] = L.pass + 2;
+        atomicAdd(&L.cnt[0], 1ull);
+      }
+    }
   }
+  if (!last) return;                                  // uniform: signal speeds and status of the final pass
   __syncthreads();
+  // status: the subcell averages v^{n+1} (the data the detectors and the
+  // subgrid scheme start from) must be admissible; a polynomial may dip below
+  // zero at a node between them, and its next candidate then fails PAD
   bool badu = false;
-  for (int w = threadIdx.x; w < LL; w += 256) badu |= !Euler2::admissible(U + w * M, L.dg.gamma);
+  for (int w = threadIdx.x; w < S2; w += 256) badu |= !Euler2::admissible(vc + w * M, L.dg.gamma);
   if (__any(badu) && (threadIdx.x & 63) == 0)
     atomicMin(&L.dg.clk->stat[(blockIdx.x + (threadIdx.x >> 6)) % kSlots].v, -5);
   double lx, ly;
   subcell_speeds<N>(U, V1, 1, L.dg.gamma, lx, ly);
   publish_lambda(*L.dg.clk, (L.dg.step + 1) % 3, lx, ly, part);
+}
+
+// The last pass's state and subcell averages become the step's result.
+__global__ void __launch_bounds__(256) lim2d_commit_kernel(Lim2Args L, int per_cell, int per_cell_v) {
+  double t;
+  __shared__ double bc2[2];
+  const double dt = step_dt2d<1>(L.dg, t, bc2, false);   // degree-independent: only dt > 0 matters
+  if (!(dt > 0.0)) return;
+  const int64_t py = L.cy + 2, cells = L.cx * L.cy;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cells * per_cell; e += (int64_t)gridDim.x * 256) {
+    const int64_t c = e / per_cell, k = e - c * per_cell;
+    const int64_t ix = c / L.cy, iy = c - ix * L.cy;
+    L.up[((ix + 1) * py + iy + 1) * per_cell + k] = L.uout[e];
+  }
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cells * per_cell_v; e += (int64_t)gridDim.x * 256)
+    L.v[e] = L.vout[e];
 }
 
 // ----------------------------------------------------------- launchers ----
@@ -632,16 +675,25 @@ hipError_t launch_lim2d_project(const Lim2Args& L, hipStream_t st) {
 }
 
 template <int N>
-static hipError_t lim2_after(const Lim2Args& L, hipStream_t st) {
-  const dim3 grid((unsigned)(L.cx * L.cy));
-  hipLaunchKernelGGL((lim2d_detect_kernel<N>), grid, dim3(256), 0, st, L);
+static hipError_t lim2_after(const Lim2Args& L0, hipStream_t st) {
+  const dim3 grid((unsigned)(L0.cx * L0.cy));
+  hipLaunchKernelGGL((lim2d_detect_kernel<N>), grid, dim3(256), 0, st, L0);
   hipError_t e = hipGetLastError();
+  for (int p = 0; p < L0.npass && e == hipSuccess; ++p) {
+    Lim2Args L = L0;
+    L.pass = p;
+    hipLaunchKernelGGL((lim2d_subgrid_kernel<N>), grid, dim3(Sub2Geo<N>::NT), 0, st, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((lim2d_subgrid0_kernel<N>), grid, dim3(256), 0, st, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((lim2d_finish_kernel<N>), grid, dim3(256), 0, st, L);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((lim2d_subgrid_kernel<N>), grid, dim3(Sub2Geo<N>::NT), 0, st, L);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((lim2d_subgrid0_kernel<N>), grid, dim3(256), 0, st, L);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((lim2d_finish_kernel<N>), grid, dim3(256), 0, st, L);
+  constexpr int n = N + 1, Ns = 2 * N + 1;
+  int64_t blocks = (L0.cx * L0.cy * Ns * Ns * 4 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(lim2d_commit_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L0, n * n * 4, Ns * Ns * 4);
   return hipGetLastError();
 }
 

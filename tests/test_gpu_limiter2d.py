@@ -131,3 +131,41 @@ def test_invalid_configs_are_refused():
         mut(cfg)
         h = ctypes.c_void_p()
         assert lib.aderdg2d_lim_init(ctypes.byref(cfg), None, ctypes.byref(h)) == abi.ADERDG_E_INVAL
+
+
+@pytest.mark.parametrize("bc", [abi.LIM_PERIODIC, abi.LIM_TRANSMISSIVE])
+def test_explosion_to_the_final_time(bc):
+    """N = 2 on 21^2 cells to t_final = 0.25 (Sec. 2.2): status 0, every node and
+    subcell admissible, the totals kept to rounding with periodic boundaries."""
+    _say("lim2d explosion to t_final", bc)
+    torch, dev = torch_dev()
+    N, C = 2, 21
+    Ns = 2 * N + 1
+    u0 = W.euler2d_explosion_nodal(C, C, N)
+    h = abi.aderdg2d_lim_init(abi.lim2d_config(N, C, C, bc=bc))
+    try:
+        u = torch.tensor(u0, device=dev)
+        v = torch.zeros((C, C, Ns, Ns, 4), dtype=torch.float64, device=dev)
+        tr = torch.zeros((C, C), dtype=torch.int32, device=dev)
+        t = torch.zeros(1, dtype=torch.float64, device=dev)
+        te = torch.full((1,), 0.25, dtype=torch.float64, device=dev)
+        dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        abi.aderdg2d_lim_project(h, u, v)
+        for _ in range(40):
+            abi.aderdg2d_lim_step(h, u, v, tr, t, te, dt, st, 64)
+            torch.cuda.synchronize()
+            if float(t[0]) >= 0.25 or int(st[0]) != 0:
+                break
+        assert int(st[0]) == 0 and float(t[0]) == 0.25
+        cnt = abi.aderdg2d_lim_counters(h)
+        assert cnt[0] > 0
+    finally:
+        abi.aderdg2d_lim_free(h)
+    un, vn = u.cpu().numpy(), v.cpu().numpy()
+    assert E2.admissible(un).all() and E2.admissible(vn).all()
+    if bc == abi.LIM_PERIODIC:
+        ops = basis.build_operators(N)
+        h2 = 2.0 / C
+        a, b = dg2d.conserved_totals2d(ops, u0, h2, h2), dg2d.conserved_totals2d(ops, un, h2, h2)
+        assert np.abs(b - a).max() <= 1e-12 * np.abs(a).max()

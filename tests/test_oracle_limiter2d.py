@@ -21,6 +21,9 @@ d = 2, module oracle/limiter2d.py).
   two directions (3.5e-5 between the two orders on the data of the third
   step, N = 2 on 10^2 cells).
 * A uniform state is kept and no cell is troubled.
+* The detection / correction cascade adds a cell whose corrected state fails
+  PAD (control flow only: its physics is parity unpinned, since no small
+  configuration triggers it; the GPU's 41^2 explosion at N = 8 does).
 """
 
 import numpy as np
@@ -171,6 +174,36 @@ def test_reconstruction_is_scaled_into_the_admissible_set():
     sub = np.einsum("si,tj,ijr->str", ops.P, ops.P, u)
     assert E2.admissible(u).all() and E2.admissible(sub).all()
     assert np.abs(np.einsum("i,j,ijr->r", ops.w, ops.w, u) - v.mean(axis=(0, 1))).max() <= 1e-14
+
+
+def test_cascade_adds_cells_that_fail_after_the_exchange(monkeypatch):
+    """The detection / correction cascade: an unlimited cell whose corrected
+    state fails PAD joins the troubled cells and the correction is redone
+    with it (control flow, with a corrected state made to fail once: no small
+    configuration of the explosion triggers the cascade within 40 steps)."""
+    N, C = 2, 10
+    ops = basis.build_operators(N)
+    u0 = _explosion(C, N)
+    h = 2.0 / C
+    dt = dg2d.cfl_dt2d(ops, E2, u0, h, h, 0.4)
+    _, bad0, _ = limiter2d.limited_step2d(ops, E2, u0, dt, h, h, "periodic")
+    target = (0, 0)
+    assert not bad0[target]
+    real, calls = limiter2d._correct, []
+
+    def failing_once(ops_, pde, u_cand, bad, *rest):
+        calls.append(bad.copy())
+        u_new, v_new = real(ops_, pde, u_cand, bad, *rest)
+        if len(calls) == 1:
+            v_new = v_new.copy()
+            v_new[target][0, 0, 0] = -1.0                 # a negative density after the exchange
+        return u_new, v_new
+
+    monkeypatch.setattr(limiter2d, "_correct", failing_once)
+    _, bad1, _ = limiter2d.limited_step2d(ops, E2, u0, dt, h, h, "periodic")
+    assert len(calls) == 2 and bad1[target] and (bad1 == (bad0 | (np.arange(C)[:, None] == 0)
+                                                          & (np.arange(C)[None, :] == 0))).all()
+    assert not calls[0][target] and calls[1][target]
 
 
 # ------------------------------------------------------ planted mistakes ----
