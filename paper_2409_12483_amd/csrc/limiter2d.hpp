@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(Sub2Geo<N>::NT) lim2d_subgrid_kernel(Lim2Args 
       if (tt == 0) sf[(2 * Ns + s) * M + r] = FS[r];
       if (tt == Ns - 1) sf[(3 * Ns + s) * M + r] = FN[r];
     }
-    if (!Euler2::admissible(vn, gamma)) atomicOr(&L.cnt[2], 1ull);
+    if (!Euler2::admissible(vn, gamma)) atomicCAS(&L.cnt[2], 0ull, (unsigned long long)(L.pass + 1));
   }
 }
 
@@ -508,7 +508,27 @@ __global__ void __launch_bounds__(256) lim2d_finish_kernel(Lim2Args L) {
   if (last && c == 0 && threadIdx.x == 0) {
     if (L.cnt[2]) atomicAdd(&L.cnt[1], 1ull);
   }
-  if (bad) {
+  // a later pass recomputes a cell only if it or a face neighbour was found
+  // troubled in the previous pass, or the first-order redo began in this pass
+  bool keep = false;
+  if (L.pass > 0) {
+    bool changed = tv == L.pass + 1 || L.cnt[2] == (unsigned long long)(L.pass + 1);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int64_t jx = ix + (f == 0 ? -1 : f == 1 ? 1 : 0), jy = iy + (f == 2 ? -1 : f == 3 ? 1 : 0);
+      const bool inside = (jx >= 0 && jx < L.cx && jy >= 0 && jy < L.cy);
+      bool m1, m2;
+      const int64_t o = lim2_src(jx, L.cx, L.bc, m1) * L.cy + lim2_src(jy, L.cy, L.bc, m2);
+      changed |= (inside || L.bc == kLim2Periodic) && L.troubled[o] == L.pass + 1;
+    }
+    if (!changed) {
+      if (!last) return;                               // uniform per workgroup
+      keep = true;                                     // the previous pass's result stands
+      for (int w = threadIdx.x; w < LL * M; w += 256) U[w] = uo[w];
+    }
+  }
+  if (keep) {
+  } else if (bad) {
     // u = (R (x) R) v through the x-reconstructed [n][Ns][M] (in S's place: T is [Ns][n])
     const double* vf = L.vfv + c * S2 * M;
     for (int k = threadIdx.x; k < S2 * M; k += 256) S[k] = vf[k];
