@@ -169,3 +169,64 @@ def test_explosion_to_the_final_time(bc):
         h2 = 2.0 / C
         a, b = dg2d.conserved_totals2d(ops, u0, h2, h2), dg2d.conserved_totals2d(ops, un, h2, h2)
         assert np.abs(b - a).max() <= 1e-12 * np.abs(a).max()
+
+
+# L1 density error of the 1-D oracle at N = 9, 50 cells, CFL 0.4, d = 2, t = 0.15
+# (the limited 1-D step's Table 9 runs; the 2-D oracle reduces to it on data
+# constant along y)
+ORACLE_L1_1D = {1: 1.26e-3, 2: 4.64e-3, 3: 2.60e-3, 4: 1.40e-3}
+
+
+@pytest.mark.parametrize("test", [1, 2, 3, 4])
+def test_table9_on_the_papers_two_dimensional_mesh(test):
+    """Table 9 as the paper runs it (Sec. 2.2): the one-dimensional Riemann
+    problem on a 50 x 10 two-dimensional mesh, N = 9, free outflow, t = 0.15:
+    status 0, rho v small, and the L1 density error of every row against the
+    exact solution within 1.5x of the 1-D oracle's.  The rows are not bitwise
+    equal: (P (x) P) u of data constant along y is constant only to rounding
+    across a cell's subcell rows, the boundary rows see their mirrored halo in
+    reverse order (7e-16 after the first step), and the limiter's threshold
+    decisions amplify such differences over the 1600 steps (measured: 3e-2
+    at one node of the shock, 8.7e-4 in L1 between rows in the Sod problem,
+    against its L1 error of 1.3e-3); so the rows are compared in the L1 norm
+    against the error itself: they differ from each other by less than from
+    the exact solution."""
+    from oracle import riemann
+    _say("lim2d Table 9 on 50 x 10", test)
+    torch, dev = torch_dev()
+    N, C, Cy, T_END = 9, 50, 10, 0.15
+    Ns = 2 * N + 1
+    u0 = _rows(W.riemann_nodal(C, N, test), Cy)
+    h = abi.aderdg2d_lim_init(abi.lim2d_config(N, C, Cy, extent=(0.0, 1.0, 0.0, 0.2)))
+    try:
+        u = torch.tensor(u0, device=dev)
+        v = torch.zeros((C, Cy, Ns, Ns, 4), dtype=torch.float64, device=dev)
+        tr = torch.zeros((C, Cy), dtype=torch.int32, device=dev)
+        t = torch.zeros(1, dtype=torch.float64, device=dev)
+        te = torch.full((1,), T_END, dtype=torch.float64, device=dev)
+        dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        st = torch.zeros(1, dtype=torch.int32, device=dev)
+        abi.aderdg2d_lim_project(h, u, v)
+        for _ in range(40):
+            abi.aderdg2d_lim_step(h, u, v, tr, t, te, dt, st, 256)
+            torch.cuda.synchronize()
+            if float(t[0]) >= T_END or int(st[0]) != 0:
+                break
+        cnt = abi.aderdg2d_lim_counters(h)
+    finally:
+        abi.aderdg2d_lim_free(h)
+    assert int(st[0]) == 0 and float(t[0]) == pytest.approx(T_END, abs=1e-14)
+    gu = u.cpu().numpy()
+    assert E2.admissible(gu).all()
+    ops = basis.build_operators(N)
+    L, R = W.RIEMANN_TESTS[test]
+    exact = riemann.density(L, R, W.cell_points(C, N + 1), float(t[0]))          # [C, n]
+    rows = np.einsum("j,cyij->yci", ops.w, gu[..., 0])                           # y-mean of rho per row
+    errs = [np.einsum("k,ck->c", ops.w, np.abs(r - exact)).mean() for r in rows]
+    spread = max(np.einsum("k,ck->c", ops.w, np.abs(r - rows[0])).mean() for r in rows)
+    assert max(errs) <= 1.5 * ORACLE_L1_1D[test]
+    assert spread <= ORACLE_L1_1D[test]
+    assert np.abs(gu[..., 2]).max() <= 0.1 * np.abs(gu[..., 1]).max()
+    print(f"[result] 2-D mesh, test {test}: troubled cell-steps {cnt[0]}, first-order redo steps {cnt[1]}, "
+          f"L1(rho) per row {min(errs):.3e}..{max(errs):.3e}, row spread {spread:.2e}, "
+          f"max |rho v| {np.abs(gu[..., 2]).max():.2e}", flush=True)
