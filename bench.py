@@ -1175,6 +1175,7 @@ class Lim2Run:
 def lim2d_time_to_solution(N, C):
     """The whole run to t_final = 0.25 (Table 14's workload): GPU wall time with
     the host loop (calls of 64 steps; steps past t_final do nothing)."""
+    import torch
     r = Lim2Run(N, C)
     _sync()
     t0 = time.perf_counter()
@@ -1187,10 +1188,31 @@ def lim2d_time_to_solution(N, C):
             break
     secs = time.perf_counter() - t0
     cnt = r.abi.aderdg2d_lim_counters(r.h)
+    u_eager = r.u.clone()
     out = {"N": N, "cells": f"{C}^2", "gpu_wall_s": round(secs, 5), "calls_of_64_steps": calls,
            "t": float(r.t.item()), "status": int(r.st.item()), "troubled_cell_steps": int(cnt[0]),
            "first_order_redo_steps": int(cnt[1]), "paper_cpu_s_tjit": PAPER_LIM2D_TJIT[(N, C)]}
     r.close()
+    # the same run from a HIP graph holding one call of 64 steps (steps past t_final do nothing)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g = Lim2Run(N, C)
+        side.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            g.steps(64)
+    _sync()
+    t0 = time.perf_counter()
+    replays = 0
+    while True:
+        graph.replay()
+        replays += 1
+        side.synchronize()
+        if float(g.t.item()) >= 0.25 or int(g.st.item()) != 0:
+            break
+    out["gpu_wall_s_graph"] = round(time.perf_counter() - t0, 5)
+    out["graph_equals_eager"] = bool(torch.equal(g.u, u_eager))
+    g.close()
     return out
 
 

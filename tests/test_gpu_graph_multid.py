@@ -57,3 +57,45 @@ def test_graph_replays_equal_eager_steps(dim):
     finally:
         free(hg)
         free(he)
+
+
+def test_limited_2d_step_in_a_graph_replays_like_eager_steps():
+    """aderdg2d_lim_step enqueues kernels only as well: three replays of a
+    captured call of 4 limited steps (the explosion, troubled cells on every
+    step) against eager calls on a second handle, state, subcell averages,
+    troubled mask, time and status bitwise."""
+    print("[case] graph replay, limited 2-D step", flush=True)
+    torch, dev = torch_dev()
+    N, C = 2, 10
+    u0 = W.euler2d_explosion_nodal(C, C, N)
+
+    def make(stream):
+        h = abi.aderdg2d_lim_init(abi.lim2d_config(N, C, C), stream=stream)
+        u, t, te, dt, st = _state(torch, dev, u0)
+        v = torch.zeros((C, C, 2 * N + 1, 2 * N + 1, 4), dtype=torch.float64, device=dev)
+        tr = torch.zeros((C, C), dtype=torch.int32, device=dev)
+        abi.aderdg2d_lim_project(h, u, v)
+        return h, (u, v, tr, t, te, dt, st)
+
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        hg, g = make(side.cuda_stream)
+        side.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            abi.aderdg2d_lim_step(hg, *g, 4)
+    he, e = make(torch.cuda.current_stream().cuda_stream)
+    try:
+        for rep in range(3):
+            graph.replay()
+            side.synchronize()
+            abi.aderdg2d_lim_step(he, *e, 4)
+            torch.cuda.synchronize()
+            for a, b in zip(g, e):
+                assert torch.equal(a, b), rep
+            assert int(g[6]) == 0 and int(g[2].sum()) > 0
+            junk = torch.ones(1 << 20, device=dev).sum()      # unrelated eager work
+            assert float(junk) == float(1 << 20)
+    finally:
+        abi.aderdg2d_lim_free(hg)
+        abi.aderdg2d_lim_free(he)
