@@ -1258,8 +1258,47 @@ def lim2d_cpu_baseline(N=2, C=11, nsteps=6):
                                         "NumPy FP64, single thread"}
 
 
+def lim2d_khi(N, t_end=0.8, C=(200, 100)):
+    """The Kelvin-Helmholtz problem of Sec. 2.2 on the paper's 200 x 100 mesh
+    of [0, 2] x [0, 1] (periodic, CFL 0.4) to the time of its first figure:
+    GPU wall time with the host loop, steps, troubled cell-steps."""
+    import torch
+    from paper_2409_12483_amd import abi
+    from paper_2409_12483_amd import workloads as W
+    dev = torch.device("cuda:0")
+    cx, cy = C
+    Ns = 2 * N + 1
+    stream = torch.cuda.current_stream()
+    h = abi.aderdg2d_lim_init(abi.lim2d_config(N, cx, cy, bc=abi.LIM_PERIODIC, extent=(0.0, 2.0, 0.0, 1.0)),
+                              stream=stream.cuda_stream)
+    u = torch.tensor(W.euler2d_khi_nodal(cx, cy, N), device=dev)
+    v = torch.zeros((cx, cy, Ns, Ns, 4), dtype=torch.float64, device=dev)
+    tr = torch.zeros((cx, cy), dtype=torch.int32, device=dev)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    te = torch.full((1,), t_end, dtype=torch.float64, device=dev)
+    dt = torch.zeros_like(t)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    abi.aderdg2d_lim_project(h, u, v)
+    _sync()
+    t0 = time.perf_counter()
+    calls = 0
+    while calls < 1000:
+        abi.aderdg2d_lim_step(h, u, v, tr, t, te, dt, st, 256)
+        calls += 1
+        _sync()
+        if float(t.item()) >= t_end or int(st.item()) != 0:
+            break
+    secs = time.perf_counter() - t0
+    cnt = abi.aderdg2d_lim_counters(h)
+    abi.aderdg2d_lim_free(h)
+    return {"N": N, "cells": f"{cx}x{cy}", "t": float(t.item()), "status": int(st.item()),
+            "gpu_wall_s": round(secs, 4), "troubled_cell_steps": int(cnt[0]),
+            "first_order_redo_steps": int(cnt[1])}
+
+
 def lim2d_section(quick=False):
     out = {"throughput_n9_41": lim2d_throughput()}
+    out["khi_200x100_t0.8"] = [lim2d_khi(2), lim2d_khi(5)]
     Ns = (1, 2, 3, 5, 9) if quick else range(1, 10)
     out["paper_table14_time_to_solution"] = [lim2d_time_to_solution(N, C) for N in Ns for C in (11, 21, 31, 41)]
     out["cpu_baseline_n2"] = lim2d_cpu_baseline()

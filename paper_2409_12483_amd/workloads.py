@@ -273,6 +273,24 @@ def euler2d_explosion_nodal(cx, cy, N, r0=0.5, inside=(1.0, 1.0), outside=(0.125
     return u
 
 
+def euler2d_khi_nodal(cx, cy, N, v0=0.1, sigma=0.05 / np.sqrt(2.0), gamma=1.4):
+    """Conserved nodal data [cx, cy, N+1, N+1, 4] of the Kelvin-Helmholtz
+    problem of Sec. 2.2 on [0, 2] x [0, 1]: p = 2.5; rho = 2 and u = -0.5 in
+    the band 0.25 < y < 0.75, rho = 1 and u = +0.5 outside; v = v0 sin(4 pi x)
+    (exp(-(y - 0.25)^2 / (2 sigma^2)) + exp(-(y - 0.75)^2 / (2 sigma^2)))."""
+    xs = cell_points(cx, N + 1, 0.0, 2.0)
+    ys = cell_points(cy, N + 1, 0.0, 1.0)
+    X = np.broadcast_to(xs[:, None, :, None], (cx, cy, N + 1, N + 1))
+    Y = np.broadcast_to(ys[None, :, None, :], (cx, cy, N + 1, N + 1))
+    band = (Y > 0.25) & (Y < 0.75)
+    rho = np.where(band, 2.0, 1.0)
+    u = np.where(band, -0.5, 0.5)
+    v = v0 * np.sin(4.0 * np.pi * X) * (np.exp(-(Y - 0.25) ** 2 / (2 * sigma ** 2))
+                                        + np.exp(-(Y - 0.75) ** 2 / (2 * sigma ** 2)))
+    p = np.full_like(rho, 2.5)
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)], axis=-1)
+
+
 def euler2d_sine_averages(cx, cy, amp=0.5, kx=1, ky=1, velocity=(1.0, 1.0), pressure=1.0, gamma=1.4,
                           npts=16, t=0.0):
     """Cell averages v[Cx, Cy, 4] of the 2-D sine wave (conserved variables) at

@@ -230,3 +230,11 @@ def test_table9_on_the_papers_two_dimensional_mesh(test):
     print(f"[result] 2-D mesh, test {test}: troubled cell-steps {cnt[0]}, first-order redo steps {cnt[1]}, "
           f"L1(rho) per row {min(errs):.3e}..{max(errs):.3e}, row spread {spread:.2e}, "
           f"max |rho v| {np.abs(gu[..., 2]).max():.2e}", flush=True)
+
+
+def test_khi_matches_oracle():
+    """The Kelvin-Helmholtz problem of Sec. 2.2 (periodic, [0, 2] x [0, 1]) on
+    16 x 8 cells, N = 2, 3 steps: state, averages and time to 1e-12."""
+    _say("lim2d KHI")
+    u0 = W.euler2d_khi_nodal(16, 8, 2)
+    _check(u0, 2, abi.LIM_PERIODIC, 3, extent=(0.0, 2.0, 0.0, 1.0))
