@@ -1359,6 +1359,10 @@ def main():
                     help="the paper's 3-D DG timing runs on every mesh for N = 6..9 too (about a minute more)")
     ap.add_argument("--fv3d-only", action="store_true",
                     help="only the 3-D ADER-WENO workloads (128^3 throughput, the paper's WENO timing meshes)")
+    ap.add_argument("--khi-only", action="store_true",
+                    help="only the Kelvin-Helmholtz runs of the limited 2-D step (200 x 100 cells)")
+    ap.add_argument("--khi-t-end", type=float, default=0.8, help="end time of the --khi-only runs")
+    ap.add_argument("--khi-degrees", default="2,5", help="comma-separated degrees of the --khi-only runs")
     ap.add_argument("--lim2d-only", action="store_true",
                     help="only the limited 2-D step (explosion: throughput at N = 9 on 41^2, Table 14 runs)")
     ap.add_argument("--limiter-only", action="store_true",
@@ -1379,7 +1383,7 @@ def main():
     # forked, which must happen before this process touches the GPU
     cpu = None
     if not a.no_cpu_baseline and not (a.dg2d_only or a.dg3d_only or a.limiter_only or a.fv2d_only or a.fv3d_only or a.autotune_only
-                                          or a.fp32_predictor_only or a.lim2d_only):
+                                          or a.fp32_predictor_only or a.lim2d_only or a.khi_only):
         cpu = cpu_baseline(N)
         emit("cpu_baseline", cpu)
 
@@ -1405,6 +1409,9 @@ def main():
         return
     if a.lim2d_only:
         print(json.dumps({"lim2d_explosion": lim2d_section()}))
+        return
+    if a.khi_only:
+        print(json.dumps({"khi_200x100": [lim2d_khi(int(k), t_end=a.khi_t_end) for k in a.khi_degrees.split(",")]}))
         return
     if a.autotune_only:
         print(json.dumps({"autotune": autotune_section()}))
