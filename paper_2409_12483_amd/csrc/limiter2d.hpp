@@ -247,11 +247,13 @@ __global__ void __launch_bounds__(Sub2Geo<N>::NT) lim2d_subgrid_kernel(Lim2Args 
   double* const va = buf;                     // [E][E][M]
   double* const wx = buf + G::VA;             // [H (x)][E (y)][2 (x node)][M]
   double* const trx = buf;                    // [H][H][2 faces][2 time][2 nodes][M] (after the sweeps)
+  const int64_t c = blockIdx.x;
+  // found troubled in this pass (uniform per workgroup); checked before the
+  // step size, whose read and barrier would otherwise cost every idle workgroup
+  if (L.troubled[c] != L.pass + 1) return;
   double t;
   const double dt = step_dt2d<N>(L.dg, t, bc2, false);
   if (!(dt > 0.0)) return;
-  const int64_t c = blockIdx.x;
-  if (L.troubled[c] != L.pass + 1) return;    // found troubled in this pass (uniform per workgroup)
   const int64_t ix = c / L.cy, iy = c - ix * L.cy;
   const double gamma = L.dg.gamma, gm1 = gamma - 1.0;
   const double dxs = L.dg.dx / Ns, dys = L.dg.dy / Ns;
@@ -435,13 +437,13 @@ template <int N>
 __global__ void __launch_bounds__(256) lim2d_subgrid0_kernel(Lim2Args L) {
   constexpr int Ns = 2 * N + 1, M = 4;
   __shared__ double bc2[2];
-  double t;
-  const double dt = step_dt2d<N>(L.dg, t, bc2, false);
-  if (!(dt > 0.0)) return;
-  if (!L.cnt[2]) return;
+  if (!L.cnt[2]) return;                       // no redo this step (checked before the step size)
   const int64_t c = blockIdx.x;
   const int tv = L.troubled[c];
   if (tv < 1 || tv > L.pass + 1) return;
+  double t;
+  const double dt = step_dt2d<N>(L.dg, t, bc2, false);
+  if (!(dt > 0.0)) return;
   const int64_t ix = c / L.cy, iy = c - ix * L.cy;
   const double gamma = L.dg.gamma;
   const double cx_ = dt / (L.dg.dx / Ns), cy_ = dt / (L.dg.dy / Ns);
@@ -486,6 +488,23 @@ __global__ void __launch_bounds__(256) lim2d_subgrid0_kernel(Lim2Args L) {
 }
 
 // ------------------------------------------------------------- finish ----
+// Whether pass L.pass can change cell c's result: it or a face neighbour was
+// found troubled in the previous pass, or the first-order redo began in this
+// pass.
+__device__ __forceinline__ bool lim2_changed(const Lim2Args& L, int64_t c) {
+  const int64_t ix = c / L.cy, iy = c - ix * L.cy;
+  bool changed = L.troubled[c] == L.pass + 1 || L.cnt[2] == (unsigned long long)(L.pass + 1);
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int64_t jx = ix + (f == 0 ? -1 : f == 1 ? 1 : 0), jy = iy + (f == 2 ? -1 : f == 3 ? 1 : 0);
+    const bool inside = (jx >= 0 && jx < L.cx && jy >= 0 && jy < L.cy);
+    bool m1, m2;
+    const int64_t o = lim2_src(jx, L.cx, L.bc, m1) * L.cy + lim2_src(jy, L.cy, L.bc, m2);
+    changed |= (inside || L.bc == kLim2Periodic) && L.troubled[o] == L.pass + 1;
+  }
+  return changed;
+}
+
 template <int N>
 __global__ void __launch_bounds__(256) lim2d_finish_kernel(Lim2Args L) {
   constexpr int n = N + 1, LL = n * n, M = 4, Ns = 2 * N + 1, S2 = Ns * Ns;
@@ -494,10 +513,13 @@ __global__ void __launch_bounds__(256) lim2d_finish_kernel(Lim2Args L) {
   __shared__ double dG[4][n * M];
   __shared__ double part[8], bc2[2], mean[M];
   __shared__ int okf;
+  const int64_t c = blockIdx.x, ix = c / L.cy, iy = c - ix * L.cy;
+  // a middle pass leaves an unchanged cell alone; decided before the step size,
+  // whose read and barrier would otherwise cost every idle workgroup
+  if (L.pass > 0 && L.pass < L.npass - 1 && !lim2_changed(L, c)) return;
   double t;
   const double dt = step_dt2d<N>(L.dg, t, bc2, false);
   if (!(dt > 0.0)) return;
-  const int64_t c = blockIdx.x, ix = c / L.cy, iy = c - ix * L.cy;
   const int64_t py = L.cy + 2;
   const double* const up = L.up + ((ix + 1) * py + iy + 1) * LL * M;    // the candidate
   double* const uo = L.uout + c * LL * M;
@@ -511,21 +533,9 @@ __global__ void __launch_bounds__(256) lim2d_finish_kernel(Lim2Args L) {
   // a later pass recomputes a cell only if it or a face neighbour was found
   // troubled in the previous pass, or the first-order redo began in this pass
   bool keep = false;
-  if (L.pass > 0) {
-    bool changed = tv == L.pass + 1 || L.cnt[2] == (unsigned long long)(L.pass + 1);
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const int64_t jx = ix + (f == 0 ? -1 : f == 1 ? 1 : 0), jy = iy + (f == 2 ? -1 : f == 3 ? 1 : 0);
-      const bool inside = (jx >= 0 && jx < L.cx && jy >= 0 && jy < L.cy);
-      bool m1, m2;
-      const int64_t o = lim2_src(jx, L.cx, L.bc, m1) * L.cy + lim2_src(jy, L.cy, L.bc, m2);
-      changed |= (inside || L.bc == kLim2Periodic) && L.troubled[o] == L.pass + 1;
-    }
-    if (!changed) {
-      if (!last) return;                               // uniform per workgroup
-      keep = true;                                     // the previous pass's result stands
-      for (int w = threadIdx.x; w < LL * M; w += 256) U[w] = uo[w];
-    }
+  if (L.pass > 0 && !lim2_changed(L, c)) {
+    keep = true;                                       // last pass: the previous pass's result stands
+    for (int w = threadIdx.x; w < LL * M; w += 256) U[w] = uo[w];
   }
   if (keep) {
   } else if (bad) {
