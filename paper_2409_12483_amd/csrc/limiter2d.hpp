@@ -26,7 +26,7 @@
 // cascade): an unlimited cell whose corrected state fails PAD is marked with
 // the next pass's number and recomputed like the others; troubled[c] holds
 // the pass in which a cell was found troubled (1 = by the detectors).  The
-// passes write uout / vout; a commit kernel copies the last one back.
+// passes write uout / vout; the last one also writes the step's result back.
 #pragma once
 
 #include "launch_lim.hpp"
@@ -648,25 +648,15 @@ __global__ void __launch_bounds__(256) lim2d_finish_kernel(Lim2Args L) {
   for (int w = threadIdx.x; w < S2; w += 256) badu |= !Euler2::admissible(vc + w * M, L.dg.gamma);
   if (__any(badu) && (threadIdx.x & 63) == 0)
     atomicMin(&L.dg.clk->stat[(blockIdx.x + (threadIdx.x >> 6)) % kSlots].v, -5);
+  // the step's result: the state into the padded state's interior (this cell's
+  // candidate is no longer read), the subcell averages into v (read by no
+  // kernel of this pass)
+  double* const upw = L.up + ((ix + 1) * py + iy + 1) * LL * M;
+  for (int w = threadIdx.x; w < LL * M; w += 256) upw[w] = U[w];
+  for (int k = threadIdx.x; k < S2 * M; k += 256) L.v[c * S2 * M + k] = vc[k];
   double lx, ly;
   subcell_speeds<N>(U, V1, 1, L.dg.gamma, lx, ly);
   publish_lambda(*L.dg.clk, (L.dg.step + 1) % 3, lx, ly, part);
-}
-
-// The last pass's state and subcell averages become the step's result.
-__global__ void __launch_bounds__(256) lim2d_commit_kernel(Lim2Args L, int per_cell, int per_cell_v) {
-  double t;
-  __shared__ double bc2[2];
-  const double dt = step_dt2d<1>(L.dg, t, bc2, false);   // degree-independent: only dt > 0 matters
-  if (!(dt > 0.0)) return;
-  const int64_t py = L.cy + 2, cells = L.cx * L.cy;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cells * per_cell; e += (int64_t)gridDim.x * 256) {
-    const int64_t c = e / per_cell, k = e - c * per_cell;
-    const int64_t ix = c / L.cy, iy = c - ix * L.cy;
-    L.up[((ix + 1) * py + iy + 1) * per_cell + k] = L.uout[e];
-  }
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < cells * per_cell_v; e += (int64_t)gridDim.x * 256)
-    L.v[e] = L.vout[e];
 }
 
 // ----------------------------------------------------------- launchers ----
@@ -719,12 +709,7 @@ static hipError_t lim2_after(const Lim2Args& L0, hipStream_t st) {
     hipLaunchKernelGGL((lim2d_finish_kernel<N>), grid, dim3(256), 0, st, L);
     e = hipGetLastError();
   }
-  if (e != hipSuccess) return e;
-  constexpr int n = N + 1, Ns = 2 * N + 1;
-  int64_t blocks = (L0.cx * L0.cy * Ns * Ns * 4 + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(lim2d_commit_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L0, n * n * 4, Ns * Ns * 4);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_lim2d_after_candidate(const Lim2Args& L, hipStream_t st) {
