@@ -284,3 +284,25 @@ def test_invalid_limiter_configs_are_rejected(mutate, needle):
     assert rc == abi.ADERDG_E_INVAL and h.value is None
     assert needle in abi.aderdg_last_error()
     assert abi.load().aderdg_lim_free(None) == abi.ADERDG_OK
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda c: setattr(c, "N", 0), "N must"),
+    (lambda c: setattr(c, "N", 10), "N must"),
+    (lambda c: setattr(c, "bc", 2), "bc must"),
+    (lambda c: setattr(c, "cells_x", 2), "cells_x"),
+    (lambda c: setattr(c, "cells_y", 70000), "cells_x"),
+    (lambda c: setattr(c, "y1", -3.0), "domain"),
+    (lambda c: setattr(c, "gamma", 1.0), "gamma"),
+    (lambda c: setattr(c, "cfl", 1.5), "cfl"),
+    (lambda c: setattr(c, "picard_tol", float("nan")), "picard_tol"),
+    (lambda c: setattr(c, "reserved", 2), "reserved"),
+])
+def test_invalid_2d_limiter_configs_are_rejected(mutate, needle):
+    cfg = abi.lim2d_config(3, 12, 10)
+    mutate(cfg)
+    h = ctypes.c_void_p()
+    rc = abi.load().aderdg2d_lim_init(ctypes.byref(cfg), None, ctypes.byref(h))
+    assert rc == abi.ADERDG_E_INVAL and h.value is None
+    assert needle in abi.aderdg_last_error()
+    assert abi.load().aderdg2d_lim_free(None) == abi.ADERDG_OK
