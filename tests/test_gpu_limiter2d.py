@@ -2,9 +2,10 @@
 oracle (oracle/limiter2d.py), through the C ABI.
 
 * The cylindrical explosion of Sec. 2.2 (troubled cells along the circle),
-  periodic and free-outflow boundaries, N = 1, 2, 3, 5 and 9: the state, the
-  subcell averages and the time after several steps to 1e-12 relative (max
-  norm), the troubled cells of the last step equal.
+  periodic and free-outflow boundaries, N = 1, 2, 3, 5 and 9, and on cells of
+  unequal sides: the state, the subcell averages and the time after several
+  steps to 1e-12 relative (max norm), the troubled cells of the last step
+  equal.
 * A Table 9 Riemann problem constant along y (and along x): the same.
 * A uniform state: kept, nothing troubled.
 * Invalid configurations are refused.
@@ -238,3 +239,13 @@ def test_khi_matches_oracle():
     _say("lim2d KHI")
     u0 = W.euler2d_khi_nodal(16, 8, 2)
     _check(u0, 2, abi.LIM_PERIODIC, 3, extent=(0.0, 2.0, 0.0, 1.0))
+
+
+@pytest.mark.parametrize("bc", [abi.LIM_PERIODIC, abi.LIM_TRANSMISSIVE])
+def test_explosion_on_cells_of_unequal_sides(bc):
+    """The explosion on 12 x 8 cells of [-1, 1] x [-0.7, 0.7] (dx = 1/6,
+    dy = 0.175), N = 3, 3 steps: state, averages and time to 1e-12."""
+    _say("lim2d explosion, unequal sides", bc)
+    extent = (-1.0, 1.0, -0.7, 0.7)
+    u0 = W.euler2d_explosion_nodal(12, 8, 3, extent=extent)
+    assert _check(u0, 3, bc, 3, extent=extent) > 0
