@@ -25,7 +25,10 @@
  *     cell's flux at face node k is replaced by
  *     sum_s F_s (integral of phi_k over sub-face s) / (N_s w_k), F_s the
  *     subgrid fluxes of the face's N_s sub-faces: every face carries one
- *     flux, and the totals telescope.
+ *     flux, and the totals telescope;
+ *   - detection / correction cascade: an unlimited cell whose state after
+ *     that exchange fails PAD joins the limited cells and the correction is
+ *     redone, three passes at most.
  *
  * Conventions (as in aderdg.h): int32 status, 0 = ADERDG_OK, negative =
  * error (codes of aderdg.h); on ADERDG_E_INVAL nothing was enqueued and
@@ -38,7 +41,10 @@
  * ix * cells_y + iy):
  *   u         [cells_x][cells_y][N+1 (x node)][N+1 (y node)][4]      fp64
  *   v         [cells_x][cells_y][2N+1 (x subcell)][2N+1 (y subcell)][4]  fp64
- *   troubled  [cells_x][cells_y]                  int32, 1 = limited in the last step
+ *   troubled  [cells_x][cells_y]                  int32, nonzero = limited in the last step:
+ *             1 = found by the detectors, 2 or 3 = added by the detection /
+ *             correction cascade (an unlimited cell whose state after the flux
+ *             exchange failed PAD; the pass that added it)
  */
 #ifndef ADERDG_LIM2D_H
 #define ADERDG_LIM2D_H
@@ -77,7 +83,7 @@ int aderdg2d_lim_project(aderdg2d_lim_handle* h, const double* u, double* v);
 
 /* nsteps limited steps of u (in/out), v (in/out: the subcell averages of the
  * step's start, then of its end: P u for unlimited cells, the subgrid result
- * for limited ones) and troubled (out).  t (in/out), t_end (in), dt (out),
+ * for limited ones) and troubled (out, the last step's).  t (in/out), t_end (in), dt (out),
  * status (out): device arrays of one value, as in aderdg2d_step; status is
  * ADERDG_E_NONPHYS if a subcell average of a final state leaves the admissible
  * set (the limiter keeps those admissible; a polynomial may dip below zero at
