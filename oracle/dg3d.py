@@ -59,6 +59,11 @@ class Euler3D:
         rho, vel, p = self.primitives(Q)
         return np.abs(vel[d]) + np.sqrt(self.gamma * p / rho)
 
+    def admissible(self, Q):
+        """rho > 0 and p > 0 (and finite): the physical admissibility of Sec. 1.6."""
+        rho, vel, p = self.primitives(Q)
+        return np.isfinite(Q).all(axis=-1) & (rho > 0) & (p > 0)
+
 
 def rusanov(pde, qm, qp, d):
     """Rusanov flux across a face of normal +e_d (qm on the minus side); parity unpinned."""
@@ -110,6 +115,23 @@ def predict3d(ops, pde, u, dt, h, tol=1e-14, max_iter=64):
     return (q_prev.reshape(shape + (n, n, n, n, M)), sweeps.reshape(shape), failed.reshape(shape))
 
 
+def face_fluxes3d(ops, pde, q, dt, h):
+    """Time-integrated Rusanov fluxes through the + face of every cell along
+    each direction d, scaled by dt/h_d: [Cx, Cy, Cz, n, n, M] per d, the two
+    face-node indices in the order of the remaining axes (periodic
+    neighbours); q [Cx, Cy, Cz, n (time), n, n, n, M]."""
+    w = ops.w
+    out = []
+    for d in range(3):
+        # traces on the minus (psi) and plus (psi~) faces along d: [Cx, Cy, Cz, a, ., ., M]
+        sub = ["p,xyzapjkr->xyzajkr", "p,xyzaipkr->xyzaikr", "p,xyzaijpr->xyzaijr"][d]
+        lo = np.einsum(sub, ops.psi0, q)
+        hi = np.einsum(sub, ops.psi1, q)
+        G = (dt / h[d]) * rusanov(pde, hi, np.roll(lo, -1, axis=d), d)   # through the + face of each cell
+        out.append(np.einsum("a,xyzastr->xyzstr", w, G))
+    return out
+
+
 def correct3d(ops, pde, u, q, dt, h):
     """u^{n+1} from u^n and the predictor (eq. ader_dg_method_full, d = 3)."""
     w = ops.w
@@ -124,14 +146,9 @@ def correct3d(ops, pde, u, q, dt, h):
         fbar = np.einsum("a,caijkr->cijkr", w, f)                                   # time quadrature
         sub = ["il,cljkr->cijkr", "jl,cilkr->cijkr", "kl,cijlr->cijkr"][d]
         out = out + np.einsum(sub, ops.Dtil, fbar) / w.reshape(wshape[d])
-    qg = q.reshape((Cx, Cy, Cz, n, n, n, n, M))
+    faces = face_fluxes3d(ops, pde, q.reshape((Cx, Cy, Cz, n, n, n, n, M)), dt, h)
     for d in range(3):
-        # traces on the minus (psi) and plus (psi~) faces along d: [Cx, Cy, Cz, a, ., ., M]
-        sub = ["p,xyzapjkr->xyzajkr", "p,xyzaipkr->xyzaikr", "p,xyzaijpr->xyzaijr"][d]
-        lo = np.einsum(sub, ops.psi0, qg)
-        hi = np.einsum(sub, ops.psi1, qg)
-        G = (dt / h[d]) * rusanov(pde, hi, np.roll(lo, -1, axis=d), d)   # through the + face of each cell
-        Gbar = np.einsum("a,xyzast r->xyzstr".replace(" ", ""), w, G)     # [Cx, Cy, Cz, ., ., M]
+        Gbar = faces[d]                                                    # [Cx, Cy, Cz, ., ., M]
         Gm = np.roll(Gbar, 1, axis=d)                                      # through the - face
         Gp = Gbar.reshape((-1,) + Gbar.shape[3:])
         Gm = Gm.reshape((-1,) + Gm.shape[3:])

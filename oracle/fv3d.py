@@ -47,11 +47,15 @@ def fv3d_dt(pde, v, h, cfl):
     return cfl / 3.0 * min(h[d] / float(pde.speed(v, d).max()) for d in range(3))
 
 
-def fv3d_step(ops, pde, v, dt, h, tol=1e-14, max_iter=64):
+def fv3d_step(ops, pde, v, dt, h, tol=1e-14, max_iter=64, fluxes=False):
+    """One ADER-WENO step of the averages; returns (v_new, sweeps, failed), and
+    with fluxes=True also the integrated fluxes through the + face of every
+    cell along x, y and z ([Cx, Cy, Cz, M] each)."""
     w_hat = reconstruct3d(v, ops)
     q, sweeps, failed = predict3d(ops, pde, w_hat, dt, h, tol, max_iter)
     w = ops.w
     v_new = np.array(v, dtype=np.float64, copy=True)
+    Fs = []
     for d in range(3):
         sub = ["p,xyzapjkr->xyzajkr", "p,xyzaipkr->xyzaikr", "p,xyzaijpr->xyzaijr"][d]
         lo = np.einsum(sub, ops.psi0, q)
@@ -59,6 +63,9 @@ def fv3d_step(ops, pde, v, dt, h, tol=1e-14, max_iter=64):
         G = (dt / h[d]) * rusanov(pde, hi, np.roll(lo, -1, axis=d), d)          # + face of every cell
         F = np.einsum("a,s,t,xyzastr->xyzr", w, w, w, G)
         v_new = v_new - (F - np.roll(F, 1, axis=d))
+        Fs.append(F)
+    if fluxes:
+        return v_new, sweeps, failed, Fs
     return v_new, sweeps, failed
 
 
